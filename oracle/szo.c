@@ -1,0 +1,830 @@
+/*
+ * szo.c -- the CPU oracle (see szo.h for what it is and what it follows).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain single-threaded C, no SIMD intrinsics,
+ * compiled with -O2 -ffp-contract=off -fno-fast-math.  Nothing here is
+ * shared with the GPU library.
+ */
+#include "szo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define SZO_MAXD 4
+#define SZO_NONE UINT64_MAX
+#define SZO_MAX_POINTS 0xFFFFFFFFull /* the format's point limit */
+
+/* ------------------------------------------------------------------ */
+/* Grid and the multilevel traversal                                   */
+/* ------------------------------------------------------------------ */
+
+struct szo_grid {
+  int ndim;
+  uint64_t dims[SZO_MAXD];
+  uint64_t strides[SZO_MAXD]; /* row-major: the last dimension is contiguous */
+  uint8_t order[SZO_MAXD];    /* the order in which dimensions are visited */
+  int pos[SZO_MAXD];          /* pos[d] = index of d in order */
+  uint64_t n;
+  int levels; /* L = max over d of ceil(log2 dims[d]) */
+};
+
+/* One pass = one (level, dimension) pair.  The multilevel interpolation of
+ * SZ3-Interp (Section 6.2) goes from the coarsest level to the finest and,
+ * inside a level, dimension by dimension.  Reading of the level structure
+ * (the defining reference is not part of the paper): level l has stride
+ * s = 2^(l-1), l = L..1.  The pass of dimension d = order[j] at stride s
+ * visits the points whose coordinate along d is an odd multiple of s, whose
+ * coordinates along the dimensions visited earlier in this level are
+ * multiples of s, and whose coordinates along the dimensions visited later
+ * are multiples of 2s.  With the origin handled first, every point is
+ * visited exactly once, and every stencil point (+-s, +-3s along d) lies on
+ * a coarser level or in an earlier pass of the same level. */
+struct szo_pass {
+  int level;
+  int j;
+  int d;
+  uint64_t s;
+  uint64_t start[SZO_MAXD];
+  uint64_t step[SZO_MAXD];
+};
+
+static int grid_init(struct szo_grid* g, int ndim, const uint64_t* dims,
+                     const uint8_t* order) {
+  if (ndim < 1 || ndim > SZO_MAXD || !dims) return SZO_ERR_ARG;
+  memset(g, 0, sizeof(*g));
+  g->ndim = ndim;
+  uint64_t n = 1;
+  int any_zero = 0;
+  for (int d = 0; d < ndim; d++) {
+    g->dims[d] = dims[d];
+    if (dims[d] == 0) any_zero = 1;
+  }
+  if (any_zero) {
+    n = 0;
+  } else {
+    for (int d = 0; d < ndim; d++) {
+      if (dims[d] > SZO_MAX_POINTS || n > SZO_MAX_POINTS / dims[d])
+        return SZO_ERR_ARG;
+      n *= dims[d];
+    }
+  }
+  g->n = n;
+  uint64_t st = 1;
+  for (int d = ndim - 1; d >= 0; d--) {
+    g->strides[d] = st;
+    st *= (dims[d] ? dims[d] : 1);
+  }
+  int seen[SZO_MAXD] = {0, 0, 0, 0};
+  for (int j = 0; j < ndim; j++) {
+    int d = order ? order[j] : j;
+    if (d < 0 || d >= ndim || seen[d]) return SZO_ERR_ARG;
+    seen[d] = 1;
+    g->order[j] = (uint8_t)d;
+    g->pos[d] = j;
+  }
+  for (int j = ndim; j < SZO_MAXD; j++) g->order[j] = (uint8_t)j;
+  int L = 0;
+  for (int d = 0; d < ndim; d++) {
+    int l = 0;
+    while (l < 63 && (1ull << l) < dims[d]) l++;
+    if (l > L) L = l;
+  }
+  g->levels = (n == 0) ? 0 : L;
+  return SZO_OK;
+}
+
+static void pass_setup(const struct szo_grid* g, struct szo_pass* p) {
+  p->s = 1ull << (p->level - 1);
+  p->d = g->order[p->j];
+  for (int e = 0; e < g->ndim; e++) {
+    if (e == p->d) {
+      p->start[e] = p->s;
+      p->step[e] = 2 * p->s;
+    } else if (g->pos[e] < p->j) {
+      p->start[e] = 0;
+      p->step[e] = p->s;
+    } else {
+      p->start[e] = 0;
+      p->step[e] = 2 * p->s;
+    }
+  }
+}
+
+static int pass_first(const struct szo_grid* g, struct szo_pass* p) {
+  if (g->levels == 0) return 0;
+  p->level = g->levels;
+  p->j = 0;
+  pass_setup(g, p);
+  return 1;
+}
+
+static int pass_next(const struct szo_grid* g, struct szo_pass* p) {
+  p->j++;
+  if (p->j == g->ndim) {
+    p->j = 0;
+    p->level--;
+    if (p->level == 0) return 0;
+  }
+  pass_setup(g, p);
+  return 1;
+}
+
+static uint64_t flat_of(const struct szo_grid* g, const uint64_t* q) {
+  uint64_t f = 0;
+  for (int e = 0; e < g->ndim; e++) f += q[e] * g->strides[e];
+  return f;
+}
+
+static uint64_t pass_point_first(const struct szo_grid* g,
+                                 const struct szo_pass* p, uint64_t* q) {
+  for (int e = 0; e < g->ndim; e++) {
+    q[e] = p->start[e];
+    if (q[e] >= g->dims[e]) return SZO_NONE;
+  }
+  return flat_of(g, q);
+}
+
+/* row-major odometer over the pass's sub-lattice */
+static uint64_t pass_point_next(const struct szo_grid* g,
+                                const struct szo_pass* p, uint64_t* q) {
+  for (int e = g->ndim - 1; e >= 0; e--) {
+    q[e] += p->step[e];
+    if (q[e] < g->dims[e]) return flat_of(g, q);
+    q[e] = p->start[e];
+  }
+  return SZO_NONE;
+}
+
+/* ------------------------------------------------------------------ */
+/* Typed arithmetic                                                    */
+/* ------------------------------------------------------------------ */
+
+#define T float
+#define FN(name) name##_f32
+#define FABS fabsf
+#define RINT rintf
+#include "szo_typed.inc"
+#undef T
+#undef FN
+#undef FABS
+#undef RINT
+
+#define T double
+#define FN(name) name##_f64
+#define FABS fabs
+#define RINT rint
+#include "szo_typed.inc"
+#undef T
+#undef FN
+#undef FABS
+#undef RINT
+
+static size_t type_size(int dtype) { return dtype == SZO_F64 ? 8 : 4; }
+
+int szo_resolve_eb(const void* x, uint64_t n, int dtype, int eb_mode,
+                   double value, double* eb_t) {
+  if (dtype != SZO_F32 && dtype != SZO_F64) return SZO_ERR_ARG;
+  if (eb_mode != SZO_ABS && eb_mode != SZO_REL) return SZO_ERR_ARG;
+  if (dtype == SZO_F32) return resolve_eb_f32((const float*)x, n, eb_mode, value, eb_t);
+  return resolve_eb_f64((const double*)x, n, eb_mode, value, eb_t);
+}
+
+static int check_common(int dtype, int predictor, uint32_t radius) {
+  if (dtype != SZO_F32 && dtype != SZO_F64) return SZO_ERR_ARG;
+  if (predictor != SZO_LINEAR && predictor != SZO_CUBIC) return SZO_ERR_ARG;
+  if (radius < 1 || radius > SZO_MAX_RADIUS) return SZO_ERR_ARG;
+  return SZO_OK;
+}
+
+int szo_predict_quantize(const void* x, int dtype, int ndim,
+                         const uint64_t* dims, const uint8_t* order,
+                         int predictor, double eb_t, uint32_t radius,
+                         uint16_t* codes, void* recon) {
+  struct szo_grid g;
+  int rc = check_common(dtype, predictor, radius);
+  if (rc) return rc;
+  if ((rc = grid_init(&g, ndim, dims, order))) return rc;
+  if (!(eb_t >= 0.0) || !isfinite(eb_t)) return SZO_ERR_ARG;
+  if (dtype == SZO_F32)
+    return predict_quantize_f32((const float*)x, &g, predictor, (float)eb_t,
+                                radius, codes, (float*)recon);
+  return predict_quantize_f64((const double*)x, &g, predictor, eb_t, radius,
+                              codes, (double*)recon);
+}
+
+int szo_reconstruct(const uint16_t* codes, const void* unpred,
+                    uint64_t n_unpred, int dtype, int ndim,
+                    const uint64_t* dims, const uint8_t* order, int predictor,
+                    double eb_t, uint32_t radius, void* out) {
+  struct szo_grid g;
+  int rc = check_common(dtype, predictor, radius);
+  if (rc) return rc;
+  if ((rc = grid_init(&g, ndim, dims, order))) return rc;
+  if (dtype == SZO_F32)
+    return reconstruct_f32(codes, (const float*)unpred, n_unpred, &g,
+                           predictor, (float)eb_t, radius, (float*)out);
+  return reconstruct_f64(codes, (const double*)unpred, n_unpred, &g, predictor,
+                         eb_t, radius, (double*)out);
+}
+
+int szo_quantize_one(int dtype, const void* x, const void* pred, double eb_t,
+                     uint32_t radius, uint16_t* code, void* recon) {
+  if (radius < 1 || radius > SZO_MAX_RADIUS) return SZO_ERR_ARG;
+  if (dtype == SZO_F32) {
+    float eb = (float)eb_t, twoeb = 2.0f * eb, inv = 1.0f / twoeb;
+    *code = quantize_f32(*(const float*)x, *(const float*)pred, eb, twoeb, inv,
+                         radius, (float*)recon);
+    return SZO_OK;
+  }
+  if (dtype == SZO_F64) {
+    double eb = eb_t, twoeb = 2.0 * eb, inv = 1.0 / twoeb;
+    *code = quantize_f64(*(const double*)x, *(const double*)pred, eb, twoeb,
+                         inv, radius, (double*)recon);
+    return SZO_OK;
+  }
+  return SZO_ERR_ARG;
+}
+
+/* Which stencil points the predictor reads: the same case analysis as
+ * predict_*() in szo_typed.inc, without data. */
+static int stencil_offsets(uint64_t i, uint64_t s, uint64_t nd, int predictor,
+                           int64_t* off) {
+  int k = 0;
+  int has_a = i >= 3 * s, has_c = i + s < nd, has_e = i + 3 * s < nd;
+  off[k++] = -1;
+  if (!has_c) {
+    if (has_a) off[k++] = -3;
+    return k;
+  }
+  off[k++] = 1;
+  if (predictor == SZO_LINEAR) return k;
+  if (has_a && has_e) {
+    off[k++] = -3;
+    off[k++] = 3;
+  } else if (has_e) {
+    off[k++] = 3;
+  } else if (has_a) {
+    off[k++] = -3;
+  }
+  return k;
+}
+
+int szo_check_traversal(int ndim, const uint64_t* dims, const uint8_t* order,
+                        int predictor, uint32_t* visits,
+                        uint64_t* early_reads) {
+  struct szo_grid g;
+  int rc = grid_init(&g, ndim, dims, order);
+  if (rc) return rc;
+  *early_reads = 0;
+  if (g.n == 0) return SZO_OK;
+  /* pass index at which each point became final; UINT32_MAX = not yet */
+  uint32_t* fin = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)g.n);
+  if (!fin) return SZO_ERR_NOMEM;
+  for (uint64_t f = 0; f < g.n; f++) {
+    fin[f] = UINT32_MAX;
+    visits[f] = 0;
+  }
+  visits[0]++;
+  fin[0] = 0;
+  uint32_t pass_id = 1;
+  struct szo_pass p;
+  for (int more = pass_first(&g, &p); more; more = pass_next(&g, &p), pass_id++) {
+    uint64_t q[SZO_MAXD];
+    for (uint64_t f = pass_point_first(&g, &p, q); f != SZO_NONE;
+         f = pass_point_next(&g, &p, q)) {
+      int64_t off[4];
+      int k = stencil_offsets(q[p.d], p.s, g.dims[p.d], predictor, off);
+      for (int t = 0; t < k; t++) {
+        int64_t c = (int64_t)q[p.d] + off[t] * (int64_t)p.s;
+        if (c < 0 || (uint64_t)c >= g.dims[p.d]) {
+          (*early_reads)++; /* out of range would be a bug too */
+          continue;
+        }
+        uint64_t nf = f + (uint64_t)(off[t] * (int64_t)p.s * (int64_t)g.strides[p.d]);
+        if (fin[nf] >= pass_id) (*early_reads)++;
+      }
+      visits[f]++;
+      if (fin[f] == UINT32_MAX) fin[f] = pass_id;
+    }
+  }
+  free(fin);
+  return SZO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Huffman stage (Section 3.2 "Encoder")                               */
+/* ------------------------------------------------------------------ */
+
+int szo_histogram(const uint16_t* codes, uint64_t n, uint32_t nsym,
+                  uint64_t* hist) {
+  memset(hist, 0, sizeof(uint64_t) * nsym);
+  for (uint64_t i = 0; i < n; i++) {
+    if (codes[i] >= nsym) return SZO_ERR_ARG;
+    hist[codes[i]]++;
+  }
+  return SZO_OK;
+}
+
+struct leaf {
+  uint64_t w;
+  uint32_t sym;
+};
+
+static int leaf_cmp(const void* a, const void* b) {
+  const struct leaf* x = (const struct leaf*)a;
+  const struct leaf* y = (const struct leaf*)b;
+  if (x->w != y->w) return x->w < y->w ? -1 : 1;
+  return x->sym < y->sym ? -1 : (x->sym > y->sym ? 1 : 0);
+}
+
+/* Greedy Huffman construction from the frequencies (Section 3.2
+ * "Encoder"), as the two-queue merge: leaves sorted by (frequency, symbol),
+ * internal nodes in a FIFO (their weights come out non-decreasing).  Each
+ * merge takes the lighter front twice, the leaf when the two fronts weigh
+ * the same.  A symbol's code length is its leaf's depth; a lone symbol gets
+ * length 1.  (Tie-breaking is a reading: the paper does not fix it.) */
+int szo_huffman_lengths(const uint64_t* hist, uint32_t nsym, uint8_t* lens) {
+  memset(lens, 0, nsym);
+  uint32_t K = 0;
+  for (uint32_t s = 0; s < nsym; s++)
+    if (hist[s]) K++;
+  if (K == 0) return 0;
+  struct leaf* lv = (struct leaf*)malloc(sizeof(struct leaf) * K);
+  if (!lv) return SZO_ERR_NOMEM;
+  K = 0;
+  for (uint32_t s = 0; s < nsym; s++)
+    if (hist[s]) {
+      lv[K].w = hist[s];
+      lv[K].sym = s;
+      K++;
+    }
+  if (K == 1) {
+    lens[lv[0].sym] = 1;
+    free(lv);
+    return 1;
+  }
+  qsort(lv, K, sizeof(struct leaf), leaf_cmp);
+  uint32_t nodes = 2 * K - 1;
+  uint64_t* w = (uint64_t*)malloc(sizeof(uint64_t) * nodes);
+  uint32_t* parent = (uint32_t*)malloc(sizeof(uint32_t) * nodes);
+  uint32_t* depth = (uint32_t*)malloc(sizeof(uint32_t) * nodes);
+  if (!w || !parent || !depth) {
+    free(lv);
+    free(w);
+    free(parent);
+    free(depth);
+    return SZO_ERR_NOMEM;
+  }
+  for (uint32_t i = 0; i < K; i++) w[i] = lv[i].w;
+  uint32_t li = 0, qi = K, qn = K;
+  while (qn < nodes) {
+    uint32_t pick[2];
+    for (int t = 0; t < 2; t++) {
+      if (li < K && (qi >= qn || w[li] <= w[qi]))
+        pick[t] = li++;
+      else
+        pick[t] = qi++;
+    }
+    w[qn] = w[pick[0]] + w[pick[1]];
+    parent[pick[0]] = qn;
+    parent[pick[1]] = qn;
+    qn++;
+  }
+  depth[nodes - 1] = 0;
+  for (uint32_t i = nodes - 1; i-- > 0;) depth[i] = depth[parent[i]] + 1;
+  int maxlen = 0;
+  int rc = 0;
+  for (uint32_t i = 0; i < K; i++) {
+    if (depth[i] > SZO_MAX_CODE_LEN) rc = SZO_ERR_ARG;
+    lens[lv[i].sym] = (uint8_t)depth[i];
+    if ((int)depth[i] > maxlen) maxlen = (int)depth[i];
+  }
+  free(lv);
+  free(w);
+  free(parent);
+  free(depth);
+  return rc ? rc : maxlen;
+}
+
+/* Canonical codes, RFC 1951 section 3.2.2: codes of one length are
+ * consecutive in symbol order, and the first code of each length follows the
+ * last code of the previous length, shifted. */
+int szo_canonical_codes(const uint8_t* lens, uint32_t nsym,
+                        uint64_t* codewords) {
+  uint64_t bl_count[SZO_MAX_CODE_LEN + 1];
+  uint64_t next_code[SZO_MAX_CODE_LEN + 1];
+  memset(bl_count, 0, sizeof(bl_count));
+  for (uint32_t s = 0; s < nsym; s++) {
+    if (lens[s] > SZO_MAX_CODE_LEN) return SZO_ERR_ARG;
+    if (lens[s]) bl_count[lens[s]]++;
+  }
+  uint64_t code = 0;
+  next_code[0] = 0;
+  for (int bits = 1; bits <= SZO_MAX_CODE_LEN; bits++) {
+    code = (code + bl_count[bits - 1]) << 1;
+    next_code[bits] = code;
+  }
+  for (uint32_t s = 0; s < nsym; s++) {
+    codewords[s] = 0;
+    if (lens[s]) codewords[s] = next_code[lens[s]]++;
+  }
+  return SZO_OK;
+}
+
+/* Chunked bit packing (reading: the paper's encoder emits one bitstream; the
+ * stream is cut into chunks of `chunk` symbols in flat order so that chunks
+ * can be decoded independently).  Inside a chunk each codeword is appended
+ * most significant bit first; stream bit b of the chunk is bit 31 - (b % 32)
+ * of the chunk's word b / 32; the chunk ends on a word boundary. */
+int szo_pack(const uint16_t* codes, uint64_t n, const uint8_t* lens,
+             const uint64_t* codewords, uint32_t chunk, uint32_t* words,
+             uint32_t* chunk_words, uint64_t* total_words) {
+  if (chunk == 0) return SZO_ERR_ARG;
+  uint64_t nchunks = (n + chunk - 1) / chunk;
+  uint64_t base = 0;
+  for (uint64_t c = 0; c < nchunks; c++) {
+    uint64_t lo = c * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    uint64_t bit = 0;
+    for (uint64_t i = lo; i < hi; i++) {
+      int len = lens[codes[i]];
+      if (len == 0) return SZO_ERR_ARG;
+      for (int b = len - 1; b >= 0; b--) {
+        if (words && ((codewords[codes[i]] >> b) & 1u))
+          words[base + (bit >> 5)] |= 0x80000000u >> (bit & 31);
+        bit++;
+      }
+    }
+    uint64_t cw = (bit + 31) / 32;
+    if (cw > UINT32_MAX) return SZO_ERR_ARG;
+    chunk_words[c] = (uint32_t)cw;
+    base += cw;
+  }
+  *total_words = base;
+  return SZO_OK;
+}
+
+/* Canonical decoding, one bit at a time: a code of length len is valid when
+ * it lies in [first[len], first[len] + count[len]). */
+struct decoder {
+  uint64_t count[SZO_MAX_CODE_LEN + 1];
+  uint64_t first[SZO_MAX_CODE_LEN + 1];
+  uint64_t offset[SZO_MAX_CODE_LEN + 1];
+  uint16_t* sorted; /* symbols sorted by (length, symbol) */
+};
+
+static int decoder_init(struct decoder* dc, const uint8_t* lens,
+                        uint32_t nsym) {
+  memset(dc, 0, sizeof(*dc));
+  uint64_t K = 0;
+  for (uint32_t s = 0; s < nsym; s++) {
+    if (lens[s] > SZO_MAX_CODE_LEN) return SZO_ERR_CORRUPT;
+    if (lens[s]) {
+      dc->count[lens[s]]++;
+      K++;
+    }
+  }
+  dc->sorted = (uint16_t*)malloc(sizeof(uint16_t) * (K ? K : 1));
+  if (!dc->sorted) return SZO_ERR_NOMEM;
+  uint64_t code = 0, off = 0;
+  for (int len = 1; len <= SZO_MAX_CODE_LEN; len++) {
+    code = (code + dc->count[len - 1]) << 1;
+    dc->first[len] = code;
+    dc->offset[len] = off;
+    off += dc->count[len];
+  }
+  uint64_t fill[SZO_MAX_CODE_LEN + 1];
+  memcpy(fill, dc->offset, sizeof(fill));
+  for (uint32_t s = 0; s < nsym; s++)
+    if (lens[s]) dc->sorted[fill[lens[s]]++] = (uint16_t)s;
+  return SZO_OK;
+}
+
+int szo_unpack(const uint32_t* words, uint64_t total_words,
+               const uint32_t* chunk_words, uint64_t n, uint32_t chunk,
+               const uint8_t* lens, uint32_t nsym, uint16_t* codes) {
+  if (chunk == 0) return SZO_ERR_ARG;
+  struct decoder dc;
+  int rc = decoder_init(&dc, lens, nsym);
+  if (rc) return rc;
+  uint64_t nchunks = (n + chunk - 1) / chunk;
+  uint64_t base = 0;
+  for (uint64_t c = 0; c < nchunks && !rc; c++) {
+    uint64_t lo = c * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    uint64_t nbits = (uint64_t)chunk_words[c] * 32;
+    if (base + chunk_words[c] > total_words) {
+      rc = SZO_ERR_CORRUPT;
+      break;
+    }
+    uint64_t bit = 0;
+    for (uint64_t i = lo; i < hi && !rc; i++) {
+      uint64_t code = 0;
+      int len = 0;
+      for (;;) {
+        if (bit >= nbits || len == SZO_MAX_CODE_LEN) {
+          rc = SZO_ERR_CORRUPT;
+          break;
+        }
+        uint32_t wv = words[base + (bit >> 5)];
+        code = (code << 1) | ((wv >> (31 - (bit & 31))) & 1u);
+        bit++;
+        len++;
+        if (dc.count[len] && code >= dc.first[len] &&
+            code - dc.first[len] < dc.count[len]) {
+          codes[i] = dc.sorted[dc.offset[len] + (code - dc.first[len])];
+          break;
+        }
+      }
+    }
+    if (!rc && (bit + 31) / 32 != chunk_words[c]) rc = SZO_ERR_CORRUPT;
+    base += chunk_words[c];
+  }
+  if (!rc && base != total_words) rc = SZO_ERR_CORRUPT;
+  free(dc.sorted);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Stream format (little-endian; sections start on 8-byte boundaries)  */
+/* ------------------------------------------------------------------ */
+/*
+ * header, 128 bytes:
+ *   0  "SZG1"            4 u16 version (1)     6 u8 dtype   7 u8 ndim
+ *   8  u64 dims[4] (unused = 1)
+ *   40 u8 predictor      41 u8 order[4]        45 u8 eb_mode  46 u16 0
+ *   48 f64 eb as given   56 f64 eb in the field type, widened
+ *   64 u32 radius        68 u32 chunk          72 u64 unpredictable count
+ *   80 u32 used symbols K                      84 u32 0
+ *   88 u64 bitstream words                     96 u64 stream bytes
+ *   104..127 zero
+ * symbol table: K x u32 (symbol | length << 16), ascending symbol
+ * chunk table:  ceil(n/chunk) x (u32 words, u32 unpredictable count)
+ * unpredictable values: count x T, flat order (the quantizer's saved state,
+ *                       Algorithm 1 "quantizer.save")
+ * bitstream:    words x u32 (Algorithm 1 "encoder.encode")
+ */
+
+static void put_u16(uint8_t* p, uint16_t v) {
+  p[0] = (uint8_t)v;
+  p[1] = (uint8_t)(v >> 8);
+}
+static void put_u32(uint8_t* p, uint32_t v) {
+  for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+static void put_u64(uint8_t* p, uint64_t v) {
+  for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+static void put_f64(uint8_t* p, double v) {
+  uint64_t u;
+  memcpy(&u, &v, 8);
+  put_u64(p, u);
+}
+static uint16_t get_u16(const uint8_t* p) {
+  return (uint16_t)(p[0] | (p[1] << 8));
+}
+static uint32_t get_u32(const uint8_t* p) {
+  uint32_t v = 0;
+  for (int i = 3; i >= 0; i--) v = (v << 8) | p[i];
+  return v;
+}
+static uint64_t get_u64(const uint8_t* p) {
+  uint64_t v = 0;
+  for (int i = 7; i >= 0; i--) v = (v << 8) | p[i];
+  return v;
+}
+static double get_f64(const uint8_t* p) {
+  uint64_t u = get_u64(p);
+  double v;
+  memcpy(&v, &u, 8);
+  return v;
+}
+static uint64_t pad8(uint64_t v) { return (v + 7) & ~7ull; }
+
+struct layout {
+  uint64_t off_sym, off_chunk, off_unpred, off_bits, size;
+};
+
+static void layout_of(uint64_t K, uint64_t nchunks, uint64_t n_unpred,
+                      size_t ts, uint64_t words, struct layout* lo) {
+  lo->off_sym = SZO_HEADER_BYTES;
+  lo->off_chunk = lo->off_sym + pad8(4 * K);
+  lo->off_unpred = lo->off_chunk + 8 * nchunks;
+  lo->off_bits = lo->off_unpred + pad8(n_unpred * ts);
+  lo->size = lo->off_bits + 4 * words;
+}
+
+int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
+                 int eb_mode, double eb, int predictor, uint32_t radius,
+                 uint32_t chunk, const uint8_t* order, uint8_t** stream,
+                 uint64_t* stream_size, uint16_t* codes_out, void* recon_out) {
+  struct szo_grid g;
+  int rc = check_common(dtype, predictor, radius);
+  if (rc) return rc;
+  if (chunk == 0) return SZO_ERR_ARG;
+  if (eb_mode != SZO_ABS && eb_mode != SZO_REL) return SZO_ERR_ARG;
+  if ((rc = grid_init(&g, ndim, dims, order))) return rc;
+  size_t ts = type_size(dtype);
+  uint64_t n = g.n;
+  double eb_t;
+  if ((rc = szo_resolve_eb(x, n, dtype, eb_mode, eb, &eb_t))) return rc;
+
+  uint32_t nsym = 2 * radius;
+  uint16_t* codes = (uint16_t*)malloc(sizeof(uint16_t) * (n ? n : 1));
+  void* recon = malloc(ts * (n ? n : 1));
+  uint64_t* hist = (uint64_t*)malloc(sizeof(uint64_t) * nsym);
+  uint8_t* lens = (uint8_t*)malloc(nsym);
+  uint64_t* cw = (uint64_t*)malloc(sizeof(uint64_t) * nsym);
+  uint64_t nchunks = (n + chunk - 1) / chunk;
+  uint32_t* chunk_words = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks ? nchunks : 1));
+  uint32_t* words = NULL;
+  uint8_t* out = NULL;
+  if (!codes || !recon || !hist || !lens || !cw || !chunk_words) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  /* Algorithm 1: predict + quantize every point */
+  rc = szo_predict_quantize(x, dtype, ndim, dims, g.order, predictor, eb_t,
+                            radius, codes, recon);
+  if (rc) goto done;
+  /* Huffman: frequencies -> lengths -> canonical codebook */
+  if ((rc = szo_histogram(codes, n, nsym, hist))) goto done;
+  rc = szo_huffman_lengths(hist, nsym, lens);
+  if (rc < 0) goto done;
+  if ((rc = szo_canonical_codes(lens, nsym, cw))) goto done;
+  uint64_t K = 0;
+  for (uint32_t s = 0; s < nsym; s++)
+    if (lens[s]) K++;
+  uint64_t total_words;
+  if ((rc = szo_pack(codes, n, lens, cw, chunk, NULL, chunk_words, &total_words)))
+    goto done;
+  words = (uint32_t*)calloc(total_words ? total_words : 1, sizeof(uint32_t));
+  if (!words) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  if ((rc = szo_pack(codes, n, lens, cw, chunk, words, chunk_words, &total_words)))
+    goto done;
+  uint64_t n_unpred = hist[0];
+  struct layout lo;
+  layout_of(K, nchunks, n_unpred, ts, total_words, &lo);
+  out = (uint8_t*)calloc(lo.size, 1);
+  if (!out) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  memcpy(out, "SZG1", 4);
+  put_u16(out + 4, 1);
+  out[6] = (uint8_t)dtype;
+  out[7] = (uint8_t)ndim;
+  for (int d = 0; d < 4; d++) put_u64(out + 8 + 8 * d, d < ndim ? g.dims[d] : 1);
+  out[40] = (uint8_t)predictor;
+  for (int d = 0; d < 4; d++) out[41 + d] = g.order[d];
+  out[45] = (uint8_t)eb_mode;
+  put_f64(out + 48, eb);
+  put_f64(out + 56, eb_t);
+  put_u32(out + 64, radius);
+  put_u32(out + 68, chunk);
+  put_u64(out + 72, n_unpred);
+  put_u32(out + 80, (uint32_t)K);
+  put_u64(out + 88, total_words);
+  put_u64(out + 96, lo.size);
+  /* encoder.save: the code lengths, ascending symbol */
+  uint64_t k = 0;
+  for (uint32_t s = 0; s < nsym; s++)
+    if (lens[s]) put_u32(out + lo.off_sym + 4 * k++, s | ((uint32_t)lens[s] << 16));
+  /* chunk table */
+  for (uint64_t c = 0; c < nchunks; c++) {
+    uint64_t a = c * chunk, b = a + chunk < n ? a + chunk : n;
+    uint32_t cu = 0;
+    for (uint64_t i = a; i < b; i++)
+      if (codes[i] == 0) cu++;
+    put_u32(out + lo.off_chunk + 8 * c, chunk_words[c]);
+    put_u32(out + lo.off_chunk + 8 * c + 4, cu);
+  }
+  /* quantizer.save: unpredictable values verbatim, flat order */
+  uint64_t u = 0;
+  for (uint64_t i = 0; i < n; i++)
+    if (codes[i] == 0) memcpy(out + lo.off_unpred + ts * u++, (const uint8_t*)x + ts * i, ts);
+  for (uint64_t w = 0; w < total_words; w++) put_u32(out + lo.off_bits + 4 * w, words[w]);
+  if (codes_out) memcpy(codes_out, codes, sizeof(uint16_t) * n);
+  if (recon_out) memcpy(recon_out, recon, ts * n);
+  *stream = out;
+  *stream_size = lo.size;
+  out = NULL;
+  rc = SZO_OK;
+done:
+  free(codes);
+  free(recon);
+  free(hist);
+  free(lens);
+  free(cw);
+  free(chunk_words);
+  free(words);
+  free(out);
+  return rc;
+}
+
+int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
+                   uint64_t out_bytes, uint16_t* codes_out) {
+  if (!s || size < SZO_HEADER_BYTES) return SZO_ERR_CORRUPT;
+  if (memcmp(s, "SZG1", 4) != 0 || get_u16(s + 4) != 1) return SZO_ERR_CORRUPT;
+  int dtype = s[6], ndim = s[7], predictor = s[40], eb_mode = s[45];
+  if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 1 || eb_mode > 1)
+    return SZO_ERR_CORRUPT;
+  uint64_t dims[4];
+  uint8_t order[4];
+  for (int d = 0; d < 4; d++) {
+    dims[d] = get_u64(s + 8 + 8 * d);
+    order[d] = s[41 + d];
+    if (d >= ndim && (dims[d] != 1 || order[d] != d)) return SZO_ERR_CORRUPT;
+  }
+  struct szo_grid g;
+  if (grid_init(&g, ndim, dims, order)) return SZO_ERR_CORRUPT;
+  double eb_t = get_f64(s + 56);
+  uint32_t radius = get_u32(s + 64), chunk = get_u32(s + 68);
+  uint64_t n_unpred = get_u64(s + 72);
+  uint64_t K = get_u32(s + 80);
+  uint64_t total_words = get_u64(s + 88), stream_bytes = get_u64(s + 96);
+  if (!(eb_t >= 0.0) || !isfinite(eb_t)) return SZO_ERR_CORRUPT;
+  if (dtype == SZO_F32 && (double)(float)eb_t != eb_t) return SZO_ERR_CORRUPT;
+  if (radius < 1 || radius > SZO_MAX_RADIUS || chunk == 0) return SZO_ERR_CORRUPT;
+  uint64_t n = g.n;
+  uint32_t nsym = 2 * radius;
+  if (K > nsym || n_unpred > n || (K == 0) != (n == 0)) return SZO_ERR_CORRUPT;
+  if (total_words > 64 * (n + 1)) return SZO_ERR_CORRUPT;
+  size_t ts = type_size(dtype);
+  uint64_t nchunks = (n + chunk - 1) / chunk;
+  struct layout lo;
+  layout_of(K, nchunks, n_unpred, ts, total_words, &lo);
+  if (lo.size != stream_bytes || stream_bytes > size) return SZO_ERR_CORRUPT;
+  if (out_bytes < n * ts) return SZO_ERR_CAPACITY;
+
+  int rc = SZO_OK;
+  uint8_t* lens = (uint8_t*)calloc(nsym, 1);
+  uint32_t* chunk_words = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks ? nchunks : 1));
+  uint32_t* words = (uint32_t*)malloc(sizeof(uint32_t) * (total_words ? total_words : 1));
+  uint16_t* codes = (uint16_t*)malloc(sizeof(uint16_t) * (n ? n : 1));
+  void* unpred = malloc(ts * (n_unpred ? n_unpred : 1));
+  if (!lens || !chunk_words || !words || !codes || !unpred) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  /* encoder.load: lengths, validated as a complete prefix code */
+  {
+    int64_t prev = -1;
+    unsigned __int128 kraft = 0;
+    for (uint64_t k = 0; k < K; k++) {
+      uint32_t e = get_u32(s + lo.off_sym + 4 * k);
+      uint32_t sym = e & 0xFFFF, len = e >> 16;
+      if ((int64_t)sym <= prev || sym >= nsym || len < 1 || len > SZO_MAX_CODE_LEN) {
+        rc = SZO_ERR_CORRUPT;
+        goto done;
+      }
+      prev = sym;
+      lens[sym] = (uint8_t)len;
+      kraft += (unsigned __int128)1 << (SZO_MAX_CODE_LEN - len);
+    }
+    unsigned __int128 full = (unsigned __int128)1 << SZO_MAX_CODE_LEN;
+    if (K == 1 ? lens[prev] != 1 : (K > 1 && kraft != full)) {
+      rc = SZO_ERR_CORRUPT;
+      goto done;
+    }
+  }
+  uint64_t sum_w = 0, sum_u = 0;
+  for (uint64_t c = 0; c < nchunks; c++) {
+    chunk_words[c] = get_u32(s + lo.off_chunk + 8 * c);
+    sum_w += chunk_words[c];
+    sum_u += get_u32(s + lo.off_chunk + 8 * c + 4);
+  }
+  if (sum_w != total_words || sum_u != n_unpred) {
+    rc = SZO_ERR_CORRUPT;
+    goto done;
+  }
+  for (uint64_t w = 0; w < total_words; w++) words[w] = get_u32(s + lo.off_bits + 4 * w);
+  memcpy(unpred, s + lo.off_unpred, ts * n_unpred);
+  if ((rc = szo_unpack(words, total_words, chunk_words, n, chunk, lens, nsym, codes)))
+    goto done;
+  /* per-chunk unpredictable counts must match the decoded codes */
+  for (uint64_t c = 0; c < nchunks; c++) {
+    uint64_t a = c * chunk, b = a + chunk < n ? a + chunk : n;
+    uint32_t cu = 0;
+    for (uint64_t i = a; i < b; i++)
+      if (codes[i] == 0) cu++;
+    if (cu != get_u32(s + lo.off_chunk + 8 * c + 4)) {
+      rc = SZO_ERR_CORRUPT;
+      goto done;
+    }
+  }
+  rc = szo_reconstruct(codes, unpred, n_unpred, dtype, ndim, g.dims, g.order,
+                       predictor, eb_t, radius, outp);
+  if (!rc && codes_out) memcpy(codes_out, codes, sizeof(uint16_t) * n);
+done:
+  free(lens);
+  free(chunk_words);
+  free(words);
+  free(codes);
+  free(unpred);
+  return rc;
+}
+
+void szo_free(void* p) { free(p); }
