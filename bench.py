@@ -1,0 +1,174 @@
+"""Throughput of the interpolation compressor hot path on one MI355X.
+
+One step = one sz_compress + one sz_decompress of the 512^3 float32
+log-normal field (cubic interpolation, range-relative bound 1e-3, radius
+32768): every stage of the path -- bound resolution, multilevel prediction and
+quantization, histogram, codebook, encode, decode, reconstruction.  Inputs are
+resident in HBM before timing.  Prints one JSON line.
+
+value = input bytes per step / step time (GB/s, 1e9 B/s), the paper's MB/s
+convention (original bytes over time) applied to a compress+decompress round
+trip; compress-only and decompress-only rates are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shape", default="512,512,512")
+    ap.add_argument("--rel", type=float, default=1e-3)
+    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path shards as independent fields with no exchange, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2111_02925_amd as szg
+    import synth
+
+    shape = tuple(int(v) for v in args.shape.split(","))
+    t0 = time.time()
+    x = synth.lognormal_grf(shape, seed=2)
+    print(f"[bench] generated {shape} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    n = x.size
+    in_bytes = x.nbytes
+    dev = torch.device("cuda:0")
+    ctx = szg.Context(0)
+    xt = torch.from_numpy(x).to(dev)
+    cap = szg.compress_bound(shape, szg.F32, 32768, args.chunk)
+    out = torch.empty(cap, dtype=torch.uint8, device=dev)
+    rec = torch.empty(shape, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream(dev)
+
+    def step():
+        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk, out=out)
+        ctx.decompress(s, out=rec)
+        return s
+
+    for _ in range(args.warmup):
+        s = step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ctx.timing_reset()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(st)
+        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk, out=out)
+        ev[i][1].record(st)
+        ctx.decompress(s, out=rec)
+        ev[i][2].record(st)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ctx.set_timing(False)
+    ms_c = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
+    ms_d = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
+    ms_step = t_total * 1e3 / args.steps
+    size = int(s.numel())
+
+    fam = {k: ctx.timing(k) for k in ("minmax", "interp", "histogram", "codebook", "encode",
+                                      "decode", "recon", "other")}
+    per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in fam.items()}
+
+    # quality (measurement only, after the timed region)
+    diff = (rec.double() - xt.double()).abs()
+    vr = float(xt.max() - xt.min())
+    mse = float((diff * diff).mean())
+    psnr = 20 * np.log10(vr) - 10 * np.log10(mse) if mse > 0 else float("inf")
+    info = szg.inspect(s[:128].cpu())
+    maxerr_over_eb = float(diff.max()) / info["eb"] if info["eb"] > 0 else 0.0
+
+    # roofline of the dominant kernel family (largest time per step)
+    dom = max(per_step, key=lambda k: per_step[k][0])
+    sT = 4
+    alg_bytes = {
+        "minmax": n * sT,
+        "interp": n * sT + 2 * n,          # read x, write codes
+        "histogram": 2 * n,                # read codes
+        "encode": 2 * n + size,            # read codes, write stream
+        "decode": size + 2 * n,            # read stream, write codes
+        "recon": 2 * n + n * sT,           # read codes, write field
+        "codebook": 0, "other": 0,
+    }
+    dom_ms = per_step[dom][0]
+    achieved = alg_bytes[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": None, "launches_per_step": per_step[dom][1],
+                "ms_per_step": round(dom_ms, 4)}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        ref = oracle.compress(x, oracle.REL, args.rel, oracle.CUBIC, 32768, args.chunk)
+        t2 = time.perf_counter()
+        back = oracle.decompress(ref)
+        t3 = time.perf_counter()
+        parity = (ref == bytes(s.cpu().numpy().tobytes())) and (
+            back.tobytes() == rec.cpu().numpy().tobytes())
+        cpu = {"value": round(in_bytes / (t3 - t1) / 1e9, 4), "unit": "GB/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the full {shape} field: one compress ({t2 - t1:.1f}s) + one "
+                         f"decompress ({t3 - t2:.1f}s), single thread, host "
+                         f"{os.cpu_count()} logical CPUs"}
+
+    res = {
+        "metric": "compress/decompress GB/s at rel eb 1e-3 (ratio fixed), % HBM roofline; batched vs per-field",
+        "value": round(in_bytes / (ms_step * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"log-normal GRF (P(k)~k^-3) {'x'.join(map(str, shape))} f32, cubic "
+                               f"interpolation, rel eb {args.rel:g}, radius 32768, chunk {args.chunk}",
+                   "shape": list(shape), "eb_mode": "rel", "eb": args.rel, "predictor": "cubic"},
+        "compress_GBps": round(in_bytes / (ms_c * 1e-3) / 1e9, 3),
+        "decompress_GBps": round(in_bytes / (ms_d * 1e-3) / 1e9, 3),
+        "compress_ms": round(ms_c, 4),
+        "decompress_ms": round(ms_d, 4),
+        "ratio": round(in_bytes / size, 4),
+        "bit_rate": round(32.0 * size / in_bytes, 4),
+        "psnr_db": round(psnr, 3),
+        "max_err_over_eb": round(maxerr_over_eb, 6),
+        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_with_oracle": parity,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * szg.h -- C ABI of the MI355X interpolation compressor.
+ *
+ * The library implements the data-parallel hot path of the SZ3-Interp
+ * pipeline of "SZ3: A Modular Framework for Composing Prediction-Based
+ * Error-Bounded Lossy Compressors" (Section 6.2): a multilevel linear/cubic
+ * interpolation predictor, the linear-scaling quantizer with a radius
+ * (Section 3.2 "Quantizer"), Huffman coding of the quantization codes
+ * (Section 3.2 "Encoder"), and the matching reconstruction, in the stage
+ * order of Algorithm 1 (Section 3.3).  Every stage runs in HIP kernels on the
+ * device; the lossless back-end of the paper (zstd) is not part of the
+ * library and, if wanted, is applied by the caller on the host.
+ *
+ * Conventions
+ *  - All functions return an sz_status (0 = success, negative = error); no
+ *    exception crosses the ABI.  sz_last_error() describes the last failure
+ *    on a context.
+ *  - "d_" pointers are device pointers (HBM of the context's device); "h_"
+ *    pointers are host pointers.  The caller owns every buffer it passes; the
+ *    library never frees them.  The context owns its scratch memory, grown on
+ *    demand and released by sz_ctx_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is ordered on that stream.  Calls that return a size to the host
+ *    synchronise the stream before returning.
+ *  - Arrays are row-major: dims[ndim-1] is the contiguous dimension.
+ *  - Alignment: field buffers (d_in of sz_compress, d_out of sz_decompress)
+ *    must be 16-byte aligned and stream buffers 8-byte aligned (SZ_ERR_ARG
+ *    otherwise); allocations from hipMalloc always are.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ *  - Limits: 1 <= ndim <= 4; a dimension may be 0 (empty field); the number
+ *    of points n = prod(dims) is at most 2^32 - 1.
+ */
+#ifndef SZG_H
+#define SZG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
+
+/* SZ_EB_ABS: eb = (T)value.  SZ_EB_REL: eb = (T)(value * (max - min)) over
+ * the finite values of the field, computed in double (Section 6.2, caption
+ * of the throughput figure: the relative bound is the bound normalised by
+ * the value range); 0 when no value is finite.  value must be finite and
+ * >= 0, and the resolved eb must be finite. */
+typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1 } sz_eb_mode;
+
+/* Interpolation along each dimension (Section 6.2, SZ3-Interp): linear
+ * (midpoint of the two neighbours at +-s) or cubic (4-point Lagrange
+ * midpoint rule, quadratic or linear near the boundary). */
+typedef enum { SZ_INTERP_LINEAR = 0, SZ_INTERP_CUBIC = 1 } sz_predictor;
+
+typedef enum {
+  SZ_OK = 0,
+  SZ_ERR_ARG = -1,        /* invalid argument (shape, bound, options, pointers) */
+  SZ_ERR_DTYPE = -2,      /* unknown dtype */
+  SZ_ERR_CAPACITY = -3,   /* output buffer too small; required size returned */
+  SZ_ERR_CORRUPT = -4,    /* stream fails validation */
+  SZ_ERR_DEVICE = -5,     /* a HIP runtime call failed */
+  SZ_ERR_NOMEM = -6,      /* device or host allocation failed */
+  SZ_ERR_UNSUPPORTED = -7 /* valid request the library does not implement */
+} sz_status;
+
+/* Options that are recorded in the stream (they change the bytes). */
+typedef struct {
+  uint32_t radius;       /* quantizer radius R, 1..32768; codes are 0..2R-1, 0 =
+                            unpredictable.  Default 32768. */
+  uint32_t chunk;        /* symbols per independently decodable Huffman chunk,
+                            a multiple of 64 in [64, 65536].  Default 4096. */
+  uint8_t dim_order[4];  /* order in which each level visits the dimensions;
+                            a permutation of 0..ndim-1.  Default identity. */
+} sz_options;
+
+/* Fields of a stream header, decoded on the host by sz_inspect. */
+typedef struct {
+  int dtype;
+  int ndim;
+  uint64_t dims[4];
+  uint64_t n;
+  int predictor;
+  uint8_t dim_order[4];
+  int eb_mode;
+  double eb_user;      /* the bound value as passed to sz_compress */
+  double eb;           /* the resolved bound in the field type, widened */
+  uint32_t radius;
+  uint32_t chunk;
+  uint64_t n_unpred;   /* unpredictable values stored verbatim */
+  uint32_t nsym;       /* symbols with a Huffman code */
+  uint64_t total_words;/* 32-bit words of Huffman bitstream */
+  uint64_t stream_bytes;
+} sz_info;
+
+typedef struct sz_ctx sz_ctx;
+
+/* Create a context bound to HIP device `device` (the device is made current
+ * for each call).  Returns NULL on failure. */
+sz_ctx* sz_ctx_create(int device);
+void sz_ctx_destroy(sz_ctx* ctx);
+/* Human-readable description of the last error on ctx (never NULL). */
+const char* sz_last_error(const sz_ctx* ctx);
+
+void sz_default_options(sz_options* opts);
+
+/* Upper bound on the compressed size in bytes for any field of this shape
+ * and type (0 on invalid arguments).  Host only. */
+size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims,
+                         const sz_options* opts);
+
+/* Compress the field d_in (device, n values of dtype) into d_out (device,
+ * out_capacity bytes).  Stages, all on the device: error-bound resolution;
+ * interpolation prediction + quantization level by level and dimension by
+ * dimension (Algorithm 1, predict/quantize loop); code histogram; Huffman
+ * code lengths and canonical codebook; chunked bit packing; compaction of the
+ * unpredictable values; stream assembly.  On success *out_size (host) is the
+ * stream length.  If the stream does not fit, returns SZ_ERR_CAPACITY with
+ * *out_size = the required size and leaves d_out partially written.
+ * opts may be NULL (defaults).  Synchronises `stream`. */
+int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
+                const uint64_t* dims, int eb_mode, double eb, int predictor,
+                const sz_options* opts, void* d_out, size_t out_capacity,
+                size_t* out_size, void* stream);
+
+/* Decompress a stream (device, stream_size bytes) into d_out (device,
+ * out_capacity bytes, n values of the stream's dtype): parse and validate
+ * the header, decode the Huffman chunks, scatter the unpredictable values,
+ * and rebuild the field with the same traversal and arithmetic as the
+ * compressor, so the result equals the compressor's reconstruction bit for
+ * bit.  Returns SZ_ERR_CORRUPT for an inconsistent stream (d_out may then be
+ * partially written), SZ_ERR_CAPACITY if d_out is too small.  Synchronises
+ * `stream`. */
+int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size,
+                  void* d_out, size_t out_capacity, void* stream);
+
+/* Decode the header of a stream held in host memory (at least the first 128
+ * bytes).  Host only; validates the header fields. */
+int sz_inspect(const void* h_stream, size_t len, sz_info* info);
+
+/* One field of a batch (sz_compress_batch).  Inputs are read, outputs
+ * (out_size, status) written by the call. */
+typedef struct {
+  const void* d_in;
+  int dtype;
+  int ndim;
+  uint64_t dims[4];
+  int eb_mode;
+  double eb;
+  int predictor;
+  void* d_out;
+  size_t out_capacity;
+  size_t out_size;  /* written: stream bytes (or required bytes on CAPACITY) */
+  int status;       /* written: sz_status of this field */
+} sz_field;
+
+/* Compress many fields of uneven shape and bound in one stream-ordered batch.
+ * Each field's stream is byte-identical to what sz_compress produces for it
+ * alone.  Returns SZ_OK when every field succeeded, else the first failing
+ * field's status.  Synchronises `stream`. */
+int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields,
+                      const sz_options* opts, void* stream);
+
+/* ---- measurement and debugging ------------------------------------------
+ * sz_set_timing(ctx, 1) records HIP events around every kernel launch on the
+ * launch stream; sz_timing_get() returns, for the kernel family `name`, the
+ * summed duration (ms) and launch count since the last sz_timing_reset().
+ * Names: "minmax", "interp", "histogram", "codebook", "encode", "decode",
+ * "recon", "other". */
+int sz_set_timing(sz_ctx* ctx, int enable);
+int sz_timing_get(sz_ctx* ctx, const char* name, double* total_ms,
+                  uint64_t* launches);
+int sz_timing_reset(sz_ctx* ctx);
+
+/* Copy the quantization codes (n u16, flat order) of the last sz_compress
+ * on ctx into d_codes (device). */
+int sz_debug_codes(sz_ctx* ctx, void* d_codes, size_t capacity, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

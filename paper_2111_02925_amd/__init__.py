@@ -1,0 +1,316 @@
+"""MI355X-native interpolation compressor (SZ3-Interp hot path) -- Python binding.
+
+Thin ctypes binding of ``libszg.so`` (C ABI in ``include/szg.h``).  It only
+marshals arguments: every stage of compression and decompression runs in the
+library's HIP kernels on the GPU.  PyTorch is used for device memory and the
+current stream.  If the library has not been built, every entry point raises
+``SzLibraryMissing`` -- there is no fallback.
+
+Paper: "SZ3: A Modular Framework for Composing Prediction-Based Error-Bounded
+Lossy Compressors" (arXiv 2111.02925), Section 6.2 (SZ3-Interp), Section 3.2
+(linear-scaling quantizer, Huffman encoder), Algorithm 1 (stage order).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libszg.so")
+
+F32, F64 = 0, 1
+ABS, REL = 0, 1
+LINEAR, CUBIC = 0, 1
+OK, ERR_ARG, ERR_DTYPE, ERR_CAPACITY, ERR_CORRUPT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "SZ_OK", -1: "SZ_ERR_ARG", -2: "SZ_ERR_DTYPE", -3: "SZ_ERR_CAPACITY",
+                -4: "SZ_ERR_CORRUPT", -5: "SZ_ERR_DEVICE", -6: "SZ_ERR_NOMEM",
+                -7: "SZ_ERR_UNSUPPORTED"}
+HEADER_BYTES = 128
+
+# every function declared in include/szg.h
+EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_options",
+           "sz_compress_bound", "sz_compress", "sz_decompress", "sz_inspect",
+           "sz_compress_batch", "sz_set_timing", "sz_timing_get", "sz_timing_reset",
+           "sz_debug_codes")
+
+
+class SzLibraryMissing(ImportError):
+    pass
+
+
+class SzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("dim_order", ctypes.c_uint8 * 4)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_uint64 * 4),
+                ("n", ctypes.c_uint64), ("predictor", ctypes.c_int),
+                ("dim_order", ctypes.c_uint8 * 4), ("eb_mode", ctypes.c_int),
+                ("eb_user", ctypes.c_double), ("eb", ctypes.c_double),
+                ("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
+                ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("dtype", ctypes.c_int), ("ndim", ctypes.c_int),
+                ("dims", ctypes.c_uint64 * 4), ("eb_mode", ctypes.c_int), ("eb", ctypes.c_double),
+                ("predictor", ctypes.c_int), ("d_out", ctypes.c_void_p),
+                ("out_capacity", ctypes.c_size_t), ("out_size", ctypes.c_size_t),
+                ("status", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libszg.so (raises SzLibraryMissing if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SzLibraryMissing(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    U64P = ctypes.POINTER(ctypes.c_uint64)
+    L.sz_ctx_create.argtypes = [I]
+    L.sz_ctx_create.restype = P
+    L.sz_ctx_destroy.argtypes = [P]
+    L.sz_ctx_destroy.restype = None
+    L.sz_last_error.argtypes = [P]
+    L.sz_last_error.restype = ctypes.c_char_p
+    L.sz_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.sz_default_options.restype = None
+    L.sz_compress_bound.argtypes = [I, I, U64P, ctypes.POINTER(Options)]
+    L.sz_compress_bound.restype = SZ
+    L.sz_compress.argtypes = [P, P, I, I, U64P, I, D, I, ctypes.POINTER(Options), P, SZ,
+                              ctypes.POINTER(SZ), P]
+    L.sz_compress.restype = I
+    L.sz_decompress.argtypes = [P, P, SZ, P, SZ, P]
+    L.sz_decompress.restype = I
+    L.sz_inspect.argtypes = [P, SZ, ctypes.POINTER(Info)]
+    L.sz_inspect.restype = I
+    L.sz_compress_batch.argtypes = [P, ctypes.POINTER(Field), I, ctypes.POINTER(Options), P]
+    L.sz_compress_batch.restype = I
+    L.sz_set_timing.argtypes = [P, I]
+    L.sz_set_timing.restype = I
+    L.sz_timing_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), U64P]
+    L.sz_timing_get.restype = I
+    L.sz_timing_reset.argtypes = [P]
+    L.sz_timing_reset.restype = I
+    L.sz_debug_codes.argtypes = [P, P, SZ, P]
+    L.sz_debug_codes.restype = I
+    _lib = L
+    return L
+
+
+def _mode(v) -> int:
+    if isinstance(v, str):
+        return {"abs": ABS, "rel": REL}[v.lower()]
+    return int(v)
+
+
+def _pred(v) -> int:
+    if isinstance(v, str):
+        return {"linear": LINEAR, "cubic": CUBIC}[v.lower()]
+    return int(v)
+
+
+def make_options(radius: int = 32768, chunk: int = 4096, dim_order=None, ndim: int = 4) -> Options:
+    o = Options()
+    o.radius = radius
+    o.chunk = chunk
+    order = list(dim_order) if dim_order is not None else list(range(ndim))
+    order += list(range(len(order), 4))
+    for j in range(4):
+        o.dim_order[j] = order[j]
+    return o
+
+
+def _dims(shape):
+    d = (ctypes.c_uint64 * 4)(1, 1, 1, 1)
+    for i, s in enumerate(shape):
+        d[i] = int(s)
+    return d
+
+
+def compress_bound(shape, dtype: int = F32, radius: int = 32768, chunk: int = 4096,
+                   dim_order=None) -> int:
+    o = make_options(radius, chunk, dim_order, len(shape))
+    return int(lib().sz_compress_bound(dtype, len(shape), _dims(shape), ctypes.byref(o)))
+
+
+def inspect(stream) -> dict:
+    """Decode a stream header held in host memory (bytes / numpy / CPU tensor)."""
+    b = bytes(stream[:HEADER_BYTES]) if not hasattr(stream, "cpu") else bytes(
+        stream[:HEADER_BYTES].cpu().numpy().tobytes())
+    buf = ctypes.create_string_buffer(b, len(b))
+    info = Info()
+    rc = lib().sz_inspect(ctypes.cast(buf, ctypes.c_void_p), len(b), ctypes.byref(info))
+    if rc:
+        raise SzError(rc, "sz_inspect")
+    return {f: (list(getattr(info, f))[: info.ndim] if f in ("dims", "dim_order") else getattr(info, f))
+            for f, _ in Info._fields_}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class Context:
+    """A library context on one GPU (owns the scratch memory)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = lib()
+        self.device = device
+        self._h = self._lib.sz_ctx_create(device)
+        if not self._h:
+            raise SzError(ERR_DEVICE, f"sz_ctx_create({device}) failed")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sz_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc, what):
+        msg = self._lib.sz_last_error(self._h)
+        return SzError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def compress(self, x, eb_mode="rel", eb: float = 1e-3, predictor="cubic",
+                 radius: int = 32768, chunk: int = 4096, dim_order=None, out=None, stream=None):
+        """Compress a contiguous float32/float64 CUDA tensor; returns a uint8
+        CUDA tensor holding the stream (a view of `out` if given)."""
+        torch = _torch()
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor")
+        opts = make_options(radius, chunk, dim_order, x.dim())
+        dims = _dims(x.shape)
+        if out is None:
+            cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), dims, ctypes.byref(opts)))
+            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+        size = ctypes.c_size_t(0)
+        rc = self._lib.sz_compress(self._h, ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
+                                   dims, _mode(eb_mode), float(eb), _pred(predictor),
+                                   ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
+                                   out.numel(), ctypes.byref(size), self._stream(stream))
+        if rc:
+            err = self._err(rc, "sz_compress")
+            err.required = size.value
+            raise err
+        return out[: size.value]
+
+    def decompress(self, stream_t, out=None, stream=None):
+        """Decompress a uint8 CUDA tensor holding a stream; returns the field."""
+        torch = _torch()
+        if not stream_t.is_cuda or stream_t.dtype != torch.uint8:
+            raise ValueError("stream must be a uint8 CUDA tensor")
+        info = inspect(stream_t[:HEADER_BYTES].cpu())
+        dt = torch.float64 if info["dtype"] == F64 else torch.float32
+        shape = tuple(info["dims"])
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=stream_t.device)
+        rc = self._lib.sz_decompress(self._h, ctypes.c_void_p(stream_t.data_ptr()),
+                                     stream_t.numel(), ctypes.c_void_p(out.data_ptr()),
+                                     out.numel() * out.element_size(), self._stream(stream))
+        if rc:
+            raise self._err(rc, "sz_decompress")
+        return out
+
+    def compress_batch(self, fields, radius: int = 32768, chunk: int = 4096, stream=None):
+        """fields: list of (tensor, eb_mode, eb, predictor).  Returns the list
+        of stream tensors (views of per-field output buffers)."""
+        torch = _torch()
+        arr = (Field * len(fields))()
+        outs = []
+        opts = make_options(radius, chunk, None, 4)
+        for i, (x, mode, eb, pred) in enumerate(fields):
+            o1 = make_options(radius, chunk, None, x.dim())
+            cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), _dims(x.shape),
+                                                  ctypes.byref(o1)))
+            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+            outs.append(out)
+            f = arr[i]
+            f.d_in = x.data_ptr()
+            f.dtype = _dtype_code(x)
+            f.ndim = x.dim()
+            for d in range(4):
+                f.dims[d] = int(x.shape[d]) if d < x.dim() else 1
+            f.eb_mode = _mode(mode)
+            f.eb = float(eb)
+            f.predictor = _pred(pred)
+            f.d_out = out.data_ptr()
+            f.out_capacity = out.numel()
+        rc = self._lib.sz_compress_batch(self._h, arr, len(fields), ctypes.byref(opts),
+                                         self._stream(stream))
+        if rc:
+            raise self._err(rc, "sz_compress_batch")
+        return [outs[i][: arr[i].out_size] for i in range(len(fields))]
+
+    def debug_codes(self, n: int, device="cuda"):
+        torch = _torch()
+        t = torch.empty(max(n, 1), dtype=torch.int16, device=device)
+        rc = self._lib.sz_debug_codes(self._h, ctypes.c_void_p(t.data_ptr()), 2 * n,
+                                      self._stream(None))
+        if rc:
+            raise self._err(rc, "sz_debug_codes")
+        return t[:n]
+
+    def set_timing(self, on: bool = True):
+        self._lib.sz_set_timing(self._h, 1 if on else 0)
+
+    def timing_reset(self):
+        self._lib.sz_timing_reset(self._h)
+
+    def timing(self, name: str):
+        ms = ctypes.c_double(0)
+        cnt = ctypes.c_uint64(0)
+        self._lib.sz_timing_get(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt))
+        return ms.value, cnt.value
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def compress(x, eb_mode="rel", eb: float = 1e-3, predictor="cubic", **kw):
+    return default_context(x.device.index or 0).compress(x, eb_mode, eb, predictor, **kw)
+
+
+def decompress(stream_t, **kw):
+    return default_context(stream_t.device.index or 0).decompress(stream_t, **kw)

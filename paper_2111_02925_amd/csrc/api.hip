@@ -1,0 +1,622 @@
+// C ABI (include/szg.h): context, scratch, stream header, and the drivers that
+// enqueue the compression and decompression kernels.
+//
+// Stream layout (little-endian; sections start on 8-byte boundaries):
+//   header, 128 bytes
+//     0 "SZG1"  4 u16 version=1  6 u8 dtype  7 u8 ndim  8 u64 dims[4] (unused=1)
+//     40 u8 predictor  41 u8 dim_order[4]  45 u8 eb_mode  46 u16 0
+//     48 f64 eb as passed  56 f64 eb in the field type  64 u32 radius
+//     68 u32 chunk  72 u64 unpredictable count  80 u32 K (coded symbols)  84 u32 0
+//     88 u64 bitstream words  96 u64 stream bytes  104..127 0
+//   symbol table   K x u32 (symbol | length << 16), ascending symbol
+//                  (the encoder's saved state, Algorithm 1 "encoder.save")
+//   chunk table    ceil(n/chunk) x (u32 words, u32 unpredictable count)
+//   unpredictable  count x T in flat order (Algorithm 1 "quantizer.save")
+//   bitstream      words x u32, each chunk MSB-first and word-padded
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace szg;
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Pending {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct Stat {
+  double ms = 0;
+  uint64_t n = 0;
+};
+
+}  // namespace
+
+struct sz_ctx {
+  int device = 0;
+  std::string err;
+  // size-dependent scratch
+  Buf rec, codes, chunk_words, chunk_unpred, word_off, unpred_off, block_sums;
+  // fixed scratch
+  Meta* meta = nullptr;
+  uint32_t* hist = nullptr;
+  uint64_t* enc_code = nullptr;
+  uint8_t* enc_len = nullptr;
+  uint32_t* symtab = nullptr;
+  uint64_t* totals = nullptr;
+  CodebookScratch cb{};
+  DecodeTables dt{};
+  Meta* h_meta = nullptr;       // pinned
+  uint8_t* h_header = nullptr;  // pinned
+  uint64_t last_n = 0;
+  // timing
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, Stat> stats;
+};
+
+namespace {
+
+int fail(sz_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int dev_fail(sz_ctx* c, hipError_t e, const char* where) {
+  return fail(c, SZ_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CHECK_HIP(expr, where)                 \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, where); \
+  } while (0)
+
+hipError_t ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return hipSuccess;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e == hipSuccess) b.cap = want;
+  return e;
+}
+
+hipEvent_t get_event(sz_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+template <class F>
+hipError_t timed(sz_ctx* c, const char* name, hipStream_t st, F&& f) {
+  if (!c->timing) return f();
+  hipEvent_t a = get_event(c), b = get_event(c);
+  (void)hipEventRecord(a, st);
+  hipError_t e = f();
+  (void)hipEventRecord(b, st);
+  c->pending.push_back({name, a, b});
+  return e;
+}
+
+void settle_timing(sz_ctx* c) {
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      Stat& s = c->stats[p.name];
+      s.ms += ms;
+      s.n += 1;
+    }
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// ---------------------------------------------------------------- shapes
+
+struct Shape {
+  int dtype = 0, ndim = 0;
+  uint64_t dims[kMaxDims] = {1, 1, 1, 1};
+  uint8_t order[kMaxDims] = {0, 1, 2, 3};
+  uint64_t n = 0;
+  uint32_t radius = kMaxRadius, chunk = 4096;
+  size_t tsize() const { return dtype == SZ_F64 ? 8 : 4; }
+  uint64_t nchunks() const { return (n + chunk - 1) / chunk; }
+};
+
+bool valid_order(int ndim, const uint8_t* order) {
+  bool seen[kMaxDims] = {false, false, false, false};
+  for (int j = 0; j < ndim; j++) {
+    if (order[j] >= ndim || seen[order[j]]) return false;
+    seen[order[j]] = true;
+  }
+  return true;
+}
+
+// Validates shape and options shared by compress and the bound.
+int make_shape(sz_ctx* c, int dtype, int ndim, const uint64_t* dims, const sz_options* opts,
+               Shape* s) {
+  if (dtype != SZ_F32 && dtype != SZ_F64) return fail(c, SZ_ERR_DTYPE, "dtype must be SZ_F32 or SZ_F64");
+  if (ndim < 1 || ndim > kMaxDims || !dims) return fail(c, SZ_ERR_ARG, "ndim must be 1..4 with dims");
+  s->dtype = dtype;
+  s->ndim = ndim;
+  bool empty = false;
+  for (int d = 0; d < ndim; d++) {
+    s->dims[d] = dims[d];
+    if (dims[d] == 0) empty = true;
+  }
+  uint64_t n = 1;
+  if (empty) {
+    n = 0;
+  } else {
+    for (int d = 0; d < ndim; d++) {
+      if (dims[d] > kMaxPoints || n > kMaxPoints / dims[d])
+        return fail(c, SZ_ERR_ARG, "field has more than 2^32-1 points");
+      n *= dims[d];
+    }
+  }
+  s->n = n;
+  if (opts) {
+    s->radius = opts->radius;
+    s->chunk = opts->chunk;
+    for (int j = 0; j < kMaxDims; j++) s->order[j] = j < ndim ? opts->dim_order[j] : (uint8_t)j;
+  }
+  if (s->radius < 1 || s->radius > kMaxRadius) return fail(c, SZ_ERR_ARG, "radius must be 1..32768");
+  if (s->chunk < 64 || s->chunk > 65536 || (s->chunk & 63))
+    return fail(c, SZ_ERR_ARG, "chunk must be a multiple of 64 in [64, 65536]");
+  if (!valid_order(ndim, s->order)) return fail(c, SZ_ERR_ARG, "dim_order must be a permutation");
+  return SZ_OK;
+}
+
+// The (level, dimension) passes of the multilevel traversal in execution
+// order: levels L..1 with stride s = 2^(l-1), and inside a level the
+// dimensions in `order`.  The origin is handled separately.
+void build_passes(const Shape& s, std::vector<PassGeom>& out) {
+  out.clear();
+  int L = 0;
+  for (int d = 0; d < s.ndim; d++) {
+    int l = 0;
+    while ((1ull << l) < s.dims[d]) l++;
+    L = std::max(L, l);
+  }
+  uint64_t stride[kMaxDims];
+  uint64_t st = 1;
+  for (int d = s.ndim - 1; d >= 0; d--) {
+    stride[d] = st;
+    st *= s.dims[d];
+  }
+  int pos[kMaxDims];
+  for (int j = 0; j < s.ndim; j++) pos[s.order[j]] = j;
+  for (int l = L; l >= 1; l--) {
+    uint64_t sp = 1ull << (l - 1);
+    for (int j = 0; j < s.ndim; j++) {
+      PassGeom g{};
+      g.ndim = s.ndim;
+      g.d = s.order[j];
+      g.s = (uint32_t)sp;
+      g.nd = (uint32_t)s.dims[g.d];
+      g.total = 1;
+      for (int e = 0; e < s.ndim; e++) {
+        uint64_t start = 0, step = 2 * sp;
+        if (e == g.d)
+          start = sp;
+        else if (pos[e] < j)
+          step = sp;
+        g.start[e] = start;
+        g.step[e] = step;
+        g.cnt[e] = start < s.dims[e] ? (uint32_t)((s.dims[e] - start + step - 1) / step) : 0;
+        g.stride[e] = stride[e];
+        g.total *= g.cnt[e];
+      }
+      if (g.total) out.push_back(g);
+    }
+  }
+}
+
+void put_le(uint8_t* p, uint64_t v, int bytes) {
+  for (int i = 0; i < bytes; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+uint64_t get_le(const uint8_t* p, int bytes) {
+  uint64_t v = 0;
+  for (int i = bytes - 1; i >= 0; i--) v = (v << 8) | p[i];
+  return v;
+}
+
+void header_template(const Shape& s, int predictor, int eb_mode, double eb_user, uint8_t* h) {
+  memset(h, 0, kHeaderBytes);
+  memcpy(h, "SZG1", 4);
+  put_le(h + 4, 1, 2);
+  h[6] = (uint8_t)s.dtype;
+  h[7] = (uint8_t)s.ndim;
+  for (int d = 0; d < kMaxDims; d++) put_le(h + 8 + 8 * d, d < s.ndim ? s.dims[d] : 1, 8);
+  h[40] = (uint8_t)predictor;
+  for (int d = 0; d < kMaxDims; d++) h[41 + d] = s.order[d];
+  h[45] = (uint8_t)eb_mode;
+  uint64_t u;
+  memcpy(&u, &eb_user, 8);
+  put_le(h + 48, u, 8);
+  put_le(h + 64, s.radius, 4);
+  put_le(h + 68, s.chunk, 4);
+}
+
+int parse_header(const uint8_t* h, sz_info* info) {
+  if (memcmp(h, "SZG1", 4) != 0 || get_le(h + 4, 2) != 1) return SZ_ERR_CORRUPT;
+  sz_info in{};
+  in.dtype = h[6];
+  in.ndim = h[7];
+  in.predictor = h[40];
+  in.eb_mode = h[45];
+  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 1 || in.eb_mode > 1)
+    return SZ_ERR_CORRUPT;
+  uint64_t n = 1;
+  bool empty = false;
+  for (int d = 0; d < kMaxDims; d++) {
+    in.dims[d] = get_le(h + 8 + 8 * d, 8);
+    in.dim_order[d] = h[41 + d];
+    if (d >= in.ndim && (in.dims[d] != 1 || in.dim_order[d] != d)) return SZ_ERR_CORRUPT;
+    if (d < in.ndim && in.dims[d] == 0) empty = true;
+  }
+  if (!valid_order(in.ndim, in.dim_order)) return SZ_ERR_CORRUPT;
+  if (empty) {
+    n = 0;
+  } else {
+    for (int d = 0; d < in.ndim; d++) {
+      if (in.dims[d] > kMaxPoints || n > kMaxPoints / in.dims[d]) return SZ_ERR_CORRUPT;
+      n *= in.dims[d];
+    }
+  }
+  in.n = n;
+  uint64_t u = get_le(h + 48, 8);
+  memcpy(&in.eb_user, &u, 8);
+  u = get_le(h + 56, 8);
+  memcpy(&in.eb, &u, 8);
+  in.radius = (uint32_t)get_le(h + 64, 4);
+  in.chunk = (uint32_t)get_le(h + 68, 4);
+  in.n_unpred = get_le(h + 72, 8);
+  in.nsym = (uint32_t)get_le(h + 80, 4);
+  in.total_words = get_le(h + 88, 8);
+  in.stream_bytes = get_le(h + 96, 8);
+  if (!(in.eb >= 0.0) || !__builtin_isfinite(in.eb)) return SZ_ERR_CORRUPT;
+  if (in.dtype == SZ_F32 && (double)(float)in.eb != in.eb) return SZ_ERR_CORRUPT;
+  if (in.radius < 1 || in.radius > kMaxRadius || in.chunk == 0) return SZ_ERR_CORRUPT;
+  if (in.nsym > 2 * in.radius || in.n_unpred > n || (in.nsym == 0) != (n == 0)) return SZ_ERR_CORRUPT;
+  if (in.total_words > 64 * (n + 1)) return SZ_ERR_CORRUPT;
+  uint64_t nchunks = (n + in.chunk - 1) / in.chunk;
+  Layout l = stream_layout(in.nsym, nchunks, in.n_unpred, in.dtype == SZ_F64 ? 8 : 4, in.total_words);
+  if (l.size != in.stream_bytes) return SZ_ERR_CORRUPT;
+  *info = in;
+  return SZ_OK;
+}
+
+int ensure_fixed(sz_ctx* ctx) {
+  if (ctx->meta) return SZ_OK;
+  CHECK_HIP(hipMalloc(&ctx->meta, sizeof(Meta)), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->hist, sizeof(uint32_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->enc_code, sizeof(uint64_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->enc_len, kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->symtab, sizeof(uint32_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->totals, sizeof(uint64_t) * 4), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.keys_a, sizeof(uint64_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.keys_b, sizeof(uint64_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.w, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.parent, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.depth, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.merged, sizeof(uint32_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.phase_end, sizeof(uint32_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->cb.leaf_sym, sizeof(uint16_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.lut, sizeof(uint32_t) << kLutBits), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.first, sizeof(uint64_t) * (kMaxCodeLen + 2)), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.count, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.offset, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.sorted_sym, sizeof(uint16_t) * kMaxSym), "hipMalloc");
+  ctx->dt.keys_a = ctx->cb.keys_a;
+  ctx->dt.keys_b = ctx->cb.keys_b;
+  CHECK_HIP(hipHostMalloc((void**)&ctx->h_meta, sizeof(Meta), hipHostMallocDefault), "hipHostMalloc");
+  CHECK_HIP(hipHostMalloc((void**)&ctx->h_header, kHeaderBytes, hipHostMallocDefault), "hipHostMalloc");
+  return SZ_OK;
+}
+
+int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
+  uint64_t nch = s.nchunks();
+  if (need_rec) CHECK_HIP(ensure(ctx->rec, s.n * s.tsize()), "hipMalloc(rec)");
+  CHECK_HIP(ensure(ctx->codes, s.n * 2), "hipMalloc(codes)");
+  CHECK_HIP(ensure(ctx->chunk_words, nch * 4), "hipMalloc");
+  CHECK_HIP(ensure(ctx->chunk_unpred, nch * 4), "hipMalloc");
+  CHECK_HIP(ensure(ctx->word_off, nch * 8), "hipMalloc");
+  CHECK_HIP(ensure(ctx->unpred_off, nch * 8), "hipMalloc");
+  CHECK_HIP(ensure(ctx->block_sums, ((nch + 1023) / 1024 + 1) * 8), "hipMalloc");
+  return SZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sz_ctx* sz_ctx_create(int device) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return nullptr;
+  if (hipSetDevice(device) != hipSuccess) return nullptr;
+  sz_ctx* ctx = new sz_ctx();
+  ctx->device = device;
+  if (ensure_fixed(ctx) != SZ_OK) {
+    sz_ctx_destroy(ctx);
+    return nullptr;
+  }
+  return ctx;
+}
+
+void sz_ctx_destroy(sz_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
+                 &ctx->unpred_off, &ctx->block_sums})
+    if (b->p) (void)hipFree(b->p);
+  void* fixed[] = {ctx->meta, ctx->hist, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
+                   ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
+                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut,
+                   ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
+  for (void* p : fixed)
+    if (p) (void)hipFree(p);
+  if (ctx->h_meta) (void)hipHostFree(ctx->h_meta);
+  if (ctx->h_header) (void)hipHostFree(ctx->h_header);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* sz_last_error(const sz_ctx* ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+void sz_default_options(sz_options* o) {
+  if (!o) return;
+  o->radius = kMaxRadius;
+  o->chunk = 4096;
+  for (int j = 0; j < kMaxDims; j++) o->dim_order[j] = (uint8_t)j;
+}
+
+size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims, const sz_options* opts) {
+  Shape s;
+  if (make_shape(nullptr, dtype, ndim, dims, opts, &s) != SZ_OK) return 0;
+  uint64_t nch = s.nchunks();
+  uint64_t ksym = std::min<uint64_t>(2ull * s.radius, s.n);
+  // Huffman is optimal, so its length is within one bit per symbol of the
+  // entropy, itself at most log2(2R) <= 16 bits; each chunk pads < 32 bits.
+  uint64_t words = (17 * s.n + 31) / 32 + nch;
+  Layout l = stream_layout(ksym, nch, s.n, s.tsize(), words);
+  return (size_t)l.size;
+}
+
+int sz_inspect(const void* h_stream, size_t len, sz_info* info) {
+  if (!h_stream || !info || len < kHeaderBytes) return SZ_ERR_ARG;
+  return parse_header(static_cast<const uint8_t*>(h_stream), info);
+}
+
+int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
+                int eb_mode, double eb, int predictor, const sz_options* opts, void* d_out,
+                size_t out_capacity, size_t* out_size, void* stream) {
+  if (!ctx) return SZ_ERR_ARG;
+  Shape s;
+  int rc = make_shape(ctx, dtype, ndim, dims, opts, &s);
+  if (rc) return rc;
+  if (!out_size) return fail(ctx, SZ_ERR_ARG, "out_size is NULL");
+  *out_size = 0;
+  if (eb_mode != SZ_EB_ABS && eb_mode != SZ_EB_REL) return fail(ctx, SZ_ERR_ARG, "bad eb_mode");
+  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC)
+    return fail(ctx, SZ_ERR_ARG, "bad predictor");
+  if (!(eb >= 0.0) || !__builtin_isfinite(eb)) return fail(ctx, SZ_ERR_ARG, "eb must be finite and >= 0");
+  if (eb_mode == SZ_EB_ABS && dtype == SZ_F32 && !__builtin_isfinite((float)eb))
+    return fail(ctx, SZ_ERR_ARG, "eb not representable in float");
+  if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
+  if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
+    return fail(ctx, SZ_ERR_ARG, "d_in must be 16-byte and d_out 8-byte aligned");
+  CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = ensure_sized(ctx, s, true))) return rc;
+  uint8_t* out = static_cast<uint8_t*>(d_out);
+  uint16_t* codes = static_cast<uint16_t*>(ctx->codes.p);
+  const uint32_t nsym = 2 * s.radius;
+  const uint64_t nch = s.nchunks();
+  uint8_t hdr[kHeaderBytes];
+  header_template(s, predictor, eb_mode, eb, hdr);
+
+  CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
+  if (eb_mode == SZ_EB_REL)
+    CHECK_HIP(timed(ctx, "minmax", st, [&] { return launch_minmax(d_in, dtype, s.n, ctx->meta, st); }),
+              "minmax");
+  CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st), "resolve_eb");
+  if (s.n) {
+    std::vector<PassGeom> passes;
+    build_passes(s, passes);
+    CHECK_HIP(timed(ctx, "interp", st, [&] {
+                return launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta, s.radius, st);
+              }), "origin");
+    for (const PassGeom& g : passes)
+      CHECK_HIP(timed(ctx, "interp", st, [&] {
+                  return launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                                              ctx->meta, s.radius, st);
+                }), "interp pass");
+  }
+  CHECK_HIP(launch_fill_u32(ctx->hist, 0, nsym, st), "fill");
+  CHECK_HIP(timed(ctx, "histogram", st,
+                  [&] { return launch_histogram(codes, s.n, nsym, s.radius, ctx->hist, st); }),
+            "histogram");
+  CHECK_HIP(timed(ctx, "codebook", st, [&] {
+              return launch_codebook(ctx->hist, nsym, ctx->cb, ctx->enc_code, ctx->enc_len,
+                                     ctx->symtab, ctx->meta, st);
+            }), "codebook");
+  uint32_t* cwords = static_cast<uint32_t*>(ctx->chunk_words.p);
+  uint32_t* cunp = static_cast<uint32_t*>(ctx->chunk_unpred.p);
+  uint64_t* woff = static_cast<uint64_t*>(ctx->word_off.p);
+  uint64_t* uoff = static_cast<uint64_t*>(ctx->unpred_off.p);
+  uint64_t* bsum = static_cast<uint64_t*>(ctx->block_sums.p);
+  CHECK_HIP(timed(ctx, "encode", st, [&] {
+              hipError_t e = launch_encode_count(codes, s.n, s.chunk, ctx->enc_len, cwords, cunp, st);
+              if (e == hipSuccess)
+                e = launch_exclusive_scan_u32(cwords, woff, nch, bsum, &ctx->meta->total_words, st);
+              if (e == hipSuccess)
+                e = launch_exclusive_scan_u32(cunp, uoff, nch, bsum, ctx->totals, st);
+              if (e == hipSuccess)
+                e = launch_encode_pack(codes, d_in, dtype, s.n, s.chunk, ctx->enc_code, ctx->enc_len,
+                                       woff, uoff, out, out_capacity, ctx->meta, st);
+              return e;
+            }), "encode");
+  CHECK_HIP(timed(ctx, "other", st, [&] {
+              return launch_write_tables(out, out_capacity, ctx->symtab, cwords, cunp, nch, hdr,
+                                         dtype, ctx->meta, st);
+            }), "write_tables");
+  CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
+  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  ctx->last_n = s.n;
+  const Meta& m = *ctx->h_meta;
+  if (m.status & kStatusEbNotFinite) return fail(ctx, SZ_ERR_ARG, "resolved error bound is not finite");
+  if (m.status & kStatusCodeTooLong) return fail(ctx, SZ_ERR_UNSUPPORTED, "Huffman code longer than 64 bits");
+  *out_size = (size_t)m.stream_bytes;
+  if (m.stream_bytes > out_capacity)
+    return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
+  return SZ_OK;
+}
+
+int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d_out,
+                  size_t out_capacity, void* stream) {
+  if (!ctx) return SZ_ERR_ARG;
+  if (!d_stream || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
+  if (((uintptr_t)d_stream % 8) || ((uintptr_t)d_out % 16))
+    return fail(ctx, SZ_ERR_ARG, "d_stream must be 8-byte and d_out 16-byte aligned");
+  if (stream_size < kHeaderBytes) return fail(ctx, SZ_ERR_CORRUPT, "stream shorter than its header");
+  CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  CHECK_HIP(hipMemcpyAsync(ctx->h_header, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, st), "memcpy");
+  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  sz_info in;
+  if (parse_header(ctx->h_header, &in) != SZ_OK) return fail(ctx, SZ_ERR_CORRUPT, "invalid header");
+  if (in.stream_bytes > stream_size) return fail(ctx, SZ_ERR_CORRUPT, "stream truncated");
+  Shape s;
+  s.dtype = in.dtype;
+  s.ndim = in.ndim;
+  for (int d = 0; d < kMaxDims; d++) {
+    s.dims[d] = in.dims[d];
+    s.order[d] = in.dim_order[d];
+  }
+  s.n = in.n;
+  s.radius = in.radius;
+  s.chunk = in.chunk;
+  if (out_capacity < s.n * s.tsize()) return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
+  int rc = ensure_sized(ctx, s, false);
+  if (rc) return rc;
+  const uint8_t* str = static_cast<const uint8_t*>(d_stream);
+  const uint64_t nch = s.nchunks();
+  Layout l = stream_layout(in.nsym, nch, in.n_unpred, s.tsize(), in.total_words);
+  uint16_t* codes = static_cast<uint16_t*>(ctx->codes.p);
+  uint32_t* cwords = static_cast<uint32_t*>(ctx->chunk_words.p);
+  uint32_t* cunp = static_cast<uint32_t*>(ctx->chunk_unpred.p);
+  uint64_t* woff = static_cast<uint64_t*>(ctx->word_off.p);
+  uint64_t* uoff = static_cast<uint64_t*>(ctx->unpred_off.p);
+  uint64_t* bsum = static_cast<uint64_t*>(ctx->block_sums.p);
+
+  CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
+  if (s.n) {
+    CHECK_HIP(timed(ctx, "codebook", st, [&] {
+                return launch_decode_tables(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt, ctx->meta, st);
+              }), "decode_tables");
+    CHECK_HIP(timed(ctx, "decode", st, [&] {
+                hipError_t e = launch_chunk_table_scan(str, l.off_chunk, nch, cwords, cunp, woff, uoff,
+                                                       bsum, ctx->totals, st);
+                if (e == hipSuccess)
+                  e = launch_check_totals(ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
+                if (e == hipSuccess)
+                  e = launch_decode_chunks(str, stream_size, l.off_unpred, l.off_bits, in.total_words,
+                                           in.n_unpred, s.n, s.chunk, s.dtype, cwords, cunp, woff, uoff,
+                                           ctx->dt, codes, d_out, ctx->meta, st);
+                return e;
+              }), "decode");
+    std::vector<PassGeom> passes;
+    build_passes(s, passes);
+    CHECK_HIP(timed(ctx, "recon", st, [&] {
+                return launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
+              }), "origin_recon");
+    for (const PassGeom& g : passes)
+      CHECK_HIP(timed(ctx, "recon", st, [&] {
+                  return launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb, s.radius, st);
+                }), "recon pass");
+  }
+  CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
+  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (ctx->h_meta->status & kStatusCorrupt) return fail(ctx, SZ_ERR_CORRUPT, "stream failed validation");
+  return SZ_OK;
+}
+
+int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields, const sz_options* opts,
+                      void* stream) {
+  if (!ctx || (nfields > 0 && !fields) || nfields < 0) return SZ_ERR_ARG;
+  int first = SZ_OK;
+  for (int i = 0; i < nfields; i++) {
+    sz_field& f = fields[i];
+    size_t sz = 0;
+    f.status = sz_compress(ctx, f.d_in, f.dtype, f.ndim, f.dims, f.eb_mode, f.eb, f.predictor, opts,
+                           f.d_out, f.out_capacity, &sz, stream);
+    f.out_size = sz;
+    if (f.status != SZ_OK && first == SZ_OK) first = f.status;
+  }
+  return first;
+}
+
+int sz_set_timing(sz_ctx* ctx, int enable) {
+  if (!ctx) return SZ_ERR_ARG;
+  ctx->timing = enable != 0;
+  return SZ_OK;
+}
+
+int sz_timing_get(sz_ctx* ctx, const char* name, double* total_ms, uint64_t* launches) {
+  if (!ctx || !name) return SZ_ERR_ARG;
+  settle_timing(ctx);
+  auto it = ctx->stats.find(name);
+  if (total_ms) *total_ms = it == ctx->stats.end() ? 0.0 : it->second.ms;
+  if (launches) *launches = it == ctx->stats.end() ? 0 : it->second.n;
+  return SZ_OK;
+}
+
+int sz_timing_reset(sz_ctx* ctx) {
+  if (!ctx) return SZ_ERR_ARG;
+  settle_timing(ctx);
+  ctx->stats.clear();
+  return SZ_OK;
+}
+
+int sz_debug_codes(sz_ctx* ctx, void* d_codes, size_t capacity, void* stream) {
+  if (!ctx || !d_codes) return SZ_ERR_ARG;
+  if (capacity < ctx->last_n * 2) return fail(ctx, SZ_ERR_CAPACITY, "capacity too small");
+  if (ctx->last_n == 0) return SZ_OK;
+  hipStream_t st = (hipStream_t)stream;
+  CHECK_HIP(hipMemcpyAsync(d_codes, ctx->codes.p, ctx->last_n * 2, hipMemcpyDeviceToDevice, st), "memcpy");
+  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return SZ_OK;
+}
+
+}  // extern "C"

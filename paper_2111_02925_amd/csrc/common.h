@@ -1,0 +1,157 @@
+// Internal declarations of the MI355X interpolation compressor library.
+//
+// Stage map (paper: SZ3, Algorithm 1 in Section 3.3, SZ3-Interp in Section 6.2):
+//   eb resolution     (range-relative bound, Section 6.2)      interp.hip
+//   predict+quantize  (Algorithm 1 loop; Section 3.2 quantizer) interp.hip
+//   histogram/codebook/encode/decode (Section 3.2 encoder)      huffman.hip
+//   reconstruction    (Appendix A.3 recover)                     interp.hip
+//   C ABI, context, stream header                                api.hip
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "szg.h"
+
+namespace szg {
+
+constexpr int kMaxDims = 4;
+constexpr uint32_t kMaxRadius = 32768;
+constexpr uint32_t kMaxSym = 2 * kMaxRadius;
+constexpr int kMaxCodeLen = 64;
+constexpr uint64_t kMaxPoints = 0xFFFFFFFFull;
+constexpr uint64_t kHeaderBytes = 128;
+constexpr int kLutBits = 12;
+
+__host__ __device__ inline uint64_t pad8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
+
+// Byte offsets of the stream sections (layout described in api.hip).
+struct Layout {
+  uint64_t off_sym, off_chunk, off_unpred, off_bits, size;
+};
+__host__ __device__ inline Layout stream_layout(uint64_t nsym_used, uint64_t nchunks,
+                                                uint64_t n_unpred, uint64_t tsize,
+                                                uint64_t words) {
+  Layout l;
+  l.off_sym = kHeaderBytes;
+  l.off_chunk = l.off_sym + pad8(4 * nsym_used);
+  l.off_unpred = l.off_chunk + 8 * nchunks;
+  l.off_bits = l.off_unpred + pad8(n_unpred * tsize);
+  l.size = l.off_bits + 4 * words;
+  return l;
+}
+
+// Per-call values produced on the device and read by later kernels, so that a
+// whole compression is one stream-ordered sequence without host round trips.
+struct Meta {
+  uint64_t key_min;    // order-preserving key of the finite minimum
+  uint64_t key_max;    // ... of the finite maximum
+  double eb;           // resolved bound in the field type, widened
+  double twoeb;        // 2 * eb in the field type
+  double inv2eb;       // 1 / (2 eb) in the field type
+  uint32_t nsym_used;  // K: symbols with a code
+  uint32_t max_len;
+  uint64_t n_unpred;
+  uint64_t total_words;
+  uint64_t stream_bytes;
+  uint32_t status;     // error bits (kStatus*)
+  uint32_t pad;
+};
+constexpr uint32_t kStatusEbNotFinite = 1u << 0;
+constexpr uint32_t kStatusCodeTooLong = 1u << 1;
+constexpr uint32_t kStatusCorrupt = 1u << 2;
+constexpr uint32_t kStatusCountMismatch = 1u << 3;
+
+// Geometry of one (level, dimension) pass of the multilevel traversal: the
+// points whose coordinate along `d` is an odd multiple of s, whose coordinates
+// along dimensions visited earlier in the level are multiples of s, and later
+// ones multiples of 2s.
+struct PassGeom {
+  int ndim;
+  int d;
+  uint32_t s;
+  uint32_t cnt[kMaxDims];    // lattice points along each dimension
+  uint64_t start[kMaxDims];
+  uint64_t step[kMaxDims];
+  uint64_t stride[kMaxDims]; // flat strides of the full field
+  uint32_t nd;               // extent along d
+  uint64_t total;            // points in the pass
+};
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+
+struct Timer;  // defined in api.hip
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+hipError_t launch_meta_init(Meta* m, hipStream_t st);
+hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, hipStream_t st);
+hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st);
+
+hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t* codes,
+                                  const Meta* m, uint32_t radius, hipStream_t st);
+hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
+                                uint16_t* codes, const PassGeom& g, const Meta* m,
+                                uint32_t radius, hipStream_t st);
+hipError_t launch_origin_recon(const uint16_t* codes, int dtype, void* out, double eb_t,
+                               uint32_t radius, hipStream_t st);
+hipError_t launch_pass_recon(const uint16_t* codes, int dtype, int predictor, void* out,
+                             const PassGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+
+hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t nsym, uint32_t radius,
+                            uint32_t* hist, hipStream_t st);
+
+struct CodebookScratch {
+  uint64_t* keys_a;    // kMaxSym
+  uint64_t* keys_b;    // kMaxSym
+  uint32_t* w;         // 2 * kMaxSym node weights
+  uint32_t* parent;    // 2 * kMaxSym
+  uint32_t* depth;     // 2 * kMaxSym
+  uint32_t* merged;    // kMaxSym
+  uint32_t* phase_end; // kMaxSym
+  uint16_t* leaf_sym;  // kMaxSym
+};
+hipError_t launch_codebook(const uint32_t* hist, uint32_t nsym, CodebookScratch s,
+                           uint64_t* enc_code, uint8_t* enc_len, uint32_t* symtab, Meta* m,
+                           hipStream_t st);
+
+hipError_t launch_encode_count(const uint16_t* codes, uint64_t n, uint32_t chunk,
+                               const uint8_t* enc_len, uint32_t* chunk_words,
+                               uint32_t* chunk_unpred, hipStream_t st);
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n,
+                                     uint64_t* block_sums, uint64_t* total, hipStream_t st);
+hipError_t launch_encode_pack(const uint16_t* codes, const void* x, int dtype, uint64_t n,
+                              uint32_t chunk, const uint64_t* enc_code, const uint8_t* enc_len,
+                              const uint64_t* word_off, const uint64_t* unpred_off,
+                              uint8_t* out, uint64_t capacity, Meta* m, hipStream_t st);
+hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
+                               const uint32_t* chunk_words, const uint32_t* chunk_unpred,
+                               uint64_t nchunks, const uint8_t* header_template, int dtype,
+                               Meta* m, hipStream_t st);
+
+struct DecodeTables {
+  uint32_t* lut;         // 1 << kLutBits entries: sym | len << 16 (len 0 = longer code)
+  uint64_t* first;       // kMaxCodeLen + 1
+  uint32_t* count;       // kMaxCodeLen + 1
+  uint32_t* offset;      // kMaxCodeLen + 1
+  uint16_t* sorted_sym;  // kMaxSym, by (length, symbol)
+  uint64_t* keys_a;
+  uint64_t* keys_b;
+};
+hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
+                                uint32_t nsym, DecodeTables t, Meta* m, hipStream_t st);
+hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
+                                   uint32_t* chunk_words, uint32_t* chunk_unpred,
+                                   uint64_t* word_off, uint64_t* unpred_off,
+                                   uint64_t* block_sums, uint64_t* totals, hipStream_t st);
+hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
+                                uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
+                                uint64_t n, uint32_t chunk, int dtype, const uint32_t* chunk_words,
+                                const uint32_t* chunk_unpred, const uint64_t* word_off,
+                                const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
+                                void* out, Meta* m, hipStream_t st);
+hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
+                               Meta* m, hipStream_t st);
+
+}  // namespace szg

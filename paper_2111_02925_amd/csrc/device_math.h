@@ -1,0 +1,109 @@
+// Per-point arithmetic of the compressor on the device: interpolation
+// stencils, the linear-scaling quantizer and its inverse.
+//
+// Paper: SZ3 (arXiv 2111.02925).  Section 6.2 (SZ3-Interp: linear and cubic
+// interpolation with constant coefficients, from reconstructed points);
+// Section 3.2 "Quantizer" (equal bins of width 2*eb, the code is the bin of
+// the prediction error, out-of-range errors are unpredictable and stored
+// separately); Appendix A.3 (quantize / recover).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace szg {
+
+__device__ __forceinline__ float fabs_t(float v) { return __builtin_fabsf(v); }
+__device__ __forceinline__ double fabs_t(double v) { return __builtin_fabs(v); }
+__device__ __forceinline__ float rint_t(float v) { return __builtin_rintf(v); }
+__device__ __forceinline__ double rint_t(double v) { return __builtin_rint(v); }
+__device__ __forceinline__ bool finite_t(float v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool finite_t(double v) { return __builtin_isfinite(v); }
+
+template <typename T>
+struct QuantParams {
+  T eb, twoeb, inv2eb;
+  uint32_t R;
+  __device__ static QuantParams from_meta(const Meta* m, uint32_t R) {
+    QuantParams q;
+    q.eb = (T)m->eb;  // exact: the stored doubles hold T values
+    q.twoeb = (T)m->twoeb;
+    q.inv2eb = (T)m->inv2eb;
+    q.R = R;
+    return q;
+  }
+};
+
+// Exact test of |x - r| <= eb.  s = fl(x - r) decides every case but
+// |s| == eb (rounding is monotone and eb is representable); there the sign of
+// the subtraction's rounding error, recovered exactly by the TwoSum
+// error-free transformation, decides.
+template <typename T>
+__device__ __forceinline__ bool bound_holds(T x, T r, T eb) {
+  const T s = x - r;
+  const T as = fabs_t(s);
+  if (as < eb) return true;
+  if (as != eb) return false;
+  const T y = -r;
+  const T sum_minus_y = s - y;
+  const T y_part = s - sum_minus_y;
+  const T err = (x - sum_minus_y) + (y - y_part);
+  return err == T(0) || ((err < T(0)) != (s < T(0)));
+}
+
+// Linear-scaling quantizer.  k = rint(|x - pred| / (2 eb)) (multiplied by the
+// precomputed reciprocal), signed like the error; the code is R + k when
+// |k| < R and the reconstruction pred + 2eb*k meets the bound, else 0
+// (unpredictable: the reconstruction is x itself).  eb == 0 codes only exact
+// predictions.
+template <typename T>
+__device__ __forceinline__ uint32_t quantize(T x, T pred, const QuantParams<T>& q, T& rec) {
+  const T diff = x - pred;
+  if (q.eb == T(0)) {
+    if (diff == T(0)) {
+      rec = pred + q.twoeb * T(0);
+      return q.R;
+    }
+    rec = x;
+    return 0;
+  }
+  const T kf = rint_t(fabs_t(diff) * q.inv2eb);
+  if (!(kf < (T)q.R)) {  // out of range, or NaN
+    rec = x;
+    return 0;
+  }
+  const int k = diff < T(0) ? -(int)kf : (int)kf;
+  const T r = pred + q.twoeb * (T)k;
+  if (!bound_holds(x, r, q.eb)) {
+    rec = x;
+    return 0;
+  }
+  rec = r;
+  return (uint32_t)((int)q.R + k);
+}
+
+template <typename T>
+__device__ __forceinline__ T recover(T pred, T twoeb, uint32_t code, uint32_t R) {
+  return pred + twoeb * (T)((int)code - (int)R);
+}
+
+// Interpolation at a point i along one dimension from a = v(i-3s), b = v(i-s),
+// c = v(i+s), e = v(i+3s) (flags say which exist).  Linear: midpoint; at the
+// high edge the line through (i-3s, i-s); with b alone, b.  Cubic: 4-point
+// Lagrange midpoint weights (-1, 9, 9, -1)/16; with one outer point missing
+// the quadratic through the three others; with both missing the midpoint; at
+// the high edge the linear rules.
+template <typename T, int PRED>
+__device__ __forceinline__ T interp_predict(T a, T b, T c, T e, bool has_a, bool has_c,
+                                            bool has_e) {
+  if (!has_c) return has_a ? (T(3) * b - a) * T(0.5) : b;
+  if (PRED == SZ_INTERP_LINEAR) return (b + c) * T(0.5);
+  if (has_a && has_e) return (T(9) * (b + c) - (a + e)) * T(0.0625);
+  if (has_e) return ((T(3) * b + T(6) * c) - e) * T(0.125);
+  if (has_a) return ((T(6) * b + T(3) * c) - a) * T(0.125);
+  return (b + c) * T(0.5);
+}
+
+}  // namespace szg

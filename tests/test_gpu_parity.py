@@ -1,0 +1,156 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact on everything: quantization codes, stream bytes (hence the
+compression ratio), and reconstructed values.  Cases span several chunks and
+levels with ragged extents, 1-D to 4-D, both predictors and dtypes, small
+radii (unpredictable path), dimension orders, chunk sizes, special values and
+degenerate shapes."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2111_02925_amd as szg
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = szg.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_roundtrip(ctx, x, mode, eb, pred, radius=32768, chunk=4096, order=None):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    s = ctx.compress(xt, mode, eb, pred, radius=radius, chunk=chunk, dim_order=order)
+    stream = bytes(s.cpu().numpy().tobytes())
+    codes = ctx.debug_codes(x.size).cpu().numpy().view(np.uint16).reshape(x.shape)
+    back = ctx.decompress(s).cpu().numpy()
+    return stream, codes, back
+
+
+def check_case(ctx, orc, x, mode, eb, pred, radius=32768, chunk=4096, order=None, label=""):
+    print(f"[case] {label} shape={x.shape} dtype={x.dtype} mode={mode} eb={eb} pred={pred} "
+          f"R={radius} C={chunk} order={order}", flush=True)
+    ref, rcodes, rrec = orc.compress(x, mode, eb, pred, radius, chunk, order, want_debug=True)
+    stream, codes, back = gpu_roundtrip(ctx, x, mode, eb, pred, radius, chunk, order)
+    assert np.array_equal(codes, rcodes), f"codes differ at {np.argwhere(codes != rcodes)[:5]}"
+    assert len(stream) == len(ref), (len(stream), len(ref))
+    if stream != ref:
+        diff = np.flatnonzero(np.frombuffer(stream, np.uint8) != np.frombuffer(ref, np.uint8))
+        raise AssertionError(f"stream bytes differ at {diff[:10]}")
+    assert back.tobytes() == rrec.tobytes(), "GPU decompress != oracle reconstruction"
+    # the GPU decoder also accepts the oracle's stream
+    st = torch.frombuffer(bytearray(ref), dtype=torch.uint8).cuda()
+    assert ctx.decompress(st).cpu().numpy().tobytes() == rrec.tobytes()
+
+
+def lognormal(shape, seed):
+    return synth.lognormal_grf(shape, seed=seed)
+
+
+CASES = [
+    # label, generator, mode, eb, pred, radius, chunk, order
+    ("cfg1-64^3-linear-abs", lambda: synth.sinusoid_field()[0], "abs", None, 0, 32768, 4096, None),
+    ("lognormal-ragged-cubic-1e-2", lambda: lognormal((97, 80, 71), 21), "rel", 1e-2, 1, 32768, 4096, None),
+    ("lognormal-ragged-cubic-1e-3", lambda: lognormal((97, 80, 71), 22), "rel", 1e-3, 1, 32768, 4096, None),
+    ("lognormal-ragged-cubic-1e-4", lambda: lognormal((97, 80, 71), 23), "rel", 1e-4, 1, 32768, 1024, None),
+    ("lognormal-linear-order", lambda: lognormal((33, 70, 45), 24), "rel", 1e-3, 0, 32768, 256, (2, 0, 1)),
+    ("climate-f64-cubic", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float64), "rel", 1e-4, 1, 32768, 4096, None),
+    ("climate-f32-linear", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float32), "rel", 1e-4, 0, 32768, 4096, None),
+    ("climate-f64-cubic-R512", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float64), "rel", 1e-4, 1, 512, 4096, None),
+    ("climate-f32-linear-R512", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float32), "rel", 1e-4, 0, 512, 64, None),
+    ("1d-long", lambda: np.cumsum(np.random.default_rng(5).standard_normal(100003)).astype(np.float32), "rel", 1e-3, 1, 32768, 65536, None),
+    ("4d", lambda: synth.random_field((9, 12, 7, 10), seed=6), "rel", 1e-3, 1, 32768, 512, (3, 1, 0, 2)),
+    ("tiny-radius", lambda: synth.random_field((40, 40), seed=7), "rel", 1e-3, 0, 4, 64, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity(ctx, orc, case):
+    label, gen, mode, eb, pred, radius, chunk, order = case
+    x = gen()
+    if eb is None:
+        eb = synth.sinusoid_field()[1]
+    check_case(ctx, orc, x, mode, eb, pred, radius, chunk, order, label)
+
+
+def test_parity_special_values(ctx, orc):
+    x = synth.random_field((30, 41), seed=8)
+    x[3, 7] = np.nan
+    x[5, 5] = np.inf
+    x[6, 6] = -np.inf
+    x[7, 0] = np.float32(1e-42)
+    x[2, 2] = -0.0
+    x[20, 30] = 3e38
+    check_case(ctx, orc, x, "rel", 1e-3, 1, label="special-values")
+
+
+@pytest.mark.parametrize("shape", [(1,), (2,), (3,), (1, 1, 1), (1, 1, 5), (2, 3, 1, 2), (65,), (64, 1)])
+def test_parity_tiny_shapes(ctx, orc, shape):
+    x = (np.arange(int(np.prod(shape)), dtype=np.float32) * 0.37 + 1).reshape(shape)
+    check_case(ctx, orc, x, "rel", 1e-2, 1, chunk=64, label=f"tiny{shape}")
+
+
+def test_parity_degenerate_bounds(ctx, orc):
+    const = np.full((17, 9, 5), 2.5, dtype=np.float32)
+    check_case(ctx, orc, const, "rel", 1e-3, 1, label="constant (eb = 0 via range)")
+    x = synth.random_field((20, 20), seed=9, dtype=np.float64)
+    check_case(ctx, orc, x, "abs", 0.0, 0, label="abs eb = 0")
+    allnan = np.full((8, 8), np.nan, dtype=np.float32)
+    check_case(ctx, orc, allnan, "rel", 1e-3, 1, label="no finite value")
+
+
+def test_empty_field(ctx, orc):
+    x = np.zeros((4, 0, 3), dtype=np.float32)
+    ref = orc.compress(x, orc.REL, 1e-3, orc.CUBIC)
+    xt = torch.zeros((4, 0, 3), dtype=torch.float32, device="cuda")
+    s = ctx.compress(xt, "rel", 1e-3, "cubic")
+    assert bytes(s.cpu().numpy().tobytes()) == ref
+    back = ctx.decompress(s)
+    assert tuple(back.shape) == (4, 0, 3)
+
+
+def test_capacity_and_corruption(ctx, orc):
+    import paper_2111_02925_amd as szg
+
+    x = synth.random_field((50, 60), seed=10)
+    xt = torch.from_numpy(x).cuda()
+    s = ctx.compress(xt, "rel", 1e-3, "cubic")
+    small = torch.zeros(len(s) - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(szg.SzError) as ei:
+        ctx.compress(xt, "rel", 1e-3, "cubic", out=small)
+    assert ei.value.status == szg.ERR_CAPACITY and ei.value.required == len(s)
+    good = ctx.decompress(s).cpu().numpy()
+    h = szg.inspect(s.cpu())
+    K = h["nsym"]
+    sym_pos = 128 + 2                      # a symbol-table length byte
+    chunk_pos = 128 + ((4 * K + 7) & ~7)   # first chunk's word count
+    for pos in (6, 45, sym_pos, chunk_pos):
+        bad = s.clone()
+        bad[pos] ^= 0x5A
+        with pytest.raises(szg.SzError) as ei:
+            ctx.decompress(bad)
+        assert ei.value.status == szg.ERR_CORRUPT
+    # flipped bitstream bits: detected, or a different (still finite-time) result
+    rng = np.random.default_rng(0)
+    nb = 4 * h["total_words"]
+    for pos in rng.integers(len(s) - nb, len(s), size=8):
+        bad = s.clone()
+        bad[int(pos)] ^= 0x08
+        try:
+            out = ctx.decompress(bad).cpu().numpy()
+        except szg.SzError as e:
+            assert e.status == szg.ERR_CORRUPT
+            continue
+        assert out.tobytes() != good.tobytes()
+    with pytest.raises(szg.SzError):
+        ctx.decompress(s[:-4])
