@@ -506,7 +506,7 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
 int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d_out,
                   size_t out_capacity, void* stream) {
   if (!ctx) return SZ_ERR_ARG;
-  if (!d_stream || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
+  if (!d_stream) return fail(ctx, SZ_ERR_ARG, "null stream");
   if (((uintptr_t)d_stream % 8) || ((uintptr_t)d_out % 16))
     return fail(ctx, SZ_ERR_ARG, "d_stream must be 8-byte and d_out 16-byte aligned");
   if (stream_size < kHeaderBytes) return fail(ctx, SZ_ERR_CORRUPT, "stream shorter than its header");
@@ -527,6 +527,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   s.n = in.n;
   s.radius = in.radius;
   s.chunk = in.chunk;
+  if (s.n && !d_out) return fail(ctx, SZ_ERR_ARG, "null output buffer");
   if (out_capacity < s.n * s.tsize()) return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
   int rc = ensure_sized(ctx, s, false);
   if (rc) return rc;

@@ -40,7 +40,8 @@ def gpu_roundtrip(ctx, x, mode, eb, pred, radius=32768, chunk=4096, order=None):
 def check_case(ctx, orc, x, mode, eb, pred, radius=32768, chunk=4096, order=None, label=""):
     print(f"[case] {label} shape={x.shape} dtype={x.dtype} mode={mode} eb={eb} pred={pred} "
           f"R={radius} C={chunk} order={order}", flush=True)
-    ref, rcodes, rrec = orc.compress(x, mode, eb, pred, radius, chunk, order, want_debug=True)
+    omode = {"abs": orc.ABS, "rel": orc.REL}[mode]
+    ref, rcodes, rrec = orc.compress(x, omode, eb, pred, radius, chunk, order, want_debug=True)
     stream, codes, back = gpu_roundtrip(ctx, x, mode, eb, pred, radius, chunk, order)
     assert np.array_equal(codes, rcodes), f"codes differ at {np.argwhere(codes != rcodes)[:5]}"
     assert len(stream) == len(ref), (len(stream), len(ref))
