@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libszg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["interp.hip", "huffman.hip", "api.hip"]
-HEADERS = ["common.h", "device_math.h"]
+SOURCES = ["interp.hip", "huffman.hip", "encode.hip", "decode.hip", "api.hip"]
+HEADERS = ["common.h", "device_math.h", "block_ops.h"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

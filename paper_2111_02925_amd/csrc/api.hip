@@ -346,6 +346,7 @@ int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
   CHECK_HIP(ensure(ctx->word_off, nch * 8), "hipMalloc");
   CHECK_HIP(ensure(ctx->unpred_off, nch * 8), "hipMalloc");
   CHECK_HIP(ensure(ctx->block_sums, ((nch + 1023) / 1024 + 1) * 8), "hipMalloc");
+
   return SZ_OK;
 }
 
@@ -374,6 +375,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
                  &ctx->unpred_off, &ctx->block_sums})
     if (b->p) (void)hipFree(b->p);
   void* fixed[] = {ctx->meta, ctx->hist, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
+
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
                    ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
@@ -471,25 +473,15 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
               return launch_codebook(ctx->hist, nsym, ctx->cb, ctx->enc_code, ctx->enc_len,
                                      ctx->symtab, ctx->meta, st);
             }), "codebook");
-  uint32_t* cwords = static_cast<uint32_t*>(ctx->chunk_words.p);
-  uint32_t* cunp = static_cast<uint32_t*>(ctx->chunk_unpred.p);
-  uint64_t* woff = static_cast<uint64_t*>(ctx->word_off.p);
-  uint64_t* uoff = static_cast<uint64_t*>(ctx->unpred_off.p);
-  uint64_t* bsum = static_cast<uint64_t*>(ctx->block_sums.p);
+  EncodeScratch es{static_cast<uint32_t*>(ctx->chunk_words.p), static_cast<uint32_t*>(ctx->chunk_unpred.p),
+                   static_cast<uint64_t*>(ctx->word_off.p), static_cast<uint64_t*>(ctx->unpred_off.p),
+                   static_cast<uint64_t*>(ctx->block_sums.p), ctx->totals};
   CHECK_HIP(timed(ctx, "encode", st, [&] {
-              hipError_t e = launch_encode_count(codes, s.n, s.chunk, ctx->enc_len, cwords, cunp, st);
-              if (e == hipSuccess)
-                e = launch_exclusive_scan_u32(cwords, woff, nch, bsum, &ctx->meta->total_words, st);
-              if (e == hipSuccess)
-                e = launch_exclusive_scan_u32(cunp, uoff, nch, bsum, ctx->totals, st);
-              if (e == hipSuccess)
-                e = launch_encode_pack(codes, d_in, dtype, s.n, s.chunk, ctx->enc_code, ctx->enc_len,
-                                       woff, uoff, out, out_capacity, ctx->meta, st);
-              return e;
+              return launch_encode(codes, d_in, dtype, s.n, s.chunk, s.radius, ctx->enc_code,
+                                   ctx->enc_len, es, out, out_capacity, ctx->meta, st);
             }), "encode");
   CHECK_HIP(timed(ctx, "other", st, [&] {
-              return launch_write_tables(out, out_capacity, ctx->symtab, cwords, cunp, nch, hdr,
-                                         dtype, ctx->meta, st);
+              return launch_write_tables(out, out_capacity, ctx->symtab, nch, hdr, dtype, ctx->meta, st);
             }), "write_tables");
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -553,7 +545,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                   e = launch_check_totals(ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
                 if (e == hipSuccess)
                   e = launch_decode_chunks(str, stream_size, l.off_unpred, l.off_bits, in.total_words,
-                                           in.n_unpred, s.n, s.chunk, s.dtype, cwords, cunp, woff, uoff,
+                                           in.n_unpred, s.n, s.chunk, in.nsym, s.dtype, cwords, cunp, woff, uoff,
                                            ctx->dt, codes, d_out, ctx->meta, st);
                 return e;
               }), "decode");

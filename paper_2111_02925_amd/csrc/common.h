@@ -23,6 +23,7 @@ constexpr int kMaxCodeLen = 64;
 constexpr uint64_t kMaxPoints = 0xFFFFFFFFull;
 constexpr uint64_t kHeaderBytes = 128;
 constexpr int kLutBits = 12;
+constexpr int kCbThreads = 512;  // threads of the single-block table kernels
 
 __host__ __device__ inline uint64_t pad8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
 
@@ -52,6 +53,8 @@ struct Meta {
   double inv2eb;       // 1 / (2 eb) in the field type
   uint32_t nsym_used;  // K: symbols with a code
   uint32_t max_len;
+  uint32_t sym_lo;     // smallest coded symbol other than 0 (0xFFFFFFFF if none)
+  uint32_t sym_hi;     // largest coded symbol other than 0
   uint64_t n_unpred;
   uint64_t total_words;
   uint64_t stream_bytes;
@@ -81,8 +84,6 @@ struct PassGeom {
 
 // ------------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
-
-struct Timer;  // defined in api.hip
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
 hipError_t launch_meta_init(Meta* m, hipStream_t st);
@@ -116,17 +117,23 @@ hipError_t launch_codebook(const uint32_t* hist, uint32_t nsym, CodebookScratch 
                            uint64_t* enc_code, uint8_t* enc_len, uint32_t* symtab, Meta* m,
                            hipStream_t st);
 
-hipError_t launch_encode_count(const uint16_t* codes, uint64_t n, uint32_t chunk,
-                               const uint8_t* enc_len, uint32_t* chunk_words,
-                               uint32_t* chunk_unpred, hipStream_t st);
 hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n,
                                      uint64_t* block_sums, uint64_t* total, hipStream_t st);
-hipError_t launch_encode_pack(const uint16_t* codes, const void* x, int dtype, uint64_t n,
-                              uint32_t chunk, const uint64_t* enc_code, const uint8_t* enc_len,
-                              const uint64_t* word_off, const uint64_t* unpred_off,
-                              uint8_t* out, uint64_t capacity, Meta* m, hipStream_t st);
+
+// Encoder scratch: per-chunk sizes and their exclusive scans.
+struct EncodeScratch {
+  uint32_t* chunk_words;
+  uint32_t* chunk_zeros;
+  uint64_t* word_off;
+  uint64_t* zero_off;
+  uint64_t* block_sums;
+  uint64_t* totals;
+};
+hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
+                         uint32_t chunk, uint32_t radius, const uint64_t* enc_code,
+                         const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
+                         Meta* m, hipStream_t st);
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
-                               const uint32_t* chunk_words, const uint32_t* chunk_unpred,
                                uint64_t nchunks, const uint8_t* header_template, int dtype,
                                Meta* m, hipStream_t st);
 
@@ -147,7 +154,7 @@ hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, ui
                                    uint64_t* block_sums, uint64_t* totals, hipStream_t st);
 hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
                                 uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
-                                uint64_t n, uint32_t chunk, int dtype, const uint32_t* chunk_words,
+                                uint64_t n, uint32_t chunk, uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
                                 const uint32_t* chunk_unpred, const uint64_t* word_off,
                                 const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
                                 void* out, Meta* m, hipStream_t st);

@@ -1,0 +1,408 @@
+// Huffman decoding (the inverse of the encoder of Section 3.2 "Encoder" in
+// SZ3, arXiv 2111.02925): rebuild canonical decoding tables from the stored
+// code lengths (the encoder's saved state), locate each chunk by prefix sums
+// over the chunk table, and decode every chunk independently, scattering the
+// verbatim unpredictable values (the quantizer's saved state) into the output.
+//
+// Every read of the stream is bounded by the section sizes the host has
+// validated; inconsistencies set a status bit instead of faulting.
+#include "block_ops.h"
+#include "common.h"
+
+namespace szg {
+
+// Three-kernel exclusive scan of u32 -> u64 (1024 elements per block).
+constexpr uint32_t kScanPerBlock = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
+                                                     uint64_t* block_sums) {
+  __shared__ uint64_t sh[16];
+  uint64_t base = blockIdx.x * (uint64_t)kScanPerBlock;
+  uint64_t v = 0;
+  for (uint32_t k = 0; k < 4; k++) {
+    uint64_t i = base + threadIdx.x * 4 + k;
+    if (i < n) v += in[i];
+  }
+  uint64_t tot;
+  block_excl_scan_u64(v, sh, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* block_sums, uint64_t nb,
+                                                      uint64_t* total) {
+  __shared__ uint64_t sh[16];
+  const uint64_t T = blockDim.x;
+  const uint64_t seg = (nb + T - 1) / T;
+  const uint64_t beg = threadIdx.x * seg < nb ? threadIdx.x * seg : nb;
+  const uint64_t end = beg + seg < nb ? beg + seg : nb;
+  uint64_t v = 0;
+  for (uint64_t i = beg; i < end; i++) v += block_sums[i];
+  uint64_t tot;
+  uint64_t run = block_excl_scan_u64(v, sh, &tot);
+  for (uint64_t i = beg; i < end; i++) {
+    uint64_t x = block_sums[i];
+    block_sums[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, uint64_t n,
+                                                    const uint64_t* block_sums, uint64_t* out) {
+  __shared__ uint64_t sh[16];
+  uint64_t base = blockIdx.x * (uint64_t)kScanPerBlock;
+  uint32_t loc[4];
+  uint64_t v = 0;
+  for (uint32_t k = 0; k < 4; k++) {
+    uint64_t i = base + threadIdx.x * 4 + k;
+    loc[k] = i < n ? in[i] : 0;
+    v += loc[k];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan_u64(v, sh, &tot) + block_sums[blockIdx.x];
+  for (uint32_t k = 0; k < 4; k++) {
+    uint64_t i = base + threadIdx.x * 4 + k;
+    if (i < n) out[i] = run;
+    run += loc[k];
+  }
+}
+
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n,
+                                     uint64_t* block_sums, uint64_t* total, hipStream_t st) {
+  uint64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, n, block_sums);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_sums, nb, total);
+  if (n) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, st, in, n,
+                            block_sums, out);
+  return hipGetLastError();
+}
+
+// Build the canonical decoding tables from the stored (symbol, length) list:
+// validate it (ascending symbols, lengths 1..64, a complete prefix code),
+// sort by (length, symbol), and fill a lookup table indexed by the next
+// kLutBits bits for codes no longer than that.
+__global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
+                                                              uint64_t off_sym, uint32_t K,
+                                                              uint32_t nsym, DecodeTables d,
+                                                              Meta* m) {
+  __shared__ uint32_t cnt[16 * kCbThreads];
+  __shared__ uint32_t sh16[16];
+  __shared__ uint32_t bl[kMaxCodeLen + 2];
+  __shared__ uint32_t bad;
+  const uint32_t T = blockDim.x, t = threadIdx.x;
+  if (t <= kMaxCodeLen + 1) bl[t] = 0;
+  if (t == 0) bad = 0;
+  for (uint32_t i = t; i < (1u << kLutBits); i += T) d.lut[i] = 0;
+  __syncthreads();
+  const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_sym);
+  for (uint32_t i = t; i < K; i += T) {
+    uint32_t e = tab[i];
+    uint32_t sym = e & 0xFFFF, len = e >> 16;
+    bool ok = sym < nsym && len >= 1 && len <= kMaxCodeLen;
+    if (i > 0 && (tab[i - 1] & 0xFFFF) >= sym) ok = false;
+    if (!ok) {
+      bad = 1;
+    } else {
+      atomicAdd(&bl[len], 1u);
+      d.keys_a[i] = ((uint64_t)len << 16) | sym;
+    }
+  }
+  __syncthreads();
+  if (t == 0 && !bad) {
+    // complete prefix code: pairing nodes from the deepest level up must leave
+    // exactly the root (a lone symbol must have length 1)
+    if (K == 1) {
+      if (bl[1] != 1) bad = 1;
+    } else if (K > 1) {
+      uint64_t carry = 0;
+      for (int l = kMaxCodeLen; l >= 1; l--) {
+        uint64_t nodes = bl[l] + carry;
+        if (nodes & 1) {
+          bad = 1;
+          break;
+        }
+        carry = nodes >> 1;
+      }
+      if (!bad && carry != 1) bad = 1;
+    }
+    uint64_t code = 0;
+    uint32_t off = 0;
+    for (int l = 1; l <= kMaxCodeLen; l++) {
+      code = (code + (l > 1 ? bl[l - 1] : 0)) << 1;
+      d.first[l] = code;
+      d.count[l] = bl[l];
+      d.offset[l] = off;
+      off += bl[l];
+    }
+    if (bad) atomicOr(&m->status, kStatusCorrupt);
+  }
+  __syncthreads();
+  if (bad || K == 0) return;
+  uint64_t* bylen = block_radix_sort(d.keys_a, d.keys_b, K, 16, 24, cnt, sh16);
+  for (uint32_t j = t; j < K; j += T) {
+    uint64_t key = bylen[j];
+    uint32_t l = (uint32_t)(key >> 16) & 0xFF, sym = (uint32_t)(key & 0xFFFF);
+    d.sorted_sym[j] = (uint16_t)sym;
+    if (l <= kLutBits) {
+      uint64_t code = d.first[l] + (j - d.offset[l]);
+      uint32_t lo = (uint32_t)(code << (kLutBits - l)), span = 1u << (kLutBits - l);
+      for (uint32_t k = 0; k < span; k++) d.lut[lo + k] = sym | (l << 16);
+    }
+  }
+}
+
+hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
+                                uint32_t nsym, DecodeTables t, Meta* m, hipStream_t st) {
+  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kCbThreads), 0, st, stream, off_sym,
+                     nsym_used, nsym, t, m);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_read_chunk_table(const uint8_t* __restrict__ stream,
+                                                          uint64_t off_chunk, uint64_t nchunks,
+                                                          uint32_t* chunk_words,
+                                                          uint32_t* chunk_unpred) {
+  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
+  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nchunks; c += gs) {
+    chunk_words[c] = tab[2 * c];
+    chunk_unpred[c] = tab[2 * c + 1];
+  }
+}
+
+hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
+                                   uint32_t* chunk_words, uint32_t* chunk_unpred,
+                                   uint64_t* word_off, uint64_t* unpred_off,
+                                   uint64_t* block_sums, uint64_t* totals, hipStream_t st) {
+  if (nchunks == 0) return hipSuccess;
+  uint64_t blocks = (nchunks + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_read_chunk_table, dim3((unsigned)blocks), dim3(256), 0, st, stream,
+                     off_chunk, nchunks, chunk_words, chunk_unpred);
+  hipError_t e = launch_exclusive_scan_u32(chunk_words, word_off, nchunks, block_sums, totals, st);
+  if (e != hipSuccess) return e;
+  return launch_exclusive_scan_u32(chunk_unpred, unpred_off, nchunks, block_sums, totals + 1, st);
+}
+
+__global__ void k_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
+                               Meta* m) {
+  if (totals[0] != total_words || totals[1] != n_unpred) atomicOr(&m->status, kStatusCorrupt);
+}
+
+hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
+                               Meta* m, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_totals, dim3(1), dim3(1), 0, st, totals, total_words, n_unpred, m);
+  return hipGetLastError();
+}
+
+
+// Decoding loop.  Each lane decodes one chunk.  The window `buf` holds the
+// next `nb` stream bits left-aligned (bits past them are zero) and the word
+// `nxt` (index rd) follows them: used + nb == 32 * rd.  Before every symbol at
+// least 32 bits are present, which covers every code of the lookup table
+// (<= kLutBits bits).  A refill appends `nxt`, loaded one refill earlier, so
+// its latency hides behind the symbols decoded in between.  Reads past the chunk's words yield zeros; a
+// code that runs past the end is detected once, from the number of bits
+// consumed, instead of per symbol.
+constexpr uint32_t kLongSymCap = 4096;  // long-code symbols kept in LDS
+constexpr uint32_t kGroup = 32;         // codes staged in LDS per lane
+
+// Codes longer than the lookup table: with canonical codes the left-justified
+// end of each length's code range grows with the length, and comparing the
+// window against the end of length k only involves its first k bits, so the
+// code length is kLutBits + 1 plus the number of ends the window reaches.
+struct LongCodes {
+  uint64_t end_lj[kMaxCodeLen + 1];  // left-justified end of length-l codes
+  uint64_t base[kMaxCodeLen + 1];    // offset[l] - first[l] (mod 2^64)
+  uint32_t max_len;
+  uint32_t long_first;               // sorted index of the first long code
+  uint32_t long_in_lds;
+};
+
+// 64 stream bits from bit `pos` of a chunk of `nw` words (zeros past its end).
+__device__ __forceinline__ uint64_t peek64(const uint32_t* __restrict__ w, uint64_t nw,
+                                           uint64_t pos) {
+  const uint64_t wi = pos >> 5;
+  const uint32_t o = (uint32_t)(pos & 31);
+  const uint64_t w0 = wi < nw ? w[wi] : 0, w1 = wi + 1 < nw ? w[wi + 1] : 0,
+                 w2 = wi + 2 < nw ? w[wi + 2] : 0;
+  uint64_t v = (w0 << 32) | w1;
+  if (o) v = (v << o) | (w2 >> (32 - o));
+  return v;
+}
+
+struct ChunkResult {
+  uint64_t used;  // stream bits consumed
+  uint64_t ucnt;  // unpredictable values taken
+  bool ok;
+};
+
+template <typename T, bool LONG_LDS>
+__device__ __forceinline__ ChunkResult decode_chunk(
+    const uint32_t* __restrict__ words, uint64_t nwords, uint32_t nt, const uint32_t* lut,
+    const LongCodes& lc, const uint16_t* long_sym, const uint16_t* __restrict__ sorted_sym,
+    uint16_t* stage, uint64_t beg, uint64_t end, uint32_t chunk, const T* __restrict__ unpred,
+    uint64_t ubase, uint64_t uexp, uint64_t n_unpred, uint16_t* codes, T* out) {
+  uint64_t ucnt = 0;
+  bool ok = true;
+  uint64_t used = 0;  // bits consumed
+  uint64_t buf = 0;
+  uint32_t nb = 0;
+  uint64_t rd = 0;  // index of the word held in nxt
+  uint32_t nxt = nwords ? words[0] : 0u;
+  // prime: two words
+  buf = (uint64_t)nxt << 32;
+  nb = 32;
+  rd = 1;
+  nxt = rd < nwords ? words[rd] : 0u;
+  buf |= nxt;
+  nb = 64;
+  rd = 2;
+  nxt = rd < nwords ? words[rd] : 0u;
+  const bool vec = (chunk & 7) == 0;
+  for (uint64_t g = beg; g < end; g += kGroup) {
+    const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
+    for (uint32_t k = 0; k < cnt; k++) {
+      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+      uint32_t len = e >> 16;
+      uint32_t sym = e & 0xFFFFu;
+      if (len == 0) {  // rare: a code longer than the table, read exactly from memory
+        const uint64_t win = peek64(words, nwords, used);
+        uint32_t l = kLutBits + 1;
+        for (uint32_t q = kLutBits + 1; q < lc.max_len; q++) l += win >= lc.end_lj[q] ? 1u : 0u;
+        const uint32_t idx = (uint32_t)(lc.base[l] + (win >> (64 - l)));
+        sym = LONG_LDS ? long_sym[idx - lc.long_first] : sorted_sym[idx];
+        len = l;
+        // rebuild the window at the new position (used + nb == 32 * rd again)
+        used += len;
+        const uint32_t o = (uint32_t)(used & 31);
+        nb = 64 - o;
+        const uint64_t v = peek64(words, nwords, used);
+        buf = o ? v & ~((1ull << o) - 1) : v;
+        rd = (used >> 5) + 2;
+        nxt = rd < nwords ? words[rd] : 0u;
+      } else {
+        used += len;
+        buf <<= len;
+        nb -= len;
+      }
+      if (nb < 32) {  // append the prefetched word, prefetch the next
+        buf |= (uint64_t)nxt << (32 - nb);
+        nb += 32;
+        rd++;
+        nxt = rd < nwords ? words[rd] : 0u;
+      }
+      stage[k * nt] = (uint16_t)sym;
+      if (sym == 0) {
+        if (ucnt >= uexp || ubase + ucnt >= n_unpred) {
+          ok = false;
+          break;
+        }
+        out[g + k] = unpred[ubase + ucnt];
+        ucnt++;
+      }
+    }
+    if (!ok) break;
+    if (vec && cnt == kGroup) {
+      uint4* dst = reinterpret_cast<uint4*>(codes + g);
+#pragma unroll
+      for (int j = 0; j < (int)(kGroup / 8); j++) {
+        uint32_t v[4];
+#pragma unroll
+        for (int h = 0; h < 4; h++)
+          v[h] = (uint32_t)stage[(8 * j + 2 * h) * nt] |
+                 ((uint32_t)stage[(8 * j + 2 * h + 1) * nt] << 16);
+        dst[j] = make_uint4(v[0], v[1], v[2], v[3]);
+      }
+    } else {
+      for (uint32_t j = 0; j < cnt; j++) codes[g + j] = stage[j * nt];
+    }
+  }
+  return ChunkResult{used, ucnt, ok};
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_decode_chunks(
+    const uint8_t* __restrict__ stream, uint64_t off_unpred, uint64_t off_bits,
+    uint64_t total_words, uint64_t n_unpred, uint64_t n, uint32_t chunk, uint64_t nchunks,
+    uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_unpred, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ unpred_off, DecodeTables d, uint16_t* codes, T* out, Meta* m) {
+  __shared__ uint32_t lut[1u << kLutBits];
+  __shared__ LongCodes lc;
+  __shared__ uint16_t long_sym[kLongSymCap];
+  __shared__ uint16_t stage_all[NT * kGroup];
+  uint16_t* stage = stage_all + threadIdx.x;
+  for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += blockDim.x) lut[i] = d.lut[i];
+  if (threadIdx.x == 0) {
+    uint32_t maxl = 0;
+    for (uint32_t l = 1; l <= (uint32_t)kMaxCodeLen; l++) {
+      if (d.count[l]) maxl = l;
+      lc.base[l] = (uint64_t)d.offset[l] - d.first[l];
+      lc.end_lj[l] = l < (uint32_t)kMaxCodeLen ? (d.first[l] + d.count[l]) << (64 - l) : ~0ull;
+    }
+    lc.max_len = maxl;
+    lc.long_first = kLutBits < maxl ? d.offset[kLutBits + 1] : nsym_used;
+    lc.long_in_lds = nsym_used - lc.long_first <= kLongSymCap;
+  }
+  __syncthreads();
+  if (lc.long_in_lds)
+    for (uint32_t i = lc.long_first + threadIdx.x; i < nsym_used; i += blockDim.x)
+      long_sym[i - lc.long_first] = d.sorted_sym[i];
+  __syncthreads();
+  const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (c >= nchunks || m->status) return;
+  const uint64_t W = chunk_words[c], wbase = word_off[c];
+  if (wbase + W > total_words) {
+    atomicOr(&m->status, kStatusCorrupt);
+    return;
+  }
+  const uint32_t* words = reinterpret_cast<const uint32_t*>(stream + off_bits) + wbase;
+  const T* unpred = reinterpret_cast<const T*>(stream + off_unpred);
+  const uint64_t ubase = unpred_off[c], uexp = chunk_unpred[c];
+  const uint64_t beg = c * chunk, end = beg + chunk < n ? beg + chunk : n;
+  const ChunkResult res =
+      lc.long_in_lds
+          ? decode_chunk<T, true>(words, W, NT, lut, lc, long_sym, d.sorted_sym, stage, beg, end,
+                                  chunk, unpred, ubase, uexp, n_unpred, codes, out)
+          : decode_chunk<T, false>(words, W, NT, lut, lc, long_sym, d.sorted_sym, stage, beg, end,
+                                   chunk, unpred, ubase, uexp, n_unpred, codes, out);
+  if (!res.ok || res.ucnt != uexp || res.used > W * 32 || (res.used + 31) / 32 != W)
+    atomicOr(&m->status, kStatusCorrupt);
+}
+
+hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
+                                uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
+                                uint64_t n, uint32_t chunk, uint32_t nsym_used, int dtype,
+                                const uint32_t* chunk_words, const uint32_t* chunk_unpred,
+                                const uint64_t* word_off, const uint64_t* unpred_off,
+                                DecodeTables t, uint16_t* codes, void* out, Meta* m,
+                                hipStream_t st) {
+  (void)stream_size;
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
+  if (nchunks == 0) return hipSuccess;
+  // 64-lane blocks when there are few chunks, so every CU gets work
+  const bool small = nchunks < 256ull * 1024;
+  const unsigned nt = small ? 64 : 256;
+  dim3 grid((unsigned)((nchunks + nt - 1) / nt)), block(nt);
+#define SZG_DECODE_LAUNCH(TT, NTT)                                                              \
+  hipLaunchKernelGGL((k_decode_chunks<TT, NTT>), grid, block, 0, st, stream, off_unpred,       \
+                     off_bits, total_words, n_unpred, n, chunk, nchunks, nsym_used, chunk_words, \
+                     chunk_unpred, word_off, unpred_off, t, codes, (TT*)out, m)
+  if (dtype == SZ_F32) {
+    if (small)
+      SZG_DECODE_LAUNCH(float, 64);
+    else
+      SZG_DECODE_LAUNCH(float, 256);
+  } else {
+    if (small)
+      SZG_DECODE_LAUNCH(double, 64);
+    else
+      SZG_DECODE_LAUNCH(double, 256);
+  }
+#undef SZG_DECODE_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace szg

@@ -1,0 +1,410 @@
+// Huffman encoding of the quantization codes and stream assembly, gfx950.
+//
+// Paper: SZ3 (arXiv 2111.02925), Section 3.2 "Encoder" (compress the codes
+// with the codebook built from their frequencies) and Algorithm 1 (the
+// quantizer's unpredictable values and the encoder's table are saved with
+// the bitstream).
+//
+// Three steps: (1) every chunk's size (code bits, unpredictable count) by one
+// wave per chunk, (2) exclusive scans of the sizes, (3) packing.  In (1) and
+// (3) lane L of the wave owns a contiguous run of m = max(32, chunk/64)
+// symbols, so every lane but the last non-empty one writes at least 32 bits:
+// a 32-bit output word then holds bits of at most two lanes, the full words a
+// lane produces are stored directly, and the one word it shares with its
+// predecessor is completed by that lane through a register shuffle.  Runs of
+// up to 64 symbols stay in registers between the two passes over them.
+//
+// Codewords are looked up in an LDS copy of the codebook window that holds
+// every coded symbol (the unpredictable symbol 0 lives in registers); when
+// the coded symbols span more than the window, or a code is longer than 32
+// bits, a variant that falls back to the global codebook runs instead.
+#include "block_ops.h"
+#include "common.h"
+
+namespace szg {
+
+constexpr uint32_t kEncWindow = 8192;  // LDS codebook entries
+constexpr int kEncWaves = 4;
+constexpr int kSeg = 64;  // symbols of a lane's run held in registers at once
+
+__device__ __forceinline__ void guarded_store_u32(uint8_t* out, uint64_t cap, uint64_t off,
+                                                  uint32_t v) {
+  if (off + 4 <= cap) *reinterpret_cast<uint32_t*>(out + off) = v;
+}
+
+struct EncTables {
+  uint32_t code[kEncWindow];
+  uint8_t len[kEncWindow];
+};
+
+struct EncWindow {
+  uint32_t lo;       // first symbol of the window
+  bool lds_only;     // every coded symbol other than 0 is in the window, codes <= 32 bits
+  uint64_t code0;    // codeword of symbol 0
+  uint32_t len0;
+};
+
+__device__ __forceinline__ EncWindow enc_window(const Meta* m, uint32_t R,
+                                                const uint64_t* __restrict__ enc_code,
+                                                const uint8_t* __restrict__ enc_len) {
+  EncWindow w;
+  const uint32_t slo = m->sym_lo, shi = m->sym_hi;
+  const bool none = slo == 0xFFFFFFFFu;
+  w.lds_only = (none || shi - slo < kEncWindow) && m->max_len <= 32;
+  w.lo = w.lds_only ? (none ? 0u : slo) : (R > kEncWindow / 2 ? R - kEncWindow / 2 : 0u);
+  w.code0 = enc_code[0];
+  w.len0 = enc_len[0];
+  return w;
+}
+
+__device__ __forceinline__ void load_tables(EncTables& t, const EncWindow& w, uint32_t nsym,
+                                            const uint64_t* __restrict__ enc_code,
+                                            const uint8_t* __restrict__ enc_len, bool codes) {
+  for (uint32_t i = threadIdx.x; i < kEncWindow; i += blockDim.x) {
+    const uint32_t s = w.lo + i;
+    const uint32_t len = s < nsym ? enc_len[s] : 0u;
+    t.len[i] = (uint8_t)(len <= 32 ? len : 0u);
+    if (codes) t.code[i] = s < nsym ? (uint32_t)enc_code[s] : 0u;
+  }
+}
+
+// Codeword of a symbol.  LDS_ONLY: straight from LDS (no global access, so
+// nothing the compiler must wait for on the common path).
+template <bool LDS_ONLY>
+__device__ __forceinline__ void lookup(uint32_t sym, const EncTables& t, const EncWindow& w,
+                                       const uint64_t* __restrict__ enc_code,
+                                       const uint8_t* __restrict__ enc_len, uint64_t& cw,
+                                       uint32_t& len) {
+  if (sym == 0) {
+    cw = w.code0;
+    len = w.len0;
+    return;
+  }
+  const uint32_t off = sym - w.lo;
+  if (LDS_ONLY) {
+    cw = t.code[off];
+    len = t.len[off];
+  } else {
+    const uint32_t l = off < kEncWindow ? t.len[off] : 0u;
+    if (l) {
+      cw = t.code[off];
+      len = l;
+    } else {
+      cw = enc_code[sym];
+      len = enc_len[sym];
+    }
+  }
+}
+
+// The lane's symbols [i0, i0 + kSeg) clipped to `end`, two per word.
+__device__ __forceinline__ void load_seg(const uint16_t* __restrict__ codes, uint64_t i0,
+                                         uint64_t end, uint32_t (&w)[kSeg / 2]) {
+  if (i0 + kSeg <= end) {
+    const uint4* p = reinterpret_cast<const uint4*>(codes + i0);
+#pragma unroll
+    for (int k = 0; k < kSeg / 8; k++) {
+      const uint4 a = p[k];
+      w[4 * k] = a.x;
+      w[4 * k + 1] = a.y;
+      w[4 * k + 2] = a.z;
+      w[4 * k + 3] = a.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSeg / 2; k++) {
+      const uint32_t a = i0 + 2 * k < end ? codes[i0 + 2 * k] : 0u;
+      const uint32_t b = i0 + 2 * k + 1 < end ? codes[i0 + 2 * k + 1] : 0u;
+      w[k] = a | (b << 16);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t sym_at(const uint32_t (&w)[kSeg / 2], int k) {
+  return (w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+}
+
+struct LaneRun {
+  uint64_t beg, end;  // the lane's symbols [beg, end)
+  uint32_t m;         // run length
+};
+
+__device__ __forceinline__ LaneRun lane_run(uint64_t c, uint32_t chunk, uint64_t n, int lane) {
+  const uint32_t m = chunk / 64 > 32 ? chunk / 64 : 32;
+  const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
+  LaneRun r;
+  r.m = m;
+  r.beg = cbeg + (uint64_t)m * lane;
+  if (r.beg > cend) r.beg = cend;
+  r.end = r.beg + m < cend ? r.beg + m : cend;
+  return r;
+}
+
+// ------------------------------------------------------------- chunk sizes
+
+template <bool LDS_ONLY>
+__device__ __forceinline__ void size_chunks(const uint16_t* __restrict__ codes, uint64_t n,
+                                            uint32_t chunk, uint64_t nchunks, const EncTables& t,
+                                            const EncWindow& w,
+                                            const uint64_t* __restrict__ enc_code,
+                                            const uint8_t* __restrict__ enc_len,
+                                            uint32_t* chunk_words, uint32_t* chunk_zeros) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+       c += wstride) {
+    const LaneRun r = lane_run(c, chunk, n, lane);
+    uint32_t bits = 0, zeros = 0;
+    for (uint64_t s0 = r.beg; s0 < r.end; s0 += kSeg) {
+      uint32_t v[kSeg / 2];
+      load_seg(codes, s0, r.end, v);
+#pragma unroll
+      for (int k = 0; k < kSeg; k++) {
+        if (s0 + k < r.end) {
+          const uint32_t sym = sym_at(v, k);
+          uint64_t cw;
+          uint32_t len;
+          lookup<LDS_ONLY>(sym, t, w, enc_code, enc_len, cw, len);
+          bits += len;
+          zeros += sym == 0;
+        }
+      }
+    }
+    bits = wave_sum_u32(bits);
+    zeros = wave_sum_u32(zeros);
+    if (lane == 0) {
+      chunk_words[c] = (bits + 31) / 32;
+      chunk_zeros[c] = zeros;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks, uint32_t R,
+    uint32_t nsym, const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
+    uint32_t* chunk_words, uint32_t* chunk_zeros, const Meta* __restrict__ m) {
+  __shared__ EncTables t;
+  const EncWindow w = enc_window(m, R, enc_code, enc_len);
+  load_tables(t, w, nsym, enc_code, enc_len, !w.lds_only);
+  __syncthreads();
+  if (w.lds_only)
+    size_chunks<true>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros);
+  else
+    size_chunks<false>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros);
+}
+
+// ------------------------------------------------------------------ packing
+
+template <typename T, bool LDS_ONLY>
+__device__ __forceinline__ void pack_chunks(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint64_t nchunks, const EncTables& t, const EncWindow& w,
+    const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
+    const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
+    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
+    const Layout& l, uint8_t* out, uint64_t cap) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+       c += wstride) {
+    const LaneRun r = lane_run(c, chunk, n, lane);
+    const bool cached = r.m <= kSeg;
+    uint32_t v[kSeg / 2];
+    // pass A: the lane's bits and unpredictable count
+    uint32_t bits = 0, zeros = 0;
+    for (uint64_t s0 = r.beg; s0 < r.end; s0 += kSeg) {
+      load_seg(codes, s0, r.end, v);
+#pragma unroll
+      for (int k = 0; k < kSeg; k++) {
+        if (s0 + k < r.end) {
+          const uint32_t sym = sym_at(v, k);
+          uint64_t cw;
+          uint32_t len;
+          lookup<LDS_ONLY>(sym, t, w, enc_code, enc_len, cw, len);
+          bits += len;
+          zeros += sym == 0;
+        }
+      }
+    }
+    const uint64_t bit0 = wave_incl_scan_u32(bits, lane) - bits;
+    uint64_t zrank = zero_off[c] + (wave_incl_scan_u32(zeros, lane) - zeros);
+    const uint64_t wbase = l.off_bits + 4 * word_off[c];
+    if (lane == 0) {
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c, chunk_words[c]);
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, chunk_zeros[c]);
+    }
+    // pass B: pack.  acc holds na pending bits left-aligned; the first word
+    // of a run that starts inside a word goes to the previous lane.
+    uint64_t wi = bit0 >> 5;
+    uint32_t na = (uint32_t)(bit0 & 31);
+    bool first_pending = na != 0;
+    uint32_t first_contrib = 0;
+    uint64_t acc = 0;
+    auto emit = [&]() {
+      const uint32_t word = (uint32_t)(acc >> 32);
+      if (first_pending) {
+        first_contrib = word;
+        first_pending = false;
+      } else {
+        guarded_store_u32(out, cap, wbase + 4 * wi, word);
+      }
+      wi++;
+      acc <<= 32;
+      na -= 32;
+    };
+    for (uint64_t s0 = r.beg; s0 < r.end; s0 += kSeg) {
+      if (!cached) load_seg(codes, s0, r.end, v);
+#pragma unroll
+      for (int k = 0; k < kSeg; k++) {
+        if (s0 + k < r.end) {
+          const uint32_t sym = sym_at(v, k);
+          uint64_t cw;
+          uint32_t len;
+          lookup<LDS_ONLY>(sym, t, w, enc_code, enc_len, cw, len);
+          if (len > 32) {
+            const uint32_t hl = len - 32;
+            acc |= (cw >> 32) << (64 - hl - na);
+            na += hl;
+            if (na >= 32) emit();
+            cw &= 0xFFFFFFFFull;
+            len = 32;
+          }
+          acc |= cw << (64 - len - na);
+          na += len;
+          if (na >= 32) emit();
+          if (sym == 0) {  // unpredictable value, verbatim, flat order
+            const uint64_t off = l.off_unpred + zrank * sizeof(T);
+            if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[s0 + k];
+            zrank++;
+          }
+        }
+      }
+    }
+    // the run's last, partial word: this lane's bits, completed with the
+    // successor's first-word bits
+    uint32_t last = 0;
+    bool has_last = false;
+    if (na) {
+      last = (uint32_t)(acc >> 32);
+      if (first_pending) {  // the whole run sits inside its first word
+        first_contrib = last;
+        first_pending = false;
+      } else {
+        has_last = true;
+      }
+    }
+    uint32_t next = __shfl_down(first_contrib, 1, 64);
+    if (lane == 63) next = 0;
+    if (has_last) guarded_store_u32(out, cap, wbase + 4 * wi, last | next);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
+    const Meta* __restrict__ m) {
+  __shared__ EncTables t;
+  const EncWindow w = enc_window(m, R, enc_code, enc_len);
+  load_tables(t, w, nsym, enc_code, enc_len, true);
+  __syncthreads();
+  const Layout l = stream_layout(m->nsym_used, nchunks, m->n_unpred, sizeof(T), m->total_words);
+  if (w.lds_only)
+    pack_chunks<T, true>(codes, x, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words,
+                         chunk_zeros, word_off, zero_off, l, out, cap);
+  else
+    pack_chunks<T, false>(codes, x, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words,
+                          chunk_zeros, word_off, zero_off, l, out, cap);
+}
+
+hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
+                         uint32_t chunk, uint32_t radius, const uint64_t* enc_code,
+                         const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
+                         Meta* m, hipStream_t st) {
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
+  if (nchunks == 0) return hipSuccess;
+  const uint32_t nsym = 2 * radius;
+  uint64_t blocks = (nchunks + kEncWaves - 1) / kEncWaves;
+  if (blocks > 2048) blocks = 2048;
+  dim3 grid((unsigned)blocks), block(kEncWaves * 64);
+  hipLaunchKernelGGL(k_encode_size, grid, block, 0, st, codes, n, chunk, nchunks, radius, nsym,
+                     enc_code, enc_len, es.chunk_words, es.chunk_zeros, m);
+  hipError_t e = launch_exclusive_scan_u32(es.chunk_words, es.word_off, nchunks, es.block_sums,
+                                           &m->total_words, st);
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan_u32(es.chunk_zeros, es.zero_off, nchunks, es.block_sums, es.totals, st);
+  if (e != hipSuccess) return e;
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL(k_encode_pack<float>, grid, block, 0, st, codes, (const float*)x, n, chunk,
+                       nchunks, radius, nsym, enc_code, enc_len, es.chunk_words, es.chunk_zeros,
+                       es.word_off, es.zero_off, out, cap, m);
+  else
+    hipLaunchKernelGGL(k_encode_pack<double>, grid, block, 0, st, codes, (const double*)x, n,
+                       chunk, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
+                       es.chunk_zeros, es.word_off, es.zero_off, out, cap, m);
+  return hipGetLastError();
+}
+
+// Header (template from the host, patched with the device-side values),
+// symbol table, and the zero padding that ends the symbol-table and
+// unpredictable sections on 8-byte boundaries.
+struct HeaderBytes {
+  uint32_t w[kHeaderBytes / 4];
+};
+
+__global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap,
+                                                      const uint32_t* __restrict__ symtab,
+                                                      uint64_t nchunks, HeaderBytes hdr,
+                                                      uint32_t tsize, Meta* m) {
+  const uint64_t K = m->nsym_used;
+  const Layout l = stream_layout(K, nchunks, m->n_unpred, tsize, m->total_words);
+  const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  if (gid < kHeaderBytes / 4) {
+    // header word gid; the device-side fields are 8-byte values at 56, 72,
+    // 80 (K, then a zero word), 88 and 96
+    const uint32_t byte = (uint32_t)gid * 4;
+    uint64_t v64 = 0;
+    bool patched = true;
+    const uint32_t at = byte & ~7u;
+    if (at == 56) {
+      const double eb = m->eb;
+      __builtin_memcpy(&v64, &eb, 8);
+    } else if (at == 72) {
+      v64 = m->n_unpred;
+    } else if (at == 80) {
+      v64 = K;
+    } else if (at == 88) {
+      v64 = m->total_words;
+    } else if (at == 96) {
+      v64 = l.size;
+    } else {
+      patched = false;
+    }
+    const uint32_t word = patched ? (uint32_t)(v64 >> ((byte & 4) ? 32 : 0)) : hdr.w[gid];
+    guarded_store_u32(out, cap, byte, word);
+  }
+  if (gid == 0) {
+    if (K & 1) guarded_store_u32(out, cap, l.off_sym + 4 * K, 0u);
+    const uint64_t ub = m->n_unpred * tsize;
+    if (ub & 7) guarded_store_u32(out, cap, l.off_unpred + ub, 0u);
+    m->stream_bytes = l.size;
+  }
+  for (uint64_t i = gid; i < K; i += gs) guarded_store_u32(out, cap, l.off_sym + 4 * i, symtab[i]);
+}
+
+hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
+                               uint64_t nchunks, const uint8_t* header_template, int dtype,
+                               Meta* m, hipStream_t st) {
+  HeaderBytes h;
+  for (int i = 0; i < (int)(kHeaderBytes / 4); i++)
+    h.w[i] = header_template[4 * i] | (header_template[4 * i + 1] << 8) |
+             (header_template[4 * i + 2] << 16) | ((uint32_t)header_template[4 * i + 3] << 24);
+  hipLaunchKernelGGL(k_write_tables, dim3(16), dim3(256), 0, st, out, capacity, symtab, nchunks,
+                     h, dtype == SZ_F32 ? 4u : 8u, m);
+  return hipGetLastError();
+}
+
+}  // namespace szg

@@ -42,6 +42,8 @@ __global__ void k_meta_init(Meta* m) {
   m->inv2eb = 0;
   m->nsym_used = 0;
   m->max_len = 0;
+  m->sym_lo = 0xFFFFFFFFu;
+  m->sym_hi = 0;
   m->n_unpred = 0;
   m->total_words = 0;
   m->stream_bytes = 0;
