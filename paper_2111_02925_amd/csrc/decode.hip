@@ -198,39 +198,35 @@ hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uin
 
 
 // Decoding loop.  Each lane decodes one chunk.  The window `buf` holds the
-// next `nb` stream bits left-aligned (bits past them are zero) and the word
-// `nxt` (index rd) follows them: used + nb == 32 * rd.  Before every symbol at
-// least 32 bits are present, which covers every code of the lookup table
-// (<= kLutBits bits).  A refill appends `nxt`, loaded one refill earlier, so
-// its latency hides behind the symbols decoded in between.  Reads past the chunk's words yield zeros; a
-// code that runs past the end is detected once, from the number of bits
-// consumed, instead of per symbol.
-constexpr uint32_t kLongSymCap = 4096;  // long-code symbols kept in LDS
-constexpr uint32_t kGroup = 32;         // codes staged in LDS per lane
+// next `nb` stream bits left-aligned and the word `nxt` (index rd) follows
+// them: used + nb == 32 * rd.  Before every symbol at least 32 bits are
+// present, which covers every code of up to 32 bits; a refill appends `nxt`,
+// loaded one refill earlier, so its latency hides behind the symbols decoded
+// in between.  Word reads are clamped to the bit-stream section instead of
+// being masked: bits past the chunk's own words never decide a code of a
+// well-formed chunk, and a chunk that runs past its words is detected once,
+// from the number of bits consumed, instead of per symbol.
+constexpr uint32_t kLongSymCap = 4096;        // long-code symbols kept in LDS
+constexpr uint32_t kGroup = 32;               // codes staged in LDS per lane
+constexpr int kWinLens = 32 - kLutBits;       // lengths resolved from the window
 
 // Codes longer than the lookup table: with canonical codes the left-justified
 // end of each length's code range grows with the length, and comparing the
 // window against the end of length k only involves its first k bits, so the
 // code length is kLutBits + 1 plus the number of ends the window reaches.
+// Lengths up to 32 are resolved from the 32-bit window with ends held in
+// registers; longer ones (only possible for extremely skewed histograms) take
+// an exact path that re-reads the stream.
 struct LongCodes {
   uint64_t end_lj[kMaxCodeLen + 1];  // left-justified end of length-l codes
   uint64_t base[kMaxCodeLen + 1];    // offset[l] - first[l] (mod 2^64)
+  uint32_t lim[kWinLens];            // see k_decode_chunks: window limits from length l0
+  uint32_t l0;                       // shortest long length whose 32-bit end is not 0
+  uint32_t base32[34];               // offset[l] - first[l] - long_first (mod 2^32)
   uint32_t max_len;
   uint32_t long_first;               // sorted index of the first long code
   uint32_t long_in_lds;
 };
-
-// 64 stream bits from bit `pos` of a chunk of `nw` words (zeros past its end).
-__device__ __forceinline__ uint64_t peek64(const uint32_t* __restrict__ w, uint64_t nw,
-                                           uint64_t pos) {
-  const uint64_t wi = pos >> 5;
-  const uint32_t o = (uint32_t)(pos & 31);
-  const uint64_t w0 = wi < nw ? w[wi] : 0, w1 = wi + 1 < nw ? w[wi + 1] : 0,
-                 w2 = wi + 2 < nw ? w[wi + 2] : 0;
-  uint64_t v = (w0 << 32) | w1;
-  if (o) v = (v << o) | (w2 >> (32 - o));
-  return v;
-}
 
 struct ChunkResult {
   uint64_t used;  // stream bits consumed
@@ -240,48 +236,62 @@ struct ChunkResult {
 
 template <typename T, bool LONG_LDS>
 __device__ __forceinline__ ChunkResult decode_chunk(
-    const uint32_t* __restrict__ words, uint64_t nwords, uint32_t nt, const uint32_t* lut,
-    const LongCodes& lc, const uint16_t* long_sym, const uint16_t* __restrict__ sorted_sym,
-    uint16_t* stage, uint64_t beg, uint64_t end, uint32_t chunk, const T* __restrict__ unpred,
-    uint64_t ubase, uint64_t uexp, uint64_t n_unpred, uint16_t* codes, T* out) {
+    const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint32_t* lut,
+    const LongCodes& lc, const uint32_t l0, const uint32_t (&lim)[kWinLens], const uint16_t* long_sym,
+    const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint64_t beg, uint64_t end,
+    uint32_t chunk, const T* __restrict__ unpred, uint64_t ubase, uint64_t uexp, uint16_t* codes,
+    T* out) {
+  auto ld = [&](uint32_t i) { return words[i < wlast ? i : wlast]; };
   uint64_t ucnt = 0;
   bool ok = true;
-  uint64_t used = 0;  // bits consumed
-  uint64_t buf = 0;
-  uint32_t nb = 0;
-  uint64_t rd = 0;  // index of the word held in nxt
-  uint32_t nxt = nwords ? words[0] : 0u;
-  // prime: two words
-  buf = (uint64_t)nxt << 32;
-  nb = 32;
-  rd = 1;
-  nxt = rd < nwords ? words[rd] : 0u;
-  buf |= nxt;
-  nb = 64;
-  rd = 2;
-  nxt = rd < nwords ? words[rd] : 0u;
+  uint64_t used = 0;
+  uint32_t w0 = ld(0), w1 = ld(1), nxt = ld(2);
+  // Take the priming loads here (an empty asm that reads the three words):
+  // left pending they would be waited for at the head of the symbol loop on
+  // every iteration.
+  asm volatile("" : "+v"(w0), "+v"(w1), "+v"(nxt));
+  uint64_t buf = ((uint64_t)w0 << 32) | w1;
+  uint32_t nb = 64, rd = 2;
   const bool vec = (chunk & 7) == 0;
   for (uint64_t g = beg; g < end; g += kGroup) {
     const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
+    uint32_t zmask = 0;  // positions of unpredictable values in this group
     for (uint32_t k = 0; k < cnt; k++) {
       const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
       uint32_t len = e >> 16;
       uint32_t sym = e & 0xFFFFu;
-      if (len == 0) {  // rare: a code longer than the table, read exactly from memory
-        const uint64_t win = peek64(words, nwords, used);
-        uint32_t l = kLutBits + 1;
-        for (uint32_t q = kLutBits + 1; q < lc.max_len; q++) l += win >= lc.end_lj[q] ? 1u : 0u;
-        const uint32_t idx = (uint32_t)(lc.base[l] + (win >> (64 - l)));
-        sym = LONG_LDS ? long_sym[idx - lc.long_first] : sorted_sym[idx];
-        len = l;
-        // rebuild the window at the new position (used + nb == 32 * rd again)
-        used += len;
-        const uint32_t o = (uint32_t)(used & 31);
-        nb = 64 - o;
-        const uint64_t v = peek64(words, nwords, used);
-        buf = o ? v & ~((1ull << o) - 1) : v;
-        rd = (used >> 5) + 2;
-        nxt = rd < nwords ? words[rd] : 0u;
+      if (len == 0) {  // a code longer than the table
+        const uint32_t win = (uint32_t)(buf >> 32);
+        uint32_t l = l0;
+#pragma unroll
+        for (int q = 0; q < kWinLens; q++) l += win > lim[q] ? 1u : 0u;
+        if (l <= 32) {
+          const uint32_t idx = lc.base32[l] + (win >> (32 - l));
+          sym = LONG_LDS ? long_sym[idx] : sorted_sym[idx + lc.long_first];
+          len = l;
+          used += len;
+          buf <<= len;
+          nb -= len;
+        } else {  // longer than 32 bits: exact read of the next 64 bits
+          const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
+          uint64_t w64 = ((uint64_t)ld(wi) << 32) | ld(wi + 1);
+          if (o) w64 = (w64 << o) | (ld(wi + 2) >> (32 - o));
+          l = 33;
+          for (uint32_t q = 33; q < lc.max_len; q++) l += w64 >= lc.end_lj[q] ? 1u : 0u;
+          const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
+          // a 32-bit read, so that this rare load is never merged with the
+          // table reads above into one generic-address load
+          const uint32_t pair = reinterpret_cast<const uint32_t*>(sorted_sym)[idx >> 1];
+          sym = (pair >> (16 * (idx & 1))) & 0xFFFFu;
+          len = l;
+          used += len;
+          const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
+          uint64_t v = ((uint64_t)ld(w2) << 32) | ld(w2 + 1);
+          buf = v & (~0ull << o2);
+          nb = 64 - o2;
+          rd = w2 + 2;
+          nxt = ld(rd);
+        }
       } else {
         used += len;
         buf <<= len;
@@ -291,17 +301,21 @@ __device__ __forceinline__ ChunkResult decode_chunk(
         buf |= (uint64_t)nxt << (32 - nb);
         nb += 32;
         rd++;
-        nxt = rd < nwords ? words[rd] : 0u;
+        nxt = ld(rd);
       }
       stage[k * nt] = (uint16_t)sym;
-      if (sym == 0) {
-        if (ucnt >= uexp || ubase + ucnt >= n_unpred) {
-          ok = false;
-          break;
-        }
-        out[g + k] = unpred[ubase + ucnt];
-        ucnt++;
+      zmask |= (sym == 0 ? 1u : 0u) << k;
+    }
+    // unpredictable values of the group, in flat order
+    while (zmask) {
+      const uint32_t k = __builtin_ctz(zmask);
+      zmask &= zmask - 1;
+      if (ucnt >= uexp) {
+        ok = false;
+        break;
       }
+      out[g + k] = unpred[ubase + ucnt];
+      ucnt++;
     }
     if (!ok) break;
     if (vec && cnt == kGroup) {
@@ -342,36 +356,62 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
       lc.base[l] = (uint64_t)d.offset[l] - d.first[l];
       lc.end_lj[l] = l < (uint32_t)kMaxCodeLen ? (d.first[l] + d.count[l]) << (64 - l) : ~0ull;
     }
+    const uint32_t lf = kLutBits < maxl ? d.offset[kLutBits + 1] : nsym_used;
+    // A window of a long code reaches the end of length l when win >= end32(l),
+    // end32(l) = (first[l] + count[l]) << (32 - l) in [0, 2^32], nondecreasing
+    // in l.  Ends that are 0 (no code of length <= l) are always reached and
+    // are folded into l0; the rest compare as win > end32 - 1 in 32 bits, and
+    // the ends past length 32 are never reached (limit 2^32 - 1), so the
+    // count gives 33 exactly for codes longer than 32 bits.
+    uint32_t l0 = kLutBits + 1;
+    while (l0 <= 32 && l0 < maxl && d.first[l0] + d.count[l0] == 0) l0++;
+    for (int q = 0; q < kWinLens; q++) {
+      const uint32_t l = l0 + q;
+      uint64_t e = 1ull << 32;
+      if (l <= 32 && l < maxl) e = (d.first[l] + d.count[l]) << (32 - l);
+      lc.lim[q] = (uint32_t)(e - 1);
+    }
+    lc.l0 = l0;
+    for (uint32_t l = 0; l <= 33; l++)
+      lc.base32[l] = l > (uint32_t)kLutBits && l <= 32 ? d.offset[l] - (uint32_t)d.first[l] - lf : 0u;
     lc.max_len = maxl;
-    lc.long_first = kLutBits < maxl ? d.offset[kLutBits + 1] : nsym_used;
-    lc.long_in_lds = nsym_used - lc.long_first <= kLongSymCap;
+    lc.long_first = lf;
+    lc.long_in_lds = nsym_used - lf <= kLongSymCap;
   }
   __syncthreads();
   if (lc.long_in_lds)
     for (uint32_t i = lc.long_first + threadIdx.x; i < nsym_used; i += blockDim.x)
       long_sym[i - lc.long_first] = d.sorted_sym[i];
   __syncthreads();
+  // the window limits are the same for every lane: keep them in scalar registers
+  uint32_t lim[kWinLens];
+#pragma unroll
+  for (int q = 0; q < kWinLens; q++) lim[q] = __builtin_amdgcn_readfirstlane(lc.lim[q]);
+  const uint32_t l0 = __builtin_amdgcn_readfirstlane(lc.l0);
   const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (c >= nchunks || m->status) return;
   const uint64_t W = chunk_words[c], wbase = word_off[c];
-  if (wbase + W > total_words) {
+  const uint64_t uexp = chunk_unpred[c], ubase = unpred_off[c];
+  // a non-empty chunk holds at least one bit; its words and unpredictable
+  // values must lie inside their sections
+  if (W == 0 || wbase + W > total_words || ubase + uexp > n_unpred) {
     atomicOr(&m->status, kStatusCorrupt);
     return;
   }
   const uint32_t* words = reinterpret_cast<const uint32_t*>(stream + off_bits) + wbase;
+  const uint64_t avail = total_words - wbase;  // >= W >= 1
+  const uint32_t wlast = (uint32_t)((avail < W + 2 ? avail : W + 2) - 1);
   const T* unpred = reinterpret_cast<const T*>(stream + off_unpred);
-  const uint64_t ubase = unpred_off[c], uexp = chunk_unpred[c];
   const uint64_t beg = c * chunk, end = beg + chunk < n ? beg + chunk : n;
   const ChunkResult res =
       lc.long_in_lds
-          ? decode_chunk<T, true>(words, W, NT, lut, lc, long_sym, d.sorted_sym, stage, beg, end,
-                                  chunk, unpred, ubase, uexp, n_unpred, codes, out)
-          : decode_chunk<T, false>(words, W, NT, lut, lc, long_sym, d.sorted_sym, stage, beg, end,
-                                   chunk, unpred, ubase, uexp, n_unpred, codes, out);
+          ? decode_chunk<T, true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+                                  beg, end, chunk, unpred, ubase, uexp, codes, out)
+          : decode_chunk<T, false>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+                                   beg, end, chunk, unpred, ubase, uexp, codes, out);
   if (!res.ok || res.ucnt != uexp || res.used > W * 32 || (res.used + 31) / 32 != W)
     atomicOr(&m->status, kStatusCorrupt);
 }
-
 hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
                                 uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
                                 uint64_t n, uint32_t chunk, uint32_t nsym_used, int dtype,
@@ -383,7 +423,7 @@ hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uin
   const uint64_t nchunks = (n + chunk - 1) / chunk;
   if (nchunks == 0) return hipSuccess;
   // 64-lane blocks when there are few chunks, so every CU gets work
-  const bool small = nchunks < 256ull * 1024;
+  const bool small = nchunks < 256ull * 256;  // fewer than one 256-lane block per CU
   const unsigned nt = small ? 64 : 256;
   dim3 grid((unsigned)((nchunks + nt - 1) / nt)), block(nt);
 #define SZG_DECODE_LAUNCH(TT, NTT)                                                              \
