@@ -13,6 +13,7 @@
 //   chunk table    ceil(n/chunk) x (u32 words, u32 unpredictable count)
 //   unpredictable  count x T in flat order (Algorithm 1 "quantizer.save")
 //   bitstream      words x u32, each chunk MSB-first and word-padded
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -60,6 +61,9 @@ struct sz_ctx {
   Meta* h_meta = nullptr;       // pinned
   uint8_t* h_header = nullptr;  // pinned
   uint64_t last_n = 0;
+  // one launch per level (fields of up to three dimensions) instead of one
+  // per (level, dimension) pass; SZG_FUSED_LEVELS=0 selects the pass kernels
+  bool fused_levels = true;
   // timing
   bool timing = false;
   std::vector<Pending> pending;
@@ -360,6 +364,7 @@ sz_ctx* sz_ctx_create(int device) {
   if (hipSetDevice(device) != hipSuccess) return nullptr;
   sz_ctx* ctx = new sz_ctx();
   ctx->device = device;
+  if (const char* e = getenv("SZG_FUSED_LEVELS")) ctx->fused_levels = strcmp(e, "0") != 0;
   if (ensure_fixed(ctx) != SZ_OK) {
     sz_ctx_destroy(ctx);
     return nullptr;
@@ -454,16 +459,26 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
               "minmax");
   CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st), "resolve_eb");
   if (s.n) {
-    std::vector<PassGeom> passes;
-    build_passes(s, passes);
     CHECK_HIP(timed(ctx, "interp", st, [&] {
                 return launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta, s.radius, st);
               }), "origin");
-    for (const PassGeom& g : passes)
-      CHECK_HIP(timed(ctx, "interp", st, [&] {
-                  return launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
-                                              ctx->meta, s.radius, st);
-                }), "interp pass");
+    std::vector<LevelGeom> levels;
+    if (ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+      // the finest level's reconstruction is not read by anything later
+      for (const LevelGeom& g : levels)
+        CHECK_HIP(timed(ctx, "interp", st, [&] {
+                    return launch_level_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                                                 ctx->meta, s.radius, g.s > 1, st);
+                  }), "interp level");
+    } else {
+      std::vector<PassGeom> passes;
+      build_passes(s, passes);
+      for (const PassGeom& g : passes)
+        CHECK_HIP(timed(ctx, "interp", st, [&] {
+                    return launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                                                ctx->meta, s.radius, st);
+                  }), "interp pass");
+    }
   }
   CHECK_HIP(launch_fill_u32(ctx->hist, 0, nsym, st), "fill");
   CHECK_HIP(timed(ctx, "histogram", st,
@@ -549,15 +564,25 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                                            ctx->dt, codes, d_out, ctx->meta, st);
                 return e;
               }), "decode");
-    std::vector<PassGeom> passes;
-    build_passes(s, passes);
     CHECK_HIP(timed(ctx, "recon", st, [&] {
                 return launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
               }), "origin_recon");
-    for (const PassGeom& g : passes)
-      CHECK_HIP(timed(ctx, "recon", st, [&] {
-                  return launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb, s.radius, st);
-                }), "recon pass");
+    std::vector<LevelGeom> levels;
+    if (ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+      for (const LevelGeom& g : levels)
+        CHECK_HIP(timed(ctx, "recon", st, [&] {
+                    return launch_level_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                                              s.radius, st);
+                  }), "recon level");
+    } else {
+      std::vector<PassGeom> passes;
+      build_passes(s, passes);
+      for (const PassGeom& g : passes)
+        CHECK_HIP(timed(ctx, "recon", st, [&] {
+                    return launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                                             s.radius, st);
+                  }), "recon pass");
+    }
   }
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");

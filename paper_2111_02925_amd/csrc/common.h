@@ -5,12 +5,16 @@
 //   predict+quantize  (Algorithm 1 loop; Section 3.2 quantizer) interp.hip
 //   histogram/codebook/encode/decode (Section 3.2 encoder)      huffman.hip
 //   reconstruction    (Appendix A.3 recover)                     interp.hip
+//   fused levels (<= 3 dimensions, compression and reconstruction) level.hip
 //   C ABI, context, stream header                                api.hip
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "szg.h"
 
@@ -99,6 +103,37 @@ hipError_t launch_origin_recon(const uint16_t* codes, int dtype, void* out, doub
                                uint32_t radius, hipStream_t st);
 hipError_t launch_pass_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                              const PassGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+
+// One level of the traversal for fields of up to three dimensions, viewed as
+// three dimensions with leading extents of 1, in lattice units of the level
+// stride s along the pass order (a, b, c).  See level.hip.
+struct LevelGeom {
+  uint32_t s;
+  uint32_t ext[3];    // lattice extents along a, b, c
+  uint64_t fs[3];     // flat-index step of one lattice unit along a, b, c
+  uint32_t tile[3];   // tile extents (lattice units)
+  uint32_t ntile[3];  // tiles along a, b, c
+  uint32_t box_b;     // LDS box extents along b and c (tile plus halo, clipped)
+  uint32_t box_c;
+  uint64_t ntiles;
+  uint32_t lds;       // LDS bytes of the box
+};
+struct LevelTuning {
+  uint32_t target_points;  // points per tile
+  uint32_t tile_b, tile_c; // initial tile extents along b and c
+  uint32_t lds_bytes;      // LDS budget of the box
+};
+constexpr uint32_t kLevelStoreValues = 1u << 0;   // store reconstructed values of the tile
+constexpr uint32_t kLevelRewriteCoarse = 1u << 1; // also store the tile's coarse points back
+
+// Plans the levels L..1 (coarsest first); false for four dimensions.
+bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize,
+                 const LevelTuning* tune, std::vector<LevelGeom>& out);
+hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* rec,
+                                 uint16_t* codes, const LevelGeom& g, const Meta* m,
+                                 uint32_t radius, bool store_rec, hipStream_t st);
+hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
+                              const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
 
 hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t nsym, uint32_t radius,
                             uint32_t* hist, hipStream_t st);

@@ -84,6 +84,35 @@ def test_parity(ctx, orc, case):
     check_case(ctx, orc, x, mode, eb, pred, radius, chunk, order, label)
 
 
+@pytest.fixture(scope="module")
+def ctx_passes():
+    """A context that runs one kernel per (level, dimension) pass instead of
+    one fused kernel per level (the path taken for four dimensions)."""
+    import paper_2111_02925_amd as szg
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    os.environ["SZG_FUSED_LEVELS"] = "0"
+    try:
+        c = szg.Context(0)
+    finally:
+        del os.environ["SZG_FUSED_LEVELS"]
+    yield c
+    c.close()
+
+
+PASS_CASES = [CASES[i] for i in (0, 2, 4, 6, 9)]
+
+
+@pytest.mark.parametrize("case", PASS_CASES, ids=[c[0] for c in PASS_CASES])
+def test_parity_pass_kernels(ctx_passes, orc, case):
+    label, gen, mode, eb, pred, radius, chunk, order = case
+    x = gen()
+    if eb is None:
+        eb = synth.sinusoid_field()[1]
+    check_case(ctx_passes, orc, x, mode, eb, pred, radius, chunk, order, "passes:" + label)
+
+
 def test_parity_special_values(ctx, orc):
     x = synth.random_field((30, 41), seed=8)
     x[3, 7] = np.nan
