@@ -22,6 +22,56 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 
+FAMILIES = ("minmax", "interp", "histogram", "codebook", "encode", "other",
+            "decode_tables", "chunk_scan", "decode", "recon")
+
+
+def algorithmic_bytes(n, s_t, stream_bytes, nchunks):
+    """Bytes each kernel family must move per step (reads + writes of its
+    inputs and outputs, once), n points of s_t bytes, u16 codes."""
+    return {
+        "minmax": n * s_t,                          # read x
+        "interp": n * s_t + 2 * n,                  # read x, write codes
+        "histogram": 2 * n,                         # read codes
+        "codebook": 0,
+        "encode": 2 * n + stream_bytes,             # read codes, write the stream
+        "other": 0,
+        "decode_tables": 0,
+        "chunk_scan": 8 * nchunks,                  # read the chunk table
+        "decode": stream_bytes + 2 * n,             # read the stream, write codes
+        "recon": 2 * n + n * s_t,                   # read codes, write the field
+    }
+
+
+def measured_traffic(family, shape, args):
+    """HBM bytes per step of `family` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), when it was
+    taken on this workload and on the kernel sources as they are now."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    doc = json.loads(m.group(1))
+    ent = doc.get("families", {}).get(family)
+    if not ent or doc.get("workload") != workload_name(shape, args):
+        return None
+    h = hashlib.sha256()
+    for src in ent["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != ent["sources_sha256"]:
+        return None  # the kernel changed since the counters were taken
+    return ent["hbm_bytes_per_step"]
+
+
+def workload_name(shape, args):
+    return (f"log-normal GRF (P(k)~k^-3) {'x'.join(map(str, shape))} f32, cubic "
+            f"interpolation, rel eb {args.rel:g}, radius 32768, chunk {args.chunk}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -31,6 +81,9 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy the input once on the device "
+                         "(a plain copy of known size, to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -88,8 +141,7 @@ def main():
     ms_step = t_total * 1e3 / args.steps
     size = int(s.numel())
 
-    fam = {k: ctx.timing(k) for k in ("minmax", "interp", "histogram", "codebook", "encode",
-                                      "decode", "recon", "other")}
+    fam = {k: ctx.timing(k) for k in FAMILIES}
     per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in fam.items()}
 
     # quality (measurement only, after the timed region)
@@ -100,24 +152,32 @@ def main():
     info = szg.inspect(s[:128].cpu())
     maxerr_over_eb = float(diff.max()) / info["eb"] if info["eb"] > 0 else 0.0
 
-    # roofline of the dominant kernel family (largest time per step)
+    if args.copy_calibration:
+        # plain device-to-device copies of the input (known size): the HIP
+        # runtime's copy kernel, then torch's elementwise copy
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        calib = torch.empty_like(xt)
+        torch.cuda.synchronize()
+        rc = hip.hipMemcpyDtoD(ctypes.c_void_p(calib.data_ptr()), ctypes.c_void_p(xt.data_ptr()),
+                               ctypes.c_size_t(in_bytes))
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyDtoD failed ({rc})")
+        calib.copy_(xt)
+        torch.cuda.synchronize()
+        del calib
+
+    # roofline of the dominant kernel family (largest time per step); the
+    # algorithmic bytes of each family per step
     dom = max(per_step, key=lambda k: per_step[k][0])
-    sT = 4
-    alg_bytes = {
-        "minmax": n * sT,
-        "interp": n * sT + 2 * n,          # read x, write codes
-        "histogram": 2 * n,                # read codes
-        "encode": 2 * n + size,            # read codes, write stream
-        "decode": size + 2 * n,            # read stream, write codes
-        "recon": 2 * n + n * sT,           # read codes, write field
-        "codebook": 0, "other": 0,
-    }
+    alg = algorithmic_bytes(n, 4, size, -(-n // args.chunk))
     dom_ms = per_step[dom][0]
-    achieved = alg_bytes[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    achieved = alg[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": None, "launches_per_step": per_step[dom][1],
-                "ms_per_step": round(dom_ms, 4)}
+                "traffic": measured_traffic(dom, shape, args), "launches_per_step": per_step[dom][1],
+                "ms_per_step": round(dom_ms, 4),
+                "alg_bytes_per_step": alg[dom]}
 
     cpu = None
     parity = None
@@ -151,8 +211,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"log-normal GRF (P(k)~k^-3) {'x'.join(map(str, shape))} f32, cubic "
-                               f"interpolation, rel eb {args.rel:g}, radius 32768, chunk {args.chunk}",
+        "config": {"workload": workload_name(shape, args),
                    "shape": list(shape), "eb_mode": "rel", "eb": args.rel, "predictor": "cubic"},
         "compress_GBps": round(in_bytes / (ms_c * 1e-3) / 1e9, 3),
         "decompress_GBps": round(in_bytes / (ms_d * 1e-3) / 1e9, 3),

@@ -166,8 +166,9 @@ int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields,
  * sz_set_timing(ctx, 1) records HIP events around every kernel launch on the
  * launch stream; sz_timing_get() returns, for the kernel family `name`, the
  * summed duration (ms) and launch count since the last sz_timing_reset().
- * Names: "minmax", "interp", "histogram", "codebook", "encode", "decode",
- * "recon", "other". */
+ * Names: compression "minmax", "interp", "histogram", "codebook", "encode",
+ * "other" (stream tables); decompression "decode_tables", "chunk_scan",
+ * "decode" (the chunk decoder alone), "recon". */
 int sz_set_timing(sz_ctx* ctx, int enable);
 int sz_timing_get(sz_ctx* ctx, const char* name, double* total_ms,
                   uint64_t* launches);

@@ -550,19 +550,20 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
 
   CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   if (s.n) {
-    CHECK_HIP(timed(ctx, "codebook", st, [&] {
+    CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
                 return launch_decode_tables(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt, ctx->meta, st);
               }), "decode_tables");
-    CHECK_HIP(timed(ctx, "decode", st, [&] {
+    CHECK_HIP(timed(ctx, "chunk_scan", st, [&] {
                 hipError_t e = launch_chunk_table_scan(str, l.off_chunk, nch, cwords, cunp, woff, uoff,
                                                        bsum, ctx->totals, st);
                 if (e == hipSuccess)
                   e = launch_check_totals(ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
-                if (e == hipSuccess)
-                  e = launch_decode_chunks(str, stream_size, l.off_unpred, l.off_bits, in.total_words,
-                                           in.n_unpred, s.n, s.chunk, in.nsym, s.dtype, cwords, cunp, woff, uoff,
-                                           ctx->dt, codes, d_out, ctx->meta, st);
                 return e;
+              }), "chunk_scan");
+    CHECK_HIP(timed(ctx, "decode", st, [&] {
+                return launch_decode_chunks(str, stream_size, l.off_unpred, l.off_bits, in.total_words,
+                                            in.n_unpred, s.n, s.chunk, in.nsym, s.dtype, cwords, cunp,
+                                            woff, uoff, ctx->dt, codes, d_out, ctx->meta, st);
               }), "decode");
     CHECK_HIP(timed(ctx, "recon", st, [&] {
                 return launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);

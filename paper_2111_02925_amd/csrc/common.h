@@ -116,7 +116,8 @@ struct LevelGeom {
   uint32_t box_b;     // LDS box extents along b and c (tile plus halo, clipped)
   uint32_t box_c;
   uint64_t ntiles;
-  uint32_t lds;       // LDS bytes of the box
+  uint32_t box_bytes; // LDS bytes of the box (16-byte multiple)
+  uint32_t lds;       // LDS bytes of the box and the tile's codes
 };
 struct LevelTuning {
   uint32_t target_points;  // points per tile

@@ -41,47 +41,45 @@ struct QuantParams {
 // the subtraction's rounding error, recovered exactly by the TwoSum
 // error-free transformation, decides.
 template <typename T>
-__device__ __forceinline__ bool bound_holds(T x, T r, T eb) {
-  const T s = x - r;
-  const T as = fabs_t(s);
-  if (as < eb) return true;
-  if (as != eb) return false;
+__device__ __forceinline__ bool bound_tie(T x, T r, T s) {
   const T y = -r;
   const T sum_minus_y = s - y;
   const T y_part = s - sum_minus_y;
   const T err = (x - sum_minus_y) + (y - y_part);
   return err == T(0) || ((err < T(0)) != (s < T(0)));
 }
+template <typename T>
+__device__ __forceinline__ bool bound_holds(T x, T r, T eb) {
+  const T s = x - r;
+  const T as = fabs_t(s);
+  bool ok = as < eb;
+  if (as == eb) ok = bound_tie(x, r, s);  // rare
+  return ok;
+}
 
 // Linear-scaling quantizer.  k = rint(|x - pred| / (2 eb)) (multiplied by the
 // precomputed reciprocal), signed like the error; the code is R + k when
 // |k| < R and the reconstruction pred + 2eb*k meets the bound, else 0
 // (unpredictable: the reconstruction is x itself).  eb == 0 codes only exact
-// predictions.
+// predictions.  Written with selects rather than branches (the tie case of
+// the bound test aside), so that a wavefront does not diverge on it.
 template <typename T>
 __device__ __forceinline__ uint32_t quantize(T x, T pred, const QuantParams<T>& q, T& rec) {
   const T diff = x - pred;
-  if (q.eb == T(0)) {
-    if (diff == T(0)) {
-      rec = pred + q.twoeb * T(0);
-      return q.R;
-    }
-    rec = x;
-    return 0;
+  if (q.eb == T(0)) {  // the same for every point
+    const bool exact = diff == T(0);
+    rec = exact ? pred + q.twoeb * T(0) : x;
+    return exact ? q.R : 0u;
   }
   const T kf = rint_t(fabs_t(diff) * q.inv2eb);
-  if (!(kf < (T)q.R)) {  // out of range, or NaN
-    rec = x;
-    return 0;
-  }
-  const int k = diff < T(0) ? -(int)kf : (int)kf;
+  const bool in_range = kf < (T)q.R;  // false for NaN
+  const int ki = (int)(in_range ? kf : T(0));
+  const int k = diff < T(0) ? -ki : ki;
   const T r = pred + q.twoeb * (T)k;
-  if (!bound_holds(x, r, q.eb)) {
-    rec = x;
-    return 0;
-  }
-  rec = r;
-  return (uint32_t)((int)q.R + k);
+  const bool holds = bound_holds(x, r, q.eb);
+  const bool ok = in_range && holds;
+  rec = ok ? r : x;
+  return ok ? (uint32_t)((int)q.R + k) : 0u;
 }
 
 template <typename T>

@@ -97,28 +97,73 @@ __device__ __forceinline__ Tile tile_of(const LevelGeom& g, uint64_t bid) {
   return T;
 }
 
-// Per-point step shared by compression and reconstruction.  Compression:
-// quantize x against the prediction (the value kept is the reconstruction).
-// Reconstruction: recover from the code, or keep the verbatim value the
-// decoder already stored for code 0.
+// The points of one pass inside a tile: a product of three coordinate
+// progressions, enumerated with c fastest.
+struct StageSet {
+  Prog pa, pb, pc;
+  FastDiv db, dc;
+  uint32_t n;
+};
+__device__ __forceinline__ StageSet stage_set(Prog pa, Prog pb, Prog pc) {
+  StageSet S;
+  S.pa = pa;
+  S.pb = pb;
+  S.pc = pc;
+  S.db = make_div(pb.count ? pb.count : 1);
+  S.dc = make_div(pc.count ? pc.count : 1);
+  S.n = pa.count * pb.count * pc.count;
+  return S;
+}
+__device__ __forceinline__ void stage_coords(const StageSet& S, uint32_t i, uint32_t& qa,
+                                             uint32_t& qb, uint32_t& qc) {
+  uint32_t jc, jb;
+  const uint32_t r = div_mod(i, S.dc, jc);
+  const uint32_t ja = div_mod(r, S.db, jb);
+  qa = S.pa.first + S.pa.step * ja;
+  qb = S.pb.first + S.pb.step * jb;
+  qc = S.pc.first + S.pc.step * jc;
+}
+
+// Per-point input and step shared by compression and reconstruction.
+// Compression: quantize x against the prediction (the value kept is the
+// reconstruction).  Reconstruction: recover from the code, or keep the
+// verbatim value the decoder already stored for code 0.
 template <typename T, bool RECON>
 struct PointOp {
   const T* __restrict__ x;
   T* v;
   uint16_t* codes;
   QuantParams<T> q;
-  __device__ __forceinline__ T apply(uint64_t f, T pred, bool own) const {
+  struct In {
+    T xv;
+    uint32_t code;
+  };
+  __device__ __forceinline__ In load(uint64_t f) const {
+    In in;
     if (RECON) {
-      const uint32_t code = codes[f];
-      return code ? recover(pred, q.twoeb, code, q.R) : v[f];
+      in.xv = T(0);
+      in.code = codes[f];
+    } else {
+      in.xv = x[f];
+      in.code = 0;
+    }
+    return in;
+  }
+  __device__ __forceinline__ T finish(uint64_t f, T pred, In in, bool own) const {
+    if (RECON) {
+      return in.code ? recover(pred, q.twoeb, in.code, q.R) : v[f];
     } else {
       T r;
-      const uint32_t code = quantize(x[f], pred, q, r);
+      const uint32_t code = quantize(in.xv, pred, q, r);
       if (own) codes[f] = (uint16_t)code;
       return r;
     }
   }
 };
+
+// Points per thread whose memory reads are issued together before any of
+// them is used, so that a workgroup keeps many reads in flight.
+constexpr int kBatch = 8;
 
 template <typename T, int PRED, bool RECON>
 __global__ __launch_bounds__(kLevelThreads) void k_level(const T* __restrict__ x, T* v,
@@ -143,110 +188,124 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(const T* __restrict__ x
   } else {
     op.q = QuantParams<T>::from_meta(m, R);
   }
+  using In = typename PointOp<T, RECON>::In;
   auto bidx = [&](uint32_t qa, uint32_t qb, uint32_t qc) {
     return ((qa - t.A0) * BB + (qb - t.Bo)) * BC + (qc - t.Co);
   };
+  auto flat = [&](uint32_t qa, uint32_t qb, uint32_t qc) { return qa * fa + qb * fb + qc * fc; };
   const uint32_t tid = threadIdx.x;
 
   // coarse points of the box (and, when asked, store them back in place so
   // that the tile's rows are written whole)
   {
-    const Prog pa = prog_even(t.A0, t.A1), pb = prog_even(t.Bo, t.Be), pc = prog_even(t.Co, t.Ce);
-    const uint32_t n = pa.count * pb.count * pc.count;
-    const FastDiv dc = make_div(pc.count ? pc.count : 1), db = make_div(pb.count ? pb.count : 1);
+    const StageSet S = stage_set(prog_even(t.A0, t.A1), prog_even(t.Bo, t.Be), prog_even(t.Co, t.Ce));
     const bool rewrite = (flags & kLevelRewriteCoarse) != 0;
-    for (uint32_t i = tid; i < n; i += kLevelThreads) {
-      uint32_t jc, jb;
-      const uint32_t r = div_mod(i, dc, jc);
-      const uint32_t ja = div_mod(r, db, jb);
-      const uint32_t qa = pa.first + 2 * ja, qb = pb.first + 2 * jb, qc = pc.first + 2 * jc;
-      const uint64_t f = qa * fa + qb * fb + qc * fc;
-      const T val = v[f];
-      box[bidx(qa, qb, qc)] = val;
-      if (rewrite && qb >= t.B0 && qb < t.B1 && qc >= t.C0 && qc < t.C1) v[f] = val;
+    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * kBatch) {
+      T val[kBatch];
+      uint32_t qa[kBatch], qb[kBatch], qc[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          stage_coords(S, i, qa[k], qb[k], qc[k]);
+          val[k] = v[flat(qa[k], qb[k], qc[k])];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          box[bidx(qa[k], qb[k], qc[k])] = val[k];
+          if (rewrite && qb[k] >= t.B0 && qb[k] < t.B1 && qc[k] >= t.C0 && qc[k] < t.C1)
+            v[flat(qa[k], qb[k], qc[k])] = val[k];
+        }
+      }
     }
   }
   __syncthreads();
 
   // pass along a on the whole box (neighbours are coarse points in memory)
   {
-    const Prog pa = prog_odd(t.A0, t.A1), pb = prog_even(t.Bo, t.Be), pc = prog_even(t.Co, t.Ce);
-    const uint32_t n = pa.count * pb.count * pc.count;
-    const FastDiv dc = make_div(pc.count ? pc.count : 1), db = make_div(pb.count ? pb.count : 1);
+    const StageSet S = stage_set(prog_odd(t.A0, t.A1), prog_even(t.Bo, t.Be), prog_even(t.Co, t.Ce));
     const uint32_t ea = g.ext[0];
-    for (uint32_t i = tid; i < n; i += kLevelThreads) {
-      uint32_t jc, jb;
-      const uint32_t r = div_mod(i, dc, jc);
-      const uint32_t ja = div_mod(r, db, jb);
-      const uint32_t qa = pa.first + 2 * ja, qb = pb.first + 2 * jb, qc = pc.first + 2 * jc;
-      const uint64_t f = qa * fa + qb * fb + qc * fc;
-      const bool has_a = qa >= 3, has_c = qa + 1 < ea, has_e = qa + 3 < ea;
-      const T b = v[f - fa];
-      const T c = has_c ? v[f + fa] : T(0);
-      const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
-      const T a = need_a ? v[f - 3 * fa] : T(0);
-      const T e = (PRED == SZ_INTERP_CUBIC && has_e) ? v[f + 3 * fa] : T(0);
-      const T pred = interp_predict<T, PRED>(a, b, c, e, has_a, has_c, has_e);
-      const bool own = qb >= t.B0 && qb < t.B1 && qc >= t.C0 && qc < t.C1;
-      const T val = op.apply(f, pred, own);
-      box[bidx(qa, qb, qc)] = val;
-      if (own && store_v) v[f] = val;
+    constexpr int KB = kBatch / 2;
+    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * KB) {
+      T na[KB], nb[KB], nc[KB], ne[KB];
+      In in[KB];
+      uint32_t qa[KB], qb[KB], qc[KB];
+#pragma unroll
+      for (int k = 0; k < KB; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          stage_coords(S, i, qa[k], qb[k], qc[k]);
+          const uint64_t f = flat(qa[k], qb[k], qc[k]);
+          const bool has_a = qa[k] >= 3, has_c = qa[k] + 1 < ea, has_e = qa[k] + 3 < ea;
+          nb[k] = v[f - fa];
+          nc[k] = has_c ? v[f + fa] : T(0);
+          const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
+          na[k] = need_a ? v[f - 3 * fa] : T(0);
+          ne[k] = (PRED == SZ_INTERP_CUBIC && has_e) ? v[f + 3 * fa] : T(0);
+          in[k] = op.load(f);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KB; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          const uint64_t f = flat(qa[k], qb[k], qc[k]);
+          const bool has_a = qa[k] >= 3, has_c = qa[k] + 1 < ea, has_e = qa[k] + 3 < ea;
+          const T pred = interp_predict<T, PRED>(na[k], nb[k], nc[k], ne[k], has_a, has_c, has_e);
+          const bool own = qb[k] >= t.B0 && qb[k] < t.B1 && qc[k] >= t.C0 && qc[k] < t.C1;
+          const T val = op.finish(f, pred, in[k], own);
+          box[bidx(qa[k], qb[k], qc[k])] = val;
+          if (own && store_v) v[f] = val;
+        }
+      }
     }
   }
   __syncthreads();
 
-  // pass along b on the tile's rows of the box
-  {
-    const Prog pa = prog_all(t.A0, t.A1), pb = prog_odd(t.B0, t.B1), pc = prog_even(t.Co, t.Ce);
-    const uint32_t n = pa.count * pb.count * pc.count;
-    const FastDiv dc = make_div(pc.count ? pc.count : 1), db = make_div(pb.count ? pb.count : 1);
-    const uint32_t eb = g.ext[1];
-    for (uint32_t i = tid; i < n; i += kLevelThreads) {
-      uint32_t jc, jb;
-      const uint32_t r = div_mod(i, dc, jc);
-      const uint32_t ja = div_mod(r, db, jb);
-      const uint32_t qa = pa.first + ja, qb = pb.first + 2 * jb, qc = pc.first + 2 * jc;
-      const uint64_t f = qa * fa + qb * fb + qc * fc;
-      const uint32_t k = bidx(qa, qb, qc);
-      const bool has_a = qb >= 3, has_c = qb + 1 < eb, has_e = qb + 3 < eb;
-      const T b = box[k - BC];
-      const T c = has_c ? box[k + BC] : T(0);
-      const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
-      const T a = need_a ? box[k - 3 * BC] : T(0);
-      const T e = (PRED == SZ_INTERP_CUBIC && has_e) ? box[k + 3 * BC] : T(0);
-      const T pred = interp_predict<T, PRED>(a, b, c, e, has_a, has_c, has_e);
-      const bool own = qc >= t.C0 && qc < t.C1;
-      const T val = op.apply(f, pred, own);
-      box[k] = val;
-      if (own && store_v) v[f] = val;
+  // pass along b on the tile's rows of the box, then along c on the tile:
+  // neighbours come from the box, `step` is the box offset of one unit
+  auto lds_pass = [&](const StageSet& S, uint32_t ext, int axis, uint32_t step, bool halo_c) {
+    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * kBatch) {
+      In in[kBatch];
+      uint32_t qa[kBatch], qb[kBatch], qc[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          stage_coords(S, i, qa[k], qb[k], qc[k]);
+          in[k] = op.load(flat(qa[k], qb[k], qc[k]));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; k++) {
+        const uint32_t i = i0 + k * kLevelThreads;
+        if (i < S.n) {
+          const uint32_t q = axis == 1 ? qb[k] : qc[k];
+          const uint32_t bk = bidx(qa[k], qb[k], qc[k]);
+          const bool has_a = q >= 3, has_c = q + 1 < ext, has_e = q + 3 < ext;
+          const T b = box[bk - step];
+          const T c = has_c ? box[bk + step] : T(0);
+          const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
+          const T a = need_a ? box[bk - 3 * step] : T(0);
+          const T e = (PRED == SZ_INTERP_CUBIC && has_e) ? box[bk + 3 * step] : T(0);
+          const T pred = interp_predict<T, PRED>(a, b, c, e, has_a, has_c, has_e);
+          const bool own = !halo_c || (qc[k] >= t.C0 && qc[k] < t.C1);
+          const uint64_t f = flat(qa[k], qb[k], qc[k]);
+          const T val = op.finish(f, pred, in[k], own);
+          if (halo_c) box[bk] = val;
+          if (own && store_v) v[f] = val;
+        }
+      }
     }
-  }
+  };
+  lds_pass(stage_set(prog_all(t.A0, t.A1), prog_odd(t.B0, t.B1), prog_even(t.Co, t.Ce)), g.ext[1],
+           1, BC, true);
   __syncthreads();
-
-  // pass along c on the tile
-  {
-    const Prog pa = prog_all(t.A0, t.A1), pb = prog_all(t.B0, t.B1), pc = prog_odd(t.C0, t.C1);
-    const uint32_t n = pa.count * pb.count * pc.count;
-    const FastDiv dc = make_div(pc.count ? pc.count : 1), db = make_div(pb.count ? pb.count : 1);
-    const uint32_t ec = g.ext[2];
-    for (uint32_t i = tid; i < n; i += kLevelThreads) {
-      uint32_t jc, jb;
-      const uint32_t r = div_mod(i, dc, jc);
-      const uint32_t ja = div_mod(r, db, jb);
-      const uint32_t qa = pa.first + ja, qb = pb.first + jb, qc = pc.first + 2 * jc;
-      const uint64_t f = qa * fa + qb * fb + qc * fc;
-      const uint32_t k = bidx(qa, qb, qc);
-      const bool has_a = qc >= 3, has_c = qc + 1 < ec, has_e = qc + 3 < ec;
-      const T b = box[k - 1];
-      const T c = has_c ? box[k + 1] : T(0);
-      const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
-      const T a = need_a ? box[k - 3] : T(0);
-      const T e = (PRED == SZ_INTERP_CUBIC && has_e) ? box[k + 3] : T(0);
-      const T pred = interp_predict<T, PRED>(a, b, c, e, has_a, has_c, has_e);
-      const T val = op.apply(f, pred, true);
-      if (store_v) v[f] = val;
-    }
-  }
+  lds_pass(stage_set(prog_all(t.A0, t.A1), prog_all(t.B0, t.B1), prog_odd(t.C0, t.C1)), g.ext[2],
+           2, 1, false);
 }
 
 // ------------------------------------------------------------------ host side
