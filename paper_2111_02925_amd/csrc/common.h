@@ -106,26 +106,30 @@ hipError_t launch_pass_recon(const uint16_t* codes, int dtype, int predictor, vo
 
 // One level of the traversal for fields of up to three dimensions, viewed as
 // three dimensions with leading extents of 1, in lattice units of the level
-// stride s along the pass order (a, b, c).  See level.hip.
+// stride s along the pass order (a, b, c).  A work item is a (b, c) tile and
+// a run of planes along a.  See level.hip.
 struct LevelGeom {
   uint32_t s;
   uint32_t ext[3];    // lattice extents along a, b, c
   uint64_t fs[3];     // flat-index step of one lattice unit along a, b, c
-  uint32_t tile[3];   // tile extents (lattice units)
-  uint32_t ntile[3];  // tiles along a, b, c
+  uint32_t tile[3];   // planes per item, tile extents along b and c
+  uint32_t ntile[3];  // items along a, b, c
+  uint32_t planes;    // planes per item (tile[0])
   uint32_t box_b;     // LDS box extents along b and c (tile plus halo, clipped)
   uint32_t box_c;
-  uint64_t ntiles;
-  uint32_t box_bytes; // LDS bytes of the box (16-byte multiple)
-  uint32_t lds;       // LDS bytes of the box and the tile's codes
+  uint32_t ring_b;    // coarse-grid extents (even b, even c of the box)
+  uint32_t ring_c;
+  uint64_t nitems;
+  uint32_t box_bytes; // LDS bytes: box | ring of 4 coarse grids | codes of the box
+  uint32_t ring_bytes;
+  uint32_t lds;
 };
 struct LevelTuning {
-  uint32_t target_points;  // points per tile
-  uint32_t tile_b, tile_c; // initial tile extents along b and c
-  uint32_t lds_bytes;      // LDS budget of the box
+  uint32_t target_points;  // minimum number of work items (planes per item shrink to reach it)
+  uint32_t tile_b, tile_c; // (b, c) tile extents
+  uint32_t lds_bytes;      // LDS budget of one workgroup
 };
 constexpr uint32_t kLevelStoreValues = 1u << 0;   // store reconstructed values of the tile
-constexpr uint32_t kLevelRewriteCoarse = 1u << 1; // also store the tile's coarse points back
 
 // Plans the levels L..1 (coarsest first); false for four dimensions.
 bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize,

@@ -46,15 +46,21 @@ __device__ __forceinline__ bool bound_tie(T x, T r, T s) {
   const T sum_minus_y = s - y;
   const T y_part = s - sum_minus_y;
   const T err = (x - sum_minus_y) + (y - y_part);
-  return err == T(0) || ((err < T(0)) != (s < T(0)));
+  // |x - r| < |s| exactly when the rounding error is zero or of the other
+  // sign (combined as integers: no short-circuit branch)
+  const uint32_t zero = err == T(0) ? 1u : 0u;
+  const uint32_t neg_err = err < T(0) ? 1u : 0u, neg_s = s < T(0) ? 1u : 0u;
+  return (zero | (neg_err ^ neg_s)) != 0u;
 }
 template <typename T>
 __device__ __forceinline__ bool bound_holds(T x, T r, T eb) {
   const T s = x - r;
   const T as = fabs_t(s);
-  bool ok = as < eb;
-  if (as == eb) ok = bound_tie(x, r, s);  // rare
-  return ok;
+  // every lane evaluates the tie test (a few operations), and the tests are
+  // combined as integers, so that the wavefront's control flow stays uniform
+  const uint32_t lt = as < eb ? 1u : 0u, eq = as == eb ? 1u : 0u;
+  const uint32_t tie = bound_tie(x, r, s) ? 1u : 0u;  // the same for every lane's path
+  return (lt | (eq & tie)) != 0u;
 }
 
 // Linear-scaling quantizer.  k = rint(|x - pred| / (2 eb)) (multiplied by the
@@ -102,6 +108,23 @@ __device__ __forceinline__ T interp_predict(T a, T b, T c, T e, bool has_a, bool
   if (has_e) return ((T(3) * b + T(6) * c) - e) * T(0.125);
   if (has_a) return ((T(6) * b + T(3) * c) - a) * T(0.125);
   return (b + c) * T(0.5);
+}
+
+// The same prediction with every rule evaluated and the right one selected
+// (no branches; each rule's operations and order are those above, so the
+// selected value is bitwise the same).  Operands of rules that do not apply
+// may hold any value.
+template <typename T, int PRED>
+__device__ __forceinline__ T interp_predict_sel(T a, T b, T c, T e, bool has_a, bool has_c,
+                                                bool has_e) {
+  const T one_sided = has_a ? (T(3) * b - a) * T(0.5) : b;
+  const T mid = (b + c) * T(0.5);
+  if (PRED == SZ_INTERP_LINEAR) return has_c ? mid : one_sided;
+  const T four = (T(9) * (b + c) - (a + e)) * T(0.0625);
+  const T quad_e = ((T(3) * b + T(6) * c) - e) * T(0.125);
+  const T quad_a = ((T(6) * b + T(3) * c) - a) * T(0.125);
+  const T two_sided = has_a ? (has_e ? four : quad_a) : (has_e ? quad_e : mid);
+  return has_c ? two_sided : one_sided;
 }
 
 }  // namespace szg

@@ -13,15 +13,27 @@
 //   pass along b: a any, b odd,  c even
 //   pass along c: a any, b any,  c odd
 // and every stencil reaches +-1 and +-3 lattice units along its dimension.
-// A workgroup owns a tile [A0,A1) x [B0,B1) x [C0,C1) and keeps in LDS a box
-// that extends it by 3 units along b and c.  It loads the box's coarse points
-// (all coordinates even, final from earlier levels), then computes the pass
-// along a on the whole box, the pass along b on the box rows of its tile,
-// and the pass along c on its tile, synchronising between passes.  Halo
-// points are recomputed by every tile that needs them; the arithmetic is the
-// same as in the tile that owns them, so the values agree bit for bit.  Only
-// points of the tile itself are stored.  A pass along a reads its neighbours
-// (coarse points) directly from memory.
+// Points with every coordinate even ("coarse") are final from earlier levels.
+//
+// Only the pass along a crosses planes of constant a, and it reads coarse
+// points only.  So a plane's passes along b and c depend on nothing of the
+// level but the plane's own pass along a, and planes can be streamed.  A
+// workgroup owns a (b, c) tile of a run of planes and keeps in LDS
+//   - the plane's box: the tile extended by 3 units along b and c,
+//   - a ring of the coarse grids (b, c even) of four even planes, which the
+//     pass along a reads (planes a-3, a-1, a+1, a+3) and even planes take
+//     their coarse points from,
+//   - the codes of the box (compression).
+// Per plane, separated by barriers: fill the box (inputs loaded during the
+// previous plane), the pass along a on the whole box (odd planes), the pass
+// along b on the tile's rows of the box, the pass along c on the tile, and
+// store the tile row by row.  Every input row is read once and whole; halo
+// points are recomputed with the same arithmetic as in the tile that owns
+// them, so the values agree bit for bit.
+//
+// Flat indices fit in 32 bits (fields have fewer than 2^32 points).
+#include <type_traits>
+
 #include "common.h"
 #include "device_math.h"
 
@@ -29,141 +41,124 @@ namespace szg {
 
 constexpr int kHalo = 3;
 constexpr int kLevelThreads = 256;
+constexpr int kLevelWaves = kLevelThreads / 64;
+constexpr int kBoxUnits = 12;   // box (row, 64-column chunk) units per wave: 48 per plane
+constexpr int kGridUnits = 6;   // coarse-grid units per wave: 24 per plane
 
-// Division by a per-tile constant: a float estimate of the quotient corrected
-// by one step (exact for dividends below 2^22 times the divisor).
-struct FastDiv {
-  uint32_t d;
-  float inv;
-};
-__device__ __forceinline__ FastDiv make_div(uint32_t d) { return FastDiv{d, 1.0f / (float)d}; }
-__device__ __forceinline__ uint32_t div_mod(uint32_t i, const FastDiv& D, uint32_t& r) {
-  uint32_t q = (uint32_t)((float)i * D.inv);
-  int32_t rr = (int32_t)(i - q * D.d);
-  if (rr < 0) {
-    q--;
-    rr += (int32_t)D.d;
-  } else if (rr >= (int32_t)D.d) {
-    q++;
-    rr -= (int32_t)D.d;
+// Workgroup barrier that orders LDS accesses only: global loads in flight
+// (the next plane's inputs) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// A box slot holds an input before its point is computed: the field value,
+// or the quantization code as an integer in the slot's bits.
+__device__ __forceinline__ float code_bits(uint32_t c, float) { return __uint_as_float(c); }
+__device__ __forceinline__ double code_bits(uint32_t c, double) {
+  return __longlong_as_double((long long)c);
+}
+__device__ __forceinline__ uint32_t bits_code(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t bits_code(double v) {
+  return (uint32_t)__double_as_longlong(v);
+}
+
+// Compression: quantize the field value against the prediction (the value
+// kept is the reconstruction).  Reconstruction: recover from the code, or
+// keep the verbatim value the decoder already stored for code 0 (at flat
+// index f(), only evaluated then).
+template <typename T, bool RECON, typename FlatFn>
+__device__ __forceinline__ T point_step(T slot, T pred, const QuantParams<T>& q, const T* v,
+                                        FlatFn f, uint32_t& code) {
+  if (RECON) {
+    code = bits_code(slot);
+    if (code) return recover(pred, q.twoeb, code, q.R);
+    // rare: take the read here (an empty asm that uses it), so that the
+    // common path never waits on it, nor on the loads in flight before it
+    T w = v[f()];
+    asm volatile("" : "+v"(w));
+    return w;
+  } else {
+    T r;
+    code = quantize(slot, pred, q, r);
+    return r;
   }
-  r = (uint32_t)rr;
-  return q;
 }
 
-// The lattice coordinates of one parity (or all) in [lo, hi).
-struct Prog {
-  uint32_t first, count, step;
+// Interpolation along one dimension at lattice coordinate qd of extent ext;
+// get(o, ok) returns the value at offset o in {-3, -1, +1, +3}, reading a
+// harmless in-bounds location instead when ok is false.  INTERIOR: every
+// stencil point exists (3 <= qd, qd + 3 < ext).  Otherwise every rule is
+// evaluated and the right one selected, so lanes never branch on it.
+template <typename T, int PRED, bool INTERIOR, typename Get>
+__device__ __forceinline__ T predict_at(uint32_t qd, uint32_t ext, Get get) {
+  if (INTERIOR) {
+    if (PRED == SZ_INTERP_CUBIC)
+      return interp_predict<T, PRED>(get(-3, true), get(-1, true), get(1, true), get(3, true),
+                                     true, true, true);
+    return interp_predict<T, PRED>(T(0), get(-1, true), get(1, true), T(0), true, true, true);
+  }
+  const bool has_a = qd >= 3, has_c = qd + 1 < ext, has_e = qd + 3 < ext;
+  return interp_predict_sel<T, PRED>(get(-3, has_a), get(-1, true), get(1, has_c),
+                                     get(3, has_e), has_a, has_c, has_e);
+}
+
+// The work item of a workgroup: a (b, c) tile, its box, and a run of planes.
+struct Item {
+  uint32_t P0, P1;            // planes
+  uint32_t B0, B1, C0, C1;    // tile
+  uint32_t Bo, Be, Co, Ce;    // box
+  uint32_t Bq, Cq;            // first even b and c of the box (coarse-grid origin)
 };
-__device__ __forceinline__ Prog prog_even(uint32_t lo, uint32_t hi) {
-  const uint32_t f = (lo + 1) & ~1u;
-  return Prog{f, hi > f ? (hi - f + 1) / 2 : 0u, 2};
-}
-__device__ __forceinline__ Prog prog_odd(uint32_t lo, uint32_t hi) {
-  const uint32_t f = lo | 1u;
-  return Prog{f, hi > f ? (hi - f + 1) / 2 : 0u, 2};
-}
-__device__ __forceinline__ Prog prog_all(uint32_t lo, uint32_t hi) {
-  return Prog{lo, hi > lo ? hi - lo : 0u, 1};
-}
 
-struct Tile {
-  uint32_t A0, A1, B0, B1, C0, C1;  // tile
-  uint32_t Bo, Be, Co, Ce;          // box along b and c
-};
-
-__device__ __forceinline__ Tile tile_of(const LevelGeom& g, uint64_t bid) {
+__device__ __forceinline__ Item item_of(const LevelGeom& g, uint32_t bid) {
   // XCD-aware order: workgroups are dealt to the 8 dies round-robin, so give
-  // each die a contiguous run of tiles (neighbours share halos and coarse
-  // points in that die's L2)
-  const uint64_t nt = g.ntiles, full = nt & ~7ull;
-  uint64_t t = bid;
+  // each die a contiguous run of items (neighbours share halos in its L2)
+  const uint32_t nt = (uint32_t)g.nitems, full = nt & ~7u;
+  uint32_t t = bid;
   if (bid < full) t = (bid & 7) * (full >> 3) + (bid >> 3);
-  const uint32_t tc = (uint32_t)(t % g.ntile[2]);
+  const uint32_t tc = t % g.ntile[2];
   t /= g.ntile[2];
-  const uint32_t tb = (uint32_t)(t % g.ntile[1]);
-  const uint32_t ta = (uint32_t)(t / g.ntile[1]);
-  Tile T;
-  T.A0 = ta * g.tile[0];
-  T.B0 = tb * g.tile[1];
-  T.C0 = tc * g.tile[2];
-  T.A1 = min(T.A0 + g.tile[0], g.ext[0]);
-  T.B1 = min(T.B0 + g.tile[1], g.ext[1]);
-  T.C1 = min(T.C0 + g.tile[2], g.ext[2]);
-  T.Bo = T.B0 >= (uint32_t)kHalo ? T.B0 - kHalo : 0u;
-  T.Co = T.C0 >= (uint32_t)kHalo ? T.C0 - kHalo : 0u;
-  T.Be = min(T.B1 + kHalo, g.ext[1]);
-  T.Ce = min(T.C1 + kHalo, g.ext[2]);
-  return T;
+  const uint32_t tb = t % g.ntile[1];
+  const uint32_t ta = t / g.ntile[1];
+  Item I;
+  I.P0 = ta * g.planes;
+  I.P1 = min(I.P0 + g.planes, g.ext[0]);
+  I.B0 = tb * g.tile[1];
+  I.C0 = tc * g.tile[2];
+  I.B1 = min(I.B0 + g.tile[1], g.ext[1]);
+  I.C1 = min(I.C0 + g.tile[2], g.ext[2]);
+  I.Bo = I.B0 >= (uint32_t)kHalo ? I.B0 - kHalo : 0u;
+  I.Co = I.C0 >= (uint32_t)kHalo ? I.C0 - kHalo : 0u;
+  I.Be = min(I.B1 + kHalo, g.ext[1]);
+  I.Ce = min(I.C1 + kHalo, g.ext[2]);
+  I.Bq = (I.Bo + 1) & ~1u;
+  I.Cq = (I.Co + 1) & ~1u;
+  return I;
 }
 
-// The points of one pass inside a tile: a product of three coordinate
-// progressions, enumerated with c fastest.
-struct StageSet {
-  Prog pa, pb, pc;
-  FastDiv db, dc;
-  uint32_t n;
+// A wave's units (row, 64-column chunk) of a row set, u = wave + 4k: lane k
+// decodes unit k into one word (row | chunk << 16), read back per unit as a
+// wave-uniform value.  Columns past the row's end repeat its last column.
+__device__ __forceinline__ uint32_t unit_word(uint32_t wave, uint32_t lane, uint32_t nrow,
+                                              uint32_t ncc) {
+  // units past the last one repeat it: their loads and stores duplicate the
+  // last unit's (same addresses, same values), which keeps the loops free of
+  // branches
+  const uint32_t n = nrow * ncc;
+  const uint32_t u = min(wave + kLevelWaves * lane, n - 1);
+  return (u / ncc) | (u % ncc) << 16;
+}
+
+// Inputs of one plane, held in registers from their loads (issued while the
+// previous plane computes) until the box is filled.
+template <typename T>
+struct PlaneIn {
+  T val[kBoxUnits];       // compression: the field's values over the box
+  uint32_t raw[kBoxUnits];// codes: all (reconstruction), of coarse rows (compression)
+  T grid[kGridUnits];     // rows (b even) of an even plane, for the ring
 };
-__device__ __forceinline__ StageSet stage_set(Prog pa, Prog pb, Prog pc) {
-  StageSet S;
-  S.pa = pa;
-  S.pb = pb;
-  S.pc = pc;
-  S.db = make_div(pb.count ? pb.count : 1);
-  S.dc = make_div(pc.count ? pc.count : 1);
-  S.n = pa.count * pb.count * pc.count;
-  return S;
-}
-__device__ __forceinline__ void stage_coords(const StageSet& S, uint32_t i, uint32_t& qa,
-                                             uint32_t& qb, uint32_t& qc) {
-  uint32_t jc, jb;
-  const uint32_t r = div_mod(i, S.dc, jc);
-  const uint32_t ja = div_mod(r, S.db, jb);
-  qa = S.pa.first + S.pa.step * ja;
-  qb = S.pb.first + S.pb.step * jb;
-  qc = S.pc.first + S.pc.step * jc;
-}
-
-// Per-point input and step shared by compression and reconstruction.
-// Compression: quantize x against the prediction (the value kept is the
-// reconstruction).  Reconstruction: recover from the code, or keep the
-// verbatim value the decoder already stored for code 0.
-template <typename T, bool RECON>
-struct PointOp {
-  const T* __restrict__ x;
-  T* v;
-  uint16_t* codes;
-  QuantParams<T> q;
-  struct In {
-    T xv;
-    uint32_t code;
-  };
-  __device__ __forceinline__ In load(uint64_t f) const {
-    In in;
-    if (RECON) {
-      in.xv = T(0);
-      in.code = codes[f];
-    } else {
-      in.xv = x[f];
-      in.code = 0;
-    }
-    return in;
-  }
-  __device__ __forceinline__ T finish(uint64_t f, T pred, In in, bool own) const {
-    if (RECON) {
-      return in.code ? recover(pred, q.twoeb, in.code, q.R) : v[f];
-    } else {
-      T r;
-      const uint32_t code = quantize(in.xv, pred, q, r);
-      if (own) codes[f] = (uint16_t)code;
-      return r;
-    }
-  }
-};
-
-// Points per thread whose memory reads are issued together before any of
-// them is used, so that a workgroup keeps many reads in flight.
-constexpr int kBatch = 8;
 
 template <typename T, int PRED, bool RECON>
 __global__ __launch_bounds__(kLevelThreads) void k_level(const T* __restrict__ x, T* v,
@@ -172,152 +167,222 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(const T* __restrict__ x
                                                          uint32_t R, uint32_t flags) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* box = reinterpret_cast<T*>(smem_raw);
-  const Tile t = tile_of(g, blockIdx.x);
-  const uint32_t BB = g.box_b, BC = g.box_c;
-  const uint64_t fa = g.fs[0], fb = g.fs[1], fc = g.fs[2];
+  T* ring = reinterpret_cast<T*>(smem_raw + g.box_bytes);
+  uint16_t* lcode = reinterpret_cast<uint16_t*>(smem_raw + g.box_bytes + g.ring_bytes);
+  const Item I = item_of(g, blockIdx.x);
+  const uint32_t BC = g.box_c, RB = g.ring_b, RC = g.ring_c;
+  const uint32_t fa = (uint32_t)g.fs[0], fb = (uint32_t)g.fs[1], fc = (uint32_t)g.fs[2];
+  const uint32_t ea = g.ext[0];
   const bool store_v = (flags & kLevelStoreValues) != 0;
-  PointOp<T, RECON> op;
-  op.x = x;
-  op.v = v;
-  op.codes = codes;
+  QuantParams<T> q;
   if (RECON) {
-    op.q.eb = T(0);
-    op.q.twoeb = twoeb;
-    op.q.inv2eb = T(0);
-    op.q.R = R;
+    q.eb = T(0);
+    q.twoeb = twoeb;
+    q.inv2eb = T(0);
+    q.R = R;
   } else {
-    op.q = QuantParams<T>::from_meta(m, R);
+    q = QuantParams<T>::from_meta(m, R);
   }
-  using In = typename PointOp<T, RECON>::In;
-  auto bidx = [&](uint32_t qa, uint32_t qb, uint32_t qc) {
-    return ((qa - t.A0) * BB + (qb - t.Bo)) * BC + (qc - t.Co);
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t nB = I.Be - I.Bo, nC = I.Ce - I.Co, ncc = (nC + 63) >> 6;
+  const uint32_t nBq = I.Be > I.Bq ? (I.Be - I.Bq + 1) / 2 : 0u;  // even b rows of the box
+  const uint32_t box_units = unit_word(wave, lane, nB, ncc);
+  const uint32_t tile_ncc = (I.C1 - I.C0 + 63) >> 6, tile_nunit = (I.B1 - I.B0) * tile_ncc;
+  const uint32_t tile_units = unit_word(wave, lane, I.B1 - I.B0, tile_ncc);
+  const uint32_t grid_units = unit_word(wave, lane, nBq, ncc);
+  auto ring_index = [&](uint32_t e, uint32_t b, uint32_t c) {
+    return (((e >> 1) & 3u) * RB + ((b - I.Bq) >> 1)) * RC + ((c - I.Cq) >> 1);
   };
-  auto flat = [&](uint32_t qa, uint32_t qb, uint32_t qc) { return qa * fa + qb * fb + qc * fc; };
-  const uint32_t tid = threadIdx.x;
+  auto ring_at = [&](uint32_t e, uint32_t b, uint32_t c) -> T& { return ring[ring_index(e, b, c)]; };
+  const uint32_t dummy = g.box_b * g.box_c;  // the box's and codes' spare last slot
 
-  // coarse points of the box (and, when asked, store them back in place so
-  // that the tile's rows are written whole)
-  {
-    const StageSet S = stage_set(prog_even(t.A0, t.A1), prog_even(t.Bo, t.Be), prog_even(t.Co, t.Ce));
-    const bool rewrite = (flags & kLevelRewriteCoarse) != 0;
-    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * kBatch) {
-      T val[kBatch];
-      uint32_t qa[kBatch], qb[kBatch], qc[kBatch];
+  // ---- loads of an even plane's coarse rows (b even), all columns
+  auto issue_grid = [&](uint32_t e, PlaneIn<T>& in) {
 #pragma unroll
-      for (int k = 0; k < kBatch; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          stage_coords(S, i, qa[k], qb[k], qc[k]);
-          val[k] = v[flat(qa[k], qb[k], qc[k])];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kBatch; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          box[bidx(qa[k], qb[k], qc[k])] = val[k];
-          if (rewrite && qb[k] >= t.B0 && qb[k] < t.B1 && qc[k] >= t.C0 && qc[k] < t.C1)
-            v[flat(qa[k], qb[k], qc[k])] = val[k];
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // pass along a on the whole box (neighbours are coarse points in memory)
-  {
-    const StageSet S = stage_set(prog_odd(t.A0, t.A1), prog_even(t.Bo, t.Be), prog_even(t.Co, t.Ce));
-    const uint32_t ea = g.ext[0];
-    constexpr int KB = kBatch / 2;
-    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * KB) {
-      T na[KB], nb[KB], nc[KB], ne[KB];
-      In in[KB];
-      uint32_t qa[KB], qb[KB], qc[KB];
-#pragma unroll
-      for (int k = 0; k < KB; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          stage_coords(S, i, qa[k], qb[k], qc[k]);
-          const uint64_t f = flat(qa[k], qb[k], qc[k]);
-          const bool has_a = qa[k] >= 3, has_c = qa[k] + 1 < ea, has_e = qa[k] + 3 < ea;
-          nb[k] = v[f - fa];
-          nc[k] = has_c ? v[f + fa] : T(0);
-          const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
-          na[k] = need_a ? v[f - 3 * fa] : T(0);
-          ne[k] = (PRED == SZ_INTERP_CUBIC && has_e) ? v[f + 3 * fa] : T(0);
-          in[k] = op.load(f);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < KB; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          const uint64_t f = flat(qa[k], qb[k], qc[k]);
-          const bool has_a = qa[k] >= 3, has_c = qa[k] + 1 < ea, has_e = qa[k] + 3 < ea;
-          const T pred = interp_predict<T, PRED>(na[k], nb[k], nc[k], ne[k], has_a, has_c, has_e);
-          const bool own = qb[k] >= t.B0 && qb[k] < t.B1 && qc[k] >= t.C0 && qc[k] < t.C1;
-          const T val = op.finish(f, pred, in[k], own);
-          box[bidx(qa[k], qb[k], qc[k])] = val;
-          if (own && store_v) v[f] = val;
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // pass along b on the tile's rows of the box, then along c on the tile:
-  // neighbours come from the box, `step` is the box offset of one unit
-  auto lds_pass = [&](const StageSet& S, uint32_t ext, int axis, uint32_t step, bool halo_c) {
-    for (uint32_t i0 = tid; i0 < S.n; i0 += kLevelThreads * kBatch) {
-      In in[kBatch];
-      uint32_t qa[kBatch], qb[kBatch], qc[kBatch];
-#pragma unroll
-      for (int k = 0; k < kBatch; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          stage_coords(S, i, qa[k], qb[k], qc[k]);
-          in[k] = op.load(flat(qa[k], qb[k], qc[k]));
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kBatch; k++) {
-        const uint32_t i = i0 + k * kLevelThreads;
-        if (i < S.n) {
-          const uint32_t q = axis == 1 ? qb[k] : qc[k];
-          const uint32_t bk = bidx(qa[k], qb[k], qc[k]);
-          const bool has_a = q >= 3, has_c = q + 1 < ext, has_e = q + 3 < ext;
-          const T b = box[bk - step];
-          const T c = has_c ? box[bk + step] : T(0);
-          const bool need_a = has_a && (!has_c || PRED == SZ_INTERP_CUBIC);
-          const T a = need_a ? box[bk - 3 * step] : T(0);
-          const T e = (PRED == SZ_INTERP_CUBIC && has_e) ? box[bk + 3 * step] : T(0);
-          const T pred = interp_predict<T, PRED>(a, b, c, e, has_a, has_c, has_e);
-          const bool own = !halo_c || (qc[k] >= t.C0 && qc[k] < t.C1);
-          const uint64_t f = flat(qa[k], qb[k], qc[k]);
-          const T val = op.finish(f, pred, in[k], own);
-          if (halo_c) box[bk] = val;
-          if (own && store_v) v[f] = val;
-        }
-      }
+    for (int k = 0; k < kGridUnits; k++) {
+      const uint32_t w = __builtin_amdgcn_readlane(grid_units, k);
+      const uint32_t c = min((w >> 16) * 64 + lane, nC - 1);
+      in.grid[k] = v[e * fa + (I.Bq + 2 * (w & 0xFFFF)) * fb + (I.Co + c) * fc];
     }
   };
-  lds_pass(stage_set(prog_all(t.A0, t.A1), prog_odd(t.B0, t.B1), prog_even(t.Co, t.Ce)), g.ext[1],
-           1, BC, true);
-  __syncthreads();
-  lds_pass(stage_set(prog_all(t.A0, t.A1), prog_all(t.B0, t.B1), prog_odd(t.C0, t.C1)), g.ext[2],
-           2, 1, false);
+  auto deposit_grid = [&](uint32_t e, const PlaneIn<T>& in) {
+#pragma unroll
+    for (int k = 0; k < kGridUnits; k++) {
+      const uint32_t w = __builtin_amdgcn_readlane(grid_units, k);
+      const uint32_t c = min((w >> 16) * 64 + lane, nC - 1);
+      const uint32_t qc = I.Co + c;
+      if ((qc & 1u) == 0) ring_at(e, I.Bq + 2 * (w & 0xFFFF), qc) = in.grid[k];
+    }
+  };
+  // ---- loads of plane p's inputs over the box (and the ring's next grid)
+  auto issue = [&](uint32_t p, PlaneIn<T>& in) {
+    const bool even_p = (p & 1u) == 0;
+#pragma unroll
+    for (int k = 0; k < kBoxUnits; k++) {
+      const uint32_t w = __builtin_amdgcn_readlane(box_units, k);
+      const uint32_t c = min((w >> 16) * 64 + lane, nC - 1);
+      const uint32_t qb = I.Bo + (w & 0xFFFF);
+      const uint32_t f = p * fa + qb * fb + (I.Co + c) * fc;
+      if (RECON) {
+        in.raw[k] = codes[f];
+      } else {
+        in.val[k] = x[f];
+        // codes of the tile's coarse points, stored back with the tile's
+        // rows (a condition on the row: the same for the whole wave)
+        if (even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1) in.raw[k] = codes[f];
+      }
+    }
+    if (!even_p && p + 3 < ea) issue_grid(p + 3, in);
+  };
+  auto deposit = [&](uint32_t p, const PlaneIn<T>& in) {
+    const bool even_p = (p & 1u) == 0;
+    if (!even_p && p + 3 < ea) deposit_grid(p + 3, in);
+#pragma unroll
+    for (int k = 0; k < kBoxUnits; k++) {
+      const uint32_t w = __builtin_amdgcn_readlane(box_units, k);
+      const uint32_t c = min((w >> 16) * 64 + lane, nC - 1);
+      const uint32_t row = w & 0xFFFF, qb = I.Bo + row, qc = I.Co + c;
+      const uint32_t slot = row * BC + c;
+      const bool coarse = even_p && ((qb | qc) & 1u) == 0;
+      // coarse points of an even plane come from the ring (deposited at
+      // least one plane earlier); other lanes read ring word 0, so that
+      // every lane takes the same path
+      const T rv = ring[coarse ? ring_index(p, qb, qc) : 0u];
+      box[slot] = coarse ? rv : (RECON ? code_bits(in.raw[k], T(0)) : in.val[k]);
+      if (!RECON && even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1)
+        lcode[slot] = (uint16_t)in.raw[k];  // other slots are overwritten when computed
+    }
+    // every input register is taken here, on every path: left possibly
+    // pending, it would make the compiler wait for all loads in flight when
+    // the register is next written
+#pragma unroll
+    for (int k = 0; k < kBoxUnits; k++) {
+      asm volatile("" ::"v"(in.val[k]));
+      asm volatile("" ::"v"(in.raw[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < kGridUnits; k++) asm volatile("" ::"v"(in.grid[k]));
+  };
+
+  // ---- a pass over rows (b) x columns (c) of the plane: slot i = row << lg | col
+  auto run_pass = [&](auto interior_tag, auto pass_tag, uint32_t p, uint32_t b_first,
+                      uint32_t b_step, uint32_t nrow, uint32_t c_first, uint32_t c_step,
+                      uint32_t ncol) {
+    constexpr bool IN = decltype(interior_tag)::value;
+    constexpr int PASS = decltype(pass_tag)::value;  // 0: along a, 1: along b, 2: along c
+    if (nrow == 0 || ncol == 0) return;
+    const uint32_t lg = ncol <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(ncol - 1);
+    const uint32_t nslot = nrow << lg;
+    // Padding slots compute a clamped duplicate of a real point and write it
+    // to the spare slot: no lane branches on its slot's validity.
+    for (uint32_t i0 = 0; i0 < nslot; i0 += kLevelThreads) {
+      const uint32_t i = i0 + tid;
+      const uint32_t jc0 = i & ((1u << lg) - 1);
+      const bool ok = i < nslot && jc0 < ncol;
+      const uint32_t jc = min(jc0, ncol - 1), jr = min(i >> lg, nrow - 1);
+      const uint32_t qb = b_first + b_step * jr, qc = c_first + c_step * jc;
+      const uint32_t bk = (qb - I.Bo) * BC + (qc - I.Co);
+      T pred;
+      // (a missing neighbour reads the point's own slot: in bounds, unused)
+      if (PASS == 0) {
+        // ring slots of planes outside the field hold other planes: unused
+        auto get = [&](int o, bool ok) { return ring_at((uint32_t)((int32_t)p + o), qb, qc); };
+        pred = predict_at<T, PRED, IN>(p, ea, get);
+      } else if (PASS == 1) {
+        auto get = [&](int o, bool ok) {
+          return box[(uint32_t)((int32_t)bk + (ok ? o * (int32_t)BC : 0))];
+        };
+        pred = predict_at<T, PRED, IN>(qb, g.ext[1], get);
+      } else {
+        auto get = [&](int o, bool ok) { return box[(uint32_t)((int32_t)bk + (ok ? o : 0))]; };
+        pred = predict_at<T, PRED, IN>(qc, g.ext[2], get);
+      }
+      uint32_t code;
+      const T val = point_step<T, RECON>(box[bk], pred, q, v,
+                                         [&] { return p * fa + qb * fb + qc * fc; }, code);
+      const uint32_t wk = ok ? bk : dummy;
+      box[wk] = val;
+      if (!RECON) lcode[wk] = (uint16_t)code;  // halo slots are never stored
+    }
+  };
+
+  // ---- the ring before the first plane: even planes P0-2, P0, P0+2
+  {
+    PlaneIn<T> pre;
+    for (int d = -2; d <= 2; d += 2) {
+      const int e = (int)I.P0 + d;
+      if (e < 0 || (uint32_t)e >= ea) continue;
+      issue_grid((uint32_t)e, pre);
+      deposit_grid((uint32_t)e, pre);
+    }
+  }
+  lds_barrier();
+
+  PlaneIn<T> in;
+  issue(I.P0, in);
+  const bool int_b = I.B0 >= 3 && I.B1 + 3 <= g.ext[1];
+  const bool int_c = I.C0 >= 3 && I.C1 + 3 <= g.ext[2];
+  for (uint32_t p = I.P0; p < I.P1; p++) {
+    deposit(p, in);
+    lds_barrier();
+    if (p + 1 < I.P1) issue(p + 1, in);
+
+    // pass along a (odd planes) on the whole box: b, c even
+    if (p & 1u) {
+      const uint32_t ncol = I.Ce > I.Cq ? (I.Ce - I.Cq + 1) / 2 : 0u;
+      if (p >= 3 && p + 3 < ea)
+        run_pass(std::true_type{}, std::integral_constant<int, 0>{}, p, I.Bq, 2, nBq, I.Cq, 2, ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 0>{}, p, I.Bq, 2, nBq, I.Cq, 2, ncol);
+      lds_barrier();
+    }
+    // pass along b on the tile's rows of the box: b odd, c even
+    {
+      const uint32_t b1 = I.B0 | 1u, nb = I.B1 > b1 ? (I.B1 - b1 + 1) / 2 : 0u;
+      const uint32_t ncol = I.Ce > I.Cq ? (I.Ce - I.Cq + 1) / 2 : 0u;
+      if (int_b)
+        run_pass(std::true_type{}, std::integral_constant<int, 1>{}, p, b1, 2, nb, I.Cq, 2, ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 1>{}, p, b1, 2, nb, I.Cq, 2, ncol);
+    }
+    lds_barrier();
+    // pass along c on the tile: c odd
+    {
+      const uint32_t c1 = I.C0 | 1u, ncol = I.C1 > c1 ? (I.C1 - c1 + 1) / 2 : 0u;
+      if (int_c)
+        run_pass(std::true_type{}, std::integral_constant<int, 2>{}, p, I.B0, 1, I.B1 - I.B0, c1,
+                 2, ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 2>{}, p, I.B0, 1, I.B1 - I.B0, c1,
+                 2, ncol);
+    }
+    lds_barrier();
+    // the tile's rows of this plane
+    {
+      const uint32_t tcn = I.C1 - I.C0;
+#pragma unroll
+      for (int k = 0; k < kBoxUnits; k++) {
+        if ((uint32_t)(wave + kLevelWaves * k) >= tile_nunit) break;  // the same for the wave
+        const uint32_t w = __builtin_amdgcn_readlane(tile_units, k);
+        const uint32_t c = (w >> 16) * 64 + lane;
+        if (c < tcn) {
+          const uint32_t qb = I.B0 + (w & 0xFFFF), qc = I.C0 + c;
+          const uint32_t f = p * fa + qb * fb + qc * fc;
+          const uint32_t bk = (qb - I.Bo) * BC + (qc - I.Co);
+          if (!RECON) codes[f] = lcode[bk];
+          if (RECON || store_v) v[f] = box[bk];
+        }
+      }
+    }
+    lds_barrier();  // the box is refilled next
+  }
 }
 
 // ------------------------------------------------------------------ host side
 
 namespace {
 uint32_t ceil_div32(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
-
-uint64_t box_bytes(const uint32_t tile[3], const uint32_t ext[3], int tsize) {
-  const uint64_t bb = std::min<uint64_t>(tile[1] + 2 * kHalo, ext[1]);
-  const uint64_t bc = std::min<uint64_t>(tile[2] + 2 * kHalo, ext[2]);
-  return (uint64_t)tile[0] * bb * bc * tsize;
-}
 }  // namespace
 
 bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize,
@@ -340,9 +405,8 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
     while ((1ull << l) < dims[d]) l++;
     L = std::max(L, l);
   }
-  int pc = 0;  // position of the contiguous dimension in the pass order
-  for (int j = 0; j < 3; j++)
-    if (O[j] == 2) pc = j;
+  const LevelTuning def{2048, 32, 58, 64 * 1024};
+  const LevelTuning& tu = tune ? *tune : def;
   for (int l = L; l >= 1; l--) {
     const uint64_t s = 1ull << (l - 1);
     LevelGeom g{};
@@ -351,34 +415,51 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
       g.ext[j] = (uint32_t)((V[O[j]] - 1) / s + 1);
       g.fs[j] = VS[O[j]] * s;
     }
-    uint32_t T[3];
-    const uint32_t target = tune ? tune->target_points : 4096;
-    const uint32_t lds_cap = tune ? tune->lds_bytes : 48 * 1024;
-    T[2] = std::min<uint32_t>(g.ext[2], pc == 2 ? (tune ? tune->tile_c : 64) : 16);
-    T[1] = std::min<uint32_t>(g.ext[1], tune ? tune->tile_b : 16);
-    T[0] = std::min<uint32_t>(g.ext[0], std::max<uint32_t>(1, target / (T[1] * T[2])));
-    while ((uint64_t)T[0] * T[1] * T[2] < target && T[1] < g.ext[1])
-      T[1] = std::min<uint32_t>(g.ext[1], 2 * T[1]);
-    while ((uint64_t)T[0] * T[1] * T[2] < target && T[2] < g.ext[2])
-      T[2] = std::min<uint32_t>(g.ext[2], 2 * T[2]);
-    while (box_bytes(T, g.ext, tsize) > lds_cap) {
-      int big = 0;
-      uint64_t bv = 0;
-      const uint64_t sz[3] = {T[0], std::min<uint64_t>(T[1] + 2 * kHalo, g.ext[1]),
-                              std::min<uint64_t>(T[2] + 2 * kHalo, g.ext[2])};
-      for (int j = 0; j < 3; j++)
-        if (T[j] > 1 && sz[j] > bv) bv = sz[j], big = j;
-      if (T[big] <= 1) return false;
-      T[big] = (T[big] + 1) / 2;
+    // (b, c) tile: 58 columns make the box rows 64 wide (one unit); a single
+    // row (one-dimensional fields) takes as many columns as the units allow
+    uint32_t TB = std::min<uint32_t>(g.ext[1], tu.tile_b);
+    uint32_t TC = std::min<uint32_t>(g.ext[2], tu.tile_c);
+    if (g.ext[1] == 1)
+      TC = std::min<uint32_t>(g.ext[2], kBoxUnits * kLevelWaves * 64 - 2 * kHalo);
+    auto fits = [&](uint32_t tb, uint32_t tcx) {
+      const uint32_t bb = std::min<uint32_t>(tb + 2 * kHalo, g.ext[1]);
+      const uint32_t bc = std::min<uint32_t>(tcx + 2 * kHalo, g.ext[2]);
+      const uint32_t ncc = (bc + 63) / 64;
+      const uint32_t rb = (bb + 1) / 2, rc = (bc + 1) / 2;
+      const uint64_t lds = ((uint64_t)(bb * bc + 1) * tsize + 15) / 16 * 16 +
+                           ((uint64_t)4 * rb * rc * tsize + 15) / 16 * 16 + (uint64_t)(bb * bc + 1) * 2;
+      return (uint64_t)bb * ncc <= (uint64_t)kBoxUnits * kLevelWaves &&
+             (uint64_t)rb * ncc <= (uint64_t)kGridUnits * kLevelWaves && lds <= tu.lds_bytes;
+    };
+    while (!fits(TB, TC)) {
+      if (TB > 1)
+        TB = (TB + 1) / 2;
+      else if (TC > 1)
+        TC = (TC + 1) / 2;
+      else
+        return false;
     }
-    for (int j = 0; j < 3; j++) {
-      g.tile[j] = T[j];
-      g.ntile[j] = ceil_div32(g.ext[j], T[j]);
-    }
-    g.box_b = std::min<uint32_t>(T[1] + 2 * kHalo, g.ext[1]);
-    g.box_c = std::min<uint32_t>(T[2] + 2 * kHalo, g.ext[2]);
-    g.ntiles = (uint64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    g.lds = (uint32_t)box_bytes(T, g.ext, tsize);
+    g.tile[1] = TB;
+    g.tile[2] = TC;
+    g.ntile[1] = ceil_div32(g.ext[1], TB);
+    g.ntile[2] = ceil_div32(g.ext[2], TC);
+    // planes per item: even runs, shortened until there are enough items
+    uint32_t P = g.ext[0] > 1 ? std::min<uint32_t>(16, (g.ext[0] + 1) & ~1u) : 1u;
+    while (P > 2 && (uint64_t)g.ntile[1] * g.ntile[2] * ceil_div32(g.ext[0], P) < tu.target_points)
+      P = std::max<uint32_t>(2, (P / 2 + 1) & ~1u);
+    g.planes = P;
+    g.tile[0] = P;
+    g.ntile[0] = ceil_div32(g.ext[0], P);
+    g.box_b = std::min<uint32_t>(TB + 2 * kHalo, g.ext[1]);
+    g.box_c = std::min<uint32_t>(TC + 2 * kHalo, g.ext[2]);
+    g.ring_b = (g.box_b + 1) / 2;
+    g.ring_c = (g.box_c + 1) / 2;
+    g.nitems = (uint64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
+    // the box and the codes carry one spare slot (writes of padding lanes)
+    g.box_bytes = (uint32_t)(((uint64_t)(g.box_b * g.box_c + 1) * tsize + 15) / 16 * 16);
+    g.ring_bytes = (uint32_t)(((uint64_t)4 * g.ring_b * g.ring_c * tsize + 15) / 16 * 16);
+    g.lds = g.box_bytes + g.ring_bytes + (g.box_b * g.box_c + 1) * 2;
+    if (g.nitems > 0x7FFFFFFFull) return false;
     out.push_back(g);
   }
   return true;
@@ -388,16 +469,16 @@ template <typename T, bool RECON>
 static hipError_t launch_level_t(const void* x, int predictor, void* v, uint16_t* codes,
                                  const LevelGeom& g, const Meta* m, double eb_t, uint32_t R,
                                  uint32_t flags, hipStream_t st) {
-  if (g.ntiles == 0) return hipSuccess;
-  if (g.ntiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  dim3 grid((unsigned)g.ntiles), block(kLevelThreads);
+  if (g.nitems == 0) return hipSuccess;
+  dim3 grid((unsigned)g.nitems), block(kLevelThreads);
   const T twoeb = RECON ? (T)2 * (T)eb_t : T(0);
+  const uint32_t lds = RECON ? g.box_bytes + g.ring_bytes : g.lds;
   if (predictor == SZ_INTERP_CUBIC)
-    hipLaunchKernelGGL((k_level<T, SZ_INTERP_CUBIC, RECON>), grid, block, g.lds, st,
-                       (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+    hipLaunchKernelGGL((k_level<T, SZ_INTERP_CUBIC, RECON>), grid, block, lds, st, (const T*)x,
+                       (T*)v, codes, g, m, twoeb, R, flags);
   else
-    hipLaunchKernelGGL((k_level<T, SZ_INTERP_LINEAR, RECON>), grid, block, g.lds, st,
-                       (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+    hipLaunchKernelGGL((k_level<T, SZ_INTERP_LINEAR, RECON>), grid, block, lds, st, (const T*)x,
+                       (T*)v, codes, g, m, twoeb, R, flags);
   return hipGetLastError();
 }
 
@@ -412,15 +493,14 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
 
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                               const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st) {
-  // at stride 1 the tile's coarse points are stored back too, so that whole
-  // rows of the output are written by one workgroup
-  const uint32_t flags = kLevelStoreValues | (g.s == 1 ? kLevelRewriteCoarse : 0u);
-  uint16_t* c = const_cast<uint16_t*>(codes);  // read only when reconstructing
+  // the tile is stored whole (its coarse points too, unchanged), so that the
+  // output rows are written by one workgroup
+  uint16_t* c = const_cast<uint16_t*>(codes);  // only read when reconstructing
   if (dtype == SZ_F32)
     return launch_level_t<float, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
-                                       flags, st);
-  return launch_level_t<double, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius, flags,
-                                      st);
+                                       kLevelStoreValues, st);
+  return launch_level_t<double, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
+                                      kLevelStoreValues, st);
 }
 
 }  // namespace szg
