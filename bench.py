@@ -43,7 +43,7 @@ def algorithmic_bytes(n, s_t, stream_bytes, nchunks):
     }
 
 
-def measured_traffic(family, shape, args):
+def measured_traffic(family, shape, args, sub):
     """HBM bytes per step of `family` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), when it was
     taken on this workload and on the kernel sources as they are now."""
@@ -57,7 +57,7 @@ def measured_traffic(family, shape, args):
         return None
     doc = json.loads(m.group(1))
     ent = doc.get("families", {}).get(family)
-    if not ent or doc.get("workload") != workload_name(shape, args):
+    if not ent or doc.get("workload") != workload_name(shape, args, sub):
         return None
     h = hashlib.sha256()
     for src in ent["sources"]:
@@ -67,9 +67,10 @@ def measured_traffic(family, shape, args):
     return ent["hbm_bytes_per_step"]
 
 
-def workload_name(shape, args):
+def workload_name(shape, args, sub):
     return (f"log-normal GRF (P(k)~k^-3) {'x'.join(map(str, shape))} f32, cubic "
-            f"interpolation, rel eb {args.rel:g}, radius 32768, chunk {args.chunk}")
+            f"interpolation, rel eb {args.rel:g}, radius 32768, chunk {args.chunk}, "
+            f"{sub} sub-chunks")
 
 
 def main():
@@ -80,6 +81,8 @@ def main():
     ap.add_argument("--shape", default="512,512,512")
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--subchunks", type=int, default=0,
+                    help="runs per chunk decoded by separate lanes (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy the input once on the device "
@@ -106,13 +109,14 @@ def main():
     dev = torch.device("cuda:0")
     ctx = szg.Context(0)
     xt = torch.from_numpy(x).to(dev)
-    cap = szg.compress_bound(shape, szg.F32, 32768, args.chunk)
+    cap = szg.compress_bound(shape, szg.F32, 32768, args.chunk, subchunks=args.subchunks)
     out = torch.empty(cap, dtype=torch.uint8, device=dev)
     rec = torch.empty(shape, dtype=torch.float32, device=dev)
     st = torch.cuda.current_stream(dev)
 
     def step():
-        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk, out=out)
+        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk,
+                         subchunks=args.subchunks, out=out)
         ctx.decompress(s, out=rec)
         return s
 
@@ -129,7 +133,8 @@ def main():
     t_start = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(st)
-        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk, out=out)
+        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk,
+                         subchunks=args.subchunks, out=out)
         ev[i][1].record(st)
         ctx.decompress(s, out=rec)
         ev[i][2].record(st)
@@ -175,7 +180,7 @@ def main():
     achieved = alg[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": measured_traffic(dom, shape, args), "launches_per_step": per_step[dom][1],
+                "traffic": measured_traffic(dom, shape, args, info["sub"]), "launches_per_step": per_step[dom][1],
                 "ms_per_step": round(dom_ms, 4),
                 "alg_bytes_per_step": alg[dom]}
 
@@ -186,7 +191,8 @@ def main():
 
         oracle.build(force=False)
         t1 = time.perf_counter()
-        ref = oracle.compress(x, oracle.REL, args.rel, oracle.CUBIC, 32768, args.chunk)
+        ref = oracle.compress(x, oracle.REL, args.rel, oracle.CUBIC, 32768, args.chunk,
+                              sub=info["sub"])
         t2 = time.perf_counter()
         back = oracle.decompress(ref)
         t3 = time.perf_counter()
@@ -211,7 +217,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload_name(shape, args),
+        "config": {"workload": workload_name(shape, args, info["sub"]),
                    "shape": list(shape), "eb_mode": "rel", "eb": args.rel, "predictor": "cubic"},
         "compress_GBps": round(in_bytes / (ms_c * 1e-3) / 1e9, 3),
         "decompress_GBps": round(in_bytes / (ms_d * 1e-3) / 1e9, 3),

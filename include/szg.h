@@ -73,6 +73,11 @@ typedef struct {
                             a multiple of 64 in [64, 65536].  Default 4096. */
   uint8_t dim_order[4];  /* order in which each level visits the dimensions;
                             a permutation of 0..ndim-1.  Default identity. */
+  uint32_t subchunks;    /* S: each chunk is split into S equal runs whose
+                            starting bit offsets are stored, so S decoder lanes
+                            share a chunk.  1, or 2, 4 or 8 where chunk/S is a
+                            multiple of max(32, chunk/64).  0 (default) picks 4,
+                            else 2, else 1. */
 } sz_options;
 
 /* Fields of a stream header, decoded on the host by sz_inspect. */
@@ -88,6 +93,7 @@ typedef struct {
   double eb;           /* the resolved bound in the field type, widened */
   uint32_t radius;
   uint32_t chunk;
+  uint32_t sub;        /* sub-chunks per chunk */
   uint64_t n_unpred;   /* unpredictable values stored verbatim */
   uint32_t nsym;       /* symbols with a Huffman code */
   uint64_t total_words;/* 32-bit words of Huffman bitstream */

@@ -64,16 +64,17 @@ def lib():
         L.szo_histogram.argtypes = [P, U64, U32, P]
         L.szo_huffman_lengths.argtypes = [P, U32, P]
         L.szo_canonical_codes.argtypes = [P, U32, P]
-        L.szo_pack.argtypes = [P, U64, P, P, U32, P, P, ctypes.POINTER(U64)]
-        L.szo_unpack.argtypes = [P, U64, P, U64, U32, P, U32, P]
-        L.szo_compress.argtypes = [P, I, I, P, I, D, I, U32, U32, P,
+        L.szo_check_sub.argtypes = [U32, U32]
+        L.szo_pack.argtypes = [P, U64, P, P, U32, U32, P, P, P, ctypes.POINTER(U64)]
+        L.szo_unpack.argtypes = [P, U64, P, U64, U32, U32, P, P, U32, P]
+        L.szo_compress.argtypes = [P, I, I, P, I, D, I, U32, U32, U32, P,
                                    ctypes.POINTER(ctypes.POINTER(ctypes.c_uint8)),
                                    ctypes.POINTER(U64), P, P]
         L.szo_decompress.argtypes = [P, U64, P, U64, P]
         L.szo_free.argtypes = [P]
         for name in ("szo_resolve_eb", "szo_predict_quantize", "szo_reconstruct",
                      "szo_quantize_one", "szo_check_traversal", "szo_histogram",
-                     "szo_huffman_lengths", "szo_canonical_codes", "szo_pack",
+                     "szo_huffman_lengths", "szo_canonical_codes", "szo_check_sub", "szo_pack",
                      "szo_unpack", "szo_compress", "szo_decompress"):
             getattr(L, name).restype = I
         _lib = L
@@ -201,43 +202,65 @@ def canonical_codes(lens: np.ndarray) -> np.ndarray:
     return cw
 
 
-def pack(codes: np.ndarray, lens: np.ndarray, cw: np.ndarray, chunk: int):
-    """Returns (words u32, chunk_words u32)."""
+def check_sub(chunk: int, sub: int) -> bool:
+    return lib().szo_check_sub(chunk, sub) == 0
+
+
+def pack(codes: np.ndarray, lens: np.ndarray, cw: np.ndarray, chunk: int, sub: int = 1):
+    """Returns (words u32, chunk_words u32), plus the sub-chunk bit offsets
+    (u32, (sub - 1) per chunk) when sub > 1."""
     codes = np.ascontiguousarray(codes, dtype=np.uint16).ravel()
     lens = np.ascontiguousarray(lens, dtype=np.uint8)
     cw = np.ascontiguousarray(cw, dtype=np.uint64)
     nchunks = (codes.size + chunk - 1) // chunk
     cwords = np.zeros(max(nchunks, 1), dtype=np.uint32)
+    sbits = np.zeros(max(nchunks * (sub - 1), 1), dtype=np.uint32)
     total = ctypes.c_uint64()
-    rc = lib().szo_pack(_ptr(codes), codes.size, _ptr(lens), _ptr(cw), chunk, None,
-                        _ptr(cwords), ctypes.byref(total))
+    rc = lib().szo_pack(_ptr(codes), codes.size, _ptr(lens), _ptr(cw), chunk, sub, None,
+                        _ptr(cwords), _ptr(sbits), ctypes.byref(total))
     if rc:
         raise OracleError(rc, "pack(count)")
     words = np.zeros(max(total.value, 1), dtype=np.uint32)
-    rc = lib().szo_pack(_ptr(codes), codes.size, _ptr(lens), _ptr(cw), chunk, _ptr(words),
-                        _ptr(cwords), ctypes.byref(total))
+    rc = lib().szo_pack(_ptr(codes), codes.size, _ptr(lens), _ptr(cw), chunk, sub, _ptr(words),
+                        _ptr(cwords), _ptr(sbits), ctypes.byref(total))
     if rc:
         raise OracleError(rc, "pack")
+    if sub > 1:
+        return words[: total.value], cwords[:nchunks], sbits[: nchunks * (sub - 1)]
     return words[: total.value], cwords[:nchunks]
 
 
 def unpack(words: np.ndarray, chunk_words: np.ndarray, n: int, chunk: int,
-           lens: np.ndarray) -> np.ndarray:
+           lens: np.ndarray, sub: int = 1, sub_bits=None) -> np.ndarray:
     words = np.ascontiguousarray(words, dtype=np.uint32)
     chunk_words = np.ascontiguousarray(chunk_words, dtype=np.uint32)
     lens = np.ascontiguousarray(lens, dtype=np.uint8)
     codes = np.zeros(max(n, 1), dtype=np.uint16)
     w = words if words.size else np.zeros(1, dtype=np.uint32)
     cwd = chunk_words if chunk_words.size else np.zeros(1, dtype=np.uint32)
-    rc = lib().szo_unpack(_ptr(w), words.size, _ptr(cwd), n, chunk, _ptr(lens), lens.size,
-                          _ptr(codes))
+    sb = None
+    if sub > 1:
+        sb = np.ascontiguousarray(sub_bits, dtype=np.uint32)
+        sb = sb if sb.size else np.zeros(1, dtype=np.uint32)
+    rc = lib().szo_unpack(_ptr(w), words.size, _ptr(cwd), n, chunk, sub, _ptr(sb), _ptr(lens),
+                          lens.size, _ptr(codes))
     if rc:
         raise OracleError(rc, "unpack")
     return codes[:n]
 
 
+def default_sub(chunk: int) -> int:
+    """The sub-chunk count used by default: 4, or fewer when the chunk is too
+    short to split that far."""
+    for s in (4, 2, 1):
+        if check_sub(chunk, s):
+            return s
+    return 1
+
+
 def compress(x: np.ndarray, eb_mode: int, eb: float, predictor: int = LINEAR,
-             radius: int = 32768, chunk: int = 4096, order=None, want_debug: bool = False):
+             radius: int = 32768, chunk: int = 4096, order=None, want_debug: bool = False,
+             sub: int = None):
     """Whole pipeline.  Returns the stream bytes, or (stream, codes, recon)."""
     x = np.ascontiguousarray(x)
     d = _dims(x.shape)
@@ -247,8 +270,10 @@ def compress(x: np.ndarray, eb_mode: int, eb: float, predictor: int = LINEAR,
     codes = np.empty(x.shape, dtype=np.uint16) if want_debug else None
     recon = np.empty_like(x) if want_debug else None
     xin = x if x.size else np.zeros(1, dtype=x.dtype)
+    if sub is None:
+        sub = default_sub(chunk)
     rc = lib().szo_compress(_ptr(xin), _dtype_code(x), x.ndim, _ptr(d), eb_mode, eb, predictor,
-                            radius, chunk, _ptr(o), ctypes.byref(out), ctypes.byref(size),
+                            radius, chunk, sub, _ptr(o), ctypes.byref(out), ctypes.byref(size),
                             _ptr(codes), _ptr(recon))
     if rc:
         raise OracleError(rc, "compress")
@@ -276,7 +301,7 @@ def parse_header(stream: bytes) -> dict:
         order=tuple(b[41:41 + ndim]), eb_mode=b[45],
         eb_user=np.frombuffer(b[48:56], dtype="<f8")[0],
         eb=np.frombuffer(b[56:64], dtype="<f8")[0],
-        radius=u32(64), chunk=u32(68), n_unpred=u64(72), nsym=u32(80),
+        radius=u32(64), chunk=u32(68), n_unpred=u64(72), nsym=u32(80), sub=u32(84),
         total_words=u64(88), stream_bytes=u64(96),
     )
 

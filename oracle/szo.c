@@ -437,16 +437,34 @@ int szo_canonical_codes(const uint8_t* lens, uint32_t nsym,
  * can be decoded independently).  Inside a chunk each codeword is appended
  * most significant bit first; stream bit b of the chunk is bit 31 - (b % 32)
  * of the chunk's word b / 32; the chunk ends on a word boundary. */
+/* Sub-chunks (reading: a chunk may be split into `sub` equal runs of
+ * symbols whose starting bit offsets are stored, so that several decoders
+ * can share a chunk; the bits themselves are unchanged). */
+int szo_check_sub(uint32_t chunk, uint32_t sub) {
+  if (sub == 1) return SZO_OK;
+  if (sub != 2 && sub != 4 && sub != 8) return SZO_ERR_ARG;
+  if (chunk == 0 || chunk % sub != 0) return SZO_ERR_ARG;
+  uint32_t run = chunk / 64 > 32 ? chunk / 64 : 32;
+  return (chunk / sub) % run == 0 ? SZO_OK : SZO_ERR_ARG;
+}
+
 int szo_pack(const uint16_t* codes, uint64_t n, const uint8_t* lens,
-             const uint64_t* codewords, uint32_t chunk, uint32_t* words,
-             uint32_t* chunk_words, uint64_t* total_words) {
-  if (chunk == 0) return SZO_ERR_ARG;
+             const uint64_t* codewords, uint32_t chunk, uint32_t sub,
+             uint32_t* words, uint32_t* chunk_words, uint32_t* sub_bits,
+             uint64_t* total_words) {
+  if (chunk == 0 || szo_check_sub(chunk, sub)) return SZO_ERR_ARG;
   uint64_t nchunks = (n + chunk - 1) / chunk;
   uint64_t base = 0;
+  uint32_t span = chunk / sub;
   for (uint64_t c = 0; c < nchunks; c++) {
     uint64_t lo = c * chunk, hi = lo + chunk < n ? lo + chunk : n;
     uint64_t bit = 0;
     for (uint64_t i = lo; i < hi; i++) {
+      uint64_t k = (i - lo) / span;
+      if (sub_bits && k > 0 && (i - lo) % span == 0) {
+        if (bit > UINT32_MAX) return SZO_ERR_ARG;
+        sub_bits[c * (sub - 1) + k - 1] = (uint32_t)bit;
+      }
       int len = lens[codes[i]];
       if (len == 0) return SZO_ERR_ARG;
       for (int b = len - 1; b >= 0; b--) {
@@ -455,6 +473,10 @@ int szo_pack(const uint16_t* codes, uint64_t n, const uint8_t* lens,
         bit++;
       }
     }
+    /* sub-chunks that start past the chunk's last symbol start at its end */
+    if (sub_bits)
+      for (uint32_t k = 1; k < sub; k++)
+        if (lo + (uint64_t)k * span >= hi) sub_bits[c * (sub - 1) + k - 1] = (uint32_t)bit;
     uint64_t cw = (bit + 31) / 32;
     if (cw > UINT32_MAX) return SZO_ERR_ARG;
     chunk_words[c] = (uint32_t)cw;
@@ -502,8 +524,10 @@ static int decoder_init(struct decoder* dc, const uint8_t* lens,
 
 int szo_unpack(const uint32_t* words, uint64_t total_words,
                const uint32_t* chunk_words, uint64_t n, uint32_t chunk,
-               const uint8_t* lens, uint32_t nsym, uint16_t* codes) {
-  if (chunk == 0) return SZO_ERR_ARG;
+               uint32_t sub, const uint32_t* sub_bits, const uint8_t* lens,
+               uint32_t nsym, uint16_t* codes) {
+  if (chunk == 0 || szo_check_sub(chunk, sub) || (sub > 1 && !sub_bits)) return SZO_ERR_ARG;
+  uint32_t span = chunk / sub;
   struct decoder dc;
   int rc = decoder_init(&dc, lens, nsym);
   if (rc) return rc;
@@ -518,6 +542,11 @@ int szo_unpack(const uint32_t* words, uint64_t total_words,
     }
     uint64_t bit = 0;
     for (uint64_t i = lo; i < hi && !rc; i++) {
+      uint64_t k = (i - lo) / span;
+      if (k > 0 && (i - lo) % span == 0 && sub_bits[c * (sub - 1) + k - 1] != bit) {
+        rc = SZO_ERR_CORRUPT;
+        break;
+      }
       uint64_t code = 0;
       int len = 0;
       for (;;) {
@@ -537,6 +566,9 @@ int szo_unpack(const uint32_t* words, uint64_t total_words,
       }
     }
     if (!rc && (bit + 31) / 32 != chunk_words[c]) rc = SZO_ERR_CORRUPT;
+    for (uint32_t k = 1; k < sub && !rc; k++)
+      if (lo + (uint64_t)k * span >= hi && sub_bits[c * (sub - 1) + k - 1] != bit)
+        rc = SZO_ERR_CORRUPT;
     base += chunk_words[c];
   }
   if (!rc && base != total_words) rc = SZO_ERR_CORRUPT;
@@ -554,11 +586,13 @@ int szo_unpack(const uint32_t* words, uint64_t total_words,
  *   40 u8 predictor      41 u8 order[4]        45 u8 eb_mode  46 u16 0
  *   48 f64 eb as given   56 f64 eb in the field type, widened
  *   64 u32 radius        68 u32 chunk          72 u64 unpredictable count
- *   80 u32 used symbols K                      84 u32 0
+ *   80 u32 used symbols K                      84 u32 sub-chunks per chunk
  *   88 u64 bitstream words                     96 u64 stream bytes
  *   104..127 zero
  * symbol table: K x u32 (symbol | length << 16), ascending symbol
  * chunk table:  ceil(n/chunk) x (u32 words, u32 unpredictable count)
+ * sub-chunk table: ceil(n/chunk) x (sub - 1) x u32 bit offsets of sub-chunks
+ *               1..sub-1 from the chunk's first bit
  * unpredictable values: count x T, flat order (the quantizer's saved state,
  *                       Algorithm 1 "quantizer.save")
  * bitstream:    words x u32 (Algorithm 1 "encoder.encode")
@@ -601,26 +635,28 @@ static double get_f64(const uint8_t* p) {
 static uint64_t pad8(uint64_t v) { return (v + 7) & ~7ull; }
 
 struct layout {
-  uint64_t off_sym, off_chunk, off_unpred, off_bits, size;
+  uint64_t off_sym, off_chunk, off_sub, off_unpred, off_bits, size;
 };
 
-static void layout_of(uint64_t K, uint64_t nchunks, uint64_t n_unpred,
+static void layout_of(uint64_t K, uint64_t nchunks, uint32_t sub, uint64_t n_unpred,
                       size_t ts, uint64_t words, struct layout* lo) {
   lo->off_sym = SZO_HEADER_BYTES;
   lo->off_chunk = lo->off_sym + pad8(4 * K);
-  lo->off_unpred = lo->off_chunk + 8 * nchunks;
+  lo->off_sub = lo->off_chunk + 8 * nchunks;
+  lo->off_unpred = lo->off_sub + pad8(4 * (uint64_t)(sub - 1) * nchunks);
   lo->off_bits = lo->off_unpred + pad8(n_unpred * ts);
   lo->size = lo->off_bits + 4 * words;
 }
 
 int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
                  int eb_mode, double eb, int predictor, uint32_t radius,
-                 uint32_t chunk, const uint8_t* order, uint8_t** stream,
-                 uint64_t* stream_size, uint16_t* codes_out, void* recon_out) {
+                 uint32_t chunk, uint32_t sub, const uint8_t* order,
+                 uint8_t** stream, uint64_t* stream_size, uint16_t* codes_out,
+                 void* recon_out) {
   struct szo_grid g;
   int rc = check_common(dtype, predictor, radius);
   if (rc) return rc;
-  if (chunk == 0) return SZO_ERR_ARG;
+  if (chunk == 0 || szo_check_sub(chunk, sub)) return SZO_ERR_ARG;
   if (eb_mode != SZO_ABS && eb_mode != SZO_REL) return SZO_ERR_ARG;
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
   size_t ts = type_size(dtype);
@@ -636,9 +672,10 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   uint64_t* cw = (uint64_t*)malloc(sizeof(uint64_t) * nsym);
   uint64_t nchunks = (n + chunk - 1) / chunk;
   uint32_t* chunk_words = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks ? nchunks : 1));
+  uint32_t* sub_bits = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks * (sub - 1) + 1));
   uint32_t* words = NULL;
   uint8_t* out = NULL;
-  if (!codes || !recon || !hist || !lens || !cw || !chunk_words) {
+  if (!codes || !recon || !hist || !lens || !cw || !chunk_words || !sub_bits) {
     rc = SZO_ERR_NOMEM;
     goto done;
   }
@@ -655,18 +692,18 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   for (uint32_t s = 0; s < nsym; s++)
     if (lens[s]) K++;
   uint64_t total_words;
-  if ((rc = szo_pack(codes, n, lens, cw, chunk, NULL, chunk_words, &total_words)))
+  if ((rc = szo_pack(codes, n, lens, cw, chunk, sub, NULL, chunk_words, NULL, &total_words)))
     goto done;
   words = (uint32_t*)calloc(total_words ? total_words : 1, sizeof(uint32_t));
   if (!words) {
     rc = SZO_ERR_NOMEM;
     goto done;
   }
-  if ((rc = szo_pack(codes, n, lens, cw, chunk, words, chunk_words, &total_words)))
+  if ((rc = szo_pack(codes, n, lens, cw, chunk, sub, words, chunk_words, sub_bits, &total_words)))
     goto done;
   uint64_t n_unpred = hist[0];
   struct layout lo;
-  layout_of(K, nchunks, n_unpred, ts, total_words, &lo);
+  layout_of(K, nchunks, sub, n_unpred, ts, total_words, &lo);
   out = (uint8_t*)calloc(lo.size, 1);
   if (!out) {
     rc = SZO_ERR_NOMEM;
@@ -686,6 +723,7 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   put_u32(out + 68, chunk);
   put_u64(out + 72, n_unpred);
   put_u32(out + 80, (uint32_t)K);
+  put_u32(out + 84, sub);
   put_u64(out + 88, total_words);
   put_u64(out + 96, lo.size);
   /* encoder.save: the code lengths, ascending symbol */
@@ -701,6 +739,7 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
     put_u32(out + lo.off_chunk + 8 * c, chunk_words[c]);
     put_u32(out + lo.off_chunk + 8 * c + 4, cu);
   }
+  for (uint64_t j = 0; j < nchunks * (sub - 1); j++) put_u32(out + lo.off_sub + 4 * j, sub_bits[j]);
   /* quantizer.save: unpredictable values verbatim, flat order */
   uint64_t u = 0;
   for (uint64_t i = 0; i < n; i++)
@@ -719,6 +758,7 @@ done:
   free(lens);
   free(cw);
   free(chunk_words);
+  free(sub_bits);
   free(words);
   free(out);
   return rc;
@@ -744,10 +784,12 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
   uint32_t radius = get_u32(s + 64), chunk = get_u32(s + 68);
   uint64_t n_unpred = get_u64(s + 72);
   uint64_t K = get_u32(s + 80);
+  uint32_t sub = get_u32(s + 84);
   uint64_t total_words = get_u64(s + 88), stream_bytes = get_u64(s + 96);
   if (!(eb_t >= 0.0) || !isfinite(eb_t)) return SZO_ERR_CORRUPT;
   if (dtype == SZO_F32 && (double)(float)eb_t != eb_t) return SZO_ERR_CORRUPT;
   if (radius < 1 || radius > SZO_MAX_RADIUS || chunk == 0) return SZO_ERR_CORRUPT;
+  if (szo_check_sub(chunk, sub)) return SZO_ERR_CORRUPT;
   uint64_t n = g.n;
   uint32_t nsym = 2 * radius;
   if (K > nsym || n_unpred > n || (K == 0) != (n == 0)) return SZO_ERR_CORRUPT;
@@ -755,17 +797,18 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
   size_t ts = type_size(dtype);
   uint64_t nchunks = (n + chunk - 1) / chunk;
   struct layout lo;
-  layout_of(K, nchunks, n_unpred, ts, total_words, &lo);
+  layout_of(K, nchunks, sub, n_unpred, ts, total_words, &lo);
   if (lo.size != stream_bytes || stream_bytes > size) return SZO_ERR_CORRUPT;
   if (out_bytes < n * ts) return SZO_ERR_CAPACITY;
 
   int rc = SZO_OK;
   uint8_t* lens = (uint8_t*)calloc(nsym, 1);
   uint32_t* chunk_words = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks ? nchunks : 1));
+  uint32_t* sub_bits = (uint32_t*)malloc(sizeof(uint32_t) * (nchunks * (sub - 1) + 1));
   uint32_t* words = (uint32_t*)malloc(sizeof(uint32_t) * (total_words ? total_words : 1));
   uint16_t* codes = (uint16_t*)malloc(sizeof(uint16_t) * (n ? n : 1));
   void* unpred = malloc(ts * (n_unpred ? n_unpred : 1));
-  if (!lens || !chunk_words || !words || !codes || !unpred) {
+  if (!lens || !chunk_words || !sub_bits || !words || !codes || !unpred) {
     rc = SZO_ERR_NOMEM;
     goto done;
   }
@@ -801,8 +844,10 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
     goto done;
   }
   for (uint64_t w = 0; w < total_words; w++) words[w] = get_u32(s + lo.off_bits + 4 * w);
+  for (uint64_t j = 0; j < nchunks * (sub - 1); j++) sub_bits[j] = get_u32(s + lo.off_sub + 4 * j);
   memcpy(unpred, s + lo.off_unpred, ts * n_unpred);
-  if ((rc = szo_unpack(words, total_words, chunk_words, n, chunk, lens, nsym, codes)))
+  if ((rc = szo_unpack(words, total_words, chunk_words, n, chunk, sub, sub_bits, lens, nsym,
+                       codes)))
     goto done;
   /* per-chunk unpredictable counts must match the decoded codes */
   for (uint64_t c = 0; c < nchunks; c++) {
@@ -821,6 +866,7 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
 done:
   free(lens);
   free(chunk_words);
+  free(sub_bits);
   free(words);
   free(codes);
   free(unpred);

@@ -101,25 +101,35 @@ int szo_huffman_lengths(const uint64_t* hist, uint32_t nsym, uint8_t* lens);
 int szo_canonical_codes(const uint8_t* lens, uint32_t nsym,
                         uint64_t* codewords);
 
+/* Sub-chunks per chunk: 1, or 2, 4 or 8 when chunk splits into sub-chunks
+ * holding a multiple of max(32, chunk/64) symbols each.  Returns SZO_OK or
+ * SZO_ERR_ARG. */
+int szo_check_sub(uint32_t chunk, uint32_t sub);
+
 /* Pack symbols chunk by chunk, MSB first into u32 words, each chunk padded
  * to a word.  chunk_words gets ceil(n/chunk) counts; words may be NULL to
- * only count. */
+ * only count.  sub_bits (may be NULL) gets, per chunk, the bit offset of
+ * sub-chunks 1..sub-1 from the chunk's first bit (sub - 1 entries). */
 int szo_pack(const uint16_t* codes, uint64_t n, const uint8_t* lens,
-             const uint64_t* codewords, uint32_t chunk, uint32_t* words,
-             uint32_t* chunk_words, uint64_t* total_words);
+             const uint64_t* codewords, uint32_t chunk, uint32_t sub,
+             uint32_t* words, uint32_t* chunk_words, uint32_t* sub_bits,
+             uint64_t* total_words);
 
-/* Decode n symbols packed by szo_pack. */
+/* Decode n symbols packed by szo_pack; sub_bits (NULL when sub == 1) must
+ * match the decoded sub-chunk starts. */
 int szo_unpack(const uint32_t* words, uint64_t total_words,
                const uint32_t* chunk_words, uint64_t n, uint32_t chunk,
-               const uint8_t* lens, uint32_t nsym, uint16_t* codes);
+               uint32_t sub, const uint32_t* sub_bits, const uint8_t* lens,
+               uint32_t nsym, uint16_t* codes);
 
 /* Whole pipeline.  order may be NULL (identity).  *stream is allocated with
  * malloc and must be released with szo_free.  codes_out / recon_out are
  * optional (n entries each). */
 int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
                  int eb_mode, double eb, int predictor, uint32_t radius,
-                 uint32_t chunk, const uint8_t* order, uint8_t** stream,
-                 uint64_t* stream_size, uint16_t* codes_out, void* recon_out);
+                 uint32_t chunk, uint32_t sub, const uint8_t* order,
+                 uint8_t** stream, uint64_t* stream_size, uint16_t* codes_out,
+                 void* recon_out);
 
 /* Parse, validate and decode a stream.  out holds n values of the stream's
  * type; codes_out is optional. */

@@ -47,7 +47,7 @@ class SzError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("dim_order", ctypes.c_uint8 * 4)]
+                ("dim_order", ctypes.c_uint8 * 4), ("subchunks", ctypes.c_uint32)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +56,7 @@ class Info(ctypes.Structure):
                 ("dim_order", ctypes.c_uint8 * 4), ("eb_mode", ctypes.c_int),
                 ("eb_user", ctypes.c_double), ("eb", ctypes.c_double),
                 ("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
+                ("sub", ctypes.c_uint32), ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
                 ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
 
 
@@ -125,10 +125,12 @@ def _pred(v) -> int:
     return int(v)
 
 
-def make_options(radius: int = 32768, chunk: int = 4096, dim_order=None, ndim: int = 4) -> Options:
+def make_options(radius: int = 32768, chunk: int = 4096, dim_order=None, ndim: int = 4,
+                 subchunks: int = 0) -> Options:
     o = Options()
     o.radius = radius
     o.chunk = chunk
+    o.subchunks = subchunks
     order = list(dim_order) if dim_order is not None else list(range(ndim))
     order += list(range(len(order), 4))
     for j in range(4):
@@ -144,8 +146,8 @@ def _dims(shape):
 
 
 def compress_bound(shape, dtype: int = F32, radius: int = 32768, chunk: int = 4096,
-                   dim_order=None) -> int:
-    o = make_options(radius, chunk, dim_order, len(shape))
+                   dim_order=None, subchunks: int = 0) -> int:
+    o = make_options(radius, chunk, dim_order, len(shape), subchunks)
     return int(lib().sz_compress_bound(dtype, len(shape), _dims(shape), ctypes.byref(o)))
 
 
@@ -208,13 +210,14 @@ class Context:
         return ctypes.c_void_p(s.cuda_stream)
 
     def compress(self, x, eb_mode="rel", eb: float = 1e-3, predictor="cubic",
-                 radius: int = 32768, chunk: int = 4096, dim_order=None, out=None, stream=None):
+                 radius: int = 32768, chunk: int = 4096, dim_order=None, subchunks: int = 0,
+                 out=None, stream=None):
         """Compress a contiguous float32/float64 CUDA tensor; returns a uint8
         CUDA tensor holding the stream (a view of `out` if given)."""
         torch = _torch()
         if not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous CUDA tensor")
-        opts = make_options(radius, chunk, dim_order, x.dim())
+        opts = make_options(radius, chunk, dim_order, x.dim(), subchunks)
         dims = _dims(x.shape)
         if out is None:
             cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), dims, ctypes.byref(opts)))
@@ -247,15 +250,16 @@ class Context:
             raise self._err(rc, "sz_decompress")
         return out
 
-    def compress_batch(self, fields, radius: int = 32768, chunk: int = 4096, stream=None):
+    def compress_batch(self, fields, radius: int = 32768, chunk: int = 4096, subchunks: int = 0,
+                       stream=None):
         """fields: list of (tensor, eb_mode, eb, predictor).  Returns the list
         of stream tensors (views of per-field output buffers)."""
         torch = _torch()
         arr = (Field * len(fields))()
         outs = []
-        opts = make_options(radius, chunk, None, 4)
+        opts = make_options(radius, chunk, None, 4, subchunks)
         for i, (x, mode, eb, pred) in enumerate(fields):
-            o1 = make_options(radius, chunk, None, x.dim())
+            o1 = make_options(radius, chunk, None, x.dim(), subchunks)
             cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), _dims(x.shape),
                                                   ctypes.byref(o1)))
             out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)

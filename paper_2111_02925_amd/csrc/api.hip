@@ -6,11 +6,14 @@
 //     0 "SZG1"  4 u16 version=1  6 u8 dtype  7 u8 ndim  8 u64 dims[4] (unused=1)
 //     40 u8 predictor  41 u8 dim_order[4]  45 u8 eb_mode  46 u16 0
 //     48 f64 eb as passed  56 f64 eb in the field type  64 u32 radius
-//     68 u32 chunk  72 u64 unpredictable count  80 u32 K (coded symbols)  84 u32 0
+//     68 u32 chunk  72 u64 unpredictable count  80 u32 K (coded symbols)
+//     84 u32 sub-chunks per chunk
 //     88 u64 bitstream words  96 u64 stream bytes  104..127 0
 //   symbol table   K x u32 (symbol | length << 16), ascending symbol
 //                  (the encoder's saved state, Algorithm 1 "encoder.save")
 //   chunk table    ceil(n/chunk) x (u32 words, u32 unpredictable count)
+//   sub-chunks     ceil(n/chunk) x (sub - 1) x u32: bit offset of sub-chunks
+//                  1..sub-1 from the chunk's first bit
 //   unpredictable  count x T in flat order (Algorithm 1 "quantizer.save")
 //   bitstream      words x u32, each chunk MSB-first and word-padded
 #include <stdlib.h>
@@ -144,7 +147,7 @@ struct Shape {
   uint64_t dims[kMaxDims] = {1, 1, 1, 1};
   uint8_t order[kMaxDims] = {0, 1, 2, 3};
   uint64_t n = 0;
-  uint32_t radius = kMaxRadius, chunk = 4096;
+  uint32_t radius = kMaxRadius, chunk = 4096, sub = 0;
   size_t tsize() const { return dtype == SZ_F64 ? 8 : 4; }
   uint64_t nchunks() const { return (n + chunk - 1) / chunk; }
 };
@@ -184,11 +187,15 @@ int make_shape(sz_ctx* c, int dtype, int ndim, const uint64_t* dims, const sz_op
   if (opts) {
     s->radius = opts->radius;
     s->chunk = opts->chunk;
+    s->sub = opts->subchunks;
     for (int j = 0; j < kMaxDims; j++) s->order[j] = j < ndim ? opts->dim_order[j] : (uint8_t)j;
   }
   if (s->radius < 1 || s->radius > kMaxRadius) return fail(c, SZ_ERR_ARG, "radius must be 1..32768");
   if (s->chunk < 64 || s->chunk > 65536 || (s->chunk & 63))
     return fail(c, SZ_ERR_ARG, "chunk must be a multiple of 64 in [64, 65536]");
+  if (s->sub == 0) s->sub = default_sub(s->chunk);
+  if (!valid_sub(s->chunk, s->sub))
+    return fail(c, SZ_ERR_ARG, "subchunks must be 1, or 2, 4 or 8 splitting chunk into whole encoder runs");
   if (!valid_order(ndim, s->order)) return fail(c, SZ_ERR_ARG, "dim_order must be a permutation");
   return SZ_OK;
 }
@@ -262,6 +269,7 @@ void header_template(const Shape& s, int predictor, int eb_mode, double eb_user,
   put_le(h + 48, u, 8);
   put_le(h + 64, s.radius, 4);
   put_le(h + 68, s.chunk, 4);
+  put_le(h + 84, s.sub, 4);
 }
 
 int parse_header(const uint8_t* h, sz_info* info) {
@@ -299,15 +307,18 @@ int parse_header(const uint8_t* h, sz_info* info) {
   in.chunk = (uint32_t)get_le(h + 68, 4);
   in.n_unpred = get_le(h + 72, 8);
   in.nsym = (uint32_t)get_le(h + 80, 4);
+  in.sub = (uint32_t)get_le(h + 84, 4);
   in.total_words = get_le(h + 88, 8);
   in.stream_bytes = get_le(h + 96, 8);
   if (!(in.eb >= 0.0) || !__builtin_isfinite(in.eb)) return SZ_ERR_CORRUPT;
   if (in.dtype == SZ_F32 && (double)(float)in.eb != in.eb) return SZ_ERR_CORRUPT;
   if (in.radius < 1 || in.radius > kMaxRadius || in.chunk == 0) return SZ_ERR_CORRUPT;
+  if (!valid_sub(in.chunk, in.sub)) return SZ_ERR_CORRUPT;
   if (in.nsym > 2 * in.radius || in.n_unpred > n || (in.nsym == 0) != (n == 0)) return SZ_ERR_CORRUPT;
   if (in.total_words > 64 * (n + 1)) return SZ_ERR_CORRUPT;
   uint64_t nchunks = (n + in.chunk - 1) / in.chunk;
-  Layout l = stream_layout(in.nsym, nchunks, in.n_unpred, in.dtype == SZ_F64 ? 8 : 4, in.total_words);
+  Layout l = stream_layout(in.nsym, nchunks, in.sub, in.n_unpred, in.dtype == SZ_F64 ? 8 : 4,
+                           in.total_words);
   if (l.size != in.stream_bytes) return SZ_ERR_CORRUPT;
   *info = in;
   return SZ_OK;
@@ -405,6 +416,7 @@ void sz_default_options(sz_options* o) {
   if (!o) return;
   o->radius = kMaxRadius;
   o->chunk = 4096;
+  o->subchunks = 0;
   for (int j = 0; j < kMaxDims; j++) o->dim_order[j] = (uint8_t)j;
 }
 
@@ -416,7 +428,7 @@ size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims, const sz_opt
   // Huffman is optimal, so its length is within one bit per symbol of the
   // entropy, itself at most log2(2R) <= 16 bits; each chunk pads < 32 bits.
   uint64_t words = (17 * s.n + 31) / 32 + nch;
-  Layout l = stream_layout(ksym, nch, s.n, s.tsize(), words);
+  Layout l = stream_layout(ksym, nch, s.sub, s.n, s.tsize(), words);
   return (size_t)l.size;
 }
 
@@ -492,11 +504,11 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
                    static_cast<uint64_t*>(ctx->word_off.p), static_cast<uint64_t*>(ctx->unpred_off.p),
                    static_cast<uint64_t*>(ctx->block_sums.p), ctx->totals};
   CHECK_HIP(timed(ctx, "encode", st, [&] {
-              return launch_encode(codes, d_in, dtype, s.n, s.chunk, s.radius, ctx->enc_code,
+              return launch_encode(codes, d_in, dtype, s.n, s.chunk, s.sub, s.radius, ctx->enc_code,
                                    ctx->enc_len, es, out, out_capacity, ctx->meta, st);
             }), "encode");
   CHECK_HIP(timed(ctx, "other", st, [&] {
-              return launch_write_tables(out, out_capacity, ctx->symtab, nch, hdr, dtype, ctx->meta, st);
+              return launch_write_tables(out, out_capacity, ctx->symtab, nch, s.sub, hdr, dtype, ctx->meta, st);
             }), "write_tables");
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -534,13 +546,14 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   s.n = in.n;
   s.radius = in.radius;
   s.chunk = in.chunk;
+  s.sub = in.sub;
   if (s.n && !d_out) return fail(ctx, SZ_ERR_ARG, "null output buffer");
   if (out_capacity < s.n * s.tsize()) return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
   int rc = ensure_sized(ctx, s, false);
   if (rc) return rc;
   const uint8_t* str = static_cast<const uint8_t*>(d_stream);
   const uint64_t nch = s.nchunks();
-  Layout l = stream_layout(in.nsym, nch, in.n_unpred, s.tsize(), in.total_words);
+  Layout l = stream_layout(in.nsym, nch, s.sub, in.n_unpred, s.tsize(), in.total_words);
   uint16_t* codes = static_cast<uint16_t*>(ctx->codes.p);
   uint32_t* cwords = static_cast<uint32_t*>(ctx->chunk_words.p);
   uint32_t* cunp = static_cast<uint32_t*>(ctx->chunk_unpred.p);
@@ -561,8 +574,9 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                 return e;
               }), "chunk_scan");
     CHECK_HIP(timed(ctx, "decode", st, [&] {
-                return launch_decode_chunks(str, stream_size, l.off_unpred, l.off_bits, in.total_words,
-                                            in.n_unpred, s.n, s.chunk, in.nsym, s.dtype, cwords, cunp,
+                return launch_decode_chunks(str, stream_size, l.off_sub, l.off_unpred, l.off_bits,
+                                            in.total_words, in.n_unpred, s.n, s.chunk, s.sub, in.nsym,
+                                            s.dtype, cwords, cunp,
                                             woff, uoff, ctx->dt, codes, d_out, ctx->meta, st);
               }), "decode");
     CHECK_HIP(timed(ctx, "recon", st, [&] {

@@ -29,19 +29,37 @@ constexpr uint64_t kHeaderBytes = 128;
 constexpr int kLutBits = 12;
 constexpr int kCbThreads = 512;  // threads of the single-block table kernels
 
+// Sub-chunks: a chunk of C symbols may be split into S in {2, 4, 8} runs of
+// C/S symbols whose starting bit offsets are stored, so that S lanes decode
+// one chunk.  A run must hold a multiple of the encoder's per-lane run,
+// max(32, C/64) symbols.
+__host__ __device__ inline bool valid_sub(uint32_t chunk, uint32_t sub) {
+  if (sub == 1) return true;
+  if (sub != 2 && sub != 4 && sub != 8) return false;
+  if (chunk == 0 || chunk % sub) return false;
+  const uint32_t run = chunk / 64 > 32 ? chunk / 64 : 32;
+  return (chunk / sub) % run == 0;
+}
+
+// Sub-chunks per chunk when the caller does not choose: 4 where valid, else 2, else 1.
+inline uint32_t default_sub(uint32_t chunk) {
+  return valid_sub(chunk, 4) ? 4 : valid_sub(chunk, 2) ? 2 : 1;
+}
+
 __host__ __device__ inline uint64_t pad8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
 
 // Byte offsets of the stream sections (layout described in api.hip).
 struct Layout {
-  uint64_t off_sym, off_chunk, off_unpred, off_bits, size;
+  uint64_t off_sym, off_chunk, off_sub, off_unpred, off_bits, size;
 };
 __host__ __device__ inline Layout stream_layout(uint64_t nsym_used, uint64_t nchunks,
-                                                uint64_t n_unpred, uint64_t tsize,
+                                                uint32_t sub, uint64_t n_unpred, uint64_t tsize,
                                                 uint64_t words) {
   Layout l;
   l.off_sym = kHeaderBytes;
   l.off_chunk = l.off_sym + pad8(4 * nsym_used);
-  l.off_unpred = l.off_chunk + 8 * nchunks;
+  l.off_sub = l.off_chunk + 8 * nchunks;
+  l.off_unpred = l.off_sub + pad8(4 * (uint64_t)(sub - 1) * nchunks);
   l.off_bits = l.off_unpred + pad8(n_unpred * tsize);
   l.size = l.off_bits + 4 * words;
   return l;
@@ -170,12 +188,12 @@ struct EncodeScratch {
   uint64_t* totals;
 };
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
-                         uint32_t chunk, uint32_t radius, const uint64_t* enc_code,
+                         uint32_t chunk, uint32_t sub, uint32_t radius, const uint64_t* enc_code,
                          const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
                          Meta* m, hipStream_t st);
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
-                               uint64_t nchunks, const uint8_t* header_template, int dtype,
-                               Meta* m, hipStream_t st);
+                               uint64_t nchunks, uint32_t sub, const uint8_t* header_template,
+                               int dtype, Meta* m, hipStream_t st);
 
 struct DecodeTables {
   uint32_t* lut;         // 1 << kLutBits entries: sym | len << 16 (len 0 = longer code)
@@ -192,9 +210,10 @@ hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, ui
                                    uint32_t* chunk_words, uint32_t* chunk_unpred,
                                    uint64_t* word_off, uint64_t* unpred_off,
                                    uint64_t* block_sums, uint64_t* totals, hipStream_t st);
-hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
-                                uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
-                                uint64_t n, uint32_t chunk, uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
+hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_sub,
+                                uint64_t off_unpred, uint64_t off_bits, uint64_t total_words,
+                                uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
+                                uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
                                 const uint32_t* chunk_unpred, const uint64_t* word_off,
                                 const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
                                 void* out, Meta* m, hipStream_t st);

@@ -197,15 +197,18 @@ hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uin
 }
 
 
-// Decoding loop.  Each lane decodes one chunk.  The window `buf` holds the
-// next `nb` stream bits left-aligned and the word `nxt` (index rd) follows
-// them: used + nb == 32 * rd.  Before every symbol at least 32 bits are
-// present, which covers every code of up to 32 bits; a refill appends `nxt`,
-// loaded one refill earlier, so its latency hides behind the symbols decoded
-// in between.  Word reads are clamped to the bit-stream section instead of
-// being masked: bits past the chunk's own words never decide a code of a
-// well-formed chunk, and a chunk that runs past its words is detected once,
-// from the number of bits consumed, instead of per symbol.
+// Decoding loop.  Each lane decodes one sub-chunk: a run of C/S symbols of a
+// chunk whose starting bit offset the stream's sub-chunk table gives (S lanes
+// share a chunk; S = 1 is the whole chunk).  The window `buf` holds the next
+// `nb` stream bits left-aligned and the word `nxt` (index rd) follows them:
+// used + nb == 32 * rd, with `used` counted from the chunk's first bit.
+// Before every symbol at least 32 bits are present, which covers every code
+// of up to 32 bits; a refill appends `nxt`, loaded one refill earlier, so its
+// latency hides behind the symbols decoded in between.  Word reads are
+// clamped to the bit-stream section instead of being masked: bits past the
+// chunk's own words never decide a code of a well-formed chunk, and a run
+// that ends anywhere but where the next one starts (or, for the last run,
+// inside the chunk's last word) is detected once, from the bits consumed.
 constexpr uint32_t kLongSymCap = 4096;        // long-code symbols kept in LDS
 constexpr uint32_t kGroup = 32;               // codes staged in LDS per lane
 constexpr int kWinLens = 32 - kLutBits;       // lengths resolved from the window
@@ -228,31 +231,32 @@ struct LongCodes {
   uint32_t long_in_lds;
 };
 
-struct ChunkResult {
-  uint64_t used;  // stream bits consumed
-  uint64_t ucnt;  // unpredictable values taken
-  bool ok;
+struct RunResult {
+  uint64_t used;   // bit offset, from the chunk's first bit, where the run ended
+  uint32_t zeros;  // unpredictable symbols (code 0) in the run
 };
 
-template <typename T, bool LONG_LDS>
-__device__ __forceinline__ ChunkResult decode_chunk(
+// Decodes symbols [beg, end) starting at bit `start` of the chunk's words,
+// writes their codes, and lists the offsets (from beg) of the code-0 symbols
+// as u32 words at `zlist`, in increasing order.
+template <bool LONG_LDS>
+__device__ __forceinline__ RunResult decode_run(
     const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint32_t* lut,
     const LongCodes& lc, const uint32_t l0, const uint32_t (&lim)[kWinLens], const uint16_t* long_sym,
     const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint64_t beg, uint64_t end,
-    uint32_t chunk, const T* __restrict__ unpred, uint64_t ubase, uint64_t uexp, uint16_t* codes,
-    T* out) {
+    uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
   auto ld = [&](uint32_t i) { return words[i < wlast ? i : wlast]; };
-  uint64_t ucnt = 0;
-  bool ok = true;
-  uint64_t used = 0;
-  uint32_t w0 = ld(0), w1 = ld(1), nxt = ld(2);
+  uint32_t zeros = 0;
+  uint64_t used = start;
+  const uint32_t wi0 = start >> 5, o0 = start & 31;
+  uint32_t w0 = ld(wi0), w1 = ld(wi0 + 1), nxt = ld(wi0 + 2);
   // Take the priming loads here (an empty asm that reads the three words):
   // left pending they would be waited for at the head of the symbol loop on
   // every iteration.
   asm volatile("" : "+v"(w0), "+v"(w1), "+v"(nxt));
-  uint64_t buf = ((uint64_t)w0 << 32) | w1;
-  uint32_t nb = 64, rd = 2;
-  const bool vec = (chunk & 7) == 0;
+  uint64_t buf = (((uint64_t)w0 << 32) | w1) << o0;
+  uint32_t nb = 64 - o0, rd = wi0 + 2;
+  const bool vec = (chunk & 31) == 0;  // every run then starts on a 32-symbol boundary
   for (uint64_t g = beg; g < end; g += kGroup) {
     const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
     uint32_t zmask = 0;  // positions of unpredictable values in this group
@@ -306,19 +310,12 @@ __device__ __forceinline__ ChunkResult decode_chunk(
       stage[k * nt] = (uint16_t)sym;
       zmask |= (sym == 0 ? 1u : 0u) << k;
     }
-    // unpredictable values of the group, in flat order
     while (zmask) {
       const uint32_t k = __builtin_ctz(zmask);
       zmask &= zmask - 1;
-      if (ucnt >= uexp) {
-        ok = false;
-        break;
-      }
-      out[g + k] = unpred[ubase + ucnt];
-      ucnt++;
+      zlist[zeros++] = (uint32_t)(g + k - beg);
     }
-    if (!ok) break;
-    if (vec && cnt == kGroup) {
+    if (vec && cnt == kGroup) {  // g is a multiple of 32 symbols: 64-byte aligned
       uint4* dst = reinterpret_cast<uint4*>(codes + g);
 #pragma unroll
       for (int j = 0; j < (int)(kGroup / 8); j++) {
@@ -333,14 +330,23 @@ __device__ __forceinline__ ChunkResult decode_chunk(
       for (uint32_t j = 0; j < cnt; j++) codes[g + j] = stage[j * nt];
     }
   }
-  return ChunkResult{used, ucnt, ok};
+  return RunResult{used, zeros};
 }
 
+// One lane per sub-chunk; the S lanes of a chunk are adjacent in a wave.
+// The unpredictable values of a chunk are stored in flat order, so a lane's
+// first one is the chunk's base plus the code-0 count of the lanes before
+// it, known only after decoding: each lane lists its code-0 offsets in its
+// own slice of the output (the slots of its run, which the values overwrite
+// later), the counts are scanned across the S lanes, and the values are then
+// scattered from the last listed offset down, so that a value never lands on
+// a list entry still to be read (the j-th code-0 position is at least j
+// slots past the run's start, above the slot of entry j and all earlier ones).
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_decode_chunks(
-    const uint8_t* __restrict__ stream, uint64_t off_unpred, uint64_t off_bits,
-    uint64_t total_words, uint64_t n_unpred, uint64_t n, uint32_t chunk, uint64_t nchunks,
-    uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
+    const uint8_t* __restrict__ stream, uint64_t off_sub, uint64_t off_unpred, uint64_t off_bits,
+    uint64_t total_words, uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
+    uint64_t nchunks, uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_unpred, const uint64_t* __restrict__ word_off,
     const uint64_t* __restrict__ unpred_off, DecodeTables d, uint16_t* codes, T* out, Meta* m) {
   __shared__ uint32_t lut[1u << kLutBits];
@@ -388,48 +394,79 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
 #pragma unroll
   for (int q = 0; q < kWinLens; q++) lim[q] = __builtin_amdgcn_readfirstlane(lc.lim[q]);
   const uint32_t l0 = __builtin_amdgcn_readfirstlane(lc.l0);
-  const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint32_t lg = __builtin_ctz(sub);
+  const uint64_t tg = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t c = tg >> lg;
+  const uint32_t k = (uint32_t)(tg & (sub - 1));
+  // S divides the block size, so the lanes of a chunk leave together
   if (c >= nchunks || m->status) return;
   const uint64_t W = chunk_words[c], wbase = word_off[c];
   const uint64_t uexp = chunk_unpred[c], ubase = unpred_off[c];
   // a non-empty chunk holds at least one bit; its words and unpredictable
-  // values must lie inside their sections
+  // values must lie inside their sections (the same verdict for all S lanes)
   if (W == 0 || wbase + W > total_words || ubase + uexp > n_unpred) {
     atomicOr(&m->status, kStatusCorrupt);
     return;
   }
+  const uint32_t* sub_bits = reinterpret_cast<const uint32_t*>(stream + off_sub) + c * (sub - 1);
+  const uint32_t start = k ? sub_bits[k - 1] : 0u;
+  const uint32_t next = k + 1 < sub ? sub_bits[k] : 0u;
   const uint32_t* words = reinterpret_cast<const uint32_t*>(stream + off_bits) + wbase;
   const uint64_t avail = total_words - wbase;  // >= W >= 1
   const uint32_t wlast = (uint32_t)((avail < W + 2 ? avail : W + 2) - 1);
-  const T* unpred = reinterpret_cast<const T*>(stream + off_unpred);
-  const uint64_t beg = c * chunk, end = beg + chunk < n ? beg + chunk : n;
-  const ChunkResult res =
+  const uint64_t span = chunk >> lg;
+  const uint64_t cend = c * chunk + chunk < n ? c * chunk + chunk : n;
+  const uint64_t beg0 = c * chunk + k * span;
+  const uint64_t beg = beg0 < cend ? beg0 : cend, end = beg + span < cend ? beg + span : cend;
+  uint32_t* zlist = reinterpret_cast<uint32_t*>(out + beg);
+  const RunResult res =
       lc.long_in_lds
-          ? decode_chunk<T, true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
-                                  beg, end, chunk, unpred, ubase, uexp, codes, out)
-          : decode_chunk<T, false>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
-                                   beg, end, chunk, unpred, ubase, uexp, codes, out);
-  if (!res.ok || res.ucnt != uexp || res.used > W * 32 || (res.used + 31) / 32 != W)
+          ? decode_run<true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage, beg,
+                             end, start, chunk, codes, zlist)
+          : decode_run<false>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+                              beg, end, start, chunk, codes, zlist);
+  bool bad = k + 1 < sub ? res.used != next : (res.used + 31) / 32 != W;
+  // exclusive scan of the code-0 counts over the chunk's S lanes
+  uint32_t incl = res.zeros;
+  for (uint32_t dlt = 1; dlt < sub; dlt <<= 1) {
+    const uint32_t v = __shfl_up(incl, dlt, sub);
+    if (k >= dlt) incl += v;
+  }
+  const uint32_t total = __shfl(incl, sub - 1, sub);
+  if (total != uexp) bad = true;
+  if (bad) {
     atomicOr(&m->status, kStatusCorrupt);
+    return;
+  }
+  const T* unpred = reinterpret_cast<const T*>(stream + off_unpred) + ubase + (incl - res.zeros);
+  for (uint32_t j = res.zeros; j-- > 0;) {
+    out[beg + zlist[j]] = unpred[j];
+    // the list is read as u32 and the values stored as T: keep each store
+    // behind the list reads before it
+    asm volatile("" ::: "memory");
+  }
 }
-hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_unpred,
-                                uint64_t off_bits, uint64_t total_words, uint64_t n_unpred,
-                                uint64_t n, uint32_t chunk, uint32_t nsym_used, int dtype,
-                                const uint32_t* chunk_words, const uint32_t* chunk_unpred,
-                                const uint64_t* word_off, const uint64_t* unpred_off,
-                                DecodeTables t, uint16_t* codes, void* out, Meta* m,
-                                hipStream_t st) {
+
+hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_sub,
+                                uint64_t off_unpred, uint64_t off_bits, uint64_t total_words,
+                                uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
+                                uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
+                                const uint32_t* chunk_unpred, const uint64_t* word_off,
+                                const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
+                                void* out, Meta* m, hipStream_t st) {
   (void)stream_size;
   const uint64_t nchunks = (n + chunk - 1) / chunk;
   if (nchunks == 0) return hipSuccess;
-  // 64-lane blocks when there are few chunks, so every CU gets work
-  const bool small = nchunks < 256ull * 256;  // fewer than one 256-lane block per CU
+  if (!valid_sub(chunk, sub)) return hipErrorInvalidValue;
+  const uint64_t lanes = nchunks * sub;
+  // 64-lane blocks when there are few runs, so every CU gets work
+  const bool small = lanes < 256ull * 256;  // fewer than one 256-lane block per CU
   const unsigned nt = small ? 64 : 256;
-  dim3 grid((unsigned)((nchunks + nt - 1) / nt)), block(nt);
-#define SZG_DECODE_LAUNCH(TT, NTT)                                                              \
-  hipLaunchKernelGGL((k_decode_chunks<TT, NTT>), grid, block, 0, st, stream, off_unpred,       \
-                     off_bits, total_words, n_unpred, n, chunk, nchunks, nsym_used, chunk_words, \
-                     chunk_unpred, word_off, unpred_off, t, codes, (TT*)out, m)
+  dim3 grid((unsigned)((lanes + nt - 1) / nt)), block(nt);
+#define SZG_DECODE_LAUNCH(TT, NTT)                                                               \
+  hipLaunchKernelGGL((k_decode_chunks<TT, NTT>), grid, block, 0, st, stream, off_sub, off_unpred, \
+                     off_bits, total_words, n_unpred, n, chunk, sub, nchunks, nsym_used,          \
+                     chunk_words, chunk_unpred, word_off, unpred_off, t, codes, (TT*)out, m)
   if (dtype == SZ_F32) {
     if (small)
       SZG_DECODE_LAUNCH(float, 64);

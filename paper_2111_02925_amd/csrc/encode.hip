@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
 template <typename T, bool LDS_ONLY>
 __device__ __forceinline__ void pack_chunks(
     const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
-    uint64_t nchunks, const EncTables& t, const EncWindow& w,
+    uint32_t sub, uint64_t nchunks, const EncTables& t, const EncWindow& w,
     const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
     const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
     const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
@@ -231,6 +231,16 @@ __device__ __forceinline__ void pack_chunks(
     if (lane == 0) {
       guarded_store_u32(out, cap, l.off_chunk + 8 * c, chunk_words[c]);
       guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, chunk_zeros[c]);
+    }
+    // sub-chunk k starts with lane k * (chunk / sub) / m: its bit offset in the
+    // chunk is that lane's exclusive prefix (the chunk's end for lanes past it)
+    if (sub > 1) {
+      const uint32_t lanes_per_sub = chunk / sub / r.m;
+      if (lane > 0 && lane % lanes_per_sub == 0) {
+        const uint32_t k = lane / lanes_per_sub;
+        if (k < sub)
+          guarded_store_u32(out, cap, l.off_sub + 4 * (c * (sub - 1) + k - 1), (uint32_t)bit0);
+      }
     }
     // pass B: pack.  acc holds na pending bits left-aligned; the first word
     // of a run that starts inside a word goes to the previous lane.
@@ -301,7 +311,7 @@ __device__ __forceinline__ void pack_chunks(
 template <typename T>
 __global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
     const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
-    uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
     const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
     const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
@@ -310,17 +320,18 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   load_tables(t, w, nsym, enc_code, enc_len, true);
   __syncthreads();
-  const Layout l = stream_layout(m->nsym_used, nchunks, m->n_unpred, sizeof(T), m->total_words);
+  const Layout l =
+      stream_layout(m->nsym_used, nchunks, sub, m->n_unpred, sizeof(T), m->total_words);
   if (w.lds_only)
-    pack_chunks<T, true>(codes, x, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words,
+    pack_chunks<T, true>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
                          chunk_zeros, word_off, zero_off, l, out, cap);
   else
-    pack_chunks<T, false>(codes, x, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words,
+    pack_chunks<T, false>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
                           chunk_zeros, word_off, zero_off, l, out, cap);
 }
 
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
-                         uint32_t chunk, uint32_t radius, const uint64_t* enc_code,
+                         uint32_t chunk, uint32_t sub, uint32_t radius, const uint64_t* enc_code,
                          const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
                          Meta* m, hipStream_t st) {
   const uint64_t nchunks = (n + chunk - 1) / chunk;
@@ -338,11 +349,11 @@ hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64
   if (e != hipSuccess) return e;
   if (dtype == SZ_F32)
     hipLaunchKernelGGL(k_encode_pack<float>, grid, block, 0, st, codes, (const float*)x, n, chunk,
-                       nchunks, radius, nsym, enc_code, enc_len, es.chunk_words, es.chunk_zeros,
-                       es.word_off, es.zero_off, out, cap, m);
+                       sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
+                       es.chunk_zeros, es.word_off, es.zero_off, out, cap, m);
   else
     hipLaunchKernelGGL(k_encode_pack<double>, grid, block, 0, st, codes, (const double*)x, n,
-                       chunk, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
+                       chunk, sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
                        es.chunk_zeros, es.word_off, es.zero_off, out, cap, m);
   return hipGetLastError();
 }
@@ -356,15 +367,15 @@ struct HeaderBytes {
 
 __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap,
                                                       const uint32_t* __restrict__ symtab,
-                                                      uint64_t nchunks, HeaderBytes hdr,
-                                                      uint32_t tsize, Meta* m) {
+                                                      uint64_t nchunks, uint32_t sub,
+                                                      HeaderBytes hdr, uint32_t tsize, Meta* m) {
   const uint64_t K = m->nsym_used;
-  const Layout l = stream_layout(K, nchunks, m->n_unpred, tsize, m->total_words);
+  const Layout l = stream_layout(K, nchunks, sub, m->n_unpred, tsize, m->total_words);
   const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   if (gid < kHeaderBytes / 4) {
     // header word gid; the device-side fields are 8-byte values at 56, 72,
-    // 80 (K, then a zero word), 88 and 96
+    // 80 (K, then the sub-chunk count from the template), 88 and 96
     const uint32_t byte = (uint32_t)gid * 4;
     uint64_t v64 = 0;
     bool patched = true;
@@ -375,7 +386,7 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
     } else if (at == 72) {
       v64 = m->n_unpred;
     } else if (at == 80) {
-      v64 = K;
+      v64 = K | ((uint64_t)hdr.w[84 / 4] << 32);
     } else if (at == 88) {
       v64 = m->total_words;
     } else if (at == 96) {
@@ -388,6 +399,7 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
   }
   if (gid == 0) {
     if (K & 1) guarded_store_u32(out, cap, l.off_sym + 4 * K, 0u);
+    if ((nchunks * (sub - 1)) & 1) guarded_store_u32(out, cap, l.off_sub + 4 * nchunks * (sub - 1), 0u);
     const uint64_t ub = m->n_unpred * tsize;
     if (ub & 7) guarded_store_u32(out, cap, l.off_unpred + ub, 0u);
     m->stream_bytes = l.size;
@@ -396,14 +408,14 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
 }
 
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
-                               uint64_t nchunks, const uint8_t* header_template, int dtype,
-                               Meta* m, hipStream_t st) {
+                               uint64_t nchunks, uint32_t sub, const uint8_t* header_template,
+                               int dtype, Meta* m, hipStream_t st) {
   HeaderBytes h;
   for (int i = 0; i < (int)(kHeaderBytes / 4); i++)
     h.w[i] = header_template[4 * i] | (header_template[4 * i + 1] << 8) |
              (header_template[4 * i + 2] << 16) | ((uint32_t)header_template[4 * i + 3] << 24);
   hipLaunchKernelGGL(k_write_tables, dim3(16), dim3(256), 0, st, out, capacity, symtab, nchunks,
-                     h, dtype == SZ_F32 ? 4u : 8u, m);
+                     sub, h, dtype == SZ_F32 ? 4u : 8u, m);
   return hipGetLastError();
 }
 

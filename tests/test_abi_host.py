@@ -55,9 +55,35 @@ def test_inspect_matches_oracle_header(orc):
     info = szg.inspect(s)
     assert info["dims"] == [12, 34, 5] and info["dtype"] == szg.F64
     assert info["dim_order"] == [2, 0, 1] and info["radius"] == 512 and info["chunk"] == 128
-    for k in ("n_unpred", "nsym", "total_words", "stream_bytes", "eb", "eb_mode", "predictor"):
+    for k in ("n_unpred", "nsym", "total_words", "stream_bytes", "eb", "eb_mode", "predictor",
+              "sub"):
         assert info[k] == h[k], k
-    assert info["n"] == x.size
+    assert info["n"] == x.size and info["sub"] == 4
+
+
+@pytest.mark.parametrize("chunk,sub,ok", [(4096, 0, True), (4096, 8, True), (4096, 3, False),
+                                          (64, 4, False), (64, 2, True), (128, 4, True),
+                                          (192, 4, False), (192, 2, True), (65536, 8, True), (1024, 16, False)])
+def test_subchunk_option_validation(chunk, sub, ok):
+    b = szg.compress_bound((1000,), szg.F32, chunk=chunk, subchunks=sub)
+    assert (b > 0) == ok
+    if ok:
+        # the bound grows with the sub-chunk table: 4 bytes per extra run
+        base = szg.compress_bound((1000,), szg.F32, chunk=chunk, subchunks=1)
+        S = sub or 4
+        nch = (1000 + chunk - 1) // chunk
+        assert b - base == ((4 * (S - 1) * nch + 7) & ~7)
+
+
+def test_inspect_rejects_bad_subchunk_count(orc):
+    x = np.linspace(0, 1, 3000).astype(np.float32)
+    s = orc.compress(x, orc.REL, 1e-2, chunk=1024, sub=2)
+    assert szg.inspect(s)["sub"] == 2
+    for v in (0, 3, 16, 1):  # invalid counts, and 1: valid but the layout no longer adds up
+        bad = bytearray(s)
+        bad[84:88] = int(v).to_bytes(4, "little")
+        with pytest.raises(szg.SzError):
+            szg.inspect(bytes(bad))
 
 
 def test_inspect_rejects_bad_headers(orc):

@@ -28,21 +28,24 @@ def ctx():
     c.close()
 
 
-def gpu_roundtrip(ctx, x, mode, eb, pred, radius=32768, chunk=4096, order=None):
+def gpu_roundtrip(ctx, x, mode, eb, pred, radius=32768, chunk=4096, order=None, sub=None):
     xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
-    s = ctx.compress(xt, mode, eb, pred, radius=radius, chunk=chunk, dim_order=order)
+    s = ctx.compress(xt, mode, eb, pred, radius=radius, chunk=chunk, dim_order=order,
+                     subchunks=sub or 0)
     stream = bytes(s.cpu().numpy().tobytes())
     codes = ctx.debug_codes(x.size).cpu().numpy().view(np.uint16).reshape(x.shape)
     back = ctx.decompress(s).cpu().numpy()
     return stream, codes, back
 
 
-def check_case(ctx, orc, x, mode, eb, pred, radius=32768, chunk=4096, order=None, label=""):
+def check_case(ctx, orc, x, mode, eb, pred, radius=32768, chunk=4096, order=None, label="",
+               sub=None):
     print(f"[case] {label} shape={x.shape} dtype={x.dtype} mode={mode} eb={eb} pred={pred} "
-          f"R={radius} C={chunk} order={order}", flush=True)
+          f"R={radius} C={chunk} S={sub} order={order}", flush=True)
     omode = {"abs": orc.ABS, "rel": orc.REL}[mode]
-    ref, rcodes, rrec = orc.compress(x, omode, eb, pred, radius, chunk, order, want_debug=True)
-    stream, codes, back = gpu_roundtrip(ctx, x, mode, eb, pred, radius, chunk, order)
+    ref, rcodes, rrec = orc.compress(x, omode, eb, pred, radius, chunk, order, want_debug=True,
+                                     sub=sub)
+    stream, codes, back = gpu_roundtrip(ctx, x, mode, eb, pred, radius, chunk, order, sub)
     assert np.array_equal(codes, rcodes), f"codes differ at {np.argwhere(codes != rcodes)[:5]}"
     assert len(stream) == len(ref), (len(stream), len(ref))
     if stream != ref:
@@ -82,6 +85,28 @@ def test_parity(ctx, orc, case):
     if eb is None:
         eb = synth.sinusoid_field()[1]
     check_case(ctx, orc, x, mode, eb, pred, radius, chunk, order, label)
+
+
+# Sub-chunk splits: S lanes decode one chunk from the stored run offsets.
+# Ragged tails leave the last chunk's later runs short or empty; small radii
+# put many unpredictable values in each run (their per-run lists and scatter).
+SUB_CASES = [
+    # label, generator, eb, pred, radius, chunk, sub
+    ("S1", lambda: lognormal((97, 80, 71), 41), 1e-3, 1, 32768, 4096, 1),
+    ("S2", lambda: lognormal((97, 80, 71), 41), 1e-3, 1, 32768, 4096, 2),
+    ("S8", lambda: lognormal((97, 80, 71), 41), 1e-3, 1, 32768, 4096, 8),
+    ("S8-1d-tail", lambda: np.cumsum(np.random.default_rng(9).standard_normal(3 * 2048 + 300)).astype(np.float32), 1e-3, 0, 32768, 2048, 8),
+    ("S2-C64", lambda: synth.random_field((45, 37), seed=12), 1e-3, 1, 32768, 64, 2),
+    ("S8-R2-unpred", lambda: synth.random_field((130, 70), seed=13), 1e-3, 0, 2, 1024, 8),
+    ("S4-R3-f64-unpred", lambda: synth.climate_2d((91, 77), seed=14, dtype=np.float64), 1e-5, 1, 3, 512, 4),
+    ("S4-C65536", lambda: lognormal((67, 61, 59), 15), 1e-4, 1, 32768, 65536, 4),
+]
+
+
+@pytest.mark.parametrize("case", SUB_CASES, ids=[c[0] for c in SUB_CASES])
+def test_parity_subchunks(ctx, orc, case):
+    label, gen, eb, pred, radius, chunk, sub = case
+    check_case(ctx, orc, gen(), "rel", eb, pred, radius, chunk, None, "sub:" + label, sub)
 
 
 @pytest.fixture(scope="module")
@@ -164,7 +189,9 @@ def test_capacity_and_corruption(ctx, orc):
     K = h["nsym"]
     sym_pos = 128 + 2                      # a symbol-table length byte
     chunk_pos = 128 + ((4 * K + 7) & ~7)   # first chunk's word count
-    for pos in (6, 45, sym_pos, chunk_pos):
+    assert h["sub"] == 4
+    sub_pos = chunk_pos + 8                # the single chunk's run offsets
+    for pos in (6, 45, sym_pos, chunk_pos, sub_pos, sub_pos + 4, sub_pos + 8, sub_pos + 9):
         bad = s.clone()
         bad[pos] ^= 0x5A
         with pytest.raises(szg.SzError) as ei:

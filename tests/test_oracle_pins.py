@@ -360,6 +360,59 @@ def test_codec_roundtrip_random(orc):
         assert np.array_equal(orc.unpack(words, cwords, n, chunk, lens), codes)
 
 
+def _sub_layout_rule(chunk, sub):
+    # the sub-chunk rule of the stream format, written out: S in {1, 2, 4, 8}
+    # equal runs, each a whole number of the encoder's per-lane runs of
+    # max(32, chunk / 64) symbols
+    if sub == 1:
+        return True
+    if sub not in (2, 4, 8) or chunk % sub:
+        return False
+    return (chunk // sub) % max(32, chunk // 64) == 0
+
+
+def test_subchunk_rule_and_default(orc):
+    for chunk in (1, 7, 32, 64, 96, 128, 256, 1000, 1024, 4096, 4160, 8192, 65536):
+        for sub in range(0, 10):
+            assert orc.check_sub(chunk, sub) == _sub_layout_rule(chunk, sub), (chunk, sub)
+    assert orc.default_sub(4096) == 4 and orc.default_sub(65536) == 4
+    assert orc.default_sub(64) == 2 and orc.default_sub(128) == 4 and orc.default_sub(96) == 1
+    assert orc.default_sub(100) == 1
+
+
+def test_subchunk_offsets_are_code_length_prefix_sums(orc):
+    """A sub-chunk starts at the sum of the code lengths of the chunk's
+    symbols before it (counted directly from the lengths here); symbols,
+    words and decoding do not depend on the split; a wrong offset is caught."""
+    rng = np.random.default_rng(31)
+    n = 3 * 4096 + 1234  # a partial last chunk whose last two runs are empty
+    codes = np.clip(np.round(rng.laplace(0, 9, size=n)) + 200, 0, 399).astype(np.uint16)
+    codes[rng.integers(0, n, size=50)] = 0
+    hist = orc.histogram(codes, 400)
+    lens = orc.huffman_lengths(hist)
+    cw = orc.canonical_codes(lens)
+    chunk = 4096
+    w1, cw1 = orc.pack(codes, lens, cw, chunk)
+    L = lens[codes].astype(np.int64)
+    for sub in (2, 4, 8):
+        words, cwords, sbits = orc.pack(codes, lens, cw, chunk, sub)
+        assert np.array_equal(words, w1) and np.array_equal(cwords, cw1)
+        span = chunk // sub
+        want = []
+        for c in range((n + chunk - 1) // chunk):
+            lo, hi = c * chunk, min(n, (c + 1) * chunk)
+            for k in range(1, sub):
+                want.append(int(L[lo:min(hi, lo + k * span)].sum()))
+        assert sbits.tolist() == want
+        assert np.array_equal(orc.unpack(words, cwords, n, chunk, lens, sub, sbits), codes)
+        for j in (0, len(want) - 1, len(want) // 2):
+            for dlt in (-1, 1):
+                bad = sbits.copy()
+                bad[j] = np.uint32(int(bad[j]) + dlt)
+                with pytest.raises(Exception):
+                    orc.unpack(words, cwords, n, chunk, lens, sub, bad)
+
+
 # ------------------------------------------------------------ quantizer
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -437,21 +490,27 @@ def test_resolve_eb(orc):
 
 # ------------------------------------------------------------- format
 
-def test_format_roundtrip_and_sections(orc):
+@pytest.mark.parametrize("chunk,sub", [(100, None), (128, 4), (64, 2), (256, 8), (256, 1)])
+def test_format_roundtrip_and_sections(orc, chunk, sub):
     rng = np.random.default_rng(2)
     x = rng.standard_normal((20, 30)).astype(np.float64)
     x[4, 4] = 1e30
-    s = orc.compress(x, orc.REL, 1e-4, orc.CUBIC, 512, 100)
+    s = orc.compress(x, orc.REL, 1e-4, orc.CUBIC, 512, chunk, sub=sub)
     h = orc.parse_header(s)
     assert h["magic"] == b"SZG1" and h["version"] == 1 and h["dims"] == (20, 30)
     assert h["stream_bytes"] == len(s)
-    K, nch = h["nsym"], (600 + 99) // 100
+    assert h["sub"] == (orc.default_sub(chunk) if sub is None else sub)
+    K, nch, S = h["nsym"], (600 + chunk - 1) // chunk, h["sub"]
     pad8 = lambda v: (v + 7) & ~7
-    off_bits = 128 + pad8(4 * K) + 8 * nch + pad8(8 * h["n_unpred"])
+    off_bits = 128 + pad8(4 * K) + 8 * nch + pad8(4 * (S - 1) * nch) + pad8(8 * h["n_unpred"])
     assert off_bits + 4 * h["total_words"] == len(s)
     assert h["n_unpred"] >= 1
     # identical input -> identical bytes (deterministic)
-    assert orc.compress(x, orc.REL, 1e-4, orc.CUBIC, 512, 100) == s
+    assert orc.compress(x, orc.REL, 1e-4, orc.CUBIC, 512, chunk, sub=sub) == s
+    # the split changes only the header field and the sub-chunk table
+    one = orc.compress(x, orc.REL, 1e-4, orc.CUBIC, 512, chunk, sub=1)
+    assert np.array_equal(orc.decompress(one), orc.decompress(s))
+    assert s[-4 * h["total_words"]:] == one[-4 * h["total_words"]:]
 
 
 def test_corruption_detected(orc):
@@ -461,9 +520,14 @@ def test_corruption_detected(orc):
     ref = orc.decompress(s)
     h = orc.parse_header(s)
     K = h["nsym"]
-    # header fields, symbol table entries and chunk table entries are all checked
-    for pos in list(range(0, 12)) + [40, 41, 45, 64, 68, 72, 80, 88, 96] + \
-            [128 + 4 * i + 2 for i in range(min(K, 8))] + [128 + ((4 * K + 7) & ~7) + 3]:
+    nch = (2000 + 255) // 256
+    assert h["sub"] == 4
+    off_sub = 128 + ((4 * K + 7) & ~7) + 8 * nch
+    # header fields, symbol table, chunk table and sub-chunk table entries are
+    # all checked
+    for pos in list(range(0, 12)) + [40, 41, 45, 64, 68, 72, 80, 84, 88, 96] + \
+            [128 + 4 * i + 2 for i in range(min(K, 8))] + [128 + ((4 * K + 7) & ~7) + 3] + \
+            [off_sub, off_sub + 4 * 3 * (nch - 1) + 8]:
         bad = bytearray(s)
         bad[pos] ^= 0x5A
         with pytest.raises(Exception):
