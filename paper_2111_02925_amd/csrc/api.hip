@@ -55,6 +55,7 @@ struct sz_ctx {
   // fixed scratch
   Meta* meta = nullptr;
   uint32_t* hist = nullptr;
+  uint32_t* hist_part = nullptr;  // partial-histogram rows
   uint64_t* enc_code = nullptr;
   uint8_t* enc_len = nullptr;
   uint32_t* symtab = nullptr;
@@ -328,6 +329,7 @@ int ensure_fixed(sz_ctx* ctx) {
   if (ctx->meta) return SZ_OK;
   CHECK_HIP(hipMalloc(&ctx->meta, sizeof(Meta)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->hist, sizeof(uint32_t) * kMaxSym), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->hist_part, histogram_scratch_bytes()), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->enc_code, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->enc_len, kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->symtab, sizeof(uint32_t) * kMaxSym), "hipMalloc");
@@ -390,7 +392,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
                  &ctx->unpred_off, &ctx->block_sums})
     if (b->p) (void)hipFree(b->p);
-  void* fixed[] = {ctx->meta, ctx->hist, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
+  void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
 
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
                    ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut,
@@ -494,7 +496,8 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
   }
   CHECK_HIP(launch_fill_u32(ctx->hist, 0, nsym, st), "fill");
   CHECK_HIP(timed(ctx, "histogram", st,
-                  [&] { return launch_histogram(codes, s.n, nsym, s.radius, ctx->hist, st); }),
+                  [&] { return launch_histogram(codes, s.n, s.radius, ctx->hist_part, ctx->hist, ctx->meta, st);
+                  }),
             "histogram");
   CHECK_HIP(timed(ctx, "codebook", st, [&] {
               return launch_codebook(ctx->hist, nsym, ctx->cb, ctx->enc_code, ctx->enc_len,

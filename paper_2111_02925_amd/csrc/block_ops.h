@@ -8,6 +8,14 @@
 
 namespace szg {
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores in
+// flight stay in flight across it (a plain __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------ block scans
 
 __device__ inline uint32_t wave_incl_scan_u32(uint32_t v, int lane) {

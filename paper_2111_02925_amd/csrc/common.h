@@ -81,7 +81,7 @@ struct Meta {
   uint64_t total_words;
   uint64_t stream_bytes;
   uint32_t status;     // error bits (kStatus*)
-  uint32_t pad;
+  uint32_t hist_far;   // some code was counted outside the histogram's window
 };
 constexpr uint32_t kStatusEbNotFinite = 1u << 0;
 constexpr uint32_t kStatusCodeTooLong = 1u << 1;
@@ -158,8 +158,10 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                               const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
 
-hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t nsym, uint32_t radius,
-                            uint32_t* hist, hipStream_t st);
+hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, uint32_t* part,
+                            uint32_t* hist, Meta* m, hipStream_t st);
+// bytes of the partial-histogram rows launch_histogram needs in `part`
+size_t histogram_scratch_bytes();
 
 struct CodebookScratch {
   uint64_t* keys_a;    // kMaxSym

@@ -80,52 +80,72 @@ hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t
 
 // Build the canonical decoding tables from the stored (symbol, length) list:
 // validate it (ascending symbols, lengths 1..64, a complete prefix code),
-// sort by (length, symbol), and fill a lookup table indexed by the next
+// order it by (length, symbol), and fill a lookup table indexed by the next
 // kLutBits bits for codes no longer than that.
+//
+// Up to kDtLdsCap coded symbols the list is handled in LDS: a symbol's place
+// in (length, symbol) order is its length's offset plus the number of
+// smaller symbols of the same length (counted a wave at a time with
+// ballots), and each lookup entry finds the short code covering it by a
+// binary search over the left-justified code starts, which ascend and tile
+// the table from 0.  Longer lists take a radix sort in global scratch.
+constexpr uint32_t kDtLdsCap = 2048;
+
+__device__ bool check_lengths(const uint32_t* bl, uint32_t K) {
+  // complete prefix code: pairing nodes from the deepest level up must leave
+  // exactly the root (a lone symbol must have length 1)
+  if (K == 1) return bl[1] == 1;
+  uint64_t carry = 0;
+  for (int l = kMaxCodeLen; l >= 1; l--) {
+    const uint64_t nodes = bl[l] + carry;
+    if (nodes & 1) return false;
+    carry = nodes >> 1;
+  }
+  return carry == 1;
+}
+
 __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
                                                               uint64_t off_sym, uint32_t K,
                                                               uint32_t nsym, DecodeTables d,
                                                               Meta* m) {
-  __shared__ uint32_t cnt[16 * kCbThreads];
+  __shared__ union {
+    uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
+    struct {
+      uint32_t e[kDtLdsCap];        // stored entries, symbol order
+      uint32_t lj[kDtLdsCap];       // left-justified start of each short code, sorted order
+      uint32_t val[kDtLdsCap];      // lookup value of each short code, sorted order
+    } s;
+  } u;
   __shared__ uint32_t sh16[16];
-  __shared__ uint32_t bl[kMaxCodeLen + 2];
+  __shared__ uint32_t bl[kMaxCodeLen + 2], run[kMaxCodeLen + 2], offs[kMaxCodeLen + 2];
+  __shared__ uint64_t firsts[kMaxCodeLen + 2];
   __shared__ uint32_t bad;
   const uint32_t T = blockDim.x, t = threadIdx.x;
-  if (t <= kMaxCodeLen + 1) bl[t] = 0;
+  if (t <= kMaxCodeLen + 1) {
+    bl[t] = 0;
+    run[t] = 0;
+  }
   if (t == 0) bad = 0;
-  for (uint32_t i = t; i < (1u << kLutBits); i += T) d.lut[i] = 0;
-  __syncthreads();
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_sym);
+  const bool in_lds = K <= kDtLdsCap;
+  if (in_lds)
+    for (uint32_t i = t; i < K; i += T) u.s.e[i] = tab[i];
+  __syncthreads();
   for (uint32_t i = t; i < K; i += T) {
-    uint32_t e = tab[i];
-    uint32_t sym = e & 0xFFFF, len = e >> 16;
+    const uint32_t e = in_lds ? u.s.e[i] : tab[i];
+    const uint32_t sym = e & 0xFFFF, len = e >> 16;
     bool ok = sym < nsym && len >= 1 && len <= kMaxCodeLen;
-    if (i > 0 && (tab[i - 1] & 0xFFFF) >= sym) ok = false;
+    if (i > 0 && ((in_lds ? u.s.e[i - 1] : tab[i - 1]) & 0xFFFF) >= sym) ok = false;
     if (!ok) {
       bad = 1;
     } else {
       atomicAdd(&bl[len], 1u);
-      d.keys_a[i] = ((uint64_t)len << 16) | sym;
+      if (!in_lds) d.keys_a[i] = ((uint64_t)len << 16) | sym;
     }
   }
   __syncthreads();
-  if (t == 0 && !bad) {
-    // complete prefix code: pairing nodes from the deepest level up must leave
-    // exactly the root (a lone symbol must have length 1)
-    if (K == 1) {
-      if (bl[1] != 1) bad = 1;
-    } else if (K > 1) {
-      uint64_t carry = 0;
-      for (int l = kMaxCodeLen; l >= 1; l--) {
-        uint64_t nodes = bl[l] + carry;
-        if (nodes & 1) {
-          bad = 1;
-          break;
-        }
-        carry = nodes >> 1;
-      }
-      if (!bad && carry != 1) bad = 1;
-    }
+  if (t == 0) {
+    if (!bad && K > 0 && !check_lengths(bl, K)) bad = 1;
     uint64_t code = 0;
     uint32_t off = 0;
     for (int l = 1; l <= kMaxCodeLen; l++) {
@@ -133,22 +153,76 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
       d.first[l] = code;
       d.count[l] = bl[l];
       d.offset[l] = off;
+      firsts[l] = code;
+      offs[l] = off;
       off += bl[l];
     }
     if (bad) atomicOr(&m->status, kStatusCorrupt);
   }
+  for (uint32_t i = t; i < (1u << kLutBits); i += T) d.lut[i] = 0;
   __syncthreads();
   if (bad || K == 0) return;
-  uint64_t* bylen = block_radix_sort(d.keys_a, d.keys_b, K, 16, 24, cnt, sh16);
-  for (uint32_t j = t; j < K; j += T) {
-    uint64_t key = bylen[j];
-    uint32_t l = (uint32_t)(key >> 16) & 0xFF, sym = (uint32_t)(key & 0xFFFF);
-    d.sorted_sym[j] = (uint16_t)sym;
-    if (l <= kLutBits) {
-      uint64_t code = d.first[l] + (j - d.offset[l]);
-      uint32_t lo = (uint32_t)(code << (kLutBits - l)), span = 1u << (kLutBits - l);
-      for (uint32_t k = 0; k < span; k++) d.lut[lo + k] = sym | (l << 16);
+  if (!in_lds) {
+    __syncthreads();  // the lookup table is cleared before it is filled
+    uint64_t* bylen = block_radix_sort(d.keys_a, d.keys_b, K, 16, 24, u.cnt, sh16);
+    for (uint32_t j = t; j < K; j += T) {
+      uint64_t key = bylen[j];
+      uint32_t l = (uint32_t)(key >> 16) & 0xFF, sym = (uint32_t)(key & 0xFFFF);
+      d.sorted_sym[j] = (uint16_t)sym;
+      if (l <= kLutBits) {
+        uint64_t code = d.first[l] + (j - d.offset[l]);
+        uint32_t lo = (uint32_t)(code << (kLutBits - l)), span = 1u << (kLutBits - l);
+        for (uint32_t k = 0; k < span; k++) d.lut[lo + k] = sym | (l << 16);
+      }
     }
+    return;
+  }
+  // (length, symbol) order, a wave of symbols at a time
+  if (t < 64) {
+    const uint32_t lane = t;
+    for (uint32_t base = 0; base < K; base += 64) {
+      const uint32_t i = base + lane;
+      const bool valid = i < K;
+      const uint32_t e = valid ? u.s.e[i] : 0u;
+      const uint32_t l = e >> 16, sym = e & 0xFFFF;
+      uint64_t same = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 7; bit++) {
+        const bool on = (l >> bit) & 1u;
+        const uint64_t bb = __ballot(on);
+        same &= on ? bb : ~bb;
+      }
+      const uint32_t below = (uint32_t)__popcll(same & ((1ull << lane) - 1));
+      const uint32_t before = valid ? run[l] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        const uint32_t r = before + below, pos = offs[l] + r;
+        d.sorted_sym[pos] = (uint16_t)sym;
+        if (l <= (uint32_t)kLutBits) {
+          u.s.lj[pos] = (uint32_t)((firsts[l] + r) << (kLutBits - l));
+          u.s.val[pos] = sym | (l << 16);
+        }
+        if ((same >> lane) == 1ull) run[l] = before + (uint32_t)__popcll(same);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  // lookup table: entry x holds the short code whose range covers it
+  const uint32_t nshort = offs[kLutBits + 1];
+  if (nshort == 0) return;
+  const uint32_t last = nshort - 1;
+  const uint32_t end = u.s.lj[last] + (1u << (kLutBits - (u.s.val[last] >> 16)));
+  for (uint32_t x = t; x < end; x += T) {
+    uint32_t lo = 0, hi = last;  // largest j with lj[j] <= x
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (u.s.lj[mid] <= x)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    d.lut[x] = u.s.val[lo];
   }
 }
 

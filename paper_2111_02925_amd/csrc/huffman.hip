@@ -16,46 +16,166 @@
 namespace szg {
 
 // -------------------------------------------------------------- histogram
-// Privatised per block: the bins nearest the radius (where the mass of an
-// error-bounded prediction residual sits) are counted in LDS, the rest with
-// global atomics.  A wave counts lanes that hit the radius bin together.
+// The codes of an error-bounded prediction residual pile up next to the
+// radius R.  Each lane counts the kHistLane codes nearest R in counters of
+// its own in LDS (no two lanes share an address, so the adds never collide);
+// the other codes within kHistShared of R go to counters shared by the
+// workgroup, code 0 (unpredictable) to a counter of its own, and codes
+// further out to two overflow counters.  Each workgroup writes its counts to
+// a row of partial histograms, which a second kernel sums into the
+// histogram; a workgroup whose overflow counters are not zero re-reads its
+// codes and adds those far codes with global atomics.
 
-constexpr uint32_t kHistWindow = 8192;
+constexpr uint32_t kHistThreads = 256;
+constexpr uint32_t kHistLane = 32;          // per-lane bins around R
+constexpr uint32_t kHistShared = 4096;      // workgroup bins around R
+constexpr uint32_t kHistSlots = kHistShared + 3;  // below | window | above | code 0
+constexpr uint32_t kHistVecs = 8;           // 8-code vectors per lane per tile
+constexpr uint32_t kHistTile = kHistThreads * kHistVecs;  // vectors per tile
+constexpr uint32_t kHistMaxBlocks = 768;
 
-__global__ __launch_bounds__(256) void k_histogram(const uint16_t* __restrict__ codes, uint64_t n,
-                                                   uint32_t nsym, uint32_t R, uint32_t* hist) {
-  __shared__ uint32_t sh[kHistWindow];
-  const uint32_t lo = R > kHistWindow / 2 ? R - kHistWindow / 2 : 0;
-  const uint32_t win = nsym - lo < kHistWindow ? nsym - lo : kHistWindow;
-  for (uint32_t i = threadIdx.x; i < win; i += blockDim.x) sh[i] = 0;
+struct HistWindow {
+  uint32_t plo;  // first per-lane bin
+  uint32_t slo;  // first workgroup bin (slot 1)
+};
+
+__host__ __device__ inline HistWindow hist_window(uint32_t R) {
+  HistWindow w;
+  w.plo = R > kHistLane / 2 ? R - kHistLane / 2 : 0;
+  w.slo = R > kHistShared / 2 ? R - kHistShared / 2 : 0;
+  return w;
+}
+
+// slot of a code in the workgroup counters
+__device__ __forceinline__ uint32_t hist_slot(uint32_t c, uint32_t slo) {
+  int v = (int)c - (int)slo + 1;
+  v = v < 0 ? 0 : (v > (int)kHistShared + 1 ? (int)kHistShared + 1 : v);
+  return c == 0 ? kHistShared + 2 : (uint32_t)v;
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __restrict__ codes,
+                                                            uint64_t n, uint32_t R,
+                                                            uint32_t* __restrict__ part,
+                                                            uint32_t* hist, Meta* m) {
+  __shared__ uint32_t lane_cnt[kHistLane * kHistThreads];
+  __shared__ uint32_t shared_cnt[kHistSlots];
+  const uint32_t t = threadIdx.x;
+  const HistWindow hw = hist_window(R);
+  for (uint32_t i = t; i < kHistLane * kHistThreads; i += kHistThreads) lane_cnt[i] = 0;
+  for (uint32_t i = t; i < kHistSlots; i += kHistThreads) shared_cnt[i] = 0;
   __syncthreads();
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += gs) {
-    uint32_t c = codes[i];
-    uint64_t same = __ballot(c == R);
-    if (c == R) {
-      if ((threadIdx.x & 63) == (uint32_t)(__ffsll((long long)same) - 1))
-        atomicAdd(&sh[R - lo], (uint32_t)__popcll(same));
-    } else if (c - lo < win) {
-      atomicAdd(&sh[c - lo], 1u);
-    } else {
-      atomicAdd(&hist[c], 1u);
+  auto count = [&](uint32_t c) {
+    const uint32_t d = c - hw.plo;
+    uint32_t* p = d < kHistLane ? &lane_cnt[d * kHistThreads + t] : &shared_cnt[hist_slot(c, hw.slo)];
+    atomicAdd(p, 1u);
+  };
+  const uint64_t nvec = n / 8;
+  const uint4* v4 = reinterpret_cast<const uint4*>(codes);
+  const uint64_t ntiles = (nvec + kHistTile - 1) / kHistTile;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t base = tile * kHistTile + t;
+    uint4 v[kHistVecs];
+#pragma unroll
+    for (uint32_t j = 0; j < kHistVecs; j++) {
+      const uint64_t i = base + (uint64_t)j * kHistThreads;
+      v[j] = i < nvec ? v4[i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kHistVecs; j++) {
+      if (base + (uint64_t)j * kHistThreads < nvec) {
+        const uint32_t w[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          count(w[h] & 0xFFFFu);
+          count(w[h] >> 16);
+        }
+      }
     }
   }
+  if (blockIdx.x == 0 && t < (n & 7)) count(codes[nvec * 8 + t]);
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < win; i += blockDim.x)
-    if (sh[i]) atomicAdd(&hist[lo + i], sh[i]);
+  // per-lane bins into the workgroup's window (rotated reads: distinct banks)
+  {
+    const uint32_t b = t & (kHistLane - 1), g = t / kHistLane;
+    const uint32_t lanes = kHistThreads / (kHistThreads / kHistLane);
+    uint32_t sum = 0;
+    for (uint32_t j = 0; j < lanes; j++)
+      sum += lane_cnt[b * kHistThreads + g * lanes + ((j + b) & (lanes - 1))];
+    if (sum) atomicAdd(&shared_cnt[hist_slot(hw.plo + b, hw.slo)], sum);
+  }
+  __syncthreads();
+  uint32_t* row = part + (uint64_t)blockIdx.x * kHistSlots;
+  for (uint32_t i = t; i < kHistSlots; i += kHistThreads) row[i] = shared_cnt[i];
+  // far codes (rare): re-read this workgroup's codes, global atomics
+  if (shared_cnt[0] | shared_cnt[kHistShared + 1]) {
+    if (t == 0) atomicOr(&m->hist_far, 1u);
+    auto far = [&](uint32_t c) {
+      const uint32_t sl = hist_slot(c, hw.slo);
+      if (sl == 0 || sl == kHistShared + 1) atomicAdd(&hist[c], 1u);
+    };
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+      for (uint32_t j = 0; j < kHistVecs; j++) {
+        const uint64_t i = tile * kHistTile + t + (uint64_t)j * kHistThreads;
+        if (i < nvec) {
+          const uint4 q = v4[i];
+          const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+          for (int h = 0; h < 4; h++) {
+            far(w[h] & 0xFFFFu);
+            far(w[h] >> 16);
+          }
+        }
+      }
+    if (blockIdx.x == 0 && t < (n & 7)) far(codes[nvec * 8 + t]);
+  }
 }
 
-hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t nsym, uint32_t radius,
-                            uint32_t* hist, hipStream_t st) {
+// Sums the partial rows: a workgroup takes 64 slots of 32 rows (a wave per
+// 8 rows, lanes on consecutive slots) and adds its column sums to the
+// histogram.
+constexpr uint32_t kHistReduceRows = 32;
+
+__global__ __launch_bounds__(256) void k_hist_reduce(const uint32_t* __restrict__ part,
+                                                     uint32_t rows, uint32_t R, uint32_t* hist) {
+  __shared__ uint32_t colsum[4][64];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t slot = blockIdx.x * 64 + lane;
+  const uint32_t r0 = blockIdx.y * kHistReduceRows + wv * (kHistReduceRows / 4);
+  uint32_t sum = 0;
+  if (slot < kHistSlots) {
+#pragma unroll
+    for (uint32_t j = 0; j < kHistReduceRows / 4; j++)
+      if (r0 + j < rows) sum += part[(uint64_t)(r0 + j) * kHistSlots + slot];
+  }
+  colsum[wv][lane] = sum;
+  __syncthreads();
+  if (wv == 0 && slot < kHistSlots) {
+    const uint32_t tot = colsum[0][lane] + colsum[1][lane] + colsum[2][lane] + colsum[3][lane];
+    const HistWindow hw = hist_window(R);
+    uint32_t sym = 0xFFFFFFFFu;
+    if (slot == kHistShared + 2)
+      sym = 0;
+    else if (slot >= 1 && slot <= kHistShared && hw.slo + slot - 1 < 2 * R)
+      sym = hw.slo + slot - 1;
+    if (tot && sym != 0xFFFFFFFFu) atomicAdd(&hist[sym], tot);
+  }
+}
+
+hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, uint32_t* part,
+                            uint32_t* hist, Meta* m, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + 256 * 32 - 1) / (256 * 32);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_histogram, dim3((unsigned)blocks), dim3(256), 0, st, codes, n, nsym,
-                     radius, hist);
+  const uint64_t tiles = (n / 8 + kHistTile - 1) / kHistTile;
+  uint32_t blocks = (uint32_t)(tiles < kHistMaxBlocks ? tiles : kHistMaxBlocks);
+  if (blocks == 0) blocks = 1;
+  // a lane counts at most ceil(tiles / blocks) * 64 + 8 codes per bin, which
+  // stays far below 2^32 for any field of up to 2^32 - 1 points
+  hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(kHistThreads), 0, st, codes, n, radius,
+                     part, hist, m);
+  dim3 rgrid((kHistSlots + 63) / 64, (blocks + kHistReduceRows - 1) / kHistReduceRows);
+  hipLaunchKernelGGL(k_hist_reduce, rgrid, dim3(256), 0, st, part, blocks, radius, hist);
   return hipGetLastError();
 }
+
+size_t histogram_scratch_bytes() { return sizeof(uint32_t) * (size_t)kHistMaxBlocks * kHistSlots; }
 
 // --------------------------------------------------------------- codebook
 // Huffman code lengths by the two-queue greedy merge (leaves sorted by
@@ -116,12 +236,10 @@ __device__ uint32_t compact_used(const uint32_t* hist, const uint8_t* lens, uint
   return K;
 }
 
-__global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restrict__ hist,
-                                                          uint32_t nsym, CodebookScratch s,
-                                                          uint64_t* enc_code, uint8_t* enc_len,
-                                                          uint32_t* symtab, Meta* m) {
-  __shared__ uint32_t cnt[16 * kCbThreads];
-  __shared__ uint32_t sh16[16];
+// Any K: the tree arrays live in global scratch.
+__device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym,
+                                CodebookScratch s, uint64_t* enc_code, uint8_t* enc_len,
+                                uint32_t* symtab, Meta* m, uint32_t* cnt, uint32_t* sh16) {
   __shared__ uint32_t sh_li, sh_qi, sh_qn, sh_cl, sh_ci, sh_done, sh_nphase;
   __shared__ uint32_t sh_maxw, sh_maxlen;
   __shared__ uint32_t bl_count[kMaxCodeLen + 2];
@@ -129,9 +247,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restr
   __shared__ uint32_t len_offset[kMaxCodeLen + 2];
   const uint32_t T = blockDim.x, t = threadIdx.x;
 
-  for (uint32_t i = t; i < nsym; i += T) enc_len[i] = 0;
   if (t == 0) {
-    m->n_unpred = hist[0];
     sh_maxw = 0;
     sh_maxlen = 0;
   }
@@ -294,6 +410,322 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restr
       atomicMax(&m->sym_hi, sym);
     }
   }
+}
+
+// K <= kCbLdsCap: the whole tree in LDS, built by one wave, so that no step
+// waits at a workgroup barrier (a wave's LDS accesses take effect in program
+// order; an empty asm with a memory clobber keeps the compiler from moving
+// them across the steps).  Leaves are sorted by (count, symbol) with a
+// bitonic network; the bounds of each merge phase come from a 64-way search;
+// canonical codes take, for each symbol, the number of smaller symbols of the
+// same length, counted a wave of symbols at a time with ballots.
+constexpr uint32_t kCbLdsCap = 2048;
+constexpr uint32_t kCbScanBatch = 8;  // uint4 loads in flight per thread while scanning bins
+
+struct CbLds {
+  union {
+    uint64_t key[kCbLdsCap];       // count << 32 | symbol-order index (until ranked)
+    struct {
+      uint16_t depth[2 * kCbLdsCap];
+      uint16_t merged[kCbLdsCap];
+      uint16_t phase_end[kCbLdsCap];
+    };
+  };
+  uint32_t w[2 * kCbLdsCap];       // node weights: leaves by rank, then internal nodes
+  uint16_t sym_of[kCbLdsCap];      // symbol of each symbol-order index
+  uint16_t idx_of[kCbLdsCap];      // symbol-order index of each leaf rank
+  uint16_t parent[2 * kCbLdsCap];
+  uint8_t len_si[kCbLdsCap];       // code length by symbol-order index
+  uint32_t bl_count[kMaxCodeLen + 2];
+  uint32_t run[kMaxCodeLen + 2];
+  uint64_t first_code[kMaxCodeLen + 2];
+};
+
+__device__ __forceinline__ void wave_step() { asm volatile("" ::: "memory"); }
+
+// number of leading entries of the ascending w[lo, hi) that are <= v (hi - lo
+// <= 4096), by two rounds of 64 probes
+__device__ __forceinline__ uint32_t wave_count_le(const uint32_t* w, uint32_t lo, uint32_t hi,
+                                                  uint64_t v, uint32_t lane) {
+  const uint32_t len = hi - lo;
+  if (len == 0) return 0;
+  const uint32_t step = (len + 63) / 64;
+  uint32_t i = lo + (lane + 1) * step - 1;
+  const uint32_t c1 = (uint32_t)__popcll(__ballot(i < hi && (uint64_t)w[i] <= v));
+  const uint32_t b = lo + c1 * step;
+  i = b + lane;
+  const uint32_t c2 = (uint32_t)__popcll(__ballot(lane < step && i < hi && (uint64_t)w[i] <= v));
+  return c1 * step + c2;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t x = __shfl_xor(v, o, 64);
+    v = x > v ? x : v;
+  }
+  return v;
+}
+
+// Leaves by rank: a bitonic network over P = 2^k >= K keys by the whole
+// workgroup (keys are distinct; padding sorts last), each thread loading all
+// its pairs of a step before exchanging them; then the weights and
+// symbol-order indices by rank.  Called by every thread.
+__device__ __forceinline__ void rank_leaves(uint32_t K, CbLds& L) {
+  constexpr uint32_t kPairs = kCbLdsCap / 2 / kCbThreads;  // pairs per thread at most
+  const uint32_t t = threadIdx.x;
+  uint32_t P = 1;
+  while (P < K) P <<= 1;
+  for (uint32_t i = K + t; i < P; i += kCbThreads) L.key[i] = ~0ull;
+  lds_barrier();
+  for (uint32_t k = 2; k <= P; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      uint64_t x[kPairs], y[kPairs];
+#pragma unroll
+      for (uint32_t q = 0; q < kPairs; q++) {
+        const uint32_t i = t + q * kCbThreads;
+        const uint32_t a = 2 * i - (i & (j - 1));
+        if (i < P / 2) {
+          x[q] = L.key[a];
+          y[q] = L.key[a + j];
+        }
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kPairs; q++) {
+        const uint32_t i = t + q * kCbThreads;
+        const uint32_t a = 2 * i - (i & (j - 1));
+        if (i < P / 2 && (x[q] > y[q]) == ((a & k) == 0)) {
+          L.key[a] = y[q];
+          L.key[a + j] = x[q];
+        }
+      }
+      lds_barrier();
+    }
+  for (uint32_t r = t; r < K; r += kCbThreads) {
+    const uint64_t key = L.key[r];
+    L.w[r] = (uint32_t)(key >> 32);
+    L.idx_of[r] = (uint16_t)(key & 0xFFFFu);
+  }
+  lds_barrier();  // the key array is dead from here on
+}
+
+// Called by wave 0 alone, after rank_leaves.
+__device__ __forceinline__ void codebook_wave(uint32_t K, uint64_t* enc_code, uint8_t* enc_len,
+                                              uint32_t* symtab, Meta* m, CbLds& L) {
+  const uint32_t lane = threadIdx.x;
+  if (K == 1) {
+    if (lane == 0) {
+      const uint32_t sym = L.sym_of[0];
+      enc_len[sym] = 1;
+      enc_code[sym] = 0;
+      symtab[0] = sym | (1u << 16);
+      m->nsym_used = 1;
+      m->max_len = 1;
+      if (sym) {
+        m->sym_lo = sym;
+        m->sym_hi = sym;
+      }
+    }
+    return;
+  }
+  for (uint32_t i = lane; i <= (uint32_t)kMaxCodeLen + 1; i += 64) {
+    L.bl_count[i] = 0;
+    L.run[i] = 0;
+  }
+  wave_step();
+
+  // two-queue merge in phases (see the header of this section)
+  uint32_t li = 0, qi = K, qn = K, nph = 0;
+  uint32_t* w = L.w;
+  constexpr uint64_t kInf = ~0ull;
+  for (;;) {
+    if ((K - li) + (qn - qi) <= 1) break;
+    const uint64_t l0 = li < K ? w[li] : kInf, l1 = li + 1 < K ? w[li + 1] : kInf;
+    const uint64_t q0 = qi < qn ? w[qi] : kInf, q1 = qi + 1 < qn ? w[qi + 1] : kInf;
+    // the lighter front twice, the leaf on equal weights
+    uint64_t tw;
+    if (l0 <= q0)
+      tw = l0 + (l1 <= q0 ? l1 : q0);
+    else
+      tw = q0 + (l0 <= q1 ? l0 : q1);
+    const uint32_t cl = wave_count_le(w, li, K, tw, lane), ci = qn - qi;
+    if (cl + ci < 2 || nph >= kCbLdsCap) {  // cannot happen with sorted leaves; never spin
+      if (lane == 0) atomicOr(&m->status, kStatusCodeTooLong);
+      return;
+    }
+    for (uint32_t x = lane; x < cl; x += 64)
+      L.merged[x + lower_bound_w(w, qi, qn, w[li + x]) - qi] = (uint16_t)(li + x);
+    for (uint32_t x = lane; x < ci; x += 64)
+      L.merged[x + upper_bound_w(w, li, li + cl, w[qi + x]) - li] = (uint16_t)(qi + x);
+    wave_step();
+    const uint32_t c = cl + ci, np = c >> 1;
+    for (uint32_t p = lane; p < np; p += 64) {
+      const uint32_t u = L.merged[2 * p], v = L.merged[2 * p + 1];
+      w[qn + p] = w[u] + w[v];
+      L.parent[u] = (uint16_t)(qn + p);
+      L.parent[v] = (uint16_t)(qn + p);
+    }
+    if (c & 1) {
+      const uint32_t last = L.merged[c - 1];
+      li += cl - (last < K ? 1 : 0);
+      qi += ci - (last >= K ? 1 : 0);
+    } else {
+      li += cl;
+      qi += ci;
+    }
+    qn += np;
+    if (lane == 0) L.phase_end[nph] = (uint16_t)qn;
+    nph++;
+    wave_step();
+  }
+
+  // depths, root first: a phase's nodes have their parents in later phases
+  const uint32_t root = 2 * K - 2;
+  if (lane == 0) L.depth[root] = 0;
+  wave_step();
+  for (int p = (int)nph - 1; p >= 0; p--) {
+    const uint32_t b0 = p == 0 ? K : L.phase_end[p - 1], b1 = L.phase_end[p];
+    for (uint32_t i = b0 + lane; i < b1; i += 64)
+      if (i != root) L.depth[i] = L.depth[L.parent[i]] + 1;
+    wave_step();
+  }
+  uint32_t maxl = 0, bad = 0;
+  for (uint32_t r = lane; r < K; r += 64) {
+    uint32_t d = L.depth[L.parent[r]] + 1u;
+    if (d > (uint32_t)kMaxCodeLen) {
+      bad = 1;
+      d = kMaxCodeLen;
+    }
+    L.len_si[L.idx_of[r]] = (uint8_t)d;
+    atomicAdd(&L.bl_count[d], 1u);
+    maxl = d > maxl ? d : maxl;
+  }
+  maxl = wave_max_u32(maxl);
+  bad = wave_max_u32(bad);
+  wave_step();
+  if (lane == 0) {
+    uint64_t code = 0;
+    for (int l = 1; l <= kMaxCodeLen; l++) {
+      code = (code + (l > 1 ? L.bl_count[l - 1] : 0)) << 1;
+      L.first_code[l] = code;
+    }
+    if (bad) atomicOr(&m->status, kStatusCodeTooLong);
+    m->nsym_used = K;
+    m->max_len = maxl;
+    const uint32_t lo = L.sym_of[0] ? L.sym_of[0] : L.sym_of[1], hi = L.sym_of[K - 1];
+    m->sym_lo = lo;
+    m->sym_hi = hi;
+  }
+  wave_step();
+  // canonical codes: within a length, consecutive in symbol order
+  for (uint32_t base = 0; base < K; base += 64) {
+    const uint32_t i = base + lane;
+    const bool valid = i < K;
+    const uint32_t l = valid ? L.len_si[i] : 0u;
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 7; bit++) {
+      const bool on = (l >> bit) & 1u;
+      const uint64_t bb = __ballot(on);
+      same &= on ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(same & ((1ull << lane) - 1));
+    const uint32_t before = valid ? L.run[l] : 0u;
+    wave_step();
+    if (valid) {
+      const uint32_t sym = L.sym_of[i];
+      enc_code[sym] = L.first_code[l] + before + below;
+      enc_len[sym] = (uint8_t)l;
+      symtab[i] = sym | (l << 16);
+      if ((same >> lane) == 1ull) L.run[l] = before + (uint32_t)__popcll(same);
+    }
+    wave_step();
+  }
+}
+
+// The used symbols are found by scanning the histogram: only the window the
+// histogram kernel counts in (and symbol 0) when no code fell outside it.
+__global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restrict__ hist,
+                                                          uint32_t nsym, CodebookScratch s,
+                                                          uint64_t* enc_code, uint8_t* enc_len,
+                                                          uint32_t* symtab, Meta* m) {
+  __shared__ union {
+    uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
+    CbLds lds;
+  } u;
+  __shared__ uint32_t sh16[16];
+  const uint32_t t = threadIdx.x;
+  {
+    uint4* z = reinterpret_cast<uint4*>(enc_len);  // kMaxSym bytes, 16-byte aligned
+    for (uint32_t i = t; i < (nsym + 15) / 16; i += kCbThreads) z[i] = make_uint4(0, 0, 0, 0);
+  }
+  if (t == 0) m->n_unpred = hist[0];
+  // bins [b0, b1) in aligned quads, plus bin 0 when the range leaves it out
+  uint32_t b0 = 0, b1 = nsym;
+  if (!m->hist_far) {
+    const HistWindow hw = hist_window(nsym / 2);
+    b0 = hw.slo;
+    b1 = hw.slo + kHistShared < nsym ? hw.slo + kHistShared : nsym;
+  }
+  const uint32_t extra0 = b0 > 0 && hist[0] != 0;  // bin 0 outside the range, used
+  const uint32_t q0 = b0 / 4, nq = (b1 + 3) / 4 - q0;   // quads to scan
+  const uint32_t per = (nq + kCbThreads - 1) / kCbThreads;
+  const uint32_t qa = q0 + (t * per < nq ? t * per : nq);
+  const uint32_t qb = q0 + ((t + 1) * per < nq ? (t + 1) * per : nq);
+  const uint4* h4 = reinterpret_cast<const uint4*>(hist);
+  auto used = [&](uint32_t sym, uint32_t c) { return c != 0 && sym >= b0 && sym < b1; };
+  uint32_t c = 0;
+  for (uint32_t q = qa; q < qb; q += kCbScanBatch) {
+    uint4 v[kCbScanBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kCbScanBatch; j++) v[j] = q + j < qb ? h4[q + j] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (uint32_t j = 0; j < kCbScanBatch; j++) {
+      const uint32_t s0 = 4 * (q + j);
+      c += used(s0, v[j].x) + used(s0 + 1, v[j].y) + used(s0 + 2, v[j].z) + used(s0 + 3, v[j].w);
+    }
+  }
+  uint32_t K;
+  uint32_t pos = block_excl_scan_u32(c, sh16, &K) + extra0;
+  K += extra0;
+  if (K == 0) {
+    if (t == 0) {
+      m->nsym_used = 0;
+      m->max_len = 0;
+    }
+    return;
+  }
+  if (K > kCbLdsCap) {
+    codebook_global(hist, nsym, s, enc_code, enc_len, symtab, m, u.cnt, sh16);
+    return;
+  }
+  // leaves in symbol order, at the scanned offsets
+  CbLds& L = u.lds;
+  if (t == 0 && extra0) {
+    L.key[0] = (uint64_t)hist[0] << 32;
+    L.sym_of[0] = 0;
+  }
+  for (uint32_t q = qa; c && q < qb; q += kCbScanBatch) {
+    uint4 v[kCbScanBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kCbScanBatch; j++) v[j] = q + j < qb ? h4[q + j] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (uint32_t j = 0; j < kCbScanBatch; j++) {
+      const uint32_t e[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+      for (int h = 0; h < 4; h++) {
+        const uint32_t sym = 4 * (q + j) + h;
+        if (used(sym, e[h])) {
+          L.key[pos] = ((uint64_t)e[h] << 32) | pos;
+          L.sym_of[pos] = (uint16_t)sym;
+          pos++;
+        }
+      }
+    }
+  }
+  lds_barrier();
+  if (K > 1) rank_leaves(K, L);
+  if (t < 64) codebook_wave(K, enc_code, enc_len, symtab, m, L);
 }
 
 hipError_t launch_codebook(const uint32_t* hist, uint32_t nsym, CodebookScratch s,

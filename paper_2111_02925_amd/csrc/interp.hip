@@ -48,7 +48,7 @@ __global__ void k_meta_init(Meta* m) {
   m->total_words = 0;
   m->stream_bytes = 0;
   m->status = 0;
-  m->pad = 0;
+  m->hist_far = 0;
 }
 
 hipError_t launch_meta_init(Meta* m, hipStream_t st) {

@@ -34,6 +34,7 @@
 // Flat indices fit in 32 bits (fields have fewer than 2^32 points).
 #include <type_traits>
 
+#include "block_ops.h"
 #include "common.h"
 #include "device_math.h"
 
@@ -45,13 +46,6 @@ constexpr int kLevelWaves = kLevelThreads / 64;
 constexpr int kBoxUnits = 12;   // box (row, 64-column chunk) units per wave: 48 per plane
 constexpr int kGridUnits = 6;   // coarse-grid units per wave: 24 per plane
 
-// Workgroup barrier that orders LDS accesses only: global loads in flight
-// (the next plane's inputs) stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // A box slot holds an input before its point is computed: the field value,
 // or the quantization code as an integer in the slot's bits.

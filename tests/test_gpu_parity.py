@@ -75,6 +75,11 @@ CASES = [
     ("1d-long", lambda: np.cumsum(np.random.default_rng(5).standard_normal(100003)).astype(np.float32), "rel", 1e-3, 1, 32768, 65536, None),
     ("4d", lambda: synth.random_field((9, 12, 7, 10), seed=6), "rel", 1e-3, 1, 32768, 512, (3, 1, 0, 2)),
     ("tiny-radius", lambda: synth.random_field((40, 40), seed=7), "rel", 1e-3, 0, 4, 64, None),
+    # wide code histograms: thousands of coded symbols (the codebook's global
+    # path), codes far from the radius (the histogram's far path), and many
+    # unpredictable values
+    ("wide-hist-1e-6", lambda: synth.random_field((64, 64, 32), seed=17), "rel", 1e-6, 1, 32768, 4096, None),
+    ("wide-hist-1e-5", lambda: lognormal((64, 64, 64), 3), "rel", 1e-5, 1, 32768, 4096, None),
 ]
 
 
