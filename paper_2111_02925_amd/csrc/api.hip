@@ -343,6 +343,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->cb.phase_end, sizeof(uint32_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.leaf_sym, sizeof(uint16_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lut, sizeof(uint32_t) << kLutBits), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.lc, sizeof(LongCodes)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.first, sizeof(uint64_t) * (kMaxCodeLen + 2)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.count, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.offset, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
@@ -357,7 +358,8 @@ int ensure_fixed(sz_ctx* ctx) {
 int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
   uint64_t nch = s.nchunks();
   if (need_rec) CHECK_HIP(ensure(ctx->rec, s.n * s.tsize()), "hipMalloc(rec)");
-  CHECK_HIP(ensure(ctx->codes, s.n * 2), "hipMalloc(codes)");
+  // whole 8-code vectors: the encoder reads the last one unmasked
+  CHECK_HIP(ensure(ctx->codes, ((s.n + 7) & ~7ull) * 2), "hipMalloc(codes)");
   CHECK_HIP(ensure(ctx->chunk_words, nch * 4), "hipMalloc");
   CHECK_HIP(ensure(ctx->chunk_unpred, nch * 4), "hipMalloc");
   CHECK_HIP(ensure(ctx->word_off, nch * 8), "hipMalloc");
@@ -395,7 +397,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
 
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
-                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut,
+                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lc,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
   for (void* p : fixed)
     if (p) (void)hipFree(p);

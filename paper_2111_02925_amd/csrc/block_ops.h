@@ -26,6 +26,20 @@ __device__ inline uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
   }
   return v;
 }
+// Inclusive scan over the 64 lanes with DPP lane moves (no LDS traffic):
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of
+// row 0 (and of row 2) added to row 1 (and row 3), then the last lane of
+// row 1 added to rows 2 and 3.  Lanes without a source add 0.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
+  return v;
+}
+
 __device__ inline uint64_t wave_incl_scan_u64(uint64_t v, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {

@@ -197,7 +197,29 @@ hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* 
                                uint64_t nchunks, uint32_t sub, const uint8_t* header_template,
                                int dtype, Meta* m, hipStream_t st);
 
+// Codes longer than the lookup table: with canonical codes the left-justified
+// end of each length's code range grows with the length, and comparing the
+// window against the end of length k only involves its first k bits, so the
+// code length is kLutBits + 1 plus the number of ends the window reaches.
+// Lengths up to 32 are resolved from a 32-bit window with ends held in
+// registers; longer ones (only possible for extremely skewed histograms) take
+// an exact path that re-reads the stream.
+constexpr int kWinLens = 32 - kLutBits;  // lengths resolved from the window
+constexpr uint32_t kLongSymCap = 4096;   // long-code symbols a decoder block keeps in LDS
+struct LongCodes {
+  uint64_t end_lj[kMaxCodeLen + 1];  // left-justified end of length-l codes
+  uint64_t base[kMaxCodeLen + 1];    // offset[l] - first[l] (mod 2^64)
+  uint32_t lim[kWinLens];            // window limits of lengths l0, l0 + 1, ...
+  uint32_t l0;                       // shortest long length whose 32-bit end is not 0
+  uint32_t base32[34];               // offset[l] - first[l] - long_first (mod 2^32)
+  uint32_t max_len;
+  uint32_t long_first;               // sorted index of the first long code
+  uint32_t long_in_lds;
+  uint32_t pad;
+};
+
 struct DecodeTables {
+  LongCodes* lc;         // derived by the table kernel for the chunk decoder
   uint32_t* lut;         // 1 << kLutBits entries: sym | len << 16 (len 0 = longer code)
   uint64_t* first;       // kMaxCodeLen + 1
   uint32_t* count;       // kMaxCodeLen + 1

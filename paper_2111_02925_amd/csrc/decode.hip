@@ -104,6 +104,53 @@ __device__ bool check_lengths(const uint32_t* bl, uint32_t K) {
   return carry == 1;
 }
 
+// The chunk decoder's view of the codes longer than the lookup table, from
+// the per-length counts, first codes and offsets (a thread per length).
+__device__ __forceinline__ void long_codes(uint32_t K, const uint32_t* bl, const uint64_t* first,
+                                           const uint32_t* off, LongCodes* lc) {
+  __shared__ uint32_t maxl, l0;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) {
+    maxl = 0;
+    l0 = 33;
+  }
+  __syncthreads();
+  if (t >= 1 && t <= (uint32_t)kMaxCodeLen && bl[t]) atomicMax(&maxl, t);
+  __syncthreads();
+  const uint32_t ml = maxl;
+  const uint32_t lf = (uint32_t)kLutBits < ml ? off[kLutBits + 1] : K;
+  // A window of a long code reaches the end of length l when win >= end32(l),
+  // end32(l) = (first[l] + count[l]) << (32 - l) in [0, 2^32], nondecreasing
+  // in l.  Ends that are 0 (no code of length <= l) are always reached and
+  // are folded into l0; the rest compare as win > end32 - 1 in 32 bits, and
+  // the ends past length 32 are never reached (limit 2^32 - 1), so the
+  // count gives 33 exactly for codes longer than 32 bits.
+  if (t > (uint32_t)kLutBits && t <= 32 && (t >= ml || first[t] + bl[t] != 0)) atomicMin(&l0, t);
+  if (t >= 1 && t <= (uint32_t)kMaxCodeLen) {
+    lc->base[t] = (uint64_t)off[t] - first[t];
+    lc->end_lj[t] = t < (uint32_t)kMaxCodeLen ? (first[t] + bl[t]) << (64 - t) : ~0ull;
+  }
+  if (t <= 33)
+    lc->base32[t] = t > (uint32_t)kLutBits && t <= 32 ? off[t] - (uint32_t)first[t] - lf : 0u;
+  if (t == 0) {
+    lc->end_lj[0] = 0;
+    lc->base[0] = 0;
+    lc->max_len = ml;
+    lc->long_first = lf;
+    lc->long_in_lds = K - lf <= kLongSymCap;
+    lc->pad = 0;
+  }
+  __syncthreads();
+  const uint32_t L0 = l0 < 33 ? l0 : 33;
+  if (t == 0) lc->l0 = L0;
+  if (t < (uint32_t)kWinLens) {
+    const uint32_t l = L0 + t;
+    uint64_t e = 1ull << 32;
+    if (l <= 32 && l < ml) e = (first[l] + bl[l]) << (32 - l);
+    lc->lim[t] = (uint32_t)(e - 1);
+  }
+}
+
 __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
                                                               uint64_t off_sym, uint32_t K,
                                                               uint32_t nsym, DecodeTables d,
@@ -162,6 +209,7 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   for (uint32_t i = t; i < (1u << kLutBits); i += T) d.lut[i] = 0;
   __syncthreads();
   if (bad || K == 0) return;
+  long_codes(K, bl, firsts, offs, d.lc);
   if (!in_lds) {
     __syncthreads();  // the lookup table is cleared before it is filled
     uint64_t* bylen = block_radix_sort(d.keys_a, d.keys_b, K, 16, 24, u.cnt, sh16);
@@ -283,27 +331,7 @@ hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uin
 // chunk's own words never decide a code of a well-formed chunk, and a run
 // that ends anywhere but where the next one starts (or, for the last run,
 // inside the chunk's last word) is detected once, from the bits consumed.
-constexpr uint32_t kLongSymCap = 4096;        // long-code symbols kept in LDS
 constexpr uint32_t kGroup = 32;               // codes staged in LDS per lane
-constexpr int kWinLens = 32 - kLutBits;       // lengths resolved from the window
-
-// Codes longer than the lookup table: with canonical codes the left-justified
-// end of each length's code range grows with the length, and comparing the
-// window against the end of length k only involves its first k bits, so the
-// code length is kLutBits + 1 plus the number of ends the window reaches.
-// Lengths up to 32 are resolved from the 32-bit window with ends held in
-// registers; longer ones (only possible for extremely skewed histograms) take
-// an exact path that re-reads the stream.
-struct LongCodes {
-  uint64_t end_lj[kMaxCodeLen + 1];  // left-justified end of length-l codes
-  uint64_t base[kMaxCodeLen + 1];    // offset[l] - first[l] (mod 2^64)
-  uint32_t lim[kWinLens];            // see k_decode_chunks: window limits from length l0
-  uint32_t l0;                       // shortest long length whose 32-bit end is not 0
-  uint32_t base32[34];               // offset[l] - first[l] - long_first (mod 2^32)
-  uint32_t max_len;
-  uint32_t long_first;               // sorted index of the first long code
-  uint32_t long_in_lds;
-};
 
 struct RunResult {
   uint64_t used;   // bit offset, from the chunk's first bit, where the run ended
@@ -423,40 +451,33 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
     uint64_t nchunks, uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_unpred, const uint64_t* __restrict__ word_off,
     const uint64_t* __restrict__ unpred_off, DecodeTables d, uint16_t* codes, T* out, Meta* m) {
-  __shared__ uint32_t lut[1u << kLutBits];
+  __shared__ __align__(16) uint32_t lut[1u << kLutBits];
   __shared__ LongCodes lc;
   __shared__ uint16_t long_sym[kLongSymCap];
   __shared__ uint16_t stage_all[NT * kGroup];
   uint16_t* stage = stage_all + threadIdx.x;
-  for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += blockDim.x) lut[i] = d.lut[i];
-  if (threadIdx.x == 0) {
-    uint32_t maxl = 0;
-    for (uint32_t l = 1; l <= (uint32_t)kMaxCodeLen; l++) {
-      if (d.count[l]) maxl = l;
-      lc.base[l] = (uint64_t)d.offset[l] - d.first[l];
-      lc.end_lj[l] = l < (uint32_t)kMaxCodeLen ? (d.first[l] + d.count[l]) << (64 - l) : ~0ull;
+  {
+    // lookup table and long-code tables: independent loads, all in flight at once
+    constexpr uint32_t kLutVecs = (1u << kLutBits) / 4 / NT;
+    const uint4* src = reinterpret_cast<const uint4*>(d.lut);
+    uint4 v[kLutVecs];
+#pragma unroll
+    for (uint32_t j = 0; j < kLutVecs; j++) v[j] = src[threadIdx.x + j * NT];
+    constexpr uint32_t kLcWords = sizeof(LongCodes) / 4;
+    static_assert(sizeof(LongCodes) % 4 == 0, "LongCodes is copied as words");
+    uint32_t lw[(kLcWords + NT - 1) / NT];
+#pragma unroll
+    for (uint32_t j = 0; j < (kLcWords + NT - 1) / NT; j++) {
+      const uint32_t i = threadIdx.x + j * NT;
+      lw[j] = i < kLcWords ? reinterpret_cast<const uint32_t*>(d.lc)[i] : 0u;
     }
-    const uint32_t lf = kLutBits < maxl ? d.offset[kLutBits + 1] : nsym_used;
-    // A window of a long code reaches the end of length l when win >= end32(l),
-    // end32(l) = (first[l] + count[l]) << (32 - l) in [0, 2^32], nondecreasing
-    // in l.  Ends that are 0 (no code of length <= l) are always reached and
-    // are folded into l0; the rest compare as win > end32 - 1 in 32 bits, and
-    // the ends past length 32 are never reached (limit 2^32 - 1), so the
-    // count gives 33 exactly for codes longer than 32 bits.
-    uint32_t l0 = kLutBits + 1;
-    while (l0 <= 32 && l0 < maxl && d.first[l0] + d.count[l0] == 0) l0++;
-    for (int q = 0; q < kWinLens; q++) {
-      const uint32_t l = l0 + q;
-      uint64_t e = 1ull << 32;
-      if (l <= 32 && l < maxl) e = (d.first[l] + d.count[l]) << (32 - l);
-      lc.lim[q] = (uint32_t)(e - 1);
+#pragma unroll
+    for (uint32_t j = 0; j < kLutVecs; j++) reinterpret_cast<uint4*>(lut)[threadIdx.x + j * NT] = v[j];
+#pragma unroll
+    for (uint32_t j = 0; j < (kLcWords + NT - 1) / NT; j++) {
+      const uint32_t i = threadIdx.x + j * NT;
+      if (i < kLcWords) reinterpret_cast<uint32_t*>(&lc)[i] = lw[j];
     }
-    lc.l0 = l0;
-    for (uint32_t l = 0; l <= 33; l++)
-      lc.base32[l] = l > (uint32_t)kLutBits && l <= 32 ? d.offset[l] - (uint32_t)d.first[l] - lf : 0u;
-    lc.max_len = maxl;
-    lc.long_first = lf;
-    lc.long_in_lds = nsym_used - lf <= kLongSymCap;
   }
   __syncthreads();
   if (lc.long_in_lds)

@@ -39,6 +39,7 @@ struct EncTables {
 
 struct EncWindow {
   uint32_t lo;       // first symbol of the window
+  uint32_t span;     // window entries to load: the coded symbols' range when lds_only
   bool lds_only;     // every coded symbol other than 0 is in the window, codes <= 32 bits
   uint64_t code0;    // codeword of symbol 0
   uint32_t len0;
@@ -52,6 +53,7 @@ __device__ __forceinline__ EncWindow enc_window(const Meta* m, uint32_t R,
   const bool none = slo == 0xFFFFFFFFu;
   w.lds_only = (none || shi - slo < kEncWindow) && m->max_len <= 32;
   w.lo = w.lds_only ? (none ? 0u : slo) : (R > kEncWindow / 2 ? R - kEncWindow / 2 : 0u);
+  w.span = w.lds_only ? (none ? 0u : shi - slo + 1) : kEncWindow;
   w.code0 = enc_code[0];
   w.len0 = enc_len[0];
   return w;
@@ -60,7 +62,7 @@ __device__ __forceinline__ EncWindow enc_window(const Meta* m, uint32_t R,
 __device__ __forceinline__ void load_tables(EncTables& t, const EncWindow& w, uint32_t nsym,
                                             const uint64_t* __restrict__ enc_code,
                                             const uint8_t* __restrict__ enc_len, bool codes) {
-  for (uint32_t i = threadIdx.x; i < kEncWindow; i += blockDim.x) {
+  for (uint32_t i = threadIdx.x; i < w.span; i += blockDim.x) {
     const uint32_t s = w.lo + i;
     const uint32_t len = s < nsym ? enc_len[s] : 0u;
     t.len[i] = (uint8_t)(len <= 32 ? len : 0u);
@@ -139,6 +141,227 @@ __device__ __forceinline__ LaneRun lane_run(uint64_t c, uint32_t chunk, uint64_t
   return r;
 }
 
+// ------------------------------------------------------ lane-parallel path
+// When every code is at most 32 bits and the coded symbols fit kFastWindow
+// LDS entries, a wave takes a chunk kStep symbols at a time, 8 consecutive
+// symbols per lane: the lanes' bit counts are scanned across the wave, and
+// a lane's codewords (joined in a 64-bit register when they total at most 64
+// bits, three buffer words at most; one by one otherwise) are ORed into a
+// per-wave LDS bit buffer at their offset, so no step depends on a branch per
+// symbol.  The buffer is stored when the chunk ends (consecutive lanes,
+// consecutive words), or earlier when another step might not fit, then its
+// partial last word moves to the front.  Stores inside the step loop would
+// make every prefetch of the next step's codes wait for them to complete.
+
+constexpr uint32_t kStep = 512;                // symbols per wave step, 8 per lane
+constexpr uint32_t kBufWords = 1024;           // bit buffer words per wave
+constexpr uint32_t kBufAlloc = kBufWords + 3;  // plus the words a last step may touch
+constexpr uint32_t kFastWindow = 3064;         // LDS codebook entries of the lane-parallel path
+
+struct FastLds {
+  // code | len << 32 by symbol - lo; the last entry is symbol 0's, with bit 40
+  // set so that summing entries >> 40 counts unpredictable values
+  uint64_t ent[kFastWindow + 1];
+  uint32_t buf[kEncWaves][kBufAlloc];
+};
+union EncLds {
+  EncTables t;
+  FastLds f;
+};
+
+__device__ __forceinline__ bool fast_path(const EncWindow& w) {
+  return w.lds_only && w.span <= kFastWindow;
+}
+
+__device__ __forceinline__ void load_fast(FastLds& f, const EncWindow& w,
+                                          const uint64_t* __restrict__ enc_code,
+                                          const uint8_t* __restrict__ enc_len) {
+  for (uint32_t i = threadIdx.x; i < w.span; i += blockDim.x)
+    f.ent[i] = ((uint64_t)enc_len[w.lo + i] << 32) | (uint32_t)enc_code[w.lo + i];
+  if (threadIdx.x == 0)
+    f.ent[kFastWindow] = (1ull << 40) | ((uint64_t)w.len0 << 32) | (uint32_t)w.code0;
+  for (uint32_t i = threadIdx.x; i < kEncWaves * kBufAlloc; i += blockDim.x)
+    (&f.buf[0][0])[i] = 0;
+}
+
+// The 8 symbols [i0, i0 + 8) of a lane, packed two per word: one load,
+// always taken (a load taken on a branch would be waited for where the
+// branches join), from the last whole vector when i0 is past it.  The code
+// buffer holds whole vectors; symbols past the field are ignored by the
+// callers, which count only the first nv.
+__device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ codes, uint64_t i0,
+                                       uint64_t last8) {
+  return *reinterpret_cast<const uint4*>(codes + (i0 < last8 ? i0 : last8));
+}
+
+// Table entries of the 8 symbols; symbols at or past nv get an empty entry.
+struct Sym8 {
+  uint32_t code[8], len[8], zeros, zmask;  // zmask bit j: symbol j is 0
+};
+__device__ __forceinline__ Sym8 lookup8(const FastLds& f, uint32_t lo, uint4 v, uint32_t nv) {
+  Sym8 r;
+  r.zeros = 0;
+  r.zmask = 0;
+  const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const uint32_t s = (wd[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+    // (clamped: symbols past the field's end may be anything)
+    const uint32_t k = s - lo < kFastWindow ? s - lo : kFastWindow;
+    uint64_t e = f.ent[s ? k : kFastWindow];
+    e = (uint32_t)j < nv ? e : 0ull;
+    r.code[j] = (uint32_t)e;
+    r.len[j] = (uint32_t)(e >> 32) & 0xFFu;
+    r.zeros += (uint32_t)(e >> 40);
+    r.zmask |= (uint32_t)(e >> 40) << j;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void wave_step() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ void size_fast(const uint16_t* __restrict__ codes, uint64_t n,
+                                          uint32_t chunk, uint64_t nchunks, const FastLds& f,
+                                          uint32_t lo, uint32_t* chunk_words,
+                                          uint32_t* chunk_zeros) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  const uint64_t last8 = (n - 1) & ~7ull;
+  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+       c += wstride) {
+    const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
+    const uint32_t clen = (uint32_t)(cend - cbeg);
+    uint32_t bits = 0, zeros = 0;
+    uint4 nxt = load8(codes, cbeg + 8 * lane, last8);
+    for (uint64_t g = cbeg; g < cend; g += kStep) {
+      const uint4 cur = nxt;
+      const uint64_t i0 = g + 8 * lane;
+      nxt = load8(codes, i0 + kStep, last8);
+      const uint32_t off = (uint32_t)(i0 - cbeg);
+      const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
+      const Sym8 r = lookup8(f, lo, cur, nv);
+#pragma unroll
+      for (int j = 0; j < 8; j++) bits += r.len[j];
+      zeros += r.zeros;
+    }
+    bits = wave_sum_u32(bits);
+    zeros = wave_sum_u32(zeros);
+    if (lane == 0) {
+      chunk_words[c] = (bits + 31) / 32;
+      chunk_zeros[c] = zeros;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pack_fast(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint32_t sub, uint64_t nchunks, FastLds& f, uint32_t lo,
+    const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
+    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
+    const Layout& l, uint8_t* out, uint64_t cap) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t* buf = f.buf[threadIdx.x >> 6];
+  const uint32_t span = chunk / sub;
+  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  const uint64_t last8 = (n - 1) & ~7ull;
+  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+       c += wstride) {
+    const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
+    const uint32_t clen = (uint32_t)(cend - cbeg);
+    const uint64_t wbyte = l.off_bits + 4 * word_off[c];
+    uint64_t zr = zero_off[c];
+    if (lane == 0) {
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c, chunk_words[c]);
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, chunk_zeros[c]);
+    }
+    uint32_t have = 0, done = 0, written = 0;  // bits in buf, chunk bits so far, words stored
+    uint32_t next_sub = span, k_sub = 1;         // start of the next sub-chunk, its number
+    uint4 nxt = load8(codes, cbeg + 8 * lane, last8);
+    for (uint64_t g = cbeg; g < cend; g += kStep) {
+      const uint4 cur = nxt;
+      const uint64_t i0 = g + 8 * lane;
+      nxt = load8(codes, i0 + kStep, last8);
+      const uint32_t off = (uint32_t)(i0 - cbeg);
+      const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
+      const Sym8 r = lookup8(f, lo, cur, nv);
+      uint32_t pre[8], t = 0;
+      uint64_t acc = 0;  // the lane's bits, right-aligned (exact while t <= 64)
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        pre[j] = t;
+        t += r.len[j];
+        acc = (acc << r.len[j]) | r.code[j];
+      }
+      const uint32_t z = r.zeros;
+      const uint32_t mine = t | (z << 16);  // t <= 256, z <= 8
+      const uint32_t incl = wave_incl_scan_dpp(mine);
+      const uint32_t tot = __builtin_amdgcn_readlane(incl, 63), excl = incl - mine;
+      const uint32_t e = excl & 0xFFFFu;
+      // sub-chunks starting in this step (their starts are multiples of 8)
+      const uint32_t step0 = (uint32_t)(g - cbeg);
+      while (k_sub < sub && next_sub < clen && next_sub < step0 + kStep) {
+        if (off == next_sub)
+          guarded_store_u32(out, cap, l.off_sub + 4 * (c * (sub - 1) + k_sub - 1), done + e);
+        next_sub += span;
+        k_sub++;
+      }
+      const uint32_t o = have + e;
+      if (t <= 64) {
+        acc = t ? acc << (64 - t) : 0ull;  // left-aligned
+        const uint32_t sh = o & 31, wd = o >> 5;
+        atomicOr(&buf[wd], (uint32_t)(acc >> (32 + sh)));
+        atomicOr(&buf[wd + 1], (uint32_t)(acc >> sh));
+        atomicOr(&buf[wd + 2], (uint32_t)(acc << (32 - sh)));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const uint32_t pos = o + pre[j], sh = pos & 31;
+          const uint64_t v = r.len[j] ? (uint64_t)r.code[j] << (64 - r.len[j] - sh) : 0ull;
+          atomicOr(&buf[pos >> 5], (uint32_t)(v >> 32));
+          atomicOr(&buf[(pos >> 5) + 1], (uint32_t)v);
+        }
+      }
+      if (z) {  // unpredictable values, verbatim, flat order
+        uint64_t rk = zr + (excl >> 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+          if ((r.zmask >> j) & 1u) {
+            const uint64_t off = l.off_unpred + rk * sizeof(T);
+            if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[i0 + j];
+            rk++;
+          }
+      }
+      have += tot & 0xFFFFu;
+      done += tot & 0xFFFFu;
+      zr += tot >> 16;
+      if (have > (kBufWords - kStep - 1) * 32) {  // the next step might not fit: store
+        wave_step();
+        const uint32_t full = have >> 5;
+        for (uint32_t k = lane; k < full; k += 64)
+          guarded_store_u32(out, cap, wbyte + 4 * (uint64_t)(written + k), buf[k]);
+        const uint32_t last = buf[full];
+        wave_step();
+        for (uint32_t k = lane; k <= full + 2; k += 64) buf[k] = k == 0 ? last : 0u;
+        wave_step();
+        written += full;
+        have &= 31;
+      }
+    }
+    wave_step();
+    const uint32_t nw = (have + 31) >> 5;
+    for (uint32_t k = lane; k < nw; k += 64)
+      guarded_store_u32(out, cap, wbyte + 4 * (uint64_t)(written + k), buf[k]);
+    wave_step();
+    for (uint32_t k = lane; k < nw + 2; k += 64) buf[k] = 0u;
+    wave_step();
+    // sub-chunks that start at or past the chunk's last symbol start at its end
+    for (uint32_t k = lane + 1; k < sub; k += 64)
+      if ((uint64_t)k * span >= clen)
+        guarded_store_u32(out, cap, l.off_sub + 4 * (c * (sub - 1) + k - 1), done);
+  }
+}
+
 // ------------------------------------------------------------- chunk sizes
 
 template <bool LDS_ONLY>
@@ -182,8 +405,15 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
     const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks, uint32_t R,
     uint32_t nsym, const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
     uint32_t* chunk_words, uint32_t* chunk_zeros, const Meta* __restrict__ m) {
-  __shared__ EncTables t;
+  __shared__ EncLds u;
+  EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
+  if (fast_path(w)) {
+    load_fast(u.f, w, enc_code, enc_len);
+    __syncthreads();
+    size_fast(codes, n, chunk, nchunks, u.f, w.lo, chunk_words, chunk_zeros);
+    return;
+  }
   load_tables(t, w, nsym, enc_code, enc_len, !w.lds_only);
   __syncthreads();
   if (w.lds_only)
@@ -316,12 +546,20 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
     const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
     const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
     const Meta* __restrict__ m) {
-  __shared__ EncTables t;
+  __shared__ EncLds u;
+  EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
-  load_tables(t, w, nsym, enc_code, enc_len, true);
-  __syncthreads();
   const Layout l =
       stream_layout(m->nsym_used, nchunks, sub, m->n_unpred, sizeof(T), m->total_words);
+  if (fast_path(w)) {
+    load_fast(u.f, w, enc_code, enc_len);
+    __syncthreads();
+    pack_fast<T>(codes, x, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros, word_off,
+                 zero_off, l, out, cap);
+    return;
+  }
+  load_tables(t, w, nsym, enc_code, enc_len, true);
+  __syncthreads();
   if (w.lds_only)
     pack_chunks<T, true>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
                          chunk_zeros, word_off, zero_off, l, out, cap);
