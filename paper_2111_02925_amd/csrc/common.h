@@ -141,6 +141,7 @@ struct LevelGeom {
   uint32_t box_bytes; // LDS bytes: box | ring of 4 coarse grids | codes of the box
   uint32_t ring_bytes;
   uint32_t lds;
+  uint32_t pitch64;   // box rows 64 slots apart, coarse-grid rows 32 (boxes of <= 64 columns)
 };
 struct LevelTuning {
   uint32_t target_points;  // minimum number of work items (planes per item shrink to reach it)

@@ -373,6 +373,260 @@ __global__ __launch_bounds__(kLevelThreads) void k_level(const T* __restrict__ x
   }
 }
 
+
+// ------------------------------------------------- boxes of up to 64 columns
+// The same schedule with a fixed geometry: box rows are 64 slots apart and
+// coarse-grid rows 32, lane l of a wave owns box column l when rows are
+// loaded, filled or stored, and wave w owns rows w, w + 4, ...  A pass maps
+// the workgroup's threads onto (row, column) once; every further row is a
+// fixed slot increment, and the stencil reaches its neighbours through
+// constant offsets.  Lanes past the pass's extents compute a clamped
+// duplicate and write it to the spare slot.
+constexpr uint32_t kPitch = 64;
+constexpr uint32_t kRingPitch = 32;
+constexpr uint32_t kRowsPerWave = 10;                    // boxes of up to 40 rows
+constexpr uint32_t kGridRowsPerWave = (kRowsPerWave + 1) / 2;
+constexpr uint32_t kMaxBoxRows64 = kRowsPerWave * kLevelWaves;
+
+template <typename T>
+struct RowIn {
+  T val[kRowsPerWave];         // compression: the field's values over the box
+  uint32_t raw[kRowsPerWave];  // codes: all (reconstruction), of coarse rows (compression)
+  T grid[kGridRowsPerWave];    // rows (b even) of an even plane, for the ring
+};
+
+template <typename T, int PRED, bool RECON>
+__global__ __launch_bounds__(kLevelThreads) void k_level64(const T* __restrict__ x, T* v,
+                                                           uint16_t* codes, LevelGeom g,
+                                                           const Meta* __restrict__ m, T twoeb,
+                                                           uint32_t R, uint32_t flags) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* box = reinterpret_cast<T*>(smem_raw);
+  T* ring = reinterpret_cast<T*>(smem_raw + g.box_bytes);
+  uint16_t* lcode = reinterpret_cast<uint16_t*>(smem_raw + g.box_bytes + g.ring_bytes);
+  const Item I = item_of(g, blockIdx.x);
+  const uint32_t ring_slot = g.ring_b * kRingPitch;  // entries per coarse grid
+  const uint32_t fa = (uint32_t)g.fs[0], fb = (uint32_t)g.fs[1], fc = (uint32_t)g.fs[2];
+  const uint32_t ea = g.ext[0];
+  const bool store_v = (flags & kLevelStoreValues) != 0;
+  QuantParams<T> q;
+  if (RECON) {
+    q.eb = T(0);
+    q.twoeb = twoeb;
+    q.inv2eb = T(0);
+    q.R = R;
+  } else {
+    q = QuantParams<T>::from_meta(m, R);
+  }
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t nB = I.Be - I.Bo, nC = I.Ce - I.Co;
+  const uint32_t nBq = I.Be > I.Bq ? (I.Be - I.Bq + 1) / 2 : 0u;  // even b rows of the box
+  const uint32_t dummy = g.box_b * kPitch;                         // spare slot
+  // this lane's box column (clamped to the box) for row-wise work
+  const uint32_t lc = min(lane, nC - 1), qc_l = I.Co + lc;
+  const uint32_t colf = qc_l * fc;
+  const bool col_in = lane < nC, qc_even = (qc_l & 1u) == 0;
+  const uint32_t ring_col = (qc_l - I.Cq) >> 1;
+  auto grid_base = [&](uint32_t e) { return ((e >> 1) & 3u) * ring_slot; };
+
+  // ---- an even plane's coarse rows (b even) into the ring.  Loads are not
+  // branched around (a register loaded on one path only would be waited for
+  // where the paths join): rows past the last repeat it.
+  auto issue_grid = [&](uint32_t e, RowIn<T>& in) {
+    if (nBq == 0) return;
+#pragma unroll
+    for (uint32_t k = 0; k < kGridRowsPerWave; k++) {
+      const uint32_t j = min(wave + kLevelWaves * k, nBq - 1);
+      in.grid[k] = v[e * fa + (I.Bq + 2 * j) * fb + colf];
+    }
+  };
+  auto deposit_grid = [&](uint32_t e, const RowIn<T>& in) {
+#pragma unroll
+    for (uint32_t k = 0; k < kGridRowsPerWave; k++) {
+      const uint32_t j = wave + kLevelWaves * k;
+      if (j < nBq && col_in && qc_even) ring[grid_base(e) + j * kRingPitch + ring_col] = in.grid[k];
+    }
+  };
+  // ---- plane p's inputs over the box (and the ring's next grid)
+  auto issue = [&](uint32_t p, RowIn<T>& in) {
+    const bool even_p = (p & 1u) == 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; k++) {
+      const uint32_t qb = I.Bo + min(wave + kLevelWaves * k, nB - 1);
+      const uint32_t f = p * fa + qb * fb + colf;
+      if (RECON) {
+        in.raw[k] = codes[f];
+      } else {
+        in.val[k] = x[f];
+        // codes of the tile's coarse points, stored back with the tile's rows
+        // (a condition on the row: the same for the whole wave)
+        if (even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1) in.raw[k] = codes[f];
+      }
+    }
+    if (!even_p && p + 3 < ea) issue_grid(p + 3, in);
+  };
+  auto deposit = [&](uint32_t p, const RowIn<T>& in) {
+    const bool even_p = (p & 1u) == 0;
+    if (!even_p && p + 3 < ea) deposit_grid(p + 3, in);
+    const uint32_t gb = grid_base(p);
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; k++) {
+      const uint32_t r = wave + kLevelWaves * k, qb = I.Bo + r;
+      if (r < nB) {
+        const uint32_t slot = r * kPitch + lane;  // columns past the box are never read
+        // coarse points of an even plane come from the ring (deposited at
+        // least one plane earlier); other lanes read ring word 0
+        const bool coarse = even_p && ((qb | qc_l) & 1u) == 0;
+        const T rv = ring[coarse ? gb + ((qb - I.Bq) >> 1) * kRingPitch + ring_col : 0u];
+        box[slot] = coarse ? rv : (RECON ? code_bits(in.raw[k], T(0)) : in.val[k]);
+        if (!RECON && even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1)
+          lcode[slot] = (uint16_t)in.raw[k];  // other slots are overwritten when computed
+      }
+    }
+    // every input register is taken here, on every path (see PlaneIn)
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; k++) {
+      asm volatile("" ::"v"(in.val[k]));
+      asm volatile("" ::"v"(in.raw[k]));
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kGridRowsPerWave; k++) asm volatile("" ::"v"(in.grid[k]));
+  };
+
+  // ---- a pass over rows qb = b_first + b_step * r (r < nrow) and columns
+  // qc = c_first + c_step * j (j < ncol <= 32)
+  auto run_pass = [&](auto interior_tag, auto pass_tag, uint32_t p, uint32_t b_first,
+                      uint32_t b_step, uint32_t nrow, uint32_t c_first, uint32_t c_step,
+                      uint32_t ncol) {
+    constexpr bool IN = decltype(interior_tag)::value;
+    constexpr int PASS = decltype(pass_tag)::value;  // 0: along a, 1: along b, 2: along c
+    if (nrow == 0 || ncol == 0) return;
+    const uint32_t lg = ncol <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(ncol - 1);
+    const uint32_t rows_per_it = kLevelThreads >> lg;
+    const uint32_t jc0 = tid & ((1u << lg) - 1), jc = min(jc0, ncol - 1), jr = tid >> lg;
+    const bool col_ok = jc0 < ncol;
+    const uint32_t qc = c_first + c_step * jc;
+    const uint32_t row0 = b_first - I.Bo;  // box row of r = 0
+    uint32_t bk = (row0 + b_step * jr) * kPitch + (qc - I.Co);
+    const uint32_t bk_last = (row0 + b_step * (nrow - 1)) * kPitch + (qc - I.Co);
+    const uint32_t dbk = rows_per_it * b_step * kPitch;
+    // pass along a: the coarse grids of planes p - 3, p - 1, p + 1, p + 3
+    // (ring slots of planes outside the field hold other planes: unused)
+    uint32_t rk = 0, rk_last = 0, drk = 0, g_m3 = 0, g_m1 = 0, g_p1 = 0, g_p3 = 0;
+    if (PASS == 0) {
+      rk = ((b_first + b_step * jr - I.Bq) >> 1) * kRingPitch + ((qc - I.Cq) >> 1);
+      rk_last = ((b_first + b_step * (nrow - 1) - I.Bq) >> 1) * kRingPitch + ((qc - I.Cq) >> 1);
+      drk = rows_per_it * kRingPitch;
+      g_m3 = grid_base(p - 3);
+      g_m1 = grid_base(p - 1);
+      g_p1 = grid_base(p + 1);
+      g_p3 = grid_base(p + 3);
+    }
+    const uint32_t nit = (nrow + rows_per_it - 1) / rows_per_it;
+    for (uint32_t it = 0; it < nit; it++) {
+      const bool ok = col_ok && bk <= bk_last;
+      const uint32_t b = min(bk, bk_last);
+      const uint32_t qb = I.Bo + (b >> 6);
+      T pred;
+      // (a missing neighbour reads the point's own slot: in bounds, unused)
+      if (PASS == 0) {
+        const uint32_t rr = min(rk, rk_last);
+        auto get = [&](int o, bool) {
+          return ring[rr + (o == -3 ? g_m3 : o == -1 ? g_m1 : o == 1 ? g_p1 : g_p3)];
+        };
+        pred = predict_at<T, PRED, IN>(p, ea, get);
+      } else if (PASS == 1) {
+        auto get = [&](int o, bool okn) {
+          return box[(uint32_t)((int32_t)b + (okn ? o * (int32_t)kPitch : 0))];
+        };
+        pred = predict_at<T, PRED, IN>(qb, g.ext[1], get);
+      } else {
+        auto get = [&](int o, bool okn) { return box[(uint32_t)((int32_t)b + (okn ? o : 0))]; };
+        pred = predict_at<T, PRED, IN>(qc, g.ext[2], get);
+      }
+      uint32_t code;
+      const T val = point_step<T, RECON>(box[b], pred, q, v,
+                                         [&] { return p * fa + qb * fb + qc * fc; }, code);
+      const uint32_t wk = ok ? b : dummy;
+      box[wk] = val;
+      if (!RECON) lcode[wk] = (uint16_t)code;  // halo slots are never stored
+      bk += dbk;
+      if (PASS == 0) rk += drk;
+    }
+  };
+
+  // ---- the ring before the first plane: even planes P0-2, P0, P0+2
+  {
+    RowIn<T> pre;
+    for (int d = -2; d <= 2; d += 2) {
+      const int e = (int)I.P0 + d;
+      if (e < 0 || (uint32_t)e >= ea) continue;
+      issue_grid((uint32_t)e, pre);
+      deposit_grid((uint32_t)e, pre);
+    }
+  }
+  lds_barrier();
+
+  RowIn<T> in;
+  issue(I.P0, in);
+  const bool int_b = I.B0 >= 3 && I.B1 + 3 <= g.ext[1];
+  const bool int_c = I.C0 >= 3 && I.C1 + 3 <= g.ext[2];
+  const uint32_t tile_rows = I.B1 - I.B0, tcn = I.C1 - I.C0;
+  for (uint32_t p = I.P0; p < I.P1; p++) {
+    deposit(p, in);
+    lds_barrier();
+    if (p + 1 < I.P1) issue(p + 1, in);
+
+    // pass along a (odd planes) on the whole box: b, c even
+    if (p & 1u) {
+      const uint32_t ncol = I.Ce > I.Cq ? (I.Ce - I.Cq + 1) / 2 : 0u;
+      if (p >= 3 && p + 3 < ea)
+        run_pass(std::true_type{}, std::integral_constant<int, 0>{}, p, I.Bq, 2, nBq, I.Cq, 2, ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 0>{}, p, I.Bq, 2, nBq, I.Cq, 2, ncol);
+      lds_barrier();
+    }
+    // pass along b on the tile's rows of the box: b odd, c even
+    {
+      const uint32_t b1 = I.B0 | 1u, nb = I.B1 > b1 ? (I.B1 - b1 + 1) / 2 : 0u;
+      const uint32_t ncol = I.Ce > I.Cq ? (I.Ce - I.Cq + 1) / 2 : 0u;
+      if (int_b)
+        run_pass(std::true_type{}, std::integral_constant<int, 1>{}, p, b1, 2, nb, I.Cq, 2, ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 1>{}, p, b1, 2, nb, I.Cq, 2, ncol);
+    }
+    lds_barrier();
+    // pass along c on the tile: c odd
+    {
+      const uint32_t c1 = I.C0 | 1u, ncol = I.C1 > c1 ? (I.C1 - c1 + 1) / 2 : 0u;
+      if (int_c)
+        run_pass(std::true_type{}, std::integral_constant<int, 2>{}, p, I.B0, 1, tile_rows, c1, 2,
+                 ncol);
+      else
+        run_pass(std::false_type{}, std::integral_constant<int, 2>{}, p, I.B0, 1, tile_rows, c1,
+                 2, ncol);
+    }
+    lds_barrier();
+    // the tile's rows of this plane
+    if (lane < tcn) {
+      const uint32_t qc = I.C0 + lane, colt = qc * fc;
+      const uint32_t bk0 = (I.B0 - I.Bo) * kPitch + (qc - I.Co);
+#pragma unroll
+      for (uint32_t k = 0; k < kRowsPerWave; k++) {
+        const uint32_t r = wave + kLevelWaves * k;
+        if (r < tile_rows) {
+          const uint32_t f = p * fa + (I.B0 + r) * fb + colt;
+          const uint32_t bk = bk0 + r * kPitch;
+          if (!RECON) codes[f] = lcode[bk];
+          if (RECON || store_v) v[f] = box[bk];
+        }
+      }
+    }
+    lds_barrier();  // the box is refilled next
+  }
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -449,10 +703,13 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
     g.ring_b = (g.box_b + 1) / 2;
     g.ring_c = (g.box_c + 1) / 2;
     g.nitems = (uint64_t)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    // the box and the codes carry one spare slot (writes of padding lanes)
-    g.box_bytes = (uint32_t)(((uint64_t)(g.box_b * g.box_c + 1) * tsize + 15) / 16 * 16);
-    g.ring_bytes = (uint32_t)(((uint64_t)4 * g.ring_b * g.ring_c * tsize + 15) / 16 * 16);
-    g.lds = g.box_bytes + g.ring_bytes + (g.box_b * g.box_c + 1) * 2;
+    // boxes of up to 64 columns (and kMaxBoxRows64 rows) take the fixed-pitch
+    // kernel; the box and the codes carry one spare slot (writes of padding lanes)
+    g.pitch64 = g.ext[1] > 1 && g.box_c <= kPitch && g.box_b <= kMaxBoxRows64 ? 1u : 0u;
+    const uint32_t bc = g.pitch64 ? kPitch : g.box_c, rc = g.pitch64 ? kRingPitch : g.ring_c;
+    g.box_bytes = (uint32_t)(((uint64_t)(g.box_b * bc + 1) * tsize + 15) / 16 * 16);
+    g.ring_bytes = (uint32_t)(((uint64_t)4 * g.ring_b * rc * tsize + 15) / 16 * 16);
+    g.lds = g.box_bytes + g.ring_bytes + (g.box_b * bc + 1) * 2;
     if (g.nitems > 0x7FFFFFFFull) return false;
     out.push_back(g);
   }
@@ -467,12 +724,20 @@ static hipError_t launch_level_t(const void* x, int predictor, void* v, uint16_t
   dim3 grid((unsigned)g.nitems), block(kLevelThreads);
   const T twoeb = RECON ? (T)2 * (T)eb_t : T(0);
   const uint32_t lds = RECON ? g.box_bytes + g.ring_bytes : g.lds;
-  if (predictor == SZ_INTERP_CUBIC)
+  if (g.pitch64) {
+    if (predictor == SZ_INTERP_CUBIC)
+      hipLaunchKernelGGL((k_level64<T, SZ_INTERP_CUBIC, RECON>), grid, block, lds, st,
+                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+    else
+      hipLaunchKernelGGL((k_level64<T, SZ_INTERP_LINEAR, RECON>), grid, block, lds, st,
+                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+  } else if (predictor == SZ_INTERP_CUBIC) {
     hipLaunchKernelGGL((k_level<T, SZ_INTERP_CUBIC, RECON>), grid, block, lds, st, (const T*)x,
                        (T*)v, codes, g, m, twoeb, R, flags);
-  else
+  } else {
     hipLaunchKernelGGL((k_level<T, SZ_INTERP_LINEAR, RECON>), grid, block, lds, st, (const T*)x,
                        (T*)v, codes, g, m, twoeb, R, flags);
+  }
   return hipGetLastError();
 }
 
