@@ -56,19 +56,20 @@ template <typename T>
 __device__ __forceinline__ bool bound_holds(T x, T r, T eb) {
   const T s = x - r;
   const T as = fabs_t(s);
-  // every lane evaluates the tie test (a few operations), and the tests are
-  // combined as integers, so that the wavefront's control flow stays uniform
-  const uint32_t lt = as < eb ? 1u : 0u, eq = as == eb ? 1u : 0u;
-  const uint32_t tie = bound_tie(x, r, s) ? 1u : 0u;  // the same for every lane's path
-  return (lt | (eq & tie)) != 0u;
+  bool holds = as < eb;
+  // the tie with the bound is rare: lanes take the exact test only then
+  if (as == eb) holds = bound_tie(x, r, s);
+  return holds;
 }
 
 // Linear-scaling quantizer.  k = rint(|x - pred| / (2 eb)) (multiplied by the
 // precomputed reciprocal), signed like the error; the code is R + k when
 // |k| < R and the reconstruction pred + 2eb*k meets the bound, else 0
 // (unpredictable: the reconstruction is x itself).  eb == 0 codes only exact
-// predictions.  Written with selects rather than branches (the tie case of
-// the bound test aside), so that a wavefront does not diverge on it.
+// predictions.  The signed k is rounded directly from the signed product:
+// multiplication and round-half-even are symmetric in the sign, so this is
+// the same integer.  Written with selects rather than branches (the tie case
+// of the bound test aside), so that a wavefront does not diverge on it.
 template <typename T>
 __device__ __forceinline__ uint32_t quantize(T x, T pred, const QuantParams<T>& q, T& rec) {
   const T diff = x - pred;
@@ -77,13 +78,12 @@ __device__ __forceinline__ uint32_t quantize(T x, T pred, const QuantParams<T>& 
     rec = exact ? pred + q.twoeb * T(0) : x;
     return exact ? q.R : 0u;
   }
-  const T kf = rint_t(fabs_t(diff) * q.inv2eb);
-  const bool in_range = kf < (T)q.R;  // false for NaN
-  const int ki = (int)(in_range ? kf : T(0));
-  const int k = diff < T(0) ? -ki : ki;
+  const T kf = rint_t(diff * q.inv2eb);
+  const bool in_range = fabs_t(kf) < (T)q.R;  // false for NaN
+  const int k = (int)(in_range ? kf : T(0));
   const T r = pred + q.twoeb * (T)k;
-  const bool holds = bound_holds(x, r, q.eb);
-  const bool ok = in_range && holds;
+  const bool holds = bound_holds(x, r, q.eb);  // evaluated for every lane: no branch on in_range
+  const bool ok = in_range & holds;
   rec = ok ? r : x;
   return ok ? (uint32_t)((int)q.R + k) : 0u;
 }
