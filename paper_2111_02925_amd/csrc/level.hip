@@ -388,15 +388,15 @@ constexpr uint32_t kRowsPerWave = 10;                    // boxes of up to 40 ro
 constexpr uint32_t kGridRowsPerWave = (kRowsPerWave + 1) / 2;
 constexpr uint32_t kMaxBoxRows64 = kRowsPerWave * kLevelWaves;
 
-template <typename T>
+template <typename T, bool RECON>
 struct RowIn {
-  T val[kRowsPerWave];         // compression: the field's values over the box
-  uint32_t raw[kRowsPerWave];  // codes: all (reconstruction), of coarse rows (compression)
-  T grid[kGridRowsPerWave];    // rows (b even) of an even plane, for the ring
+  T val[RECON ? 1 : kRowsPerWave];         // compression: the field's values over the box
+  uint32_t raw[RECON ? kRowsPerWave : 1];  // reconstruction: the codes over the box
+  T grid[kGridRowsPerWave];                // rows (b even) of an even plane, for the ring
 };
 
 template <typename T, int PRED, bool RECON>
-__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_level64(const T* __restrict__ x, T* v,
+__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_level64(const T* __restrict__ x, T* v,
                                                            uint16_t* codes, LevelGeom g,
                                                            const Meta* __restrict__ m, T twoeb,
                                                            uint32_t R, uint32_t flags) {
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
   // ---- an even plane's coarse rows (b even) into the ring.  Loads are not
   // branched around (a register loaded on one path only would be waited for
   // where the paths join): rows past the last repeat it.
-  auto issue_grid = [&](uint32_t e, RowIn<T>& in) {
+  auto issue_grid = [&](uint32_t e, RowIn<T, RECON>& in) {
     if (nBq == 0) return;
 #pragma unroll
     for (uint32_t k = 0; k < kGridRowsPerWave; k++) {
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
       in.grid[k] = v[e * fa + (I.Bq + 2 * j) * fb + colf];
     }
   };
-  auto deposit_grid = [&](uint32_t e, const RowIn<T>& in) {
+  auto deposit_grid = [&](uint32_t e, const RowIn<T, RECON>& in) {
 #pragma unroll
     for (uint32_t k = 0; k < kGridRowsPerWave; k++) {
       const uint32_t j = wave + kLevelWaves * k;
@@ -449,24 +449,20 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
     }
   };
   // ---- plane p's inputs over the box (and the ring's next grid)
-  auto issue = [&](uint32_t p, RowIn<T>& in) {
+  auto issue = [&](uint32_t p, RowIn<T, RECON>& in) {
     const bool even_p = (p & 1u) == 0;
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; k++) {
       const uint32_t qb = I.Bo + min(wave + kLevelWaves * k, nB - 1);
       const uint32_t f = p * fa + qb * fb + colf;
-      if (RECON) {
+      if (RECON)
         in.raw[k] = codes[f];
-      } else {
+      else
         in.val[k] = x[f];
-        // codes of the tile's coarse points, stored back with the tile's rows
-        // (a condition on the row: the same for the whole wave)
-        if (even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1) in.raw[k] = codes[f];
-      }
     }
     if (!even_p && p + 3 < ea) issue_grid(p + 3, in);
   };
-  auto deposit = [&](uint32_t p, const RowIn<T>& in) {
+  auto deposit = [&](uint32_t p, const RowIn<T, RECON>& in) {
     const bool even_p = (p & 1u) == 0;
     if (!even_p && p + 3 < ea) deposit_grid(p + 3, in);
     const uint32_t gb = grid_base(p);
@@ -479,16 +475,19 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
         // least one plane earlier); other lanes read ring word 0
         const bool coarse = even_p && ((qb | qc_l) & 1u) == 0;
         const T rv = ring[coarse ? gb + ((qb - I.Bq) >> 1) * kRingPitch + ring_col : 0u];
-        box[slot] = coarse ? rv : (RECON ? code_bits(in.raw[k], T(0)) : in.val[k]);
-        if (!RECON && even_p && (qb & 1u) == 0 && qb >= I.B0 && qb < I.B1)
-          lcode[slot] = (uint16_t)in.raw[k];  // other slots are overwritten when computed
+        if (RECON)
+          box[slot] = coarse ? rv : code_bits(in.raw[k], T(0));
+        else
+          box[slot] = coarse ? rv : in.val[k];
       }
     }
     // every input register is taken here, on every path (see PlaneIn)
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; k++) {
-      asm volatile("" ::"v"(in.val[k]));
-      asm volatile("" ::"v"(in.raw[k]));
+      if (RECON)
+        asm volatile("" ::"v"(in.raw[k]));
+      else
+        asm volatile("" ::"v"(in.val[k]));
     }
 #pragma unroll
     for (uint32_t k = 0; k < kGridRowsPerWave; k++) asm volatile("" ::"v"(in.grid[k]));
@@ -558,7 +557,7 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
 
   // ---- the ring before the first plane: even planes P0-2, P0, P0+2
   {
-    RowIn<T> pre;
+    RowIn<T, RECON> pre;
     for (int d = -2; d <= 2; d += 2) {
       const int e = (int)I.P0 + d;
       if (e < 0 || (uint32_t)e >= ea) continue;
@@ -568,7 +567,7 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
   }
   lds_barrier();
 
-  RowIn<T> in;
+  RowIn<T, RECON> in;
   issue(I.P0, in);
   const bool int_b = I.B0 >= 3 && I.B1 + 3 <= g.ext[1];
   const bool int_c = I.C0 >= 3 && I.C1 + 3 <= g.ext[2];
@@ -608,17 +607,20 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
                  2, ncol);
     }
     lds_barrier();
-    // the tile's rows of this plane
+    // the tile's rows of this plane (compression leaves the codes of coarse
+    // points, written at earlier levels, as they are)
     if (lane < tcn) {
       const uint32_t qc = I.C0 + lane, colt = qc * fc;
       const uint32_t bk0 = (I.B0 - I.Bo) * kPitch + (qc - I.Co);
+      const bool even_pc = (p & 1u) == 0 && (qc & 1u) == 0;
 #pragma unroll
       for (uint32_t k = 0; k < kRowsPerWave; k++) {
         const uint32_t r = wave + kLevelWaves * k;
         if (r < tile_rows) {
-          const uint32_t f = p * fa + (I.B0 + r) * fb + colt;
+          const uint32_t qb = I.B0 + r;
+          const uint32_t f = p * fa + qb * fb + colt;
           const uint32_t bk = bk0 + r * kPitch;
-          if (!RECON) codes[f] = lcode[bk];
+          if (!RECON && !(even_pc && (qb & 1u) == 0)) codes[f] = lcode[bk];
           if (RECON || store_v) v[f] = box[bk];
         }
       }
