@@ -169,13 +169,17 @@ int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields,
                       const sz_options* opts, void* stream);
 
 /* ---- measurement and debugging ------------------------------------------
- * sz_set_timing(ctx, 1) records HIP events around every kernel launch on the
- * launch stream; sz_timing_get() returns, for the kernel family `name`, the
- * summed duration (ms) and launch count since the last sz_timing_reset().
- * Names: compression "minmax", "interp", "histogram", "codebook", "encode",
+ * sz_set_timing(ctx, 1) records a pair of HIP events on the launch stream
+ * around the kernels of each family a call runs; sz_timing_get() returns,
+ * for the family `name`, the summed duration (ms) and the number of timed
+ * regions since the last sz_timing_reset().  Names: compression "minmax",
+ * "interp" (the origin and every level), "histogram", "codebook", "encode",
  * "other" (stream tables); decompression "decode_tables", "chunk_scan",
- * "decode" (the chunk decoder alone), "recon". */
+ * "decode" (the chunk decoder alone), "recon" (the origin and every level).
+ * sz_set_timing_family(ctx, name) restricts the events to that family (NULL
+ * or "": every family), which keeps the cost of timing off the others. */
 int sz_set_timing(sz_ctx* ctx, int enable);
+int sz_set_timing_family(sz_ctx* ctx, const char* name);
 int sz_timing_get(sz_ctx* ctx, const char* name, double* total_ms,
                   uint64_t* launches);
 int sz_timing_reset(sz_ctx* ctx);

@@ -31,7 +31,8 @@ HEADER_BYTES = 128
 # every function declared in include/szg.h
 EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_options",
            "sz_compress_bound", "sz_compress", "sz_decompress", "sz_inspect",
-           "sz_compress_batch", "sz_set_timing", "sz_timing_get", "sz_timing_reset",
+           "sz_compress_batch", "sz_set_timing", "sz_set_timing_family", "sz_timing_get",
+           "sz_timing_reset",
            "sz_debug_codes")
 
 
@@ -103,6 +104,8 @@ def lib():
     L.sz_compress_batch.restype = I
     L.sz_set_timing.argtypes = [P, I]
     L.sz_set_timing.restype = I
+    L.sz_set_timing_family.argtypes = [P, ctypes.c_char_p]
+    L.sz_set_timing_family.restype = I
     L.sz_timing_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), U64P]
     L.sz_timing_get.restype = I
     L.sz_timing_reset.argtypes = [P]
@@ -292,6 +295,10 @@ class Context:
 
     def set_timing(self, on: bool = True):
         self._lib.sz_set_timing(self._h, 1 if on else 0)
+
+    def set_timing_family(self, name=None):
+        """Time only the kernel family `name` (None: every family)."""
+        self._lib.sz_set_timing_family(self._h, name.encode() if name else None)
 
     def timing_reset(self):
         self._lib.sz_timing_reset(self._h)

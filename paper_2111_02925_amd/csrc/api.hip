@@ -70,6 +70,7 @@ struct sz_ctx {
   bool fused_levels = true;
   // timing
   bool timing = false;
+  std::string timing_family;  // the one family timed; empty: every family
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, Stat> stats;
@@ -117,7 +118,7 @@ hipEvent_t get_event(sz_ctx* c) {
 
 template <class F>
 hipError_t timed(sz_ctx* c, const char* name, hipStream_t st, F&& f) {
-  if (!c->timing) return f();
+  if (!c->timing || (!c->timing_family.empty() && c->timing_family != name)) return f();
   hipEvent_t a = get_event(c), b = get_event(c);
   (void)hipEventRecord(a, st);
   hipError_t e = f();
@@ -475,26 +476,28 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
               "minmax");
   CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st), "resolve_eb");
   if (s.n) {
+    // the origin and every level, timed as one region
     CHECK_HIP(timed(ctx, "interp", st, [&] {
-                return launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta, s.radius, st);
-              }), "origin");
-    std::vector<LevelGeom> levels;
-    if (ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
-      // the finest level's reconstruction is not read by anything later
-      for (const LevelGeom& g : levels)
-        CHECK_HIP(timed(ctx, "interp", st, [&] {
-                    return launch_level_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
-                                                 ctx->meta, s.radius, g.s > 1, st);
-                  }), "interp level");
-    } else {
-      std::vector<PassGeom> passes;
-      build_passes(s, passes);
-      for (const PassGeom& g : passes)
-        CHECK_HIP(timed(ctx, "interp", st, [&] {
-                    return launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
-                                                ctx->meta, s.radius, st);
-                  }), "interp pass");
-    }
+                hipError_t e =
+                    launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta, s.radius, st);
+                std::vector<LevelGeom> levels;
+                if (ctx->fused_levels &&
+                    plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+                  // the finest level's reconstruction is not read by anything later
+                  for (const LevelGeom& g : levels)
+                    if (e == hipSuccess)
+                      e = launch_level_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                                                ctx->meta, s.radius, g.s > 1, st);
+                } else {
+                  std::vector<PassGeom> passes;
+                  build_passes(s, passes);
+                  for (const PassGeom& g : passes)
+                    if (e == hipSuccess)
+                      e = launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                                               ctx->meta, s.radius, st);
+                }
+                return e;
+              }), "interp");
   }
   CHECK_HIP(launch_fill_u32(ctx->hist, 0, nsym, st), "fill");
   CHECK_HIP(timed(ctx, "histogram", st,
@@ -585,24 +588,24 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                                             woff, uoff, ctx->dt, codes, d_out, ctx->meta, st);
               }), "decode");
     CHECK_HIP(timed(ctx, "recon", st, [&] {
-                return launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
-              }), "origin_recon");
-    std::vector<LevelGeom> levels;
-    if (ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
-      for (const LevelGeom& g : levels)
-        CHECK_HIP(timed(ctx, "recon", st, [&] {
-                    return launch_level_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
-                                              s.radius, st);
-                  }), "recon level");
-    } else {
-      std::vector<PassGeom> passes;
-      build_passes(s, passes);
-      for (const PassGeom& g : passes)
-        CHECK_HIP(timed(ctx, "recon", st, [&] {
-                    return launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                hipError_t e = launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
+                std::vector<LevelGeom> levels;
+                if (ctx->fused_levels &&
+                    plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+                  for (const LevelGeom& g : levels)
+                    if (e == hipSuccess)
+                      e = launch_level_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
                                              s.radius, st);
-                  }), "recon pass");
-    }
+                } else {
+                  std::vector<PassGeom> passes;
+                  build_passes(s, passes);
+                  for (const PassGeom& g : passes)
+                    if (e == hipSuccess)
+                      e = launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                                            s.radius, st);
+                }
+                return e;
+              }), "recon");
   }
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -628,6 +631,12 @@ int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields, const sz_optio
 int sz_set_timing(sz_ctx* ctx, int enable) {
   if (!ctx) return SZ_ERR_ARG;
   ctx->timing = enable != 0;
+  return SZ_OK;
+}
+
+int sz_set_timing_family(sz_ctx* ctx, const char* name) {
+  if (!ctx) return SZ_ERR_ARG;
+  ctx->timing_family = name ? name : "";
   return SZ_OK;
 }
 
