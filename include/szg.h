@@ -168,6 +168,53 @@ typedef struct {
 int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields,
                       const sz_options* opts, void* stream);
 
+/* ---- request server -------------------------------------------------------
+ * Many compression and decompression calls (Section 3.1's interfaces) run
+ * side by side by a pool of `workers` threads, each with its own context and
+ * HIP stream.  Requests are admitted in arrival order while the device
+ * memory the library needs for them fits `budget_bytes`: every worker's
+ * fixed tables, the scratch idle workers keep for reuse, and the scratch of
+ * running requests (idle workers release theirs when the next request would
+ * not fit otherwise).  The caller's input and output buffers are not counted
+ * and must stay valid until the request is done.  A request's output is
+ * byte-identical to the same sz_compress / sz_decompress call alone. */
+typedef enum { SZ_REQ_COMPRESS = 0, SZ_REQ_DECOMPRESS = 1 } sz_request_kind;
+typedef struct {
+  int kind;               /* sz_request_kind */
+  const void* d_in;       /* compress: the field; decompress: the stream (device) */
+  size_t in_size;         /* decompress: stream bytes */
+  int dtype;              /* compress: as sz_compress */
+  int ndim;
+  uint64_t dims[4];
+  int eb_mode;
+  double eb;
+  int predictor;
+  int has_options;        /* compress: 0 = default options */
+  sz_options options;
+  void* d_out;            /* the stream (compress) or the field (decompress) */
+  size_t out_capacity;
+} sz_request;
+typedef struct sz_server sz_server;
+
+/* NULL if the device is missing, workers is outside 1..64, or the workers'
+ * fixed tables alone exceed the budget. */
+sz_server* sz_server_create(int device, size_t budget_bytes, int workers);
+/* Queues a request; *ticket identifies it.  SZ_ERR_ARG for a malformed
+ * request, SZ_ERR_CORRUPT for an unreadable stream header, SZ_ERR_NOMEM when
+ * the request could never fit the budget.  Errors of the call itself are
+ * reported by poll / wait. */
+int sz_server_submit(sz_server* s, const sz_request* req, uint64_t* ticket);
+/* Non-blocking: *done = 1 once finished, with the call's status and output
+ * bytes (stream bytes, or field bytes for decompression); a finished ticket
+ * is then forgotten.  SZ_ERR_ARG for an unknown ticket. */
+int sz_server_poll(sz_server* s, uint64_t ticket, int* done, int* status, size_t* out_size);
+/* Blocks until the request is done, then as poll. */
+int sz_server_wait(sz_server* s, uint64_t ticket, int* status, size_t* out_size);
+/* Device bytes counted against the budget now. */
+size_t sz_server_used_bytes(sz_server* s);
+/* Finishes every submitted request, then frees the workers. */
+void sz_server_destroy(sz_server* s);
+
 /* ---- measurement and debugging ------------------------------------------
  * sz_set_timing(ctx, 1) records a pair of HIP events on the launch stream
  * around the kernels of each family a call runs; sz_timing_get() returns,

@@ -33,7 +33,8 @@ EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_optio
            "sz_compress_bound", "sz_compress", "sz_decompress", "sz_inspect",
            "sz_compress_batch", "sz_set_timing", "sz_set_timing_family", "sz_timing_get",
            "sz_timing_reset",
-           "sz_debug_codes")
+           "sz_debug_codes", "sz_server_create", "sz_server_submit", "sz_server_poll",
+           "sz_server_wait", "sz_server_used_bytes", "sz_server_destroy")
 
 
 class SzLibraryMissing(ImportError):
@@ -59,6 +60,17 @@ class Info(ctypes.Structure):
                 ("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("sub", ctypes.c_uint32), ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
                 ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("d_in", ctypes.c_void_p), ("in_size", ctypes.c_size_t),
+                ("dtype", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_uint64 * 4),
+                ("eb_mode", ctypes.c_int), ("eb", ctypes.c_double), ("predictor", ctypes.c_int),
+                ("has_options", ctypes.c_int), ("options", Options), ("d_out", ctypes.c_void_p),
+                ("out_capacity", ctypes.c_size_t)]
+
+
+REQ_COMPRESS, REQ_DECOMPRESS = 0, 1
 
 
 class Field(ctypes.Structure):
@@ -112,6 +124,19 @@ def lib():
     L.sz_timing_reset.restype = I
     L.sz_debug_codes.argtypes = [P, P, SZ, P]
     L.sz_debug_codes.restype = I
+    L.sz_server_create.argtypes = [I, SZ, I]
+    L.sz_server_create.restype = P
+    L.sz_server_submit.argtypes = [P, ctypes.POINTER(Request), U64P]
+    L.sz_server_submit.restype = I
+    L.sz_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I), ctypes.POINTER(I),
+                                 ctypes.POINTER(SZ)]
+    L.sz_server_poll.restype = I
+    L.sz_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I), ctypes.POINTER(SZ)]
+    L.sz_server_wait.restype = I
+    L.sz_server_used_bytes.argtypes = [P]
+    L.sz_server_used_bytes.restype = SZ
+    L.sz_server_destroy.argtypes = [P]
+    L.sz_server_destroy.restype = None
     _lib = L
     return L
 
@@ -325,3 +350,106 @@ def compress(x, eb_mode="rel", eb: float = 1e-3, predictor="cubic", **kw):
 
 def decompress(stream_t, **kw):
     return default_context(stream_t.device.index or 0).decompress(stream_t, **kw)
+
+
+class Server:
+    """Request server on one GPU: compression / decompression requests run
+    concurrently by `workers` threads within a device-memory budget.  The
+    tensors of a request are kept referenced until it is done."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 8 << 30, workers: int = 4):
+        self._lib = lib()
+        self.device = device
+        self._h = self._lib.sz_server_create(device, int(budget_bytes), int(workers))
+        if not self._h:
+            raise SzError(ERR_DEVICE, f"sz_server_create({device}, {budget_bytes}, {workers}) failed")
+        self._keep = {}
+
+    def submit_compress(self, x, eb_mode="rel", eb: float = 1e-3, predictor="cubic",
+                        radius: int = 32768, chunk: int = 4096, dim_order=None, subchunks: int = 0,
+                        out=None) -> int:
+        torch = _torch()
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous CUDA tensor")
+        opts = make_options(radius, chunk, dim_order, x.dim(), subchunks)
+        if out is None:
+            cap = compress_bound(tuple(x.shape), _dtype_code(x), radius, chunk, dim_order, subchunks)
+            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+        r = Request()
+        r.kind = REQ_COMPRESS
+        r.d_in = x.data_ptr()
+        r.dtype = _dtype_code(x)
+        r.ndim = x.dim()
+        for d in range(4):
+            r.dims[d] = int(x.shape[d]) if d < x.dim() else 1
+        r.eb_mode = _mode(eb_mode)
+        r.eb = float(eb)
+        r.predictor = _pred(predictor)
+        r.has_options = 1
+        r.options = opts
+        r.d_out = out.data_ptr()
+        r.out_capacity = out.numel()
+        return self._submit(r, (x, out))
+
+    def submit_decompress(self, stream_t, out=None) -> int:
+        torch = _torch()
+        info = inspect(stream_t[:HEADER_BYTES].cpu())
+        if out is None:
+            dt = torch.float64 if info["dtype"] == F64 else torch.float32
+            out = torch.empty(tuple(info["dims"]), dtype=dt, device=stream_t.device)
+        r = Request()
+        r.kind = REQ_DECOMPRESS
+        r.d_in = stream_t.data_ptr()
+        r.in_size = stream_t.numel()
+        r.d_out = out.data_ptr()
+        r.out_capacity = out.numel() * out.element_size()
+        return self._submit(r, (stream_t, out))
+
+    def _submit(self, r, keep) -> int:
+        t = ctypes.c_uint64(0)
+        rc = self._lib.sz_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
+        if rc:
+            raise SzError(rc, "sz_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running; else (status, output tensor view)."""
+        done, st, sz = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_size_t(0)
+        rc = self._lib.sz_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st),
+                                      ctypes.byref(sz))
+        if rc:
+            raise SzError(rc, "sz_server_poll")
+        if not done.value:
+            return None
+        return self._finish(ticket, st.value, sz.value)
+
+    def wait(self, ticket: int):
+        st, sz = ctypes.c_int(0), ctypes.c_size_t(0)
+        rc = self._lib.sz_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(sz))
+        if rc:
+            raise SzError(rc, "sz_server_wait")
+        return self._finish(ticket, st.value, sz.value)
+
+    def _finish(self, ticket, status, size):
+        x, out = self._keep.pop(ticket)
+        if status:
+            return status, None
+        if out.dtype == _torch().uint8:
+            return status, out[:size]
+        return status, out
+
+    def used_bytes(self) -> int:
+        return int(self._lib.sz_server_used_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sz_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -372,6 +372,47 @@ int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
 
 }  // namespace
 
+// ---- scratch accounting for the server (server.hip)
+
+namespace szg {
+
+size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress) {
+  auto grown = [](uint64_t b) { return b + b / 8; };  // what ensure() allocates
+  const uint64_t nch = chunk ? (n + chunk - 1) / chunk : 0;
+  uint64_t total = grown(((n + 7) & ~7ull) * 2) + 2 * grown(nch * 4) + 2 * grown(nch * 8) +
+                   grown(((nch + 1023) / 1024 + 1) * 8);
+  if (compress) total += grown(n * tsize);
+  return (size_t)total;
+}
+
+size_t ctx_scratch_bytes(const sz_ctx* ctx) {
+  size_t t = 0;
+  for (const Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred,
+                       &ctx->word_off, &ctx->unpred_off, &ctx->block_sums})
+    t += b->cap;
+  return t;
+}
+
+void ctx_trim(sz_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
+                 &ctx->unpred_off, &ctx->block_sums}) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+}
+
+size_t ctx_fixed_bytes() {
+  return sizeof(Meta) + sizeof(uint32_t) * kMaxSym * 2 + histogram_scratch_bytes() +
+         (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 +
+         sizeof(uint64_t) * kMaxSym * 2 + sizeof(uint32_t) * kMaxSym * 9 + sizeof(uint16_t) * kMaxSym +
+         (sizeof(uint32_t) << kLutBits) + sizeof(LongCodes) + 16 * (kMaxCodeLen + 2) +
+         sizeof(uint16_t) * kMaxSym;
+}
+
+}  // namespace szg
+
 extern "C" {
 
 sz_ctx* sz_ctx_create(int device) {

@@ -104,6 +104,14 @@ struct PassGeom {
   uint64_t total;            // points in the pass
 };
 
+// ---- scratch accounting (api.hip), used by the request server (server.hip)
+// Bytes a compression (or decompression) of n points allocates in a context
+// at most; the bytes a context holds now; freeing them; a context's fixed part.
+size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress);
+size_t ctx_scratch_bytes(const sz_ctx* ctx);
+void ctx_trim(sz_ctx* ctx);
+size_t ctx_fixed_bytes();
+
 // ------------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 

@@ -108,3 +108,40 @@ def test_null_context_is_rejected():
     assert rc == szg.ERR_ARG
     assert L.sz_decompress(None, None, 0, None, 0, None) == szg.ERR_ARG
     assert L.sz_last_error(None) == b"no context"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the C header's sizes and offsets."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    fields = {
+        "sz_options": (szg.Options, ["radius", "chunk", "dim_order", "subchunks"]),
+        "sz_info": (szg.Info, ["dtype", "dims", "n", "eb", "chunk", "sub", "n_unpred", "stream_bytes"]),
+        "sz_request": (szg.Request, ["kind", "d_in", "in_size", "dims", "eb", "options", "d_out",
+                                     "out_capacity"]),
+        "sz_field": (szg.Field, ["d_in", "dims", "eb", "d_out", "out_size", "status"]),
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "szg.h"', "int main(void) {"]
+    for st, (_, names) in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in names:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st, (cls, names) in fields.items():
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in names:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
+
+
+def test_server_create_fails_cleanly_without_device():
+    # an absent device index yields NULL rather than a crash
+    assert not szg.lib().sz_server_create(10_000, 1 << 30, 2)
+    assert not szg.lib().sz_server_create(0, 1 << 30, 0)
