@@ -73,6 +73,60 @@ def workload_name(shape, args, sub):
             f"{sub} sub-chunks")
 
 
+def batch_measurement(szg, torch, np, synth, workers, reps=3):
+    """Batched vs per-field compression of a mixed set of fields at rel eb
+    1e-3: a loop of sz_compress calls on one stream, against the request
+    server (workers with their own contexts and streams).  Outputs must be
+    byte-identical."""
+    n_large = 4
+    flds = synth.batch_fields(seed=4, n_large=n_large)
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(f).to(dev) for f, _ in flds]
+    total = sum(x.numel() * x.element_size() for x in xs)
+    outs = [torch.empty(szg.compress_bound(tuple(x.shape), szg.F32), dtype=torch.uint8, device=dev)
+            for x in xs]
+    ctx = szg.Context(0)
+
+    def per_field():
+        sizes = []
+        for x, o in zip(xs, outs):
+            sizes.append(int(ctx.compress(x, "rel", 1e-3, "cubic", out=o).numel()))
+        torch.cuda.synchronize()
+        return sizes
+
+    ref_sizes = per_field()
+    ref = [bytes(o[:n].cpu().numpy().tobytes()) for o, n in zip(outs, ref_sizes)]
+    t_pf = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        per_field()
+        t_pf.append(time.perf_counter() - t0)
+    srv = szg.Server(0, budget_bytes=64 << 30, workers=workers)
+    souts = [torch.empty_like(o) for o in outs]
+
+    def served():
+        ts = [srv.submit_compress(x, "rel", 1e-3, "cubic", out=o) for x, o in zip(xs, souts)]
+        return [srv.wait(t) for t in ts]
+
+    res = served()
+    identical = all(st == 0 and bytes(v.cpu().numpy().tobytes()) == r
+                    for (st, v), r in zip(res, ref))
+    t_sv = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        served()
+        t_sv.append(time.perf_counter() - t0)
+    srv.close()
+    ctx.close()
+    pf, sv = float(np.median(t_pf)), float(np.median(t_sv))
+    return {"workload": f"{n_large} x 100x500x500 + 64 fields of dims U{{16..96}}^3 f32, offset + "
+                        f"scale * GRF (slope U[-4,-2]), cubic, rel eb 1e-3",
+            "fields": len(xs), "input_bytes": total,
+            "per_field_GBps": round(total / pf / 1e9, 3), "per_field_ms": round(pf * 1e3, 3),
+            "server_GBps": round(total / sv / 1e9, 3), "server_ms": round(sv * 1e3, 3),
+            "server_workers": workers, "outputs_identical": identical}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +138,9 @@ def main():
     ap.add_argument("--subchunks", type=int, default=0,
                     help="runs per chunk decoded by separate lanes (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched vs per-field measurement")
+    ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy the input once on the device "
                          "(a plain copy of known size, to scale HBM counters)")
@@ -198,6 +255,9 @@ def main():
                 "ms_per_step": round(dom_ms, 4),
                 "alg_bytes_per_step": alg[dom]}
 
+    batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
+                                                           args.batch_workers)
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -245,6 +305,7 @@ def main():
         "kernel_ms_note": "per family, from a separate run of the same steps with events around every family",
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
         "parity_with_oracle": parity,
     }
     print(json.dumps(res), flush=True)
