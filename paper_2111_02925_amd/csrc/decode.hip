@@ -338,85 +338,44 @@ struct RunResult {
   uint32_t zeros;  // unpredictable symbols (code 0) in the run
 };
 
+// A lane's next stream words are staged in an LDS ring of kRing words,
+// fetched kPre at a time at group boundaries (every lane passes them at the
+// same symbol counts): the loads issued at one boundary are written to the
+// ring at the next, a group of symbols later, so refills read the ring and
+// never wait on memory while the lane stays within kPre words (256 bits) per
+// group.  A lane that runs ahead reads the stream directly (taking the load
+// inside the branch, so that the common path never waits on it).  The codes
+// of a group are stored at the next boundary, before the next fetch: the wait
+// for a fetch then only covers stores issued before it, a group earlier.
+constexpr uint32_t kRing = 16;  // staged words per lane
+constexpr uint32_t kPre = 8;    // words fetched per lane per group
+
 // Decodes symbols [beg, end) starting at bit `start` of the chunk's words,
 // writes their codes, and lists the offsets (from beg) of the code-0 symbols
-// as u32 words at `zlist`, in increasing order.
+// as u32 words at `zlist`, in increasing order.  ring: this lane's column of
+// the ring (slot i at ring[i * nt]).
 template <bool LONG_LDS>
 __device__ __forceinline__ RunResult decode_run(
     const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint32_t* lut,
     const LongCodes& lc, const uint32_t l0, const uint32_t (&lim)[kWinLens], const uint16_t* long_sym,
-    const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint64_t beg, uint64_t end,
-    uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
+    const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint32_t* ring, uint64_t beg,
+    uint64_t end, uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
   auto ld = [&](uint32_t i) { return words[i < wlast ? i : wlast]; };
   uint32_t zeros = 0;
   uint64_t used = start;
   const uint32_t wi0 = start >> 5, o0 = start & 31;
-  uint32_t w0 = ld(wi0), w1 = ld(wi0 + 1), nxt = ld(wi0 + 2);
-  // Take the priming loads here (an empty asm that reads the three words):
-  // left pending they would be waited for at the head of the symbol loop on
-  // every iteration.
-  asm volatile("" : "+v"(w0), "+v"(w1), "+v"(nxt));
+  uint32_t w0 = ld(wi0), w1 = ld(wi0 + 1);
+  asm volatile("" : "+v"(w0), "+v"(w1));
   uint64_t buf = (((uint64_t)w0 << 32) | w1) << o0;
   uint32_t nb = 64 - o0, rd = wi0 + 2;
-  const bool vec = (chunk & 31) == 0;  // every run then starts on a 32-symbol boundary
-  for (uint64_t g = beg; g < end; g += kGroup) {
-    const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
-    uint32_t zmask = 0;  // positions of unpredictable values in this group
-    for (uint32_t k = 0; k < cnt; k++) {
-      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-      uint32_t len = e >> 16;
-      uint32_t sym = e & 0xFFFFu;
-      if (len == 0) {  // a code longer than the table
-        const uint32_t win = (uint32_t)(buf >> 32);
-        uint32_t l = l0;
+  uint32_t avail = rd;  // words [rd, avail) are in the ring
+  uint32_t q[kPre];     // words [qp, qp + kPre), in flight since the last boundary
+  uint32_t qp = rd;
+  bool qwant = true;
 #pragma unroll
-        for (int q = 0; q < kWinLens; q++) l += win > lim[q] ? 1u : 0u;
-        if (l <= 32) {
-          const uint32_t idx = lc.base32[l] + (win >> (32 - l));
-          sym = LONG_LDS ? long_sym[idx] : sorted_sym[idx + lc.long_first];
-          len = l;
-          used += len;
-          buf <<= len;
-          nb -= len;
-        } else {  // longer than 32 bits: exact read of the next 64 bits
-          const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
-          uint64_t w64 = ((uint64_t)ld(wi) << 32) | ld(wi + 1);
-          if (o) w64 = (w64 << o) | (ld(wi + 2) >> (32 - o));
-          l = 33;
-          for (uint32_t q = 33; q < lc.max_len; q++) l += w64 >= lc.end_lj[q] ? 1u : 0u;
-          const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
-          // a 32-bit read, so that this rare load is never merged with the
-          // table reads above into one generic-address load
-          const uint32_t pair = reinterpret_cast<const uint32_t*>(sorted_sym)[idx >> 1];
-          sym = (pair >> (16 * (idx & 1))) & 0xFFFFu;
-          len = l;
-          used += len;
-          const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
-          uint64_t v = ((uint64_t)ld(w2) << 32) | ld(w2 + 1);
-          buf = v & (~0ull << o2);
-          nb = 64 - o2;
-          rd = w2 + 2;
-          nxt = ld(rd);
-        }
-      } else {
-        used += len;
-        buf <<= len;
-        nb -= len;
-      }
-      if (nb < 32) {  // append the prefetched word, prefetch the next
-        buf |= (uint64_t)nxt << (32 - nb);
-        nb += 32;
-        rd++;
-        nxt = ld(rd);
-      }
-      stage[k * nt] = (uint16_t)sym;
-      zmask |= (sym == 0 ? 1u : 0u) << k;
-    }
-    while (zmask) {
-      const uint32_t k = __builtin_ctz(zmask);
-      zmask &= zmask - 1;
-      zlist[zeros++] = (uint32_t)(g + k - beg);
-    }
+  for (uint32_t k = 0; k < kPre; k++) q[k] = ld(qp + k);
+  const bool vec = (chunk & 31) == 0;  // every run then starts on a 32-symbol boundary
+  auto flush = [&](uint64_t g, uint32_t cnt) {
     if (vec && cnt == kGroup) {  // g is a multiple of 32 symbols: 64-byte aligned
       uint4* dst = reinterpret_cast<uint4*>(codes + g);
 #pragma unroll
@@ -431,7 +390,97 @@ __device__ __forceinline__ RunResult decode_run(
     } else {
       for (uint32_t j = 0; j < cnt; j++) codes[g + j] = stage[j * nt];
     }
+  };
+  uint64_t prev_g = beg;
+  uint32_t prev_cnt = 0;
+  for (uint64_t g = beg; g < end; g += kGroup) {
+    // the words fetched at the last boundary into the ring
+#pragma unroll
+    for (uint32_t k = 0; k < kPre; k++) asm volatile("" ::"v"(q[k]));
+    if (qwant) {
+#pragma unroll
+      for (uint32_t k = 0; k < kPre; k++) ring[((qp + k) & (kRing - 1)) * nt] = q[k];
+      avail = qp + kPre;
+    }
+    if (prev_cnt) flush(prev_g, prev_cnt);
+    // the next words, if the ring has room for them
+    qp = avail > rd ? avail : rd;
+    qwant = qp + kPre <= rd + kRing;
+#pragma unroll
+    for (uint32_t k = 0; k < kPre; k++) q[k] = ld(qp + k);
+
+    const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
+    uint32_t zmask = 0;  // positions of unpredictable values in this group
+    for (uint32_t k = 0; k < cnt; k++) {
+      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+      uint32_t len = e >> 16;
+      uint32_t sym = e & 0xFFFFu;
+      if (len == 0) {  // a code longer than the table
+        const uint32_t win = (uint32_t)(buf >> 32);
+        uint32_t l = l0;
+#pragma unroll
+        for (int qq = 0; qq < kWinLens; qq++) l += win > lim[qq] ? 1u : 0u;
+        if (l <= 32) {
+          const uint32_t idx = lc.base32[l] + (win >> (32 - l));
+          sym = LONG_LDS ? long_sym[idx] : sorted_sym[idx + lc.long_first];
+          len = l;
+          used += len;
+          buf <<= len;
+          nb -= len;
+        } else {  // longer than 32 bits: exact read of the next 64 bits
+          const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
+          uint32_t a = ld(wi), b = ld(wi + 1), c = ld(wi + 2);
+          asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+          uint64_t w64 = ((uint64_t)a << 32) | b;
+          if (o) w64 = (w64 << o) | (c >> (32 - o));
+          l = 33;
+          for (uint32_t qq = 33; qq < lc.max_len; qq++) l += w64 >= lc.end_lj[qq] ? 1u : 0u;
+          const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
+          // a 32-bit read, so that this rare load is never merged with the
+          // table reads above into one generic-address load
+          uint32_t pair = reinterpret_cast<const uint32_t*>(sorted_sym)[idx >> 1];
+          asm volatile("" : "+v"(pair));
+          sym = (pair >> (16 * (idx & 1))) & 0xFFFFu;
+          len = l;
+          used += len;
+          const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
+          uint32_t d = ld(w2), f = ld(w2 + 1);
+          asm volatile("" : "+v"(d), "+v"(f));
+          buf = (((uint64_t)d << 32) | f) & (~0ull << o2);
+          nb = 64 - o2;
+          rd = w2 + 2;
+        }
+      } else {
+        used += len;
+        buf <<= len;
+        nb -= len;
+      }
+      if (nb < 32) {  // append the next word: from the ring, or read directly
+        uint32_t wv;
+        if (rd < avail) {
+          wv = ring[(rd & (kRing - 1)) * nt];
+        } else {
+          wv = ld(rd);
+          asm volatile("" : "+v"(wv));
+        }
+        buf |= (uint64_t)wv << (32 - nb);
+        nb += 32;
+        rd++;
+      }
+      stage[k * nt] = (uint16_t)sym;
+      zmask |= (sym == 0 ? 1u : 0u) << k;
+    }
+    while (zmask) {
+      const uint32_t k = __builtin_ctz(zmask);
+      zmask &= zmask - 1;
+      zlist[zeros++] = (uint32_t)(g + k - beg);
+    }
+    prev_g = g;
+    prev_cnt = cnt;
   }
+  if (prev_cnt) flush(prev_g, prev_cnt);
+#pragma unroll
+  for (uint32_t k = 0; k < kPre; k++) asm volatile("" ::"v"(q[k]));
   return RunResult{used, zeros};
 }
 
@@ -455,7 +504,9 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   __shared__ LongCodes lc;
   __shared__ uint16_t long_sym[kLongSymCap];
   __shared__ uint16_t stage_all[NT * kGroup];
+  __shared__ uint32_t ring_all[NT * kRing];
   uint16_t* stage = stage_all + threadIdx.x;
+  uint32_t* ring = ring_all + threadIdx.x;
   {
     // lookup table and long-code tables: independent loads, all in flight at once
     constexpr uint32_t kLutVecs = (1u << kLutBits) / 4 / NT;
@@ -516,10 +567,10 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   uint32_t* zlist = reinterpret_cast<uint32_t*>(out + beg);
   const RunResult res =
       lc.long_in_lds
-          ? decode_run<true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage, beg,
-                             end, start, chunk, codes, zlist)
+          ? decode_run<true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+                             ring, beg, end, start, chunk, codes, zlist)
           : decode_run<false>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
-                              beg, end, start, chunk, codes, zlist);
+                              ring, beg, end, start, chunk, codes, zlist);
   bool bad = k + 1 < sub ? res.used != next : (res.used + 31) / 32 != W;
   // exclusive scan of the code-0 counts over the chunk's S lanes
   uint32_t incl = res.zeros;
