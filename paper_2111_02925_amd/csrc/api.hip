@@ -344,6 +344,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->cb.phase_end, sizeof(uint32_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.leaf_sym, sizeof(uint16_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lut, sizeof(uint32_t) << kLutBits), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.lut2, sizeof(uint64_t) << kLutBits), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lc, sizeof(LongCodes)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.first, sizeof(uint64_t) * (kMaxCodeLen + 2)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.count, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
@@ -407,7 +408,7 @@ size_t ctx_fixed_bytes() {
   return sizeof(Meta) + sizeof(uint32_t) * kMaxSym * 2 + histogram_scratch_bytes() +
          (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 +
          sizeof(uint64_t) * kMaxSym * 2 + sizeof(uint32_t) * kMaxSym * 9 + sizeof(uint16_t) * kMaxSym +
-         (sizeof(uint32_t) << kLutBits) + sizeof(LongCodes) + 16 * (kMaxCodeLen + 2) +
+         (sizeof(uint32_t) << kLutBits) + (sizeof(uint64_t) << kLutBits) + sizeof(LongCodes) + 16 * (kMaxCodeLen + 2) +
          sizeof(uint16_t) * kMaxSym;
 }
 
@@ -439,7 +440,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
 
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
-                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lc,
+                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lut2, ctx->dt.lc,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
   for (void* p : fixed)
     if (p) (void)hipFree(p);

@@ -230,6 +230,7 @@ struct LongCodes {
 struct DecodeTables {
   LongCodes* lc;         // derived by the table kernel for the chunk decoder
   uint32_t* lut;         // 1 << kLutBits entries: sym | len << 16 (len 0 = longer code)
+  uint64_t* lut2;        // 1 << kLutBits entries: up to three whole codes of the window
   uint64_t* first;       // kMaxCodeLen + 1
   uint32_t* count;       // kMaxCodeLen + 1
   uint32_t* offset;      // kMaxCodeLen + 1

@@ -151,6 +151,35 @@ __device__ __forceinline__ void long_codes(uint32_t K, const uint32_t* bl, const
   }
 }
 
+// Multi-symbol table: for every kLutBits-bit window, the whole codes it holds
+// from its start, up to three, with their symbols and the bits they end at
+// (each found by a lookup of the window shifted past the codes before it; a
+// code that fits the remaining bits is decided by them alone).  Count 0: the
+// first code is longer than the window.  Called by every thread.
+constexpr uint32_t kMultiSyms = 3;
+__device__ __forceinline__ uint64_t multi_entry(uint32_t c, const uint32_t (&sym)[kMultiSyms],
+                                                const uint32_t (&end)[kMultiSyms]) {
+  return (uint64_t)sym[0] | ((uint64_t)sym[1] << 16) | ((uint64_t)sym[2] << 32) |
+         ((uint64_t)c << 48) | ((uint64_t)end[0] << 50) | ((uint64_t)end[1] << 54) |
+         ((uint64_t)end[2] << 58);
+}
+__device__ void multi_symbol_table(DecodeTables d) {
+  __syncthreads();  // the single-code table is complete
+  for (uint32_t x = threadIdx.x; x < (1u << kLutBits); x += blockDim.x) {
+    uint32_t sym[kMultiSyms] = {0, 0, 0}, end[kMultiSyms] = {0, 0, 0}, c = 0, pos = 0;
+    for (uint32_t j = 0; j < kMultiSyms; j++) {
+      const uint32_t e = d.lut[(x << pos) & ((1u << kLutBits) - 1)];
+      const uint32_t l = e >> 16;
+      if (l == 0 || pos + l > (uint32_t)kLutBits) break;
+      sym[j] = e & 0xFFFFu;
+      pos += l;
+      end[j] = pos;
+      c++;
+    }
+    d.lut2[x] = multi_entry(c, sym, end);
+  }
+}
+
 __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
                                                               uint64_t off_sym, uint32_t K,
                                                               uint32_t nsym, DecodeTables d,
@@ -223,6 +252,7 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
         for (uint32_t k = 0; k < span; k++) d.lut[lo + k] = sym | (l << 16);
       }
     }
+    multi_symbol_table(d);
     return;
   }
   // (length, symbol) order, a wave of symbols at a time
@@ -258,20 +288,22 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   __syncthreads();
   // lookup table: entry x holds the short code whose range covers it
   const uint32_t nshort = offs[kLutBits + 1];
-  if (nshort == 0) return;
-  const uint32_t last = nshort - 1;
-  const uint32_t end = u.s.lj[last] + (1u << (kLutBits - (u.s.val[last] >> 16)));
-  for (uint32_t x = t; x < end; x += T) {
-    uint32_t lo = 0, hi = last;  // largest j with lj[j] <= x
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (u.s.lj[mid] <= x)
-        lo = mid;
-      else
-        hi = mid - 1;
+  if (nshort > 0) {
+    const uint32_t last = nshort - 1;
+    const uint32_t end = u.s.lj[last] + (1u << (kLutBits - (u.s.val[last] >> 16)));
+    for (uint32_t x = t; x < end; x += T) {
+      uint32_t lo = 0, hi = last;  // largest j with lj[j] <= x
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (u.s.lj[mid] <= x)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      d.lut[x] = u.s.val[lo];
     }
-    d.lut[x] = u.s.val[lo];
   }
+  multi_symbol_table(d);
 }
 
 hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
@@ -356,7 +388,7 @@ constexpr uint32_t kPre = 8;    // words fetched per lane per group
 // the ring (slot i at ring[i * nt]).
 template <bool LONG_LDS>
 __device__ __forceinline__ RunResult decode_run(
-    const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint32_t* lut,
+    const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint64_t* lut2,
     const LongCodes& lc, const uint32_t l0, const uint32_t (&lim)[kWinLens], const uint16_t* long_sym,
     const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint32_t* ring, uint64_t beg,
     uint64_t end, uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
@@ -411,11 +443,29 @@ __device__ __forceinline__ RunResult decode_run(
 
     const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
     uint32_t zmask = 0;  // positions of unpredictable values in this group
-    for (uint32_t k = 0; k < cnt; k++) {
-      const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-      uint32_t len = e >> 16;
-      uint32_t sym = e & 0xFFFFu;
-      if (len == 0) {  // a code longer than the table
+    for (uint32_t k = 0; k < cnt;) {
+      // up to three whole codes of the next kLutBits bits at once; the
+      // symbols past the group's end are written to the spare stage slots
+      // and not counted
+      const uint64_t e2 = lut2[(uint32_t)(buf >> (64 - kLutBits))];
+      const uint32_t c = (uint32_t)(e2 >> 48) & 3u;
+      if (c) {
+        const uint32_t rem = cnt - k, mm = c < rem ? c : rem;
+        const uint32_t s0 = (uint32_t)e2 & 0xFFFFu, s1 = (uint32_t)(e2 >> 16) & 0xFFFFu,
+                       s2 = (uint32_t)(e2 >> 32) & 0xFFFFu;
+        const uint32_t bits = mm == 1 ? (uint32_t)(e2 >> 50) & 15u
+                                      : (mm == 2 ? (uint32_t)(e2 >> 54) & 15u : (uint32_t)(e2 >> 58) & 15u);
+        stage[k * nt] = (uint16_t)s0;
+        stage[(k + 1) * nt] = (uint16_t)s1;
+        stage[(k + 2) * nt] = (uint16_t)s2;
+        const uint32_t z = (s0 == 0 ? 1u : 0u) | (s1 == 0 ? 2u : 0u) | (s2 == 0 ? 4u : 0u);
+        zmask |= (z & ((1u << mm) - 1u)) << k;
+        used += bits;
+        buf <<= bits;
+        nb -= bits;
+        k += mm;
+      } else {  // a code longer than the table
+        uint32_t sym, len;
         const uint32_t win = (uint32_t)(buf >> 32);
         uint32_t l = l0;
 #pragma unroll
@@ -429,10 +479,10 @@ __device__ __forceinline__ RunResult decode_run(
           nb -= len;
         } else {  // longer than 32 bits: exact read of the next 64 bits
           const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
-          uint32_t a = ld(wi), b = ld(wi + 1), c = ld(wi + 2);
-          asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+          uint32_t a = ld(wi), b = ld(wi + 1), cc = ld(wi + 2);
+          asm volatile("" : "+v"(a), "+v"(b), "+v"(cc));
           uint64_t w64 = ((uint64_t)a << 32) | b;
-          if (o) w64 = (w64 << o) | (c >> (32 - o));
+          if (o) w64 = (w64 << o) | (cc >> (32 - o));
           l = 33;
           for (uint32_t qq = 33; qq < lc.max_len; qq++) l += w64 >= lc.end_lj[qq] ? 1u : 0u;
           const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
@@ -444,16 +494,15 @@ __device__ __forceinline__ RunResult decode_run(
           len = l;
           used += len;
           const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
-          uint32_t d = ld(w2), f = ld(w2 + 1);
-          asm volatile("" : "+v"(d), "+v"(f));
-          buf = (((uint64_t)d << 32) | f) & (~0ull << o2);
+          uint32_t dd = ld(w2), f = ld(w2 + 1);
+          asm volatile("" : "+v"(dd), "+v"(f));
+          buf = (((uint64_t)dd << 32) | f) & (~0ull << o2);
           nb = 64 - o2;
           rd = w2 + 2;
         }
-      } else {
-        used += len;
-        buf <<= len;
-        nb -= len;
+        stage[k * nt] = (uint16_t)sym;
+        zmask |= (sym == 0 ? 1u : 0u) << k;
+        k++;
       }
       if (nb < 32) {  // append the next word: from the ring, or read directly
         uint32_t wv;
@@ -467,8 +516,6 @@ __device__ __forceinline__ RunResult decode_run(
         nb += 32;
         rd++;
       }
-      stage[k * nt] = (uint16_t)sym;
-      zmask |= (sym == 0 ? 1u : 0u) << k;
     }
     while (zmask) {
       const uint32_t k = __builtin_ctz(zmask);
@@ -500,17 +547,17 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
     uint64_t nchunks, uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_unpred, const uint64_t* __restrict__ word_off,
     const uint64_t* __restrict__ unpred_off, DecodeTables d, uint16_t* codes, T* out, Meta* m) {
-  __shared__ __align__(16) uint32_t lut[1u << kLutBits];
+  __shared__ __align__(16) uint64_t lut2[1u << kLutBits];
   __shared__ LongCodes lc;
   __shared__ uint16_t long_sym[kLongSymCap];
-  __shared__ uint16_t stage_all[NT * kGroup];
+  __shared__ uint16_t stage_all[NT * (kGroup + 2)];  // two spare slots per lane
   __shared__ uint32_t ring_all[NT * kRing];
   uint16_t* stage = stage_all + threadIdx.x;
   uint32_t* ring = ring_all + threadIdx.x;
   {
     // lookup table and long-code tables: independent loads, all in flight at once
-    constexpr uint32_t kLutVecs = (1u << kLutBits) / 4 / NT;
-    const uint4* src = reinterpret_cast<const uint4*>(d.lut);
+    constexpr uint32_t kLutVecs = (1u << kLutBits) / 2 / NT;
+    const uint4* src = reinterpret_cast<const uint4*>(d.lut2);
     uint4 v[kLutVecs];
 #pragma unroll
     for (uint32_t j = 0; j < kLutVecs; j++) v[j] = src[threadIdx.x + j * NT];
@@ -523,7 +570,7 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
       lw[j] = i < kLcWords ? reinterpret_cast<const uint32_t*>(d.lc)[i] : 0u;
     }
 #pragma unroll
-    for (uint32_t j = 0; j < kLutVecs; j++) reinterpret_cast<uint4*>(lut)[threadIdx.x + j * NT] = v[j];
+    for (uint32_t j = 0; j < kLutVecs; j++) reinterpret_cast<uint4*>(lut2)[threadIdx.x + j * NT] = v[j];
 #pragma unroll
     for (uint32_t j = 0; j < (kLcWords + NT - 1) / NT; j++) {
       const uint32_t i = threadIdx.x + j * NT;
@@ -567,9 +614,9 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   uint32_t* zlist = reinterpret_cast<uint32_t*>(out + beg);
   const RunResult res =
       lc.long_in_lds
-          ? decode_run<true>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+          ? decode_run<true>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, stage,
                              ring, beg, end, start, chunk, codes, zlist)
-          : decode_run<false>(words, wlast, NT, lut, lc, l0, lim, long_sym, d.sorted_sym, stage,
+          : decode_run<false>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, stage,
                               ring, beg, end, start, chunk, codes, zlist);
   bool bad = k + 1 < sub ? res.used != next : (res.used + 31) / 32 != W;
   // exclusive scan of the code-0 counts over the chunk's S lanes
