@@ -150,11 +150,21 @@ struct LevelGeom {
   uint32_t ring_bytes;
   uint32_t lds;
   uint32_t pitch64;   // box rows 64 slots apart, coarse-grid rows 32 (boxes of <= 64 columns)
+  // stride-1 level of a three-dimensional field as row strips (fine.hip)
+  uint32_t fine;      // 1: planned for the strip kernel
+  uint32_t f_waves;   // waves per workgroup (128 columns each)
+  uint32_t f_wins;    // column windows
+  uint32_t f_atiles;  // plane groups
+  uint32_t f_runs;    // row runs
+  uint32_t f_rows;    // rows per run (even)
+  uint32_t f_items;   // workgroups
 };
 struct LevelTuning {
   uint32_t target_points;  // minimum number of work items (planes per item shrink to reach it)
   uint32_t tile_b, tile_c; // (b, c) tile extents
   uint32_t lds_bytes;      // LDS budget of one workgroup
+  uint32_t fine;           // 0: never plan the strip kernel
+  uint32_t fine_rows;      // rows per run of the strip kernel (0: chosen from the shape)
 };
 constexpr uint32_t kLevelStoreValues = 1u << 0;   // store reconstructed values of the tile
 
@@ -166,6 +176,16 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
                                  uint32_t radius, bool store_rec, hipStream_t st);
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                               const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+// The strip kernel of the stride-1 level (fine.hip): planned by plan_fine
+// (sets g.fine), launched when fine_usable (the field's pointers hold whole
+// column pairs).
+bool plan_fine(LevelGeom& g, int tsize, uint32_t rows);
+bool fine_usable(const LevelGeom& g, int dtype, const void* x, const void* v);
+hipError_t launch_fine_compress(const void* x, int dtype, int predictor, void* rec,
+                                uint16_t* codes, const LevelGeom& g, const Meta* m,
+                                uint32_t radius, hipStream_t st);
+hipError_t launch_fine_recon(const uint16_t* codes, int dtype, int predictor, void* out,
+                             const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
 
 hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, uint32_t* part,
                             uint32_t* hist, Meta* m, hipStream_t st);

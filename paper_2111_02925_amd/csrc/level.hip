@@ -655,7 +655,7 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
     while ((1ull << l) < dims[d]) l++;
     L = std::max(L, l);
   }
-  const LevelTuning def{2048, 32, 58, 64 * 1024};
+  const LevelTuning def{2048, 32, 58, 64 * 1024, 1, 0};
   const LevelTuning& tu = tune ? *tune : def;
   for (int l = L; l >= 1; l--) {
     const uint64_t s = 1ull << (l - 1);
@@ -713,6 +713,7 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
     g.ring_bytes = (uint32_t)(((uint64_t)4 * g.ring_b * rc * tsize + 15) / 16 * 16);
     g.lds = g.box_bytes + g.ring_bytes + (g.box_b * bc + 1) * 2;
     if (g.nitems > 0x7FFFFFFFull) return false;
+    if (tu.fine) plan_fine(g, tsize, tu.fine_rows);
     out.push_back(g);
   }
   return true;
@@ -747,6 +748,9 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
                                  uint16_t* codes, const LevelGeom& g, const Meta* m,
                                  uint32_t radius, bool store_rec, hipStream_t st) {
   const uint32_t flags = store_rec ? kLevelStoreValues : 0u;
+  // (the strip kernel stores no reconstruction: it runs the last level only)
+  if (!store_rec && fine_usable(g, dtype, x, rec))
+    return launch_fine_compress(x, dtype, predictor, rec, codes, g, m, radius, st);
   if (dtype == SZ_F32)
     return launch_level_t<float, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags, st);
   return launch_level_t<double, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags, st);
@@ -756,6 +760,8 @@ hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, v
                               const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st) {
   // the tile is stored whole (its coarse points too, unchanged), so that the
   // output rows are written by one workgroup
+  if (fine_usable(g, dtype, out, out))
+    return launch_fine_recon(codes, dtype, predictor, out, g, eb_t, radius, st);
   uint16_t* c = const_cast<uint16_t*>(codes);  // only read when reconstructing
   if (dtype == SZ_F32)
     return launch_level_t<float, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,

@@ -83,7 +83,23 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+# The stride-1 level of 3-D fields with an even last extent runs as row strips
+# (one to four waves of 128 columns, one or more column windows, runs of rows
+# and groups of planes with ragged ends).
+FINE_CASES = [
+    ("fine-2win-ragged", lambda: lognormal((20, 37, 600), 31), "rel", 1e-3, 1, 32768, 4096, None),
+    ("fine-3win", lambda: lognormal((9, 130, 1030), 32), "rel", 1e-4, 1, 32768, 4096, None),
+    ("fine-3wave-f64-linear", lambda: synth.random_field((11, 50, 260), seed=33, dtype=np.float64), "rel", 1e-4, 0, 32768, 4096, None),
+    ("fine-2wave-f64-cubic", lambda: synth.random_field((13, 41, 200), seed=34, dtype=np.float64), "rel", 1e-3, 1, 32768, 4096, None),
+    ("fine-3planes", lambda: lognormal((3, 16, 200), 35), "rel", 1e-2, 1, 32768, 4096, None),
+    ("fine-2planes", lambda: lognormal((2, 300, 256), 36), "rel", 1e-3, 1, 32768, 4096, None),
+    ("fine-unpred", lambda: synth.random_field((16, 40, 300), seed=37), "rel", 1e-6, 1, 32768, 4096, None),
+    ("fine-unpred-R2", lambda: synth.random_field((10, 33, 140), seed=38), "rel", 1e-3, 0, 2, 1024, None),
+    ("fine-4col", lambda: lognormal((12, 10, 4), 39), "rel", 1e-3, 1, 32768, 256, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES + FINE_CASES, ids=[c[0] for c in CASES + FINE_CASES])
 def test_parity(ctx, orc, case):
     label, gen, mode, eb, pred, radius, chunk, order = case
     x = gen()
