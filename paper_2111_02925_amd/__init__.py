@@ -266,11 +266,12 @@ class Context:
         torch = _torch()
         if not stream_t.is_cuda or stream_t.dtype != torch.uint8:
             raise ValueError("stream must be a uint8 CUDA tensor")
-        info = inspect(stream_t[:HEADER_BYTES].cpu())
-        dt = torch.float64 if info["dtype"] == F64 else torch.float32
-        shape = tuple(info["dims"])
-        if out is None:
-            out = torch.empty(shape, dtype=dt, device=stream_t.device)
+        if out is None:  # (with `out` given, the library reads the header itself)
+            info = inspect(stream_t[:HEADER_BYTES].cpu())
+            dt = torch.float64 if info["dtype"] == F64 else torch.float32
+            out = torch.empty(tuple(info["dims"]), dtype=dt, device=stream_t.device)
+        elif not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA tensor")
         rc = self._lib.sz_decompress(self._h, ctypes.c_void_p(stream_t.data_ptr()),
                                      stream_t.numel(), ctypes.c_void_p(out.data_ptr()),
                                      out.numel() * out.element_size(), self._stream(stream))

@@ -366,7 +366,7 @@ int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
   CHECK_HIP(ensure(ctx->chunk_unpred, nch * 4), "hipMalloc");
   CHECK_HIP(ensure(ctx->word_off, nch * 8), "hipMalloc");
   CHECK_HIP(ensure(ctx->unpred_off, nch * 8), "hipMalloc");
-  CHECK_HIP(ensure(ctx->block_sums, ((nch + 1023) / 1024 + 1) * 8), "hipMalloc");
+  CHECK_HIP(ensure(ctx->block_sums, (2 * ((nch + 1023) / 1024) + 1) * 8), "hipMalloc");
 
   return SZ_OK;
 }
@@ -381,7 +381,7 @@ size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress) {
   auto grown = [](uint64_t b) { return b + b / 8; };  // what ensure() allocates
   const uint64_t nch = chunk ? (n + chunk - 1) / chunk : 0;
   uint64_t total = grown(((n + 7) & ~7ull) * 2) + 2 * grown(nch * 4) + 2 * grown(nch * 8) +
-                   grown(((nch + 1023) / 1024 + 1) * 8);
+                   grown((2 * ((nch + 1023) / 1024) + 1) * 8);
   if (compress) total += grown(n * tsize);
   return (size_t)total;
 }
@@ -617,11 +617,9 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                 return launch_decode_tables(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt, ctx->meta, st);
               }), "decode_tables");
     CHECK_HIP(timed(ctx, "chunk_scan", st, [&] {
-                hipError_t e = launch_chunk_table_scan(str, l.off_chunk, nch, cwords, cunp, woff, uoff,
-                                                       bsum, ctx->totals, st);
-                if (e == hipSuccess)
-                  e = launch_check_totals(ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
-                return e;
+                return launch_chunk_table_scan(str, l.off_chunk, nch, cwords, cunp, woff, uoff,
+                                               bsum, ctx->totals, in.total_words, in.n_unpred,
+                                               ctx->meta, st);
               }), "chunk_scan");
     CHECK_HIP(timed(ctx, "decode", st, [&] {
                 return launch_decode_chunks(str, stream_size, l.off_sub, l.off_unpred, l.off_bits,

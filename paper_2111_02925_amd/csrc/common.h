@@ -208,6 +208,11 @@ hipError_t launch_codebook(const uint32_t* hist, uint32_t nsym, CodebookScratch 
 
 hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n,
                                      uint64_t* block_sums, uint64_t* total, hipStream_t st);
+// Both exclusive scans of two u32 arrays with the launches of one scan;
+// block_sums holds 2 * ceil(n / 1024) entries; totals to a_total and b_total.
+hipError_t launch_scan_pair(const uint32_t* a, const uint32_t* b, uint64_t n, uint64_t* a_off,
+                            uint64_t* b_off, uint64_t* block_sums, uint64_t* a_total,
+                            uint64_t* b_total, hipStream_t st);
 
 // Encoder scratch: per-chunk sizes and their exclusive scans.
 struct EncodeScratch {
@@ -263,7 +268,8 @@ hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_
 hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
                                    uint32_t* chunk_words, uint32_t* chunk_unpred,
                                    uint64_t* word_off, uint64_t* unpred_off,
-                                   uint64_t* block_sums, uint64_t* totals, hipStream_t st);
+                                   uint64_t* block_sums, uint64_t* totals, uint64_t total_words,
+                                   uint64_t n_unpred, Meta* m, hipStream_t st);
 hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_sub,
                                 uint64_t off_unpred, uint64_t off_bits, uint64_t total_words,
                                 uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,

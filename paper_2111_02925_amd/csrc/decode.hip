@@ -67,6 +67,117 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
   }
 }
 
+// Both exclusive scans of two u32 sequences a[i * stride], b[i * stride] with
+// the same three launches as one scan (1024 entries per block): block sums of
+// both, a one-block scan of both block-sum rows (thread 0 writes the totals
+// and, given a Meta, flags totals other than the expected ones), then the
+// offsets (and copies of the inputs, when asked).
+struct PairScan {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t stride;
+  uint64_t n;
+  uint32_t* a_copy;
+  uint32_t* b_copy;
+  uint64_t* a_off;
+  uint64_t* b_off;
+  uint64_t* sums;     // 2 * nb: block sums of a, then of b
+  uint64_t* a_total;
+  uint64_t* b_total;
+  uint64_t want_a, want_b;
+  Meta* m;            // non-null: check the totals
+};
+
+__global__ __launch_bounds__(256) void k_scan2_reduce(PairScan p) {
+  __shared__ uint64_t sh[16];
+  const uint64_t base = blockIdx.x * (uint64_t)kScanPerBlock;
+  uint64_t va = 0, vb = 0;
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint64_t i = base + threadIdx.x * 4 + k;
+    if (i < p.n) {
+      va += p.a[i * p.stride];
+      vb += p.b[i * p.stride];
+    }
+  }
+  uint64_t ta, tb;
+  block_excl_scan_u64(va, sh, &ta);
+  block_excl_scan_u64(vb, sh, &tb);
+  if (threadIdx.x == 0) {
+    p.sums[blockIdx.x] = ta;
+    p.sums[gridDim.x + blockIdx.x] = tb;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan2_blocks(PairScan p, uint64_t nb) {
+  __shared__ uint64_t sh[16];
+  const uint64_t T = blockDim.x;
+  const uint64_t seg = (nb + T - 1) / T;
+  const uint64_t beg = threadIdx.x * seg < nb ? threadIdx.x * seg : nb;
+  const uint64_t end = beg + seg < nb ? beg + seg : nb;
+  uint64_t tot[2];
+  for (int h = 0; h < 2; h++) {
+    uint64_t* bs = p.sums + h * nb;
+    uint64_t v = 0;
+    for (uint64_t i = beg; i < end; i++) v += bs[i];
+    uint64_t run = block_excl_scan_u64(v, sh, &tot[h]);
+    for (uint64_t i = beg; i < end; i++) {
+      const uint64_t x = bs[i];
+      bs[i] = run;
+      run += x;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (p.a_total) *p.a_total = tot[0];
+    if (p.b_total) *p.b_total = tot[1];
+    if (p.m && (tot[0] != p.want_a || tot[1] != p.want_b)) atomicOr(&p.m->status, kStatusCorrupt);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan2_apply(PairScan p) {
+  __shared__ uint64_t sh[16];
+  const uint64_t base = blockIdx.x * (uint64_t)kScanPerBlock;
+  uint32_t la[4], lb[4];
+  uint64_t va = 0, vb = 0;
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint64_t i = base + threadIdx.x * 4 + k;
+    la[k] = i < p.n ? p.a[i * p.stride] : 0;
+    lb[k] = i < p.n ? p.b[i * p.stride] : 0;
+    va += la[k];
+    vb += lb[k];
+  }
+  uint64_t ta, tb;
+  uint64_t ra = block_excl_scan_u64(va, sh, &ta) + p.sums[blockIdx.x];
+  uint64_t rb = block_excl_scan_u64(vb, sh, &tb) + p.sums[gridDim.x + blockIdx.x];
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint64_t i = base + threadIdx.x * 4 + k;
+    if (i < p.n) {
+      if (p.a_copy) p.a_copy[i] = la[k];
+      if (p.b_copy) p.b_copy[i] = lb[k];
+      p.a_off[i] = ra;
+      p.b_off[i] = rb;
+    }
+    ra += la[k];
+    rb += lb[k];
+  }
+}
+
+static hipError_t launch_scan2(const PairScan& p, hipStream_t st) {
+  uint64_t nb = (p.n + kScanPerBlock - 1) / kScanPerBlock;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_scan2_reduce, dim3((unsigned)nb), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(k_scan2_blocks, dim3(1), dim3(1024), 0, st, p, nb);
+  if (p.n) hipLaunchKernelGGL(k_scan2_apply, dim3((unsigned)nb), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_pair(const uint32_t* a, const uint32_t* b, uint64_t n, uint64_t* a_off,
+                            uint64_t* b_off, uint64_t* block_sums, uint64_t* a_total,
+                            uint64_t* b_total, hipStream_t st) {
+  PairScan p{a, b, 1u, n, nullptr, nullptr, a_off, b_off, block_sums, a_total, b_total, 0, 0,
+             nullptr};
+  return launch_scan2(p, st);
+}
+
 hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n,
                                      uint64_t* block_sums, uint64_t* total, hipStream_t st) {
   uint64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
@@ -313,30 +424,18 @@ hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_read_chunk_table(const uint8_t* __restrict__ stream,
-                                                          uint64_t off_chunk, uint64_t nchunks,
-                                                          uint32_t* chunk_words,
-                                                          uint32_t* chunk_unpred) {
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
-  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nchunks; c += gs) {
-    chunk_words[c] = tab[2 * c];
-    chunk_unpred[c] = tab[2 * c + 1];
-  }
-}
-
 hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
                                    uint32_t* chunk_words, uint32_t* chunk_unpred,
                                    uint64_t* word_off, uint64_t* unpred_off,
-                                   uint64_t* block_sums, uint64_t* totals, hipStream_t st) {
+                                   uint64_t* block_sums, uint64_t* totals, uint64_t total_words,
+                                   uint64_t n_unpred, Meta* m, hipStream_t st) {
   if (nchunks == 0) return hipSuccess;
-  uint64_t blocks = (nchunks + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_read_chunk_table, dim3((unsigned)blocks), dim3(256), 0, st, stream,
-                     off_chunk, nchunks, chunk_words, chunk_unpred);
-  hipError_t e = launch_exclusive_scan_u32(chunk_words, word_off, nchunks, block_sums, totals, st);
-  if (e != hipSuccess) return e;
-  return launch_exclusive_scan_u32(chunk_unpred, unpred_off, nchunks, block_sums, totals + 1, st);
+  // the table's (words, unpredictable) pairs read in place, copied out for
+  // the decoder, scanned, and their totals checked
+  const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
+  PairScan p{tab, tab + 1, 2u, nchunks, chunk_words, chunk_unpred, word_off, unpred_off,
+             block_sums, totals, totals + 1, total_words, n_unpred, m};
+  return launch_scan2(p, st);
 }
 
 __global__ void k_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,

@@ -580,10 +580,8 @@ hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64
   dim3 grid((unsigned)blocks), block(kEncWaves * 64);
   hipLaunchKernelGGL(k_encode_size, grid, block, 0, st, codes, n, chunk, nchunks, radius, nsym,
                      enc_code, enc_len, es.chunk_words, es.chunk_zeros, m);
-  hipError_t e = launch_exclusive_scan_u32(es.chunk_words, es.word_off, nchunks, es.block_sums,
-                                           &m->total_words, st);
-  if (e != hipSuccess) return e;
-  e = launch_exclusive_scan_u32(es.chunk_zeros, es.zero_off, nchunks, es.block_sums, es.totals, st);
+  hipError_t e = launch_scan_pair(es.chunk_words, es.chunk_zeros, nchunks, es.word_off,
+                                  es.zero_off, es.block_sums, &m->total_words, es.totals, st);
   if (e != hipSuccess) return e;
   if (dtype == SZ_F32)
     hipLaunchKernelGGL(k_encode_pack<float>, grid, block, 0, st, codes, (const float*)x, n, chunk,

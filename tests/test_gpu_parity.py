@@ -80,6 +80,8 @@ CASES = [
     # unpredictable values
     ("wide-hist-1e-6", lambda: synth.random_field((64, 64, 32), seed=17), "rel", 1e-6, 1, 32768, 4096, None),
     ("wide-hist-1e-5", lambda: lognormal((64, 64, 64), 3), "rel", 1e-5, 1, 32768, 4096, None),
+    # more than 65536 chunks: the chunk-size scans take the multi-launch path
+    ("many-chunks", lambda: lognormal((200, 150, 141), 40), "rel", 1e-3, 1, 32768, 64, None),
 ]
 
 
