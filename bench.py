@@ -73,6 +73,25 @@ def workload_name(shape, args, sub):
             f"{sub} sub-chunks")
 
 
+def lossless_measurement(szg, s, in_bytes, level=1):
+    """The host lossless stage (zlib standing in for zstd) on the step's
+    stream, outside the timed region: one thread of the host, the stream
+    already in host memory.  Checked to restore the stream exactly."""
+    host = bytes(s.cpu().numpy().tobytes())
+    t0 = time.perf_counter()
+    packed = szg.lossless_pack(host, level)
+    t1 = time.perf_counter()
+    back = szg.lossless_unpack(packed, len(host))
+    t2 = time.perf_counter()
+    return {"codec": "zlib (stand-in for zstd)", "level": level, "host_threads": 1,
+            "stream_bytes": len(host), "packed_bytes": len(packed),
+            "ratio_with_stage": round(in_bytes / len(packed), 4),
+            "gain": round(len(host) / len(packed), 4),
+            "pack_MBps": round(len(host) / (t1 - t0) / 1e6, 1),
+            "unpack_MBps": round(len(host) / (t2 - t1) / 1e6, 1),
+            "restored": back == host}
+
+
 def batch_measurement(szg, torch, np, synth, workers, reps=3):
     """Batched vs per-field compression of a mixed set of fields at rel eb
     1e-3: a loop of sz_compress calls on one stream, against the request
@@ -257,6 +276,7 @@ def main():
 
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
+    lossless = lossless_measurement(szg, s, in_bytes)
 
     cpu = None
     parity = None
@@ -306,6 +326,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "lossless": lossless,
         "parity_with_oracle": parity,
     }
     print(json.dumps(res), flush=True)

@@ -145,6 +145,27 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size,
  * bytes).  Host only; validates the header fields. */
 int sz_inspect(const void* h_stream, size_t len, sz_info* info);
 
+/* Host lossless stage on a finished stream (paper Section 3: the lossless
+ * module ends every pipeline; SZ3-Interp and SZ3-LR use zstd, Section 6.2,
+ * for which zlib's deflate stands in here).  Both calls work on host memory
+ * and treat the stream as opaque bytes; the GPU path does not depend on them.
+ *
+ * sz_lossless_bound: the largest packed size of n bytes.
+ * sz_lossless_pack: h_in[0, n) to a zlib stream (RFC 1950) at `level` 0..9
+ *   (zlib's levels; 1 is fastest) in h_out[0, capacity); *out_size = its
+ *   length.  SZ_ERR_CAPACITY (with *out_size = the bound) when it does not
+ *   fit; SZ_ERR_ARG for a bad level or null pointers; SZ_ERR_UNSUPPORTED for
+ *   n >= 2^32.  The output equals zlib's compress2 of the same bytes.
+ * sz_lossless_unpack: the inverse into h_out[0, capacity); *out_size = the
+ *   restored length.  SZ_ERR_CAPACITY when the restored bytes do not fit,
+ *   SZ_ERR_CORRUPT for invalid or truncated input or bytes after its end.
+ * The caller owns every buffer; nothing is kept between calls. */
+size_t sz_lossless_bound(size_t n);
+int sz_lossless_pack(const void* h_in, size_t n, void* h_out, size_t capacity,
+                     size_t* out_size, int level);
+int sz_lossless_unpack(const void* h_in, size_t n, void* h_out, size_t capacity,
+                       size_t* out_size);
+
 /* One field of a batch (sz_compress_batch).  Inputs are read, outputs
  * (out_size, status) written by the call. */
 typedef struct {

@@ -318,3 +318,20 @@ def decompress(stream: bytes, want_codes: bool = False):
     if rc:
         raise OracleError(rc, "decompress")
     return (out, codes) if want_codes else out
+
+
+def lossless_pack(stream: bytes, level: int = 1) -> bytes:
+    """The pipeline's last, lossless stage on a finished stream (paper
+    Section 3; SZ3-Interp ends with zstd, Section 6.2).  zlib stands in for
+    zstd: Python's zlib module (RFC 1950 framing around deflate) at the given
+    level, the stream taken as opaque bytes."""
+    import zlib
+
+    return zlib.compress(bytes(stream), level)
+
+
+def lossless_unpack(packed: bytes) -> bytes:
+    """Inverse of lossless_pack."""
+    import zlib
+
+    return zlib.decompress(bytes(packed))

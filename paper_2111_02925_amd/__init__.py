@@ -34,7 +34,8 @@ EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_optio
            "sz_compress_batch", "sz_set_timing", "sz_set_timing_family", "sz_timing_get",
            "sz_timing_reset",
            "sz_debug_codes", "sz_server_create", "sz_server_submit", "sz_server_poll",
-           "sz_server_wait", "sz_server_used_bytes", "sz_server_destroy")
+           "sz_server_wait", "sz_server_used_bytes", "sz_server_destroy",
+           "sz_lossless_bound", "sz_lossless_pack", "sz_lossless_unpack")
 
 
 class SzLibraryMissing(ImportError):
@@ -137,6 +138,12 @@ def lib():
     L.sz_server_used_bytes.restype = SZ
     L.sz_server_destroy.argtypes = [P]
     L.sz_server_destroy.restype = None
+    L.sz_lossless_bound.argtypes = [SZ]
+    L.sz_lossless_bound.restype = SZ
+    L.sz_lossless_pack.argtypes = [ctypes.c_char_p, SZ, P, SZ, ctypes.POINTER(SZ), I]
+    L.sz_lossless_pack.restype = I
+    L.sz_lossless_unpack.argtypes = [ctypes.c_char_p, SZ, P, SZ, ctypes.POINTER(SZ)]
+    L.sz_lossless_unpack.restype = I
     _lib = L
     return L
 
@@ -190,6 +197,47 @@ def inspect(stream) -> dict:
         raise SzError(rc, "sz_inspect")
     return {f: (list(getattr(info, f))[: info.ndim] if f in ("dims", "dim_order") else getattr(info, f))
             for f, _ in Info._fields_}
+
+
+def lossless_pack(data, level: int = 1) -> bytes:
+    """The host lossless stage: zlib stream of `data` (bytes, numpy or a CPU
+    uint8 tensor) at zlib level 0..9."""
+    b = _host_bytes(data)
+    cap = int(lib().sz_lossless_bound(ctypes.c_size_t(len(b))))
+    out = ctypes.create_string_buffer(max(cap, 1))
+    size = ctypes.c_size_t(0)
+    rc = lib().sz_lossless_pack(b, ctypes.c_size_t(len(b)), out, ctypes.c_size_t(cap),
+                                ctypes.byref(size), int(level))
+    if rc:
+        raise SzError(rc, "sz_lossless_pack")
+    return out.raw[: size.value]
+
+
+def lossless_unpack(data, size_hint: int = 0) -> bytes:
+    """Inverse of lossless_pack; the output buffer grows until it fits."""
+    b = _host_bytes(data)
+    cap = max(size_hint, 4 * len(b) + 4096)
+    while True:
+        out = ctypes.create_string_buffer(cap)
+        size = ctypes.c_size_t(0)
+        rc = lib().sz_lossless_unpack(b, ctypes.c_size_t(len(b)), out, ctypes.c_size_t(cap),
+                                      ctypes.byref(size))
+        if rc == -3:  # SZ_ERR_CAPACITY
+            cap *= 2
+            continue
+        if rc:
+            raise SzError(rc, "sz_lossless_unpack")
+        return out.raw[: size.value]
+
+
+def _host_bytes(data) -> bytes:
+    if isinstance(data, (bytes, bytearray)):
+        return bytes(data)
+    if hasattr(data, "is_cuda"):
+        if data.is_cuda:
+            raise ValueError("the lossless stage works on host memory")
+        return data.numpy().tobytes()
+    return bytes(memoryview(data).cast("B"))
 
 
 def _torch():

@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["interp.hip", "level.hip", "fine.hip", "huffman.hip", "encode.hip", "decode.hip", "api.hip",
-           "server.hip"]
+           "server.hip", "lossless.cpp"]
 HEADERS = ["common.h", "device_math.h", "block_ops.h"]
 
 FLAGS = [
@@ -38,7 +38,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -57,7 +57,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs])
+    subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs, "-lz"])
     os.replace(tmp, LIB)
     return LIB
 

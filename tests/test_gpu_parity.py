@@ -234,3 +234,20 @@ def test_capacity_and_corruption(ctx, orc):
         assert out.tobytes() != good.tobytes()
     with pytest.raises(szg.SzError):
         ctx.decompress(s[:-4])
+
+
+def test_lossless_stage_roundtrip(ctx, orc):
+    """GPU stream -> host lossless stage -> back -> GPU decompress: the same
+    bytes and the oracle's reconstruction."""
+    import paper_2111_02925_amd as szg
+
+    x = lognormal((48, 40, 64), 42)
+    ref = orc.compress(x, orc.REL, 1e-3, orc.CUBIC, 32768, 4096)
+    s = ctx.compress(torch.from_numpy(x).cuda(), "rel", 1e-3, "cubic")
+    host = bytes(s.cpu().numpy().tobytes())
+    assert host == ref
+    packed = szg.lossless_pack(host, 1)
+    assert packed == orc.lossless_pack(ref, 1)
+    back = szg.lossless_unpack(packed)
+    st = torch.frombuffer(bytearray(back), dtype=torch.uint8).cuda()
+    assert ctx.decompress(st).cpu().numpy().tobytes() == orc.decompress(ref).tobytes()
