@@ -47,7 +47,15 @@ typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
  * of the throughput figure: the relative bound is the bound normalised by
  * the value range); 0 when no value is finite.  value must be finite and
  * >= 0, and the resolved eb must be finite. */
-typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1 } sz_eb_mode;
+/* SZ_EB_PWREL: point-wise relative, |x - x'| <= value * |x| for every
+ * normal x, with 0 < value < 1 and value above the type's precision
+ * (SZ_ERR_ARG otherwise).  A logarithmic preprocessor (Section 3.1 and
+ * Section 3.2 "Preprocessor") maps y = log2|x| to a double field that the
+ * same pipeline compresses with an absolute bound; the sign bits are stored
+ * (a bit per value) when any is set.  Zeros and subnormal values come back
+ * as signed zeros, infinities and NaN as themselves (NaN payloads are not
+ * kept).  Size the output with sz_compress_bound_pwrel. */
+typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1, SZ_EB_PWREL = 2 } sz_eb_mode;
 
 /* Interpolation along each dimension (Section 6.2, SZ3-Interp): linear
  * (midpoint of the two neighbours at +-s) or cubic (4-point Lagrange
@@ -98,6 +106,10 @@ typedef struct {
   uint32_t nsym;       /* symbols with a Huffman code */
   uint64_t total_words;/* 32-bit words of Huffman bitstream */
   uint64_t stream_bytes;
+  int coded_dtype;     /* dtype of the coded field: dtype, or SZ_F64 (the
+                          logarithms) in the point-wise relative mode */
+  int signs;           /* point-wise relative mode: 1 if a sign section follows */
+  uint64_t off_signs;  /* byte offset of that section (0 if none) */
 } sz_info;
 
 typedef struct sz_ctx sz_ctx;
@@ -116,6 +128,11 @@ void sz_default_options(sz_options* opts);
 size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims,
                          const sz_options* opts);
 
+/* The same bound for eb_mode SZ_EB_PWREL (a double field of logarithms and
+ * a sign section).  Host only. */
+size_t sz_compress_bound_pwrel(int dtype, int ndim, const uint64_t* dims,
+                               const sz_options* opts);
+
 /* Compress the field d_in (device, n values of dtype) into d_out (device,
  * out_capacity bytes).  Stages, all on the device: error-bound resolution;
  * interpolation prediction + quantization level by level and dimension by
@@ -124,7 +141,9 @@ size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims,
  * unpredictable values; stream assembly.  On success *out_size (host) is the
  * stream length.  If the stream does not fit, returns SZ_ERR_CAPACITY with
  * *out_size = the required size and leaves d_out partially written.
- * opts may be NULL (defaults).  Synchronises `stream`. */
+ * opts may be NULL (defaults).  With eb_mode SZ_EB_PWREL the field first
+ * goes through the logarithmic preprocessor (see sz_eb_mode) and the stream
+ * ends with the sign section.  Synchronises `stream`. */
 int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
                 const uint64_t* dims, int eb_mode, double eb, int predictor,
                 const sz_options* opts, void* d_out, size_t out_capacity,
@@ -135,7 +154,8 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
  * the header, decode the Huffman chunks, scatter the unpredictable values,
  * and rebuild the field with the same traversal and arithmetic as the
  * compressor, so the result equals the compressor's reconstruction bit for
- * bit.  Returns SZ_ERR_CORRUPT for an inconsistent stream (d_out may then be
+ * bit (point-wise relative streams: then through the inverse transform,
+ * into the original dtype).  Returns SZ_ERR_CORRUPT for an inconsistent stream (d_out may then be
  * partially written), SZ_ERR_CAPACITY if d_out is too small.  Synchronises
  * `stream`. */
 int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size,

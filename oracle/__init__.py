@@ -22,7 +22,7 @@ SOURCES = [os.path.join(_HERE, "szo.c")]
 DEPS = SOURCES + [os.path.join(_HERE, "szo.h"), os.path.join(_HERE, "szo_typed.inc")]
 
 F32, F64 = 0, 1
-ABS, REL = 0, 1
+ABS, REL, PWREL = 0, 1, 2
 LINEAR, CUBIC = 0, 1
 OK, ERR_ARG, ERR_CAPACITY, ERR_CORRUPT, ERR_NOMEM = 0, -1, -3, -4, -6
 HEADER_BYTES = 128
@@ -72,6 +72,11 @@ def lib():
                                    ctypes.POINTER(U64), P, P]
         L.szo_decompress.argtypes = [P, U64, P, U64, P]
         L.szo_free.argtypes = [P]
+        for name in ("szo_log2", "szo_exp2"):
+            getattr(L, name).argtypes = [D]
+            getattr(L, name).restype = D
+        L.szo_pwrel_delta.argtypes = [D, I]
+        L.szo_pwrel_delta.restype = D
         for name in ("szo_resolve_eb", "szo_predict_quantize", "szo_reconstruct",
                      "szo_quantize_one", "szo_check_traversal", "szo_histogram",
                      "szo_huffman_lengths", "szo_canonical_codes", "szo_check_sub", "szo_pack",
@@ -286,6 +291,19 @@ def compress(x: np.ndarray, eb_mode: int, eb: float, predictor: int = LINEAR,
     return stream
 
 
+def log2(a: float) -> float:
+    """The point-wise relative mode's logarithm (series in szo.c)."""
+    return lib().szo_log2(float(a))
+
+
+def exp2(y: float) -> float:
+    return lib().szo_exp2(float(y))
+
+
+def pwrel_delta(eps: float, dtype: int = F32) -> float:
+    return lib().szo_pwrel_delta(float(eps), dtype)
+
+
 def parse_header(stream: bytes) -> dict:
     """Decode the fixed 128-byte header (layout documented in szo.c)."""
     b = stream
@@ -303,12 +321,13 @@ def parse_header(stream: bytes) -> dict:
         eb=np.frombuffer(b[56:64], dtype="<f8")[0],
         radius=u32(64), chunk=u32(68), n_unpred=u64(72), nsym=u32(80), sub=u32(84),
         total_words=u64(88), stream_bytes=u64(96),
+        out_dtype=b[104] if b[45] == PWREL else b[6], signs=b[105], off_signs=u64(112),
     )
 
 
 def decompress(stream: bytes, want_codes: bool = False):
     h = parse_header(stream)
-    dt = np.float64 if h["dtype"] == F64 else np.float32
+    dt = np.float64 if h["out_dtype"] == F64 else np.float32
     shape = h["dims"]
     out = np.empty(shape, dtype=dt)
     codes = np.empty(shape, dtype=np.uint16) if want_codes else None

@@ -648,11 +648,294 @@ static void layout_of(uint64_t K, uint64_t nchunks, uint32_t sub, uint64_t n_unp
   lo->size = lo->off_bits + 4 * words;
 }
 
+/* ------------------------------------------ point-wise relative mode ----
+ * The logarithmic preprocessor (paper Section 3.1 / 3.2 "Preprocessor"):
+ * x -> y = log2|x| as a double field, compressed with the absolute bound
+ * szo_pwrel_delta(eps); the signs are kept as a bit per value when any is
+ * set.  Zeros and subnormal values of T map to a level far below every
+ * normal value's logarithm and come back as signed zeros; infinities map to
+ * +inf, NaN to NaN (both unpredictable in the log field, stored verbatim).
+ * The series below are evaluated in the order written (no contraction). */
+#define SZO_SQRT_HALF 0.70710678118654752440
+#define SZO_INV_LN2 1.4426950408889634074
+#define SZO_LN2 0.69314718055994530942
+#define SZO_LOG_ZERO (-1100.0)      /* log-domain level of zeros and subnormals */
+#define SZO_LOG_ZERO_BELOW (-1050.0) /* reconstructed levels below this are zeros */
+
+double szo_log2(double a) {
+  int e;
+  double m = frexp(a, &e); /* a = m 2^e, m in [1/2, 1) */
+  if (m < SZO_SQRT_HALF) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  /* atanh(s) / s = 1 + s^2/3 + s^4/5 + ... + s^28/29 */
+  double t = 1.0 / 29.0;
+  t = t * s2 + 1.0 / 27.0;
+  t = t * s2 + 1.0 / 25.0;
+  t = t * s2 + 1.0 / 23.0;
+  t = t * s2 + 1.0 / 21.0;
+  t = t * s2 + 1.0 / 19.0;
+  t = t * s2 + 1.0 / 17.0;
+  t = t * s2 + 1.0 / 15.0;
+  t = t * s2 + 1.0 / 13.0;
+  t = t * s2 + 1.0 / 11.0;
+  t = t * s2 + 1.0 / 9.0;
+  t = t * s2 + 1.0 / 7.0;
+  t = t * s2 + 1.0 / 5.0;
+  t = t * s2 + 1.0 / 3.0;
+  t = t * s2 + 1.0;
+  const double ln_m = 2.0 * s * t;
+  return (double)e + ln_m * SZO_INV_LN2;
+}
+
+double szo_exp2(double y) {
+  const double k = rint(y);
+  const double t = (y - k) * SZO_LN2; /* |t| <= ln(2)/2 */
+  /* exp(t) = 1 + t + t^2/2! + ... + t^18/18! */
+  double p = 1.0 / 6402373705728000.0;
+  p = p * t + 1.0 / 355687428096000.0;
+  p = p * t + 1.0 / 20922789888000.0;
+  p = p * t + 1.0 / 1307674368000.0;
+  p = p * t + 1.0 / 87178291200.0;
+  p = p * t + 1.0 / 6227020800.0;
+  p = p * t + 1.0 / 479001600.0;
+  p = p * t + 1.0 / 39916800.0;
+  p = p * t + 1.0 / 3628800.0;
+  p = p * t + 1.0 / 362880.0;
+  p = p * t + 1.0 / 40320.0;
+  p = p * t + 1.0 / 5040.0;
+  p = p * t + 1.0 / 720.0;
+  p = p * t + 1.0 / 120.0;
+  p = p * t + 1.0 / 24.0;
+  p = p * t + 1.0 / 6.0;
+  p = p * t + 0.5;
+  p = p * t + 1.0;
+  p = p * t + 1.0;
+  return ldexp(p, (int)k);
+}
+
+double szo_pwrel_delta(double eps, int dtype) {
+  if (!(eps > 0.0) || !(eps < 1.0)) return -1.0;
+  const double u = dtype == SZO_F64 ? 0x1p-53 : 0x1p-24;
+  const double r = (1.0 + eps) / (1.0 + 4.0 * u);
+  if (!(r > 1.0)) return -1.0;
+  return szo_log2(r) * (1.0 - 0x1p-20);
+}
+
+/* the log-domain value of one field value (widened to double) */
+static double log_of(double v, int dtype) {
+  if (isnan(v)) return NAN;
+  const double a = fabs(v);
+  if (isinf(a)) return INFINITY;
+  const double tmin = dtype == SZO_F64 ? 0x1p-1022 : 0x1p-126;
+  if (a < tmin) return SZO_LOG_ZERO;
+  return szo_log2(a);
+}
+
+/* one reconstructed value of T from its log-domain value and sign */
+static void exp_of(double y, int neg, int dtype, void* out, uint64_t i) {
+  if (dtype == SZO_F64) {
+    uint64_t bits;
+    if (isnan(y)) {
+      bits = 0x7FF8000000000000ull;
+    } else {
+      double v;
+      if (y == INFINITY)
+        v = INFINITY;
+      else if (y < SZO_LOG_ZERO_BELOW)
+        v = 0.0;
+      else if (y > 1100.0)
+        v = 0x1.fffffffffffffp+1023;
+      else {
+        v = szo_exp2(y);
+        if (v > 0x1.fffffffffffffp+1023) v = 0x1.fffffffffffffp+1023;
+      }
+      memcpy(&bits, &v, 8);
+    }
+    if (neg) bits |= 0x8000000000000000ull;
+    memcpy((uint8_t*)out + 8 * i, &bits, 8);
+  } else {
+    uint32_t bits;
+    if (isnan(y)) {
+      bits = 0x7FC00000u;
+    } else {
+      double v;
+      if (y == INFINITY)
+        v = INFINITY;
+      else if (y < SZO_LOG_ZERO_BELOW)
+        v = 0.0;
+      else if (y > 1100.0)
+        v = 0x1.fffffep+127;
+      else {
+        v = szo_exp2(y);
+        if (v > 0x1.fffffep+127) v = 0x1.fffffep+127;
+      }
+      const float f = (float)v;
+      memcpy(&bits, &f, 4);
+    }
+    if (neg) bits |= 0x80000000u;
+    memcpy((uint8_t*)out + 4 * i, &bits, 4);
+  }
+}
+
+static int sign_of(const void* x, int dtype, uint64_t i) {
+  if (dtype == SZO_F64) {
+    uint64_t b;
+    memcpy(&b, (const uint8_t*)x + 8 * i, 8);
+    return (int)(b >> 63);
+  }
+  uint32_t b;
+  memcpy(&b, (const uint8_t*)x + 4 * i, 4);
+  return (int)(b >> 31);
+}
+
+static int compress_pwrel(const void* x, int dtype, int ndim, const uint64_t* dims, double eps,
+                          int predictor, uint32_t radius, uint32_t chunk, uint32_t sub,
+                          const uint8_t* order, uint8_t** stream, uint64_t* stream_size,
+                          uint16_t* codes_out, void* recon_out) {
+  if (dtype != SZO_F32 && dtype != SZO_F64) return SZO_ERR_ARG;
+  const double delta = szo_pwrel_delta(eps, dtype);
+  if (!(delta > 0.0)) return SZO_ERR_ARG;
+  struct szo_grid g;
+  int rc = grid_init(&g, ndim, dims, order);
+  if (rc) return rc;
+  const uint64_t n = g.n, nsw = (n + 63) / 64;
+  double* y = (double*)malloc(sizeof(double) * (n ? n : 1));
+  double* yrec = (double*)malloc(sizeof(double) * (n ? n : 1));
+  uint64_t* signs = (uint64_t*)calloc(nsw ? nsw : 1, sizeof(uint64_t));
+  uint8_t* ys = NULL;
+  uint64_t ysize = 0;
+  if (!y || !yrec || !signs) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  int any = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    const double v = dtype == SZO_F64 ? ((const double*)x)[i] : (double)((const float*)x)[i];
+    y[i] = log_of(v, dtype);
+    if (sign_of(x, dtype, i)) {
+      signs[i / 64] |= 1ull << (i % 64);
+      any = 1;
+    }
+  }
+  /* the log field through the interpolation pipeline, absolute bound delta */
+  rc = szo_compress(y, SZO_F64, ndim, dims, SZO_ABS, delta, predictor, radius, chunk, sub, order,
+                    &ys, &ysize, codes_out, yrec);
+  if (rc) goto done;
+  {
+    const uint64_t off_signs = any ? pad8(ysize) : 0;
+    const uint64_t total = any ? off_signs + 8 * nsw : ysize;
+    uint8_t* out = (uint8_t*)calloc(total ? total : 1, 1);
+    if (!out) {
+      rc = SZO_ERR_NOMEM;
+      goto done;
+    }
+    memcpy(out, ys, ysize);
+    out[45] = SZO_PWREL;
+    put_f64(out + 48, eps);
+    put_u64(out + 96, total);
+    out[104] = (uint8_t)dtype; /* the field's type; the coded (log) field is f64 */
+    out[105] = (uint8_t)any;
+    put_u64(out + 112, off_signs);
+    for (uint64_t w = 0; w < (any ? nsw : 0); w++) put_u64(out + off_signs + 8 * w, signs[w]);
+    if (recon_out)
+      for (uint64_t i = 0; i < n; i++)
+        exp_of(yrec[i], (int)((signs[i / 64] >> (i % 64)) & 1), dtype, recon_out, i);
+    *stream = out;
+    *stream_size = total;
+  }
+done:
+  free(y);
+  free(yrec);
+  free(signs);
+  free(ys);
+  return rc;
+}
+
+static int decompress_pwrel(const uint8_t* s, uint64_t size, void* outp, uint64_t out_bytes,
+                            uint16_t* codes_out) {
+  const int out_dtype = s[104], any = s[105];
+  if (s[6] != SZO_F64 || out_dtype > 1 || any > 1) return SZO_ERR_CORRUPT;
+  for (int k = 106; k < 112; k++)
+    if (s[k]) return SZO_ERR_CORRUPT;
+  for (int k = 120; k < 128; k++)
+    if (s[k]) return SZO_ERR_CORRUPT;
+  const uint64_t total = get_u64(s + 96), off_signs = get_u64(s + 112);
+  if (total > size) return SZO_ERR_CORRUPT;
+  const int ndim = s[7];
+  if (ndim < 1 || ndim > 4) return SZO_ERR_CORRUPT;
+  uint64_t n = 1;
+  for (int d = 0; d < ndim; d++) {
+    const uint64_t e = get_u64(s + 8 + 8 * d);
+    if (e && n > UINT64_MAX / e) return SZO_ERR_CORRUPT;
+    n *= e;
+  }
+  const uint64_t nsw = (n + 63) / 64;
+  /* the log stream: its own header (absolute mode, its own size) */
+  uint64_t ysize;
+  if (any) {
+    if (off_signs < SZO_HEADER_BYTES || off_signs % 8 || off_signs + 8 * nsw != total)
+      return SZO_ERR_CORRUPT;
+    ysize = off_signs; /* (the log stream, padded to 8 bytes) */
+  } else {
+    if (off_signs != 0) return SZO_ERR_CORRUPT;
+    ysize = total;
+  }
+  const size_t ts = out_dtype == SZO_F64 ? 8 : 4;
+  if (out_bytes < n * ts) return SZO_ERR_CAPACITY;
+  uint8_t* ys = (uint8_t*)malloc(ysize);
+  double* y = (double*)malloc(sizeof(double) * (n ? n : 1));
+  int rc = SZO_OK;
+  if (!ys || !y) {
+    rc = SZO_ERR_NOMEM;
+    goto done;
+  }
+  memcpy(ys, s, ysize);
+  ys[45] = SZO_ABS;
+  memset(ys + 104, 0, 24);
+  {
+    /* the log stream's size: the layout's, which must land on ysize
+       (exactly, or padded to 8 when the sign section follows) */
+    const uint64_t ylen = get_u64(ys + 96);
+    (void)ylen;
+    const uint64_t K = get_u32(ys + 80), n_unpred = get_u64(ys + 72);
+    const uint32_t chunk = get_u32(ys + 68), sub = get_u32(ys + 84);
+    const uint64_t words = get_u64(ys + 88);
+    if (chunk == 0 || szo_check_sub(chunk, sub) || K > 65536 || n_unpred > n) {
+      rc = SZO_ERR_CORRUPT;
+      goto done;
+    }
+    struct layout lo;
+    layout_of(K, (n + chunk - 1) / chunk, sub, n_unpred, 8, words, &lo);
+    if (any ? pad8(lo.size) != ysize : lo.size != ysize) {
+      rc = SZO_ERR_CORRUPT;
+      goto done;
+    }
+    put_u64(ys + 96, lo.size);
+    rc = szo_decompress(ys, lo.size, y, sizeof(double) * n, codes_out);
+    if (rc) goto done;
+  }
+  for (uint64_t i = 0; i < n; i++) {
+    const int neg = any ? (int)((get_u64(s + off_signs + 8 * (i / 64)) >> (i % 64)) & 1) : 0;
+    exp_of(y[i], neg, out_dtype, outp, i);
+  }
+done:
+  free(ys);
+  free(y);
+  return rc;
+}
+
 int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
                  int eb_mode, double eb, int predictor, uint32_t radius,
                  uint32_t chunk, uint32_t sub, const uint8_t* order,
                  uint8_t** stream, uint64_t* stream_size, uint16_t* codes_out,
                  void* recon_out) {
+  if (eb_mode == SZO_PWREL)
+    return compress_pwrel(x, dtype, ndim, dims, eb, predictor, radius, chunk, sub, order, stream,
+                          stream_size, codes_out, recon_out);
   struct szo_grid g;
   int rc = check_common(dtype, predictor, radius);
   if (rc) return rc;
@@ -768,6 +1051,7 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
                    uint64_t out_bytes, uint16_t* codes_out) {
   if (!s || size < SZO_HEADER_BYTES) return SZO_ERR_CORRUPT;
   if (memcmp(s, "SZG1", 4) != 0 || get_u16(s + 4) != 1) return SZO_ERR_CORRUPT;
+  if (s[45] == SZO_PWREL) return decompress_pwrel(s, size, outp, out_bytes, codes_out);
   int dtype = s[6], ndim = s[7], predictor = s[40], eb_mode = s[45];
   if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 1 || eb_mode > 1)
     return SZO_ERR_CORRUPT;

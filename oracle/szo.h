@@ -44,7 +44,7 @@ extern "C" {
 #endif
 
 enum { SZO_F32 = 0, SZO_F64 = 1 };
-enum { SZO_ABS = 0, SZO_REL = 1 };
+enum { SZO_ABS = 0, SZO_REL = 1, SZO_PWREL = 2 };
 enum { SZO_LINEAR = 0, SZO_CUBIC = 1 };
 enum {
   SZO_OK = 0,
@@ -121,6 +121,23 @@ int szo_unpack(const uint32_t* words, uint64_t total_words,
                const uint32_t* chunk_words, uint64_t n, uint32_t chunk,
                uint32_t sub, const uint32_t* sub_bits, const uint8_t* lens,
                uint32_t nsym, uint16_t* codes);
+
+/* The logarithmic preprocessor of the point-wise relative mode (paper
+ * Section 3.1 and 3.2 "Preprocessor": the data go to the logarithmic domain
+ * and are compressed there with an absolute bound derived from the
+ * point-wise relative one).  The maps are written out from their series so
+ * that every implementation computes the same bits:
+ *   szo_log2(a), a finite and > 0: a = m 2^e with m in [sqrt(1/2), sqrt(2));
+ *     log2 a = e + ln(m) / ln 2, ln m = 2 atanh(s), s = (m - 1)/(m + 1),
+ *     atanh by its Maclaurin series to s^29 (Horner in s^2);
+ *   szo_exp2(y), y finite: y = k + f, k = rint(y), |f| <= 1/2;
+ *     2^y = 2^k exp(f ln 2), exp by its Taylor series to t^18 (Horner).
+ * szo_pwrel_delta: the log field's absolute bound for a point-wise relative
+ * bound eps of a T field: log2((1 + eps)/(1 + 4u)) (1 - 2^-20), u the unit
+ * roundoff of T; <= 0 (unusable) when eps is too small for T. */
+double szo_log2(double a);
+double szo_exp2(double y);
+double szo_pwrel_delta(double eps, int dtype);
 
 /* Whole pipeline.  order may be NULL (identity).  *stream is allocated with
  * malloc and must be released with szo_free.  codes_out / recon_out are

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libszg.so")
 
 F32, F64 = 0, 1
-ABS, REL = 0, 1
+ABS, REL, PWREL = 0, 1, 2
 LINEAR, CUBIC = 0, 1
 OK, ERR_ARG, ERR_DTYPE, ERR_CAPACITY, ERR_CORRUPT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7)
@@ -30,7 +30,8 @@ HEADER_BYTES = 128
 
 # every function declared in include/szg.h
 EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_options",
-           "sz_compress_bound", "sz_compress", "sz_decompress", "sz_inspect",
+           "sz_compress_bound", "sz_compress_bound_pwrel", "sz_compress", "sz_decompress",
+           "sz_inspect",
            "sz_compress_batch", "sz_set_timing", "sz_set_timing_family", "sz_timing_get",
            "sz_timing_reset",
            "sz_debug_codes", "sz_server_create", "sz_server_submit", "sz_server_poll",
@@ -60,7 +61,9 @@ class Info(ctypes.Structure):
                 ("eb_user", ctypes.c_double), ("eb", ctypes.c_double),
                 ("radius", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("sub", ctypes.c_uint32), ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
-                ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
+                ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64),
+                ("coded_dtype", ctypes.c_int), ("signs", ctypes.c_int),
+                ("off_signs", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -106,6 +109,8 @@ def lib():
     L.sz_default_options.restype = None
     L.sz_compress_bound.argtypes = [I, I, U64P, ctypes.POINTER(Options)]
     L.sz_compress_bound.restype = SZ
+    L.sz_compress_bound_pwrel.argtypes = [I, I, U64P, ctypes.POINTER(Options)]
+    L.sz_compress_bound_pwrel.restype = SZ
     L.sz_compress.argtypes = [P, P, I, I, U64P, I, D, I, ctypes.POINTER(Options), P, SZ,
                               ctypes.POINTER(SZ), P]
     L.sz_compress.restype = I
@@ -150,7 +155,7 @@ def lib():
 
 def _mode(v) -> int:
     if isinstance(v, str):
-        return {"abs": ABS, "rel": REL}[v.lower()]
+        return {"abs": ABS, "rel": REL, "pwrel": PWREL}[v.lower()]
     return int(v)
 
 
@@ -181,9 +186,10 @@ def _dims(shape):
 
 
 def compress_bound(shape, dtype: int = F32, radius: int = 32768, chunk: int = 4096,
-                   dim_order=None, subchunks: int = 0) -> int:
+                   dim_order=None, subchunks: int = 0, eb_mode=ABS) -> int:
     o = make_options(radius, chunk, dim_order, len(shape), subchunks)
-    return int(lib().sz_compress_bound(dtype, len(shape), _dims(shape), ctypes.byref(o)))
+    fn = lib().sz_compress_bound_pwrel if _mode(eb_mode) == PWREL else lib().sz_compress_bound
+    return int(fn(dtype, len(shape), _dims(shape), ctypes.byref(o)))
 
 
 def inspect(stream) -> dict:
@@ -296,7 +302,9 @@ class Context:
         opts = make_options(radius, chunk, dim_order, x.dim(), subchunks)
         dims = _dims(x.shape)
         if out is None:
-            cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), dims, ctypes.byref(opts)))
+            fn = (self._lib.sz_compress_bound_pwrel if _mode(eb_mode) == PWREL
+                  else self._lib.sz_compress_bound)
+            cap = int(fn(_dtype_code(x), x.dim(), dims, ctypes.byref(opts)))
             out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
         size = ctypes.c_size_t(0)
         rc = self._lib.sz_compress(self._h, ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
@@ -337,8 +345,9 @@ class Context:
         opts = make_options(radius, chunk, None, 4, subchunks)
         for i, (x, mode, eb, pred) in enumerate(fields):
             o1 = make_options(radius, chunk, None, x.dim(), subchunks)
-            cap = int(self._lib.sz_compress_bound(_dtype_code(x), x.dim(), _dims(x.shape),
-                                                  ctypes.byref(o1)))
+            fn = (self._lib.sz_compress_bound_pwrel if _mode(mode) == PWREL
+                  else self._lib.sz_compress_bound)
+            cap = int(fn(_dtype_code(x), x.dim(), _dims(x.shape), ctypes.byref(o1)))
             out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
             outs.append(out)
             f = arr[i]
@@ -422,7 +431,8 @@ class Server:
             raise ValueError("x must be a contiguous CUDA tensor")
         opts = make_options(radius, chunk, dim_order, x.dim(), subchunks)
         if out is None:
-            cap = compress_bound(tuple(x.shape), _dtype_code(x), radius, chunk, dim_order, subchunks)
+            cap = compress_bound(tuple(x.shape), _dtype_code(x), radius, chunk, dim_order, subchunks,
+                                 eb_mode)
             out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
         r = Request()
         r.kind = REQ_COMPRESS

@@ -52,6 +52,7 @@ struct sz_ctx {
   std::string err;
   // size-dependent scratch
   Buf rec, codes, chunk_words, chunk_unpred, word_off, unpred_off, block_sums;
+  Buf ylog, signs;  // point-wise relative mode: the log field and the sign words
   // fixed scratch
   Meta* meta = nullptr;
   uint32_t* hist = nullptr;
@@ -281,8 +282,24 @@ int parse_header(const uint8_t* h, sz_info* info) {
   in.ndim = h[7];
   in.predictor = h[40];
   in.eb_mode = h[45];
-  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 1 || in.eb_mode > 1)
+  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 1 || in.eb_mode > 2)
     return SZ_ERR_CORRUPT;
+  // point-wise relative mode: the coded field holds the logarithms (f64);
+  // bytes 104.. give the field's own dtype and the sign section
+  const bool pw = in.eb_mode == SZ_EB_PWREL;
+  in.coded_dtype = in.dtype;
+  in.signs = 0;
+  in.off_signs = 0;
+  if (pw) {
+    if (in.coded_dtype != SZ_F64 || h[104] > 1 || h[105] > 1) return SZ_ERR_CORRUPT;
+    for (int k = 106; k < 112; k++)
+      if (h[k]) return SZ_ERR_CORRUPT;
+    for (int k = 120; k < 128; k++)
+      if (h[k]) return SZ_ERR_CORRUPT;
+    in.dtype = h[104];
+    in.signs = h[105];
+    in.off_signs = get_le(h + 112, 8);
+  }
   uint64_t n = 1;
   bool empty = false;
   for (int d = 0; d < kMaxDims; d++) {
@@ -313,15 +330,20 @@ int parse_header(const uint8_t* h, sz_info* info) {
   in.total_words = get_le(h + 88, 8);
   in.stream_bytes = get_le(h + 96, 8);
   if (!(in.eb >= 0.0) || !__builtin_isfinite(in.eb)) return SZ_ERR_CORRUPT;
-  if (in.dtype == SZ_F32 && (double)(float)in.eb != in.eb) return SZ_ERR_CORRUPT;
+  if (in.coded_dtype == SZ_F32 && (double)(float)in.eb != in.eb) return SZ_ERR_CORRUPT;
   if (in.radius < 1 || in.radius > kMaxRadius || in.chunk == 0) return SZ_ERR_CORRUPT;
   if (!valid_sub(in.chunk, in.sub)) return SZ_ERR_CORRUPT;
   if (in.nsym > 2 * in.radius || in.n_unpred > n || (in.nsym == 0) != (n == 0)) return SZ_ERR_CORRUPT;
   if (in.total_words > 64 * (n + 1)) return SZ_ERR_CORRUPT;
   uint64_t nchunks = (n + in.chunk - 1) / in.chunk;
-  Layout l = stream_layout(in.nsym, nchunks, in.sub, in.n_unpred, in.dtype == SZ_F64 ? 8 : 4,
+  Layout l = stream_layout(in.nsym, nchunks, in.sub, in.n_unpred, in.coded_dtype == SZ_F64 ? 8 : 4,
                            in.total_words);
-  if (l.size != in.stream_bytes) return SZ_ERR_CORRUPT;
+  if (pw && in.signs) {
+    if (in.off_signs != pad8(l.size) || in.stream_bytes != in.off_signs + 8 * ((n + 63) / 64))
+      return SZ_ERR_CORRUPT;
+  } else if (in.off_signs != 0 || l.size != in.stream_bytes) {
+    return SZ_ERR_CORRUPT;
+  }
   *info = in;
   return SZ_OK;
 }
@@ -377,6 +399,11 @@ int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
 
 namespace szg {
 
+size_t pwrel_scratch_need(uint64_t n, bool compress) {
+  auto grown = [](uint64_t b) { return b + b / 8; };
+  return (size_t)(grown(n * 8) + (compress ? grown(((n + 63) / 64) * 8) : 0));
+}
+
 size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress) {
   auto grown = [](uint64_t b) { return b + b / 8; };  // what ensure() allocates
   const uint64_t nch = chunk ? (n + chunk - 1) / chunk : 0;
@@ -389,7 +416,8 @@ size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress) {
 size_t ctx_scratch_bytes(const sz_ctx* ctx) {
   size_t t = 0;
   for (const Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred,
-                       &ctx->word_off, &ctx->unpred_off, &ctx->block_sums})
+                       &ctx->word_off, &ctx->unpred_off, &ctx->block_sums, &ctx->ylog,
+                       &ctx->signs})
     t += b->cap;
   return t;
 }
@@ -397,7 +425,7 @@ size_t ctx_scratch_bytes(const sz_ctx* ctx) {
 void ctx_trim(sz_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
-                 &ctx->unpred_off, &ctx->block_sums}) {
+                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->cap = 0;
@@ -479,14 +507,22 @@ size_t sz_compress_bound(int dtype, int ndim, const uint64_t* dims, const sz_opt
   return (size_t)l.size;
 }
 
+size_t sz_compress_bound_pwrel(int dtype, int ndim, const uint64_t* dims, const sz_options* opts) {
+  Shape s;
+  if (make_shape(nullptr, dtype, ndim, dims, opts, &s) != SZ_OK) return 0;
+  const size_t core = sz_compress_bound(SZ_F64, ndim, dims, opts);
+  if (core == 0) return 0;
+  return core + 8 + 8 * (size_t)((s.n + 63) / 64);
+}
+
 int sz_inspect(const void* h_stream, size_t len, sz_info* info) {
   if (!h_stream || !info || len < kHeaderBytes) return SZ_ERR_ARG;
   return parse_header(static_cast<const uint8_t*>(h_stream), info);
 }
 
-int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
-                int eb_mode, double eb, int predictor, const sz_options* opts, void* d_out,
-                size_t out_capacity, size_t* out_size, void* stream) {
+static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
+                         int eb_mode, double eb, int predictor, const sz_options* opts,
+                         void* d_out, size_t out_capacity, size_t* out_size, void* stream) {
   if (!ctx) return SZ_ERR_ARG;
   Shape s;
   int rc = make_shape(ctx, dtype, ndim, dims, opts, &s);
@@ -572,6 +608,64 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
   return SZ_OK;
 }
 
+// The point-wise relative mode: the logarithmic transform into the log
+// field (and the sign words), the log field through compress_core with the
+// absolute bound delta, then the sign section and the mode's header fields.
+static int compress_pwrel(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
+                          const uint64_t* dims, double eps, int predictor,
+                          const sz_options* opts, void* d_out, size_t out_capacity,
+                          size_t* out_size, void* stream) {
+  Shape s;
+  int rc = make_shape(ctx, dtype, ndim, dims, opts, &s);
+  if (rc) return rc;
+  if (!out_size) return fail(ctx, SZ_ERR_ARG, "out_size is NULL");
+  *out_size = 0;
+  const double delta = pwrel_delta(eps, dtype);
+  if (!(delta > 0.0))
+    return fail(ctx, SZ_ERR_ARG, "point-wise relative bound must be in (0, 1) and above the type's precision");
+  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC)
+    return fail(ctx, SZ_ERR_ARG, "bad predictor");
+  if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
+  if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
+    return fail(ctx, SZ_ERR_ARG, "d_in must be 16-byte and d_out 8-byte aligned");
+  CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t nsw = (s.n + 63) / 64;
+  CHECK_HIP(ensure(ctx->ylog, s.n * 8), "hipMalloc(ylog)");
+  CHECK_HIP(ensure(ctx->signs, nsw * 8), "hipMalloc(signs)");
+  double* y = static_cast<double*>(ctx->ylog.p);
+  uint64_t* signs = static_cast<uint64_t*>(ctx->signs.p);
+  uint32_t* any = reinterpret_cast<uint32_t*>(ctx->totals + 3);
+  CHECK_HIP(launch_fill_u32(any, 0, 2, st), "fill");
+  CHECK_HIP(launch_pwrel_forward(d_in, dtype, y, signs, s.n, any, st), "pwrel_forward");
+  size_t ylen = 0;
+  rc = compress_core(ctx, y, SZ_F64, ndim, dims, SZ_EB_ABS, delta, predictor, opts, d_out,
+                     out_capacity, &ylen, stream);
+  if (rc && rc != SZ_ERR_CAPACITY) return rc;
+  uint32_t any_h = 0;
+  CHECK_HIP(hipMemcpy(&any_h, any, sizeof(any_h), hipMemcpyDeviceToHost), "hipMemcpy");
+  const uint64_t off_signs = any_h ? pad8(ylen) : 0;
+  const uint64_t total = any_h ? off_signs + 8 * nsw : ylen;
+  *out_size = (size_t)total;
+  if (total > out_capacity) return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
+  CHECK_HIP(launch_pwrel_finish(static_cast<uint8_t*>(d_out), ylen, off_signs, signs, nsw, total,
+                                eps, dtype, st),
+            "pwrel_finish");
+  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return SZ_OK;
+}
+
+int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
+                int eb_mode, double eb, int predictor, const sz_options* opts, void* d_out,
+                size_t out_capacity, size_t* out_size, void* stream) {
+  if (!ctx) return SZ_ERR_ARG;
+  if (eb_mode == SZ_EB_PWREL)
+    return compress_pwrel(ctx, d_in, dtype, ndim, dims, eb, predictor, opts, d_out, out_capacity,
+                          out_size, stream);
+  return compress_core(ctx, d_in, dtype, ndim, dims, eb_mode, eb, predictor, opts, d_out,
+                       out_capacity, out_size, stream);
+}
+
 int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d_out,
                   size_t out_capacity, void* stream) {
   if (!ctx) return SZ_ERR_ARG;
@@ -587,7 +681,8 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   if (parse_header(ctx->h_header, &in) != SZ_OK) return fail(ctx, SZ_ERR_CORRUPT, "invalid header");
   if (in.stream_bytes > stream_size) return fail(ctx, SZ_ERR_CORRUPT, "stream truncated");
   Shape s;
-  s.dtype = in.dtype;
+  const bool pw = in.eb_mode == SZ_EB_PWREL;
+  s.dtype = in.coded_dtype;  // the pipeline decodes the coded field
   s.ndim = in.ndim;
   for (int d = 0; d < kMaxDims; d++) {
     s.dims[d] = in.dims[d];
@@ -598,9 +693,17 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   s.chunk = in.chunk;
   s.sub = in.sub;
   if (s.n && !d_out) return fail(ctx, SZ_ERR_ARG, "null output buffer");
-  if (out_capacity < s.n * s.tsize()) return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
+  if (out_capacity < s.n * (in.dtype == SZ_F64 ? 8 : 4))
+    return fail(ctx, SZ_ERR_CAPACITY, "output capacity too small");
   int rc = ensure_sized(ctx, s, false);
   if (rc) return rc;
+  // point-wise relative mode: the pipeline rebuilds the log field, then the
+  // inverse transform writes the field
+  void* field_out = d_out;
+  if (pw) {
+    CHECK_HIP(ensure(ctx->ylog, s.n * 8), "hipMalloc(ylog)");
+    d_out = ctx->ylog.p;
+  }
   const uint8_t* str = static_cast<const uint8_t*>(d_stream);
   const uint64_t nch = s.nchunks();
   Layout l = stream_layout(in.nsym, nch, s.sub, in.n_unpred, s.tsize(), in.total_words);
@@ -646,6 +749,12 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                 }
                 return e;
               }), "recon");
+    if (pw)
+      CHECK_HIP(launch_pwrel_inverse(static_cast<const double*>(d_out),
+                                     in.signs ? reinterpret_cast<const uint64_t*>(str + in.off_signs)
+                                              : nullptr,
+                                     s.n, in.dtype, field_out, st),
+                "pwrel_inverse");
   }
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");

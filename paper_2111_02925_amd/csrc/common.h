@@ -108,6 +108,8 @@ struct PassGeom {
 // Bytes a compression (or decompression) of n points allocates in a context
 // at most; the bytes a context holds now; freeing them; a context's fixed part.
 size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress);
+// the point-wise relative mode's extra scratch (the log field, the sign words)
+size_t pwrel_scratch_need(uint64_t n, bool compress);
 size_t ctx_scratch_bytes(const sz_ctx* ctx);
 void ctx_trim(sz_ctx* ctx);
 size_t ctx_fixed_bytes();
@@ -186,6 +188,17 @@ hipError_t launch_fine_compress(const void* x, int dtype, int predictor, void* r
                                 uint32_t radius, hipStream_t st);
 hipError_t launch_fine_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                              const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+
+// Point-wise relative mode (pwrel.hip): the log field's absolute bound, and
+// the transforms before and after the pipeline.
+double pwrel_delta(double eps, int dtype);
+hipError_t launch_pwrel_forward(const void* x, int dtype, double* y, uint64_t* signs, uint64_t n,
+                                uint32_t* any, hipStream_t st);
+hipError_t launch_pwrel_inverse(const double* y, const uint64_t* signs, uint64_t n, int dtype,
+                                void* out, hipStream_t st);
+hipError_t launch_pwrel_finish(uint8_t* out, uint64_t ylen, uint64_t off_signs,
+                               const uint64_t* signs, uint64_t nsw, uint64_t total, double eps,
+                               int dtype, hipStream_t st);
 
 hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, uint32_t* part,
                             uint32_t* hist, Meta* m, hipStream_t st);

@@ -166,11 +166,15 @@ int sz_server_submit(sz_server* s, const sz_request* r, uint64_t* ticket) {
     sz_options o;
     sz_default_options(&o);
     if (r->has_options) o = r->options;
-    const size_t bound = sz_compress_bound(r->dtype, r->ndim, r->dims, &o);
+    const bool pw = r->eb_mode == SZ_EB_PWREL;
+    const size_t bound = pw ? sz_compress_bound_pwrel(r->dtype, r->ndim, r->dims, &o)
+                            : sz_compress_bound(r->dtype, r->ndim, r->dims, &o);
     if (bound == 0) return SZ_ERR_ARG;
     uint64_t n = 1;
     for (int d = 0; d < r->ndim; d++) n *= r->dims[d];
-    need = scratch_need(n, r->dtype == SZ_F64 ? 8 : 4, o.chunk, true);
+    // (the point-wise relative mode codes a double field of logarithms)
+    need = pw ? scratch_need(n, 8, o.chunk, true) + pwrel_scratch_need(n, true)
+              : scratch_need(n, r->dtype == SZ_F64 ? 8 : 4, o.chunk, true);
   } else if (r->kind == SZ_REQ_DECOMPRESS) {
     if (!r->d_in || r->in_size < kHeaderBytes) return SZ_ERR_ARG;
     uint8_t h[kHeaderBytes];
@@ -178,7 +182,8 @@ int sz_server_submit(sz_server* s, const sz_request* r, uint64_t* ticket) {
     if (hipMemcpy(h, r->d_in, kHeaderBytes, hipMemcpyDeviceToHost) != hipSuccess) return SZ_ERR_DEVICE;
     sz_info info;
     if (sz_inspect(h, kHeaderBytes, &info) != SZ_OK) return SZ_ERR_CORRUPT;
-    need = scratch_need(info.n, info.dtype == SZ_F64 ? 8 : 4, info.chunk, false);
+    need = scratch_need(info.n, info.coded_dtype == SZ_F64 ? 8 : 4, info.chunk, false);
+    if (info.eb_mode == SZ_EB_PWREL) need += pwrel_scratch_need(info.n, false);
     out_bytes = info.n * (info.dtype == SZ_F64 ? 8 : 4);
   } else {
     return SZ_ERR_ARG;

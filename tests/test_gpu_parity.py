@@ -42,7 +42,7 @@ def check_case(ctx, orc, x, mode, eb, pred, radius=32768, chunk=4096, order=None
                sub=None):
     print(f"[case] {label} shape={x.shape} dtype={x.dtype} mode={mode} eb={eb} pred={pred} "
           f"R={radius} C={chunk} S={sub} order={order}", flush=True)
-    omode = {"abs": orc.ABS, "rel": orc.REL}[mode]
+    omode = {"abs": orc.ABS, "rel": orc.REL, "pwrel": orc.PWREL}[mode]
     ref, rcodes, rrec = orc.compress(x, omode, eb, pred, radius, chunk, order, want_debug=True,
                                      sub=sub)
     stream, codes, back = gpu_roundtrip(ctx, x, mode, eb, pred, radius, chunk, order, sub)
@@ -101,7 +101,40 @@ FINE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES + FINE_CASES, ids=[c[0] for c in CASES + FINE_CASES])
+def mixed_signs(shape, seed, dtype=np.float32):
+    """Both signs, exact zeros and six decades of magnitude."""
+    x = synth.random_field(shape, seed=seed, dtype=dtype)
+    x = (np.sign(x - np.median(x)) * np.exp(3 * x)).astype(dtype)
+    x.flat[::53] = 0
+    return x
+
+
+def specials(shape, seed):
+    x = lognormal(shape, seed)
+    x.flat[5] = np.inf
+    x.flat[77] = -np.inf
+    x.flat[123] = np.nan
+    x.flat[200] = np.float32(1e-40)
+    x.flat[201] = -0.0
+    x.flat[300] = -x.flat[300]
+    return x
+
+
+# The point-wise relative mode: the logarithmic preprocessor, the double log
+# field through the same kernels (the strip kernel's f64 variant where the
+# last extent is even), and the inverse transform with the sign section.
+PW_CASES = [
+    ("pw-lognormal-cubic-1e-3", lambda: lognormal((40, 36, 46), 51), "pwrel", 1e-3, 1, 32768, 4096, None),
+    ("pw-lognormal-linear-1e-2", lambda: lognormal((33, 27, 31), 52), "pwrel", 1e-2, 0, 32768, 4096, None),
+    ("pw-mixed-signs-zeros", lambda: mixed_signs((30, 28, 26), 53), "pwrel", 1e-3, 1, 32768, 4096, None),
+    ("pw-f64-2d", lambda: synth.climate_2d((91, 77), seed=54, dtype=np.float64), "pwrel", 1e-6, 1, 32768, 4096, None),
+    ("pw-specials", lambda: specials((20, 22, 24), 55), "pwrel", 1e-2, 1, 32768, 4096, None),
+    ("pw-R512-unpred", lambda: mixed_signs((24, 20, 18), 56), "pwrel", 1e-4, 1, 512, 1024, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES + FINE_CASES + PW_CASES,
+                         ids=[c[0] for c in CASES + FINE_CASES + PW_CASES])
 def test_parity(ctx, orc, case):
     label, gen, mode, eb, pred, radius, chunk, order = case
     x = gen()
