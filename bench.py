@@ -73,6 +73,40 @@ def workload_name(shape, args, sub):
             f"{sub} sub-chunks")
 
 
+def pwrel_measurement(szg, torch, np, ctx, xt, in_bytes, eps=1e-3, reps=3):
+    """The point-wise relative mode on the same field (logarithmic
+    preprocessor, the double log field through the same kernels, inverse
+    transform), outside the timed region: throughput of compress and of
+    decompress, ratio, and the largest point-wise relative error over the
+    normal values, which must not exceed eps.  (The CPU-baseline leg adds
+    a byte-for-byte comparison with the oracle on a 128^3 corner.)"""
+    cap = szg.compress_bound(tuple(xt.shape), szg.F32, eb_mode="pwrel")
+    out = torch.empty(cap, dtype=torch.uint8, device=xt.device)
+    rec = torch.empty_like(xt)
+    s = ctx.compress(xt, "pwrel", eps, "cubic", out=out)
+    ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s = ctx.compress(xt, "pwrel", eps, "cubic", out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    xd, rd = xt.double(), rec.double()
+    normal = torch.isfinite(xd) & (xd.abs() >= float(np.finfo(np.float32).tiny))
+    rel = float(((xd - rd).abs() / xd.abs())[normal].max().item())
+    del xd, rd
+    res = {"eps": eps, "workload": "the same field, point-wise relative bound, cubic",
+           "ratio": round(in_bytes / s.numel(), 4),
+           "compress_GBps": round(in_bytes * reps / (t1 - t0) / 1e9, 3),
+           "decompress_GBps": round(in_bytes * reps / (t2 - t1) / 1e9, 3),
+           "max_pointwise_rel_err": rel, "bound_holds": rel <= eps}
+    return res
+
+
 def lossless_measurement(szg, s, in_bytes, level=1):
     """The host lossless stage (zlib standing in for zstd) on the step's
     stream, outside the timed region: one thread of the host, the stream
@@ -277,6 +311,7 @@ def main():
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
     lossless = lossless_measurement(szg, s, in_bytes)
+    pwrel = pwrel_measurement(szg, torch, np, ctx, xt, in_bytes)
 
     cpu = None
     parity = None
@@ -292,6 +327,14 @@ def main():
         t3 = time.perf_counter()
         parity = (ref == bytes(s.cpu().numpy().tobytes())) and (
             back.tobytes() == rec.cpu().numpy().tobytes())
+        # the point-wise relative mode on a 128^3 corner, byte for byte
+        corner = np.ascontiguousarray(x[:128, :128, :128])
+        pref = oracle.compress(corner, oracle.PWREL, pwrel["eps"], oracle.CUBIC)
+        sc = ctx.compress(torch.from_numpy(corner).to(dev), "pwrel", pwrel["eps"], "cubic")
+        pback = ctx.decompress(sc)
+        pwrel["parity_with_oracle_128cubed"] = (
+            bytes(sc.cpu().numpy().tobytes()) == pref
+            and pback.cpu().numpy().tobytes() == oracle.decompress(pref).tobytes())
         cpu = {"value": round(in_bytes / (t3 - t1) / 1e9, 4), "unit": "GB/s", "cores": 1,
                "kind": "oracle",
                "sample": f"the full {shape} field: one compress ({t2 - t1:.1f}s) + one "
@@ -327,6 +370,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "lossless": lossless,
+        "pwrel": pwrel,
         "parity_with_oracle": parity,
     }
     print(json.dumps(res), flush=True)
