@@ -107,6 +107,36 @@ def pwrel_measurement(szg, torch, np, ctx, xt, in_bytes, eps=1e-3, reps=3):
     return res
 
 
+def adaptive_measurement(szg, torch, ctx, xt, in_bytes, rel, chunk, reps=3):
+    """Adaptive interpolation on the same field and bound, outside the timed
+    region: each level's predictor chosen from the two cost sums, throughput
+    of compress (estimation included) and of decompress, ratio, the level
+    mask, and the largest error over the bound."""
+    cap = szg.compress_bound(tuple(xt.shape), szg.F32, 32768, chunk)
+    out = torch.empty(cap, dtype=torch.uint8, device=xt.device)
+    rec = torch.empty_like(xt)
+    s = ctx.compress(xt, "rel", rel, "adaptive", chunk=chunk, out=out)
+    ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s = ctx.compress(xt, "rel", rel, "adaptive", chunk=chunk, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = szg.inspect(s[:128].cpu())
+    err = float((xt.double() - rec.double()).abs().max().item())
+    return {"workload": "the same field and bound, adaptive linear/cubic per level",
+            "ratio": round(in_bytes / s.numel(), 4),
+            "level_mask": bin(info["level_mask"]),
+            "compress_GBps": round(in_bytes * reps / (t1 - t0) / 1e9, 3),
+            "decompress_GBps": round(in_bytes * reps / (t2 - t1) / 1e9, 3),
+            "max_abs_err_over_eb": err / info["eb"] if info["eb"] > 0 else 0.0}
+
+
 def lossless_measurement(szg, s, in_bytes, level=1):
     """The host lossless stage (zlib standing in for zstd) on the step's
     stream, outside the timed region: one thread of the host, the stream
@@ -312,6 +342,7 @@ def main():
                                                            args.batch_workers)
     lossless = lossless_measurement(szg, s, in_bytes)
     pwrel = pwrel_measurement(szg, torch, np, ctx, xt, in_bytes)
+    adaptive = adaptive_measurement(szg, torch, ctx, xt, in_bytes, args.rel, args.chunk)
 
     cpu = None
     parity = None
@@ -371,6 +402,7 @@ def main():
         "batched": batched,
         "lossless": lossless,
         "pwrel": pwrel,
+        "adaptive": adaptive,
         "parity_with_oracle": parity,
     }
     print(json.dumps(res), flush=True)

@@ -59,8 +59,14 @@ typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1, SZ_EB_PWREL = 2 } sz_eb_mode;
 
 /* Interpolation along each dimension (Section 6.2, SZ3-Interp): linear
  * (midpoint of the two neighbours at +-s) or cubic (4-point Lagrange
- * midpoint rule, quadratic or linear near the boundary). */
-typedef enum { SZ_INTERP_LINEAR = 0, SZ_INTERP_CUBIC = 1 } sz_predictor;
+ * midpoint rule, quadratic or linear near the boundary).  SZ_INTERP_ADAPTIVE
+ * picks one of the two per level before compressing (SZ3-Interp selects
+ * among its interpolation predictors): every point of the level is
+ * predicted both ways from the original values, its cost is the quantizer's
+ * bin index |k| capped at the radius, and the level takes cubic unless its
+ * linear cost sum is smaller.  The choice is stored in the stream (a bit per
+ * level) and costs one extra read of the field and one host round trip. */
+typedef enum { SZ_INTERP_LINEAR = 0, SZ_INTERP_CUBIC = 1, SZ_INTERP_ADAPTIVE = 2 } sz_predictor;
 
 typedef enum {
   SZ_OK = 0,
@@ -110,6 +116,8 @@ typedef struct {
                           logarithms) in the point-wise relative mode */
   int signs;           /* point-wise relative mode: 1 if a sign section follows */
   uint64_t off_signs;  /* byte offset of that section (0 if none) */
+  uint32_t level_mask; /* adaptive predictor: bit l - 1 set when level l
+                          (stride 2^(l-1)) is cubic; 0 otherwise */
 } sz_info;
 
 typedef struct sz_ctx sz_ctx;

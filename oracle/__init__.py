@@ -23,7 +23,7 @@ DEPS = SOURCES + [os.path.join(_HERE, "szo.h"), os.path.join(_HERE, "szo_typed.i
 
 F32, F64 = 0, 1
 ABS, REL, PWREL = 0, 1, 2
-LINEAR, CUBIC = 0, 1
+LINEAR, CUBIC, ADAPTIVE = 0, 1, 2
 OK, ERR_ARG, ERR_CAPACITY, ERR_CORRUPT, ERR_NOMEM = 0, -1, -3, -4, -6
 HEADER_BYTES = 128
 
@@ -322,6 +322,7 @@ def parse_header(stream: bytes) -> dict:
         radius=u32(64), chunk=u32(68), n_unpred=u64(72), nsym=u32(80), sub=u32(84),
         total_words=u64(88), stream_bytes=u64(96),
         out_dtype=b[104] if b[45] == PWREL else b[6], signs=b[105], off_signs=u64(112),
+        level_mask=u32(124),
     )
 
 

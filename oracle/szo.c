@@ -192,9 +192,30 @@ int szo_resolve_eb(const void* x, uint64_t n, int dtype, int eb_mode,
 
 static int check_common(int dtype, int predictor, uint32_t radius) {
   if (dtype != SZO_F32 && dtype != SZO_F64) return SZO_ERR_ARG;
-  if (predictor != SZO_LINEAR && predictor != SZO_CUBIC) return SZO_ERR_ARG;
+  if (predictor != SZO_LINEAR && predictor != SZO_CUBIC && predictor != SZO_ADAPTIVE)
+    return SZO_ERR_ARG;
   if (radius < 1 || radius > SZO_MAX_RADIUS) return SZO_ERR_ARG;
   return SZO_OK;
+}
+
+/* The predictor of every level: the fixed one, or (SZO_ADAPTIVE) the one
+ * choose_levels picks from the original values. */
+static void level_predictors(const void* x, int dtype, const struct szo_grid* g, int predictor,
+                             double eb_t, uint32_t radius, uint8_t* level_pred) {
+  memset(level_pred, predictor == SZO_ADAPTIVE ? SZO_CUBIC : predictor, 64);
+  if (predictor != SZO_ADAPTIVE) return;
+  if (dtype == SZO_F32)
+    choose_levels_f32((const float*)x, g, (float)eb_t, radius, level_pred);
+  else
+    choose_levels_f64((const double*)x, g, eb_t, radius, level_pred);
+}
+
+/* bit l - 1 set: level l is cubic */
+static uint32_t level_mask(const uint8_t* level_pred, int levels) {
+  uint32_t mask = 0;
+  for (int l = 1; l <= levels; l++)
+    if (level_pred[l] == SZO_CUBIC) mask |= 1u << (l - 1);
+  return mask;
 }
 
 int szo_predict_quantize(const void* x, int dtype, int ndim,
@@ -206,11 +227,22 @@ int szo_predict_quantize(const void* x, int dtype, int ndim,
   if (rc) return rc;
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
   if (!(eb_t >= 0.0) || !isfinite(eb_t)) return SZO_ERR_ARG;
+  uint8_t lp[64];
+  level_predictors(x, dtype, &g, predictor, eb_t, radius, lp);
   if (dtype == SZO_F32)
-    return predict_quantize_f32((const float*)x, &g, predictor, (float)eb_t,
-                                radius, codes, (float*)recon);
-  return predict_quantize_f64((const double*)x, &g, predictor, eb_t, radius,
-                              codes, (double*)recon);
+    return predict_quantize_f32((const float*)x, &g, lp, (float)eb_t, radius, codes,
+                                (float*)recon);
+  return predict_quantize_f64((const double*)x, &g, lp, eb_t, radius, codes, (double*)recon);
+}
+
+static int reconstruct_levels(const uint16_t* codes, const void* unpred, uint64_t n_unpred,
+                              int dtype, const struct szo_grid* g, const uint8_t* lp,
+                              double eb_t, uint32_t radius, void* out) {
+  if (dtype == SZO_F32)
+    return reconstruct_f32(codes, (const float*)unpred, n_unpred, g, lp, (float)eb_t, radius,
+                           (float*)out);
+  return reconstruct_f64(codes, (const double*)unpred, n_unpred, g, lp, eb_t, radius,
+                         (double*)out);
 }
 
 int szo_reconstruct(const uint16_t* codes, const void* unpred,
@@ -220,12 +252,11 @@ int szo_reconstruct(const uint16_t* codes, const void* unpred,
   struct szo_grid g;
   int rc = check_common(dtype, predictor, radius);
   if (rc) return rc;
+  if (predictor == SZO_ADAPTIVE) return SZO_ERR_ARG; /* (needs the stream's level mask) */
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
-  if (dtype == SZO_F32)
-    return reconstruct_f32(codes, (const float*)unpred, n_unpred, &g,
-                           predictor, (float)eb_t, radius, (float*)out);
-  return reconstruct_f64(codes, (const double*)unpred, n_unpred, &g, predictor,
-                         eb_t, radius, (double*)out);
+  uint8_t lp[64];
+  memset(lp, predictor, 64);
+  return reconstruct_levels(codes, unpred, n_unpred, dtype, &g, lp, eb_t, radius, out);
 }
 
 int szo_quantize_one(int dtype, const void* x, const void* pred, double eb_t,
@@ -861,7 +892,7 @@ static int decompress_pwrel(const uint8_t* s, uint64_t size, void* outp, uint64_
   if (s[6] != SZO_F64 || out_dtype > 1 || any > 1) return SZO_ERR_CORRUPT;
   for (int k = 106; k < 112; k++)
     if (s[k]) return SZO_ERR_CORRUPT;
-  for (int k = 120; k < 128; k++)
+  for (int k = 120; k < 124; k++)
     if (s[k]) return SZO_ERR_CORRUPT;
   const uint64_t total = get_u64(s + 96), off_signs = get_u64(s + 112);
   if (total > size) return SZO_ERR_CORRUPT;
@@ -895,7 +926,7 @@ static int decompress_pwrel(const uint8_t* s, uint64_t size, void* outp, uint64_
   }
   memcpy(ys, s, ysize);
   ys[45] = SZO_ABS;
-  memset(ys + 104, 0, 24);
+  memset(ys + 104, 0, 20); /* (bytes 124.. keep the level mask) */
   {
     /* the log stream's size: the layout's, which must land on ysize
        (exactly, or padded to 8 when the sign section follows) */
@@ -962,9 +993,15 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
     rc = SZO_ERR_NOMEM;
     goto done;
   }
-  /* Algorithm 1: predict + quantize every point */
-  rc = szo_predict_quantize(x, dtype, ndim, dims, g.order, predictor, eb_t,
-                            radius, codes, recon);
+  /* Algorithm 1: predict + quantize every point (adaptive: each level's
+     predictor chosen first) */
+  uint8_t lp[64];
+  level_predictors(x, dtype, &g, predictor, eb_t, radius, lp);
+  if (dtype == SZO_F32)
+    rc = predict_quantize_f32((const float*)x, &g, lp, (float)eb_t, radius, codes,
+                              (float*)recon);
+  else
+    rc = predict_quantize_f64((const double*)x, &g, lp, eb_t, radius, codes, (double*)recon);
   if (rc) goto done;
   /* Huffman: frequencies -> lengths -> canonical codebook */
   if ((rc = szo_histogram(codes, n, nsym, hist))) goto done;
@@ -1009,6 +1046,7 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   put_u32(out + 84, sub);
   put_u64(out + 88, total_words);
   put_u64(out + 96, lo.size);
+  if (predictor == SZO_ADAPTIVE) put_u32(out + 124, level_mask(lp, g.levels));
   /* encoder.save: the code lengths, ascending symbol */
   uint64_t k = 0;
   for (uint32_t s = 0; s < nsym; s++)
@@ -1053,7 +1091,7 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
   if (memcmp(s, "SZG1", 4) != 0 || get_u16(s + 4) != 1) return SZO_ERR_CORRUPT;
   if (s[45] == SZO_PWREL) return decompress_pwrel(s, size, outp, out_bytes, codes_out);
   int dtype = s[6], ndim = s[7], predictor = s[40], eb_mode = s[45];
-  if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 1 || eb_mode > 1)
+  if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 2 || eb_mode > 1)
     return SZO_ERR_CORRUPT;
   uint64_t dims[4];
   uint8_t order[4];
@@ -1144,8 +1182,24 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
       goto done;
     }
   }
-  rc = szo_reconstruct(codes, unpred, n_unpred, dtype, ndim, g.dims, g.order,
-                       predictor, eb_t, radius, outp);
+  {
+    /* each level's predictor: the fixed one, or the stream's level mask
+       (adaptive; bits past the last level must be clear) */
+    uint8_t lp[64];
+    memset(lp, predictor == SZO_ADAPTIVE ? SZO_LINEAR : predictor, 64);
+    const uint32_t mask = get_u32(s + 124);
+    if (predictor == SZO_ADAPTIVE) {
+      if (g.levels < 32 && (mask >> g.levels) != 0) {
+        rc = SZO_ERR_CORRUPT;
+        goto done;
+      }
+      for (int l = 1; l <= g.levels; l++) lp[l] = (mask >> (l - 1)) & 1 ? SZO_CUBIC : SZO_LINEAR;
+    } else if (mask != 0) {
+      rc = SZO_ERR_CORRUPT;
+      goto done;
+    }
+    rc = reconstruct_levels(codes, unpred, n_unpred, dtype, &g, lp, eb_t, radius, outp);
+  }
   if (!rc && codes_out) memcpy(codes_out, codes, sizeof(uint16_t) * n);
 done:
   free(lens);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libszg.so")
 
 F32, F64 = 0, 1
 ABS, REL, PWREL = 0, 1, 2
-LINEAR, CUBIC = 0, 1
+LINEAR, CUBIC, ADAPTIVE = 0, 1, 2
 OK, ERR_ARG, ERR_DTYPE, ERR_CAPACITY, ERR_CORRUPT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7)
 STATUS_NAMES = {0: "SZ_OK", -1: "SZ_ERR_ARG", -2: "SZ_ERR_DTYPE", -3: "SZ_ERR_CAPACITY",
@@ -63,7 +63,7 @@ class Info(ctypes.Structure):
                 ("sub", ctypes.c_uint32), ("n_unpred", ctypes.c_uint64), ("nsym", ctypes.c_uint32),
                 ("total_words", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64),
                 ("coded_dtype", ctypes.c_int), ("signs", ctypes.c_int),
-                ("off_signs", ctypes.c_uint64)]
+                ("off_signs", ctypes.c_uint64), ("level_mask", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -161,7 +161,7 @@ def _mode(v) -> int:
 
 def _pred(v) -> int:
     if isinstance(v, str):
-        return {"linear": LINEAR, "cubic": CUBIC}[v.lower()]
+        return {"linear": LINEAR, "cubic": CUBIC, "adaptive": ADAPTIVE}[v.lower()]
     return int(v)
 
 

@@ -61,6 +61,7 @@ struct sz_ctx {
   uint8_t* enc_len = nullptr;
   uint32_t* symtab = nullptr;
   uint64_t* totals = nullptr;
+  uint64_t* lvl_cost = nullptr;  // adaptive interpolation: [level][linear, cubic] cost sums
   CodebookScratch cb{};
   DecodeTables dt{};
   Meta* h_meta = nullptr;       // pinned
@@ -203,17 +204,23 @@ int make_shape(sz_ctx* c, int dtype, int ndim, const uint64_t* dims, const sz_op
   return SZ_OK;
 }
 
+// The number of levels: L = max over dimensions of ceil(log2 n_d).
+int level_count(int ndim, const uint64_t* dims) {
+  int L = 0;
+  for (int d = 0; d < ndim; d++) {
+    int l = 0;
+    while (l < 63 && (1ull << l) < dims[d]) l++;
+    L = l > L ? l : L;
+  }
+  return L;
+}
+
 // The (level, dimension) passes of the multilevel traversal in execution
 // order: levels L..1 with stride s = 2^(l-1), and inside a level the
 // dimensions in `order`.  The origin is handled separately.
 void build_passes(const Shape& s, std::vector<PassGeom>& out) {
   out.clear();
-  int L = 0;
-  for (int d = 0; d < s.ndim; d++) {
-    int l = 0;
-    while ((1ull << l) < s.dims[d]) l++;
-    L = std::max(L, l);
-  }
+  const int L = level_count(s.ndim, s.dims);
   uint64_t stride[kMaxDims];
   uint64_t st = 1;
   for (int d = s.ndim - 1; d >= 0; d--) {
@@ -282,8 +289,10 @@ int parse_header(const uint8_t* h, sz_info* info) {
   in.ndim = h[7];
   in.predictor = h[40];
   in.eb_mode = h[45];
-  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 1 || in.eb_mode > 2)
+  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 2 || in.eb_mode > 2)
     return SZ_ERR_CORRUPT;
+  // adaptive interpolation: bit l - 1 of the level mask set = level l cubic
+  in.level_mask = (uint32_t)get_le(h + 124, 4);
   // point-wise relative mode: the coded field holds the logarithms (f64);
   // bytes 104.. give the field's own dtype and the sign section
   const bool pw = in.eb_mode == SZ_EB_PWREL;
@@ -294,7 +303,7 @@ int parse_header(const uint8_t* h, sz_info* info) {
     if (in.coded_dtype != SZ_F64 || h[104] > 1 || h[105] > 1) return SZ_ERR_CORRUPT;
     for (int k = 106; k < 112; k++)
       if (h[k]) return SZ_ERR_CORRUPT;
-    for (int k = 120; k < 128; k++)
+    for (int k = 120; k < 124; k++)
       if (h[k]) return SZ_ERR_CORRUPT;
     in.dtype = h[104];
     in.signs = h[105];
@@ -318,6 +327,12 @@ int parse_header(const uint8_t* h, sz_info* info) {
     }
   }
   in.n = n;
+  {
+    const int L = level_count(in.ndim, in.dims);
+    if (in.predictor == SZ_INTERP_ADAPTIVE ? (L < 32 && (in.level_mask >> L) != 0)
+                                           : in.level_mask != 0)
+      return SZ_ERR_CORRUPT;
+  }
   uint64_t u = get_le(h + 48, 8);
   memcpy(&in.eb_user, &u, 8);
   u = get_le(h + 56, 8);
@@ -357,6 +372,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->enc_len, kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->symtab, sizeof(uint32_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->totals, sizeof(uint64_t) * 4), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * 2 * kMaxLevels), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_a, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_b, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.w, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
@@ -530,7 +546,8 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   if (!out_size) return fail(ctx, SZ_ERR_ARG, "out_size is NULL");
   *out_size = 0;
   if (eb_mode != SZ_EB_ABS && eb_mode != SZ_EB_REL) return fail(ctx, SZ_ERR_ARG, "bad eb_mode");
-  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC)
+  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
+      predictor != SZ_INTERP_ADAPTIVE)
     return fail(ctx, SZ_ERR_ARG, "bad predictor");
   if (!(eb >= 0.0) || !__builtin_isfinite(eb)) return fail(ctx, SZ_ERR_ARG, "eb must be finite and >= 0");
   if (eb_mode == SZ_EB_ABS && dtype == SZ_F32 && !__builtin_isfinite((float)eb))
@@ -553,6 +570,30 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     CHECK_HIP(timed(ctx, "minmax", st, [&] { return launch_minmax(d_in, dtype, s.n, ctx->meta, st); }),
               "minmax");
   CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st), "resolve_eb");
+  // each level's predictor: the fixed one, or (adaptive) the cheaper one by
+  // the levels' cost sums (cubic on ties), recorded as a mask in the header
+  int lvl_pred[kMaxLevels + 1];
+  for (int l = 0; l <= kMaxLevels; l++)
+    lvl_pred[l] = predictor == SZ_INTERP_ADAPTIVE ? SZ_INTERP_CUBIC : predictor;
+  if (predictor == SZ_INTERP_ADAPTIVE && s.n) {
+    CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0, 4 * kMaxLevels, st),
+              "fill");
+    const EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);
+    CHECK_HIP(timed(ctx, "estimate", st, [&] {
+                return launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, ctx->lvl_cost, st);
+              }), "estimate");
+    uint64_t cost[2 * kMaxLevels];
+    CHECK_HIP(hipMemcpyAsync(cost, ctx->lvl_cost, sizeof(cost), hipMemcpyDeviceToHost, st),
+              "memcpy");
+    CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    uint32_t mask = 0;
+    for (int l = 1; l <= kMaxLevels; l++) {
+      lvl_pred[l] = cost[2 * (l - 1) + 1] <= cost[2 * (l - 1)] ? SZ_INTERP_CUBIC : SZ_INTERP_LINEAR;
+      if (lvl_pred[l] == SZ_INTERP_CUBIC && l <= level_count(s.ndim, s.dims)) mask |= 1u << (l - 1);
+    }
+    put_le(hdr + 124, mask, 4);
+  }
+  auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
   if (s.n) {
     // the origin and every level, timed as one region
     CHECK_HIP(timed(ctx, "interp", st, [&] {
@@ -564,14 +605,14 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                   // the finest level's reconstruction is not read by anything later
                   for (const LevelGeom& g : levels)
                     if (e == hipSuccess)
-                      e = launch_level_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                      e = launch_level_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
                                                 ctx->meta, s.radius, g.s > 1, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);
                   for (const PassGeom& g : passes)
                     if (e == hipSuccess)
-                      e = launch_pass_compress(d_in, dtype, predictor, ctx->rec.p, codes, g,
+                      e = launch_pass_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
                                                ctx->meta, s.radius, st);
                 }
                 return e;
@@ -623,7 +664,8 @@ static int compress_pwrel(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
   const double delta = pwrel_delta(eps, dtype);
   if (!(delta > 0.0))
     return fail(ctx, SZ_ERR_ARG, "point-wise relative bound must be in (0, 1) and above the type's precision");
-  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC)
+  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
+      predictor != SZ_INTERP_ADAPTIVE)
     return fail(ctx, SZ_ERR_ARG, "bad predictor");
   if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
   if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
@@ -730,6 +772,12 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                                             s.dtype, cwords, cunp,
                                             woff, uoff, ctx->dt, codes, d_out, ctx->meta, st);
               }), "decode");
+    int lvl_pred[kMaxLevels + 1];
+    for (int l = 0; l <= kMaxLevels; l++)
+      lvl_pred[l] = in.predictor != SZ_INTERP_ADAPTIVE   ? in.predictor
+                    : l >= 1 && ((in.level_mask >> (l - 1)) & 1u) ? SZ_INTERP_CUBIC
+                                                                    : SZ_INTERP_LINEAR;
+    auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
     CHECK_HIP(timed(ctx, "recon", st, [&] {
                 hipError_t e = launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
                 std::vector<LevelGeom> levels;
@@ -737,14 +785,14 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                     plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
                   for (const LevelGeom& g : levels)
                     if (e == hipSuccess)
-                      e = launch_level_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                      e = launch_level_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                              s.radius, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);
                   for (const PassGeom& g : passes)
                     if (e == hipSuccess)
-                      e = launch_pass_recon(codes, s.dtype, in.predictor, d_out, g, in.eb,
+                      e = launch_pass_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                             s.radius, st);
                 }
                 return e;

@@ -92,6 +92,8 @@ constexpr uint32_t kStatusCountMismatch = 1u << 3;
 // points whose coordinate along `d` is an odd multiple of s, whose coordinates
 // along dimensions visited earlier in the level are multiples of s, and later
 // ones multiples of 2s.
+constexpr int kMaxLevels = 32;  // levels of a field of fewer than 2^32 points per dimension
+
 struct PassGeom {
   int ndim;
   int d;
@@ -124,6 +126,21 @@ hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStre
 
 hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t* codes,
                                   const Meta* m, uint32_t radius, hipStream_t st);
+// adaptive interpolation: every level's cost sums under both predictors in
+// one launch, added to cost[2 (l - 1)] (linear) and cost[2 (l - 1) + 1]
+// (cubic) for level l
+struct EstGeom {
+  int ndim;
+  uint64_t dims[kMaxDims];
+  uint64_t stride[kMaxDims];
+  uint8_t pos[kMaxDims];  // position of each dimension in the traversal order
+  uint32_t pairs;         // column pairs a lane takes per unit (1, 2 or 4)
+  uint64_t segs;          // units per row along the last dimension
+  uint64_t units;         // rows x segs
+};
+EstGeom make_estimate_geom(int ndim, const uint64_t* dims, const uint8_t* order);
+hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
+                           uint32_t radius, uint64_t* cost, hipStream_t st);
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const PassGeom& g, const Meta* m,
                                 uint32_t radius, hipStream_t st);

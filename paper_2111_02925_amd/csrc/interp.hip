@@ -270,6 +270,290 @@ hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t*
   return hipGetLastError();
 }
 
+// Adaptive interpolation: every level's cost under both predictors, from the
+// ORIGINAL values at the stencil points (the level's choice is made on the
+// host from these sums).  A point's cost under a predictor is the quantizer's
+// bin index |k| = rint(|x - pred| / (2 eb)) capped at R (R when not finite;
+// with eb = 0, 0 for an exact prediction and R otherwise).  Integer sums, so
+// the order of accumulation does not change them.
+//
+// One launch covers every level: a point q other than the origin belongs to
+// level t + 1, t = min over dimensions of ctz(q_e) (ctz(0) counting as
+// infinite), and to the pass of that level along the dimension d, last in
+// the traversal order, with ctz(q_d) = t (earlier dimensions of the order are
+// at multiples of s = 2^t there, later ones at multiples of 2s).
+//
+// Work units are segments of one row along the last dimension; a lane takes
+// pairs of columns (even, odd).  With t_row the fewest trailing zeros among
+// the row's other coordinates (d_row that dimension, last in the order):
+//  - the odd column is on level 1, along the row when t_row > 0 or the last
+//    dimension comes after d_row in the order, else along d_row;
+//  - the even column is on level 1 along d_row when t_row = 0, and on a
+//    coarser level otherwise (a quarter of the rows in 3-D: 1/8 of the
+//    points), where each lane finds its own level and dimension.
+// So 7/8 of the points take a path with block-uniform geometry.  Blocks of
+// one XCD (dealt round-robin, block b on XCD b mod 8) share one contiguous
+// eighth of the units and step through it together, neighbouring blocks on
+// neighbouring rows, so the rows and planes the stencils reach are read by
+// blocks of the same XCD at about the same time.  Flat indices fit 32 bits
+// (fields hold fewer than 2^32 points).
+constexpr uint32_t kEstThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ uint32_t est_cost(T d, T eb, T inv2eb, uint32_t R) {
+  if (eb == T(0)) return d == T(0) ? 0u : R;
+  const T k = rint_t(fabs_t(d) * inv2eb);
+  return k < (T)R ? (uint32_t)k : R;  // (NaN: R)
+}
+
+// Both costs of the point at flat index f predicted along a dimension with
+// flat step sd (= s x stride), position i and extent nd.  Where the whole
+// wave is away from the ends (both neighbours on each side), the two
+// interior rules alone are evaluated.
+template <typename T>
+__device__ __forceinline__ void est_point(const T* __restrict__ x, uint32_t f, uint32_t i,
+                                          uint32_t nd, uint32_t s, uint32_t sd, T eb, T inv2eb,
+                                          uint32_t R, uint32_t& cl, uint32_t& cc) {
+  // i >= s and i < nd; the comparisons avoid 32-bit overflow
+  const bool ha = ((i - s) >> 1) >= s;                 // i >= 3s
+  const bool hc = nd - i > s;                          // i + s < nd
+  const bool he = hc && ((nd - i - s - 1) >> 1) >= s;  // i + 3s < nd
+  const T xv = x[f];
+  const T vb = x[f - sd];
+  const T vc = x[hc ? f + sd : f];
+  const T va = x[ha ? f - 3 * sd : f];
+  const T ve = x[he ? f + 3 * sd : f];
+  T pl, pc;
+  if (__builtin_amdgcn_ballot_w64(!(ha && he)) == 0) {
+    pl = (vb + vc) * T(0.5);
+    pc = (T(9) * (vb + vc) - (va + ve)) * T(0.0625);
+  } else {
+    pl = interp_predict_sel<T, SZ_INTERP_LINEAR>(va, vb, vc, ve, ha, hc, he);
+    pc = interp_predict_sel<T, SZ_INTERP_CUBIC>(va, vb, vc, ve, ha, hc, he);
+  }
+  cl = est_cost(xv - pl, eb, inv2eb, R);
+  cc = est_cost(xv - pc, eb, inv2eb, R);
+}
+
+template <typename T, int J>
+__global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ x, EstGeom g,
+                                                          const Meta* __restrict__ m, uint32_t R,
+                                                          unsigned long long* cost) {
+  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
+  __shared__ unsigned long long sh[2 * kMaxLevels];
+  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads) sh[i] = 0;
+  __syncthreads();
+  const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
+  const int last = g.ndim - 1;
+  const uint32_t ncol = (uint32_t)g.dims[last];
+  const int pos_last = g.pos[last];
+  uint64_t acc1l = 0, acc1c = 0, acc2l = 0, acc2c = 0;  // levels 1 and 2
+  const uint32_t nx = gridDim.x % 8 == 0 ? 8 : 1;
+  const uint32_t bpx = gridDim.x / nx, xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
+  const uint64_t region = (g.units + nx - 1) / nx;
+  const uint64_t u_end = (xcd + 1) * region < g.units ? (xcd + 1) * region : g.units;
+  // (block-uniform; loops unrolled so the geometry stays in scalar
+  // registers) the unit u as (row, segment) and the row as coordinates
+  // q[0..last-1], divided out once and then advanced by bpx units a step
+  // with mixed-radix carries
+  uint64_t u = xcd * region + slot;
+  uint32_t seg = (uint32_t)(u % g.segs);
+  uint32_t q[kMaxDims] = {0, 0, 0, 0}, qi[kMaxDims] = {0, 0, 0, 0};
+  {
+    uint64_t r = u / g.segs, ri = bpx / g.segs;
+#pragma unroll
+    for (int e = kMaxDims - 2; e >= 0; --e) {
+      if (e < last) {
+        q[e] = (uint32_t)(r % g.dims[e]);
+        r /= g.dims[e];
+        qi[e] = (uint32_t)(ri % g.dims[e]);
+        ri /= g.dims[e];
+      }
+    }
+  }
+  const uint32_t seg_inc = (uint32_t)(bpx % g.segs);
+  for (; u < u_end; u += bpx) {
+    if (u != xcd * region + slot) {
+      seg += seg_inc;
+      uint32_t carry = 0;
+      if (seg >= g.segs) {
+        seg -= (uint32_t)g.segs;
+        carry = 1;
+      }
+#pragma unroll
+      for (int e = kMaxDims - 2; e >= 0; --e) {
+        if (e < last) {
+          const uint64_t v = (uint64_t)q[e] + qi[e] + carry;
+          carry = v >= g.dims[e] ? 1u : 0u;
+          q[e] = (uint32_t)(carry ? v - g.dims[e] : v);
+        }
+      }
+    }
+    uint32_t base = 0;
+#pragma unroll
+    for (int e = 0; e < kMaxDims - 1; e++)
+      if (e < last) base += q[e] * (uint32_t)g.stride[e];
+    int trow = 64, prow = -1;
+    uint32_t qrow = 0, srow = 0, nrow = 0;
+#pragma unroll
+    for (int e = 0; e < kMaxDims - 1; e++) {
+      const int te = q[e] ? __builtin_ctz(q[e]) : 64;
+      if (e < last && (te < trow || (te == trow && (int)g.pos[e] > prow))) {
+        trow = te;
+        prow = g.pos[e];
+        qrow = q[e];
+        srow = (uint32_t)g.stride[e];
+        nrow = (uint32_t)g.dims[e];
+      }
+    }
+    const uint32_t c0 = seg * kSeg;
+    const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
+    const bool odd_along_row = trow > 0 || pos_last > prow;
+    // the unit's first point and, for the level-1 passes along d_row (rows
+    // with t_row = 0, s = 1), the neighbouring rows and which exist
+    const T* __restrict__ pu = x + base + c0;
+    const uint64_t rs = srow;
+    const bool da = trow == 0 && qrow >= 3, dc = trow == 0 && nrow - qrow > 1,
+               de = dc && nrow - qrow > 3;
+    uint32_t s1l = 0, s1c = 0, s2l = 0, s2c = 0;
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      // the even column c0 + o (o signed: the stencil reaches o - 2)
+      const int o = 2 * (int)(threadIdx.x + j * kEstThreads);
+      const uint64_t ce64 = (uint64_t)c0 + (uint32_t)o;
+      // (wave-uniform) the wave's first even column, and whether every pair
+      // of the wave is whole and its odd column has both neighbours on each
+      // side along the row
+      const uint64_t cw = __builtin_amdgcn_readfirstlane((uint32_t)o) + (uint64_t)c0;
+      const bool interior = cw >= 2 && cw + 130 < ncol && cw + 127 < c1;
+      uint32_t cl, cc;
+      if (ce64 < c1) {
+        const uint32_t ce = (uint32_t)ce64;
+        const bool has_odd = ce + 1 < c1;
+        const T xe = pu[o];
+        const T xo = pu[has_odd ? o + 1 : o];
+        if (odd_along_row) {  // the odd column along the row: level 1
+          T pl, pc;
+          if (interior) {
+            const T va = pu[o - 2], vc = pu[o + 2], ve = pu[o + 4];
+            pl = (xe + vc) * T(0.5);
+            pc = (T(9) * (xe + vc) - (va + ve)) * T(0.0625);
+          } else {
+            const bool ha = ce >= 2, hc = ncol - ce > 2, he = ncol - ce > 4;
+            const T va = pu[ha ? o - 2 : o], vc = pu[hc ? o + 2 : o], ve = pu[he ? o + 4 : o];
+            pl = interp_predict_sel<T, SZ_INTERP_LINEAR>(va, xe, vc, ve, ha, hc, he);
+            pc = interp_predict_sel<T, SZ_INTERP_CUBIC>(va, xe, vc, ve, ha, hc, he);
+          }
+          if (has_odd) {
+            s1l += est_cost(xo - pl, eb, inv2eb, R);
+            s1c += est_cost(xo - pc, eb, inv2eb, R);
+          }
+        }
+        if (trow == 0) {
+          // level 1 along d_row: the even column, and the odd one unless it
+          // went along the row (flags uniform: one rule each)
+          const T* __restrict__ pe = pu + o;
+          const T bE = pe[-(int64_t)rs];
+          const T cE = dc ? pe[rs] : T(0);
+          const T aE = da ? pe[-3 * (int64_t)rs] : T(0);
+          const T eE = de ? pe[3 * rs] : T(0);
+          s1l += est_cost(xe - interp_predict<T, SZ_INTERP_LINEAR>(aE, bE, cE, eE, da, dc, de), eb,
+                          inv2eb, R);
+          s1c += est_cost(xe - interp_predict<T, SZ_INTERP_CUBIC>(aE, bE, cE, eE, da, dc, de), eb,
+                          inv2eb, R);
+          if (!odd_along_row && has_odd) {
+            const T bO = pe[1 - (int64_t)rs];
+            const T cO = dc ? pe[1 + rs] : T(0);
+            const T aO = da ? pe[1 - 3 * (int64_t)rs] : T(0);
+            const T eO = de ? pe[1 + 3 * rs] : T(0);
+            s1l += est_cost(xo - interp_predict<T, SZ_INTERP_LINEAR>(aO, bO, cO, eO, da, dc, de),
+                            eb, inv2eb, R);
+            s1c += est_cost(xo - interp_predict<T, SZ_INTERP_CUBIC>(aO, bO, cO, eO, da, dc, de),
+                            eb, inv2eb, R);
+          }
+        } else {
+          // the even column on a coarser level (each lane its own)
+          const int tc = ce ? __builtin_ctz(ce) : 64;
+          const int t = tc < trow ? tc : trow;
+          if (t != 64) {  // (t = 64: the origin)
+            const bool along_row = tc < trow || (tc == trow && pos_last > prow);
+            const uint32_t sp = 1u << t;
+            if (along_row)
+              est_point(x, base + ce, ce, ncol, sp, sp, eb, inv2eb, R, cl, cc);
+            else
+              est_point(x, base + ce, qrow, nrow, sp, sp * srow, eb, inv2eb, R, cl, cc);
+            if (t == 1) {
+              s2l += cl;
+              s2c += cc;
+            } else {
+              atomicAdd(&sh[2 * t], (unsigned long long)cl);
+              atomicAdd(&sh[2 * t + 1], (unsigned long long)cc);
+            }
+          }
+        }
+      }
+    }
+    acc1l += s1l;
+    acc1c += s1c;
+    acc2l += s2l;
+    acc2c += s2c;
+  }
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t v[4] = {acc1l, acc1c, acc2l, acc2c};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if (lane == 0 && v[k]) atomicAdd(&sh[k], (unsigned long long)v[k]);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads)
+    if (sh[i]) atomicAdd(cost + i, sh[i]);
+}
+
+hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
+                           uint32_t radius, uint64_t* cost, hipStream_t st) {
+  if (g.units == 0) return hipSuccess;
+  dim3 grid((unsigned)(g.units < 4096 ? g.units : 4096)), block(kEstThreads);
+  auto* c = reinterpret_cast<unsigned long long*>(cost);
+#define SZG_EST(J)                                                                         \
+  do {                                                                                     \
+    if (dtype == SZ_F32)                                                                   \
+      hipLaunchKernelGGL((k_estimate<float, J>), grid, block, 0, st, (const float*)x, g, m, \
+                         radius, c);                                                       \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_estimate<double, J>), grid, block, 0, st, (const double*)x, g, \
+                         m, radius, c);                                                    \
+  } while (0)
+  if (g.pairs == 1)
+    SZG_EST(1);
+  else if (g.pairs == 2)
+    SZG_EST(2);
+  else
+    SZG_EST(4);
+#undef SZG_EST
+  return hipGetLastError();
+}
+
+// Units of 512, 1024 or 2048 columns (one, two or four column pairs a lane),
+// the smallest that holds a row when one does.
+EstGeom make_estimate_geom(int ndim, const uint64_t* dims, const uint8_t* order) {
+  EstGeom g{};
+  g.ndim = ndim;
+  uint64_t st = 1;
+  for (int e = ndim - 1; e >= 0; e--) {
+    g.dims[e] = dims[e];
+    g.stride[e] = st;
+    st *= dims[e];
+  }
+  for (int j = 0; j < ndim; j++) g.pos[order[j]] = (uint8_t)j;
+  const uint64_t ncol = dims[ndim - 1];
+  g.pairs = ncol <= 2 * kEstThreads ? 1 : ncol <= 4 * kEstThreads ? 2 : 4;
+  const uint64_t seg = 2ull * kEstThreads * g.pairs;
+  g.segs = ncol ? (ncol + seg - 1) / seg : 0;
+  g.units = ncol ? st / ncol * g.segs : 0;
+  return g;
+}
+
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const PassGeom& g, const Meta* m,
                                 uint32_t radius, hipStream_t st) {

@@ -1,0 +1,106 @@
+"""Pins of adaptive interpolation in the oracle: exact polynomial fields
+(cubic reproduces them, so every level takes cubic), a step (linear wins at
+the fine levels), a brute-force computation of the level costs on small 1-D
+fields, consistency with the fixed predictors, and the stored level mask."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def _mask(orc, s):
+    return orc.parse_header(s)["level_mask"]
+
+
+@pytest.mark.parametrize("shape", [(300,), (40, 37), (17, 20, 23)])
+def test_polynomials_take_cubic(orc, shape):
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    L = max(int(np.ceil(np.log2(n))) for n in shape)
+    for x in (sum(0.5 * g for g in grids) + 3.0,           # linear
+              sum(0.01 * g * g for g in grids),            # quadratic: linear errs, cubic exact
+              sum(1e-4 * g ** 3 - 0.02 * g for g in grids)):  # cubic
+        x = x.astype(np.float64)
+        s = orc.compress(x, orc.ABS, 1e-6, orc.ADAPTIVE)
+        assert _mask(orc, s) == (1 << L) - 1
+        # then the stream equals the cubic one apart from the predictor byte and the mask
+        c = orc.compress(x, orc.ABS, 1e-6, orc.CUBIC)
+        a = bytearray(s)
+        a[40] = orc.CUBIC
+        a[124:128] = b"\0\0\0\0"
+        assert bytes(a) == c
+
+
+def _costs_1d(x, eb, R, L):
+    """Level costs of a 1-D field, straight from the definitions: every point
+    of level l predicted both ways from the original values, cost min(|k|, R)."""
+    x = x.astype(np.float32)
+    two = np.float32(2) * np.float32(eb)
+    inv = np.float32(1) / two
+    n = x.size
+    cost = {}
+    for l in range(L, 0, -1):
+        s = 1 << (l - 1)
+        c = [0, 0]
+        for i in range(s, n, 2 * s):
+            b = x[i - s]
+            has_a, has_c, has_e = i >= 3 * s, i + s < n, i + 3 * s < n
+            for k in (0, 1):
+                if not has_c:
+                    p = (np.float32(3) * b - x[i - 3 * s]) * np.float32(0.5) if has_a else b
+                elif k == 0:
+                    p = (b + x[i + s]) * np.float32(0.5)
+                elif has_a and has_e:
+                    p = (np.float32(9) * (b + x[i + s]) - (x[i - 3 * s] + x[i + 3 * s])) * np.float32(0.0625)
+                elif has_e:
+                    p = ((np.float32(3) * b + np.float32(6) * x[i + s]) - x[i + 3 * s]) * np.float32(0.125)
+                elif has_a:
+                    p = ((np.float32(6) * b + np.float32(3) * x[i + s]) - x[i - 3 * s]) * np.float32(0.125)
+                else:
+                    p = (b + x[i + s]) * np.float32(0.5)
+                kf = np.rint(np.abs(np.float32(x[i] - p)) * inv)
+                c[k] += int(kf) if kf < R else R
+        cost[l] = c
+    return cost
+
+
+@pytest.mark.parametrize("seed,n", [(1, 97), (2, 256), (3, 1000)])
+def test_level_costs_brute_force(orc, seed, n):
+    rng = np.random.default_rng(seed)
+    x = np.cumsum(rng.standard_normal(n)).astype(np.float32)
+    x[n // 3:] += 7.0  # a step
+    eb = 0.05
+    L = int(np.ceil(np.log2(n)))
+    cost = _costs_1d(x, eb, 32768, L)
+    want = sum(1 << (l - 1) for l in range(1, L + 1) if cost[l][1] <= cost[l][0])
+    s = orc.compress(x, orc.ABS, eb, orc.ADAPTIVE)
+    assert _mask(orc, s) == want
+
+
+def test_step_prefers_linear_at_fine_levels(orc):
+    x = (np.arange(512) > 200.5).astype(np.float32) * 5 + 1
+    m = _mask(orc, orc.compress(x, orc.ABS, 1e-4, orc.ADAPTIVE))
+    assert m & 1 == 0  # the finest level: linear errs at one point, cubic overshoots at more
+
+
+def test_roundtrip_and_mixed_mask(orc):
+    x = synth.climate_2d((181, 362), seed=3, dtype=np.float32)
+    s, codes, rec = orc.compress(x, orc.REL, 1e-3, orc.ADAPTIVE, want_debug=True)
+    assert orc.decompress(s).tobytes() == rec.tobytes()
+    m = _mask(orc, s)
+    L = 9
+    assert 0 < m < (1 << L) - 1 and m >> L == 0
+    err = np.abs(orc.decompress(s).astype(np.float64) - x)
+    assert err.max() <= orc.parse_header(s)["eb"]
+
+
+def test_bad_masks_rejected(orc):
+    x = synth.random_field((30, 20), seed=2)
+    s = bytearray(orc.compress(x, orc.REL, 1e-3, orc.ADAPTIVE))
+    bad = bytearray(s)
+    bad[124 + 3] |= 0x80  # a level the field does not have
+    with pytest.raises(Exception):
+        orc.decompress(bytes(bad))
+    fixed = bytearray(orc.compress(x, orc.REL, 1e-3, orc.CUBIC))
+    fixed[124] = 1  # a mask on a fixed-predictor stream
+    with pytest.raises(Exception):
+        orc.decompress(bytes(fixed))

@@ -133,8 +133,31 @@ PW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES + FINE_CASES + PW_CASES,
-                         ids=[c[0] for c in CASES + FINE_CASES + PW_CASES])
+def step_1d(n, at):
+    x = np.cumsum(np.random.default_rng(at).standard_normal(n) * 0.01).astype(np.float32)
+    x[at:] += 5.0
+    return x
+
+
+# Adaptive interpolation: each level's predictor chosen from the two cost
+# sums on the GPU, the level mask in the header, and the per-level predictor
+# in every kernel (fused levels, the strip kernel, the decoder side).
+ADAPT_CASES = [
+    ("ad-lognormal-ragged", lambda: lognormal((97, 80, 71), 61), "rel", 1e-3, 2, 32768, 4096, None),
+    ("ad-climate-f32", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float32), "rel", 1e-3, 2, 32768, 4096, None),
+    ("ad-climate-f64-1e-5", lambda: synth.climate_2d((181, 362), seed=62, dtype=np.float64), "rel", 1e-5, 2, 32768, 4096, None),
+    ("ad-step-1d", lambda: step_1d(70001, 23456), "abs", 1e-3, 2, 32768, 4096, None),
+    ("ad-4d-order", lambda: synth.random_field((9, 12, 7, 10), seed=63), "rel", 1e-3, 2, 32768, 512, (3, 1, 0, 2)),
+    ("ad-fine-3win", lambda: lognormal((9, 130, 1030), 64), "rel", 1e-4, 2, 32768, 4096, None),
+    ("ad-eb0", lambda: synth.random_field((20, 30, 18), seed=65), "abs", 0.0, 2, 32768, 4096, None),
+    ("ad-R2-unpred", lambda: synth.random_field((10, 33, 140), seed=66), "rel", 1e-3, 2, 2, 1024, None),
+    ("ad-pw-mixed-signs", lambda: mixed_signs((30, 28, 26), 67), "pwrel", 1e-3, 2, 32768, 4096, None),
+    ("ad-specials", lambda: specials((20, 22, 24), 68), "rel", 1e-2, 2, 32768, 4096, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES + FINE_CASES + PW_CASES + ADAPT_CASES,
+                         ids=[c[0] for c in CASES + FINE_CASES + PW_CASES + ADAPT_CASES])
 def test_parity(ctx, orc, case):
     label, gen, mode, eb, pred, radius, chunk, order = case
     x = gen()
@@ -182,7 +205,7 @@ def ctx_passes():
     c.close()
 
 
-PASS_CASES = [CASES[i] for i in (0, 2, 4, 6, 9)]
+PASS_CASES = [CASES[i] for i in (0, 2, 4, 6, 9)] + [ADAPT_CASES[i] for i in (0, 3)]
 
 
 @pytest.mark.parametrize("case", PASS_CASES, ids=[c[0] for c in PASS_CASES])
