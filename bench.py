@@ -224,6 +224,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs per-field measurement")
     ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the lossless, point-wise relative and adaptive measurements "
+                         "(for profiler runs that count the step's kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy the input once on the device "
                          "(a plain copy of known size, to scale HBM counters)")
@@ -340,9 +343,11 @@ def main():
 
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
-    lossless = lossless_measurement(szg, s, in_bytes)
-    pwrel = pwrel_measurement(szg, torch, np, ctx, xt, in_bytes)
-    adaptive = adaptive_measurement(szg, torch, ctx, xt, in_bytes, args.rel, args.chunk)
+    lossless = pwrel = adaptive = None
+    if not args.no_extras:
+        lossless = lossless_measurement(szg, s, in_bytes)
+        pwrel = pwrel_measurement(szg, torch, np, ctx, xt, in_bytes)
+        adaptive = adaptive_measurement(szg, torch, ctx, xt, in_bytes, args.rel, args.chunk)
 
     cpu = None
     parity = None
@@ -358,14 +363,23 @@ def main():
         t3 = time.perf_counter()
         parity = (ref == bytes(s.cpu().numpy().tobytes())) and (
             back.tobytes() == rec.cpu().numpy().tobytes())
-        # the point-wise relative mode on a 128^3 corner, byte for byte
+        # the point-wise relative and adaptive modes on a 128^3 corner, byte for byte
         corner = np.ascontiguousarray(x[:128, :128, :128])
-        pref = oracle.compress(corner, oracle.PWREL, pwrel["eps"], oracle.CUBIC)
-        sc = ctx.compress(torch.from_numpy(corner).to(dev), "pwrel", pwrel["eps"], "cubic")
-        pback = ctx.decompress(sc)
-        pwrel["parity_with_oracle_128cubed"] = (
-            bytes(sc.cpu().numpy().tobytes()) == pref
-            and pback.cpu().numpy().tobytes() == oracle.decompress(pref).tobytes())
+        if pwrel is not None:
+            pref = oracle.compress(corner, oracle.PWREL, pwrel["eps"], oracle.CUBIC)
+            sc = ctx.compress(torch.from_numpy(corner).to(dev), "pwrel", pwrel["eps"], "cubic")
+            pback = ctx.decompress(sc)
+            pwrel["parity_with_oracle_128cubed"] = (
+                bytes(sc.cpu().numpy().tobytes()) == pref
+                and pback.cpu().numpy().tobytes() == oracle.decompress(pref).tobytes())
+        if adaptive is not None:
+            aref = oracle.compress(corner, oracle.REL, args.rel, oracle.ADAPTIVE, 32768, args.chunk)
+            sa = ctx.compress(torch.from_numpy(corner).to(dev), "rel", args.rel, "adaptive",
+                              chunk=args.chunk)
+            aback = ctx.decompress(sa)
+            adaptive["parity_with_oracle_128cubed"] = (
+                bytes(sa.cpu().numpy().tobytes()) == aref
+                and aback.cpu().numpy().tobytes() == oracle.decompress(aref).tobytes())
         cpu = {"value": round(in_bytes / (t3 - t1) / 1e9, 4), "unit": "GB/s", "cores": 1,
                "kind": "oracle",
                "sample": f"the full {shape} field: one compress ({t2 - t1:.1f}s) + one "
