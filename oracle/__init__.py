@@ -23,7 +23,7 @@ DEPS = SOURCES + [os.path.join(_HERE, "szo.h"), os.path.join(_HERE, "szo_typed.i
 
 F32, F64 = 0, 1
 ABS, REL, PWREL = 0, 1, 2
-LINEAR, CUBIC, ADAPTIVE = 0, 1, 2
+LINEAR, CUBIC, ADAPTIVE, LORENZO = 0, 1, 2, 3
 OK, ERR_ARG, ERR_CAPACITY, ERR_CORRUPT, ERR_NOMEM = 0, -1, -3, -4, -6
 HEADER_BYTES = 128
 

@@ -192,7 +192,8 @@ int szo_resolve_eb(const void* x, uint64_t n, int dtype, int eb_mode,
 
 static int check_common(int dtype, int predictor, uint32_t radius) {
   if (dtype != SZO_F32 && dtype != SZO_F64) return SZO_ERR_ARG;
-  if (predictor != SZO_LINEAR && predictor != SZO_CUBIC && predictor != SZO_ADAPTIVE)
+  if (predictor != SZO_LINEAR && predictor != SZO_CUBIC && predictor != SZO_ADAPTIVE &&
+      predictor != SZO_LORENZO)
     return SZO_ERR_ARG;
   if (radius < 1 || radius > SZO_MAX_RADIUS) return SZO_ERR_ARG;
   return SZO_OK;
@@ -208,6 +209,32 @@ static void level_predictors(const void* x, int dtype, const struct szo_grid* g,
     choose_levels_f32((const float*)x, g, (float)eb_t, radius, level_pred);
   else
     choose_levels_f64((const double*)x, g, eb_t, radius, level_pred);
+}
+
+/* The Lorenzo predictor runs in flat order: the dimension order must be
+ * the identity. */
+static int identity_order(const struct szo_grid* g) {
+  for (int j = 0; j < g->ndim; j++)
+    if (g->order[j] != j) return 0;
+  return 1;
+}
+
+static void lorenzo_quantize(const void* x, int dtype, const struct szo_grid* g, double eb_t,
+                             uint32_t radius, uint16_t* codes, void* recon) {
+  if (dtype == SZO_F32)
+    lorenzo_quantize_f32((const float*)x, g, (float)eb_t, radius, codes, (float*)recon);
+  else
+    lorenzo_quantize_f64((const double*)x, g, eb_t, radius, codes, (double*)recon);
+}
+
+static int lorenzo_reconstruct(const uint16_t* codes, const void* unpred, uint64_t n_unpred,
+                               int dtype, const struct szo_grid* g, double eb_t,
+                               uint32_t radius, void* out) {
+  if (dtype == SZO_F32)
+    return lorenzo_reconstruct_f32(codes, (const float*)unpred, n_unpred, g, (float)eb_t, radius,
+                                   (float*)out);
+  return lorenzo_reconstruct_f64(codes, (const double*)unpred, n_unpred, g, eb_t, radius,
+                                 (double*)out);
 }
 
 /* bit l - 1 set: level l is cubic */
@@ -227,6 +254,11 @@ int szo_predict_quantize(const void* x, int dtype, int ndim,
   if (rc) return rc;
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
   if (!(eb_t >= 0.0) || !isfinite(eb_t)) return SZO_ERR_ARG;
+  if (predictor == SZO_LORENZO) {
+    if (!identity_order(&g)) return SZO_ERR_ARG;
+    lorenzo_quantize(x, dtype, &g, eb_t, radius, codes, recon);
+    return SZO_OK;
+  }
   uint8_t lp[64];
   level_predictors(x, dtype, &g, predictor, eb_t, radius, lp);
   if (dtype == SZO_F32)
@@ -254,6 +286,10 @@ int szo_reconstruct(const uint16_t* codes, const void* unpred,
   if (rc) return rc;
   if (predictor == SZO_ADAPTIVE) return SZO_ERR_ARG; /* (needs the stream's level mask) */
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
+  if (predictor == SZO_LORENZO) {
+    if (!identity_order(&g)) return SZO_ERR_ARG;
+    return lorenzo_reconstruct(codes, unpred, n_unpred, dtype, &g, eb_t, radius, out);
+  }
   uint8_t lp[64];
   memset(lp, predictor, 64);
   return reconstruct_levels(codes, unpred, n_unpred, dtype, &g, lp, eb_t, radius, out);
@@ -973,6 +1009,7 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   if (chunk == 0 || szo_check_sub(chunk, sub)) return SZO_ERR_ARG;
   if (eb_mode != SZO_ABS && eb_mode != SZO_REL) return SZO_ERR_ARG;
   if ((rc = grid_init(&g, ndim, dims, order))) return rc;
+  if (predictor == SZO_LORENZO && !identity_order(&g)) return SZO_ERR_ARG;
   size_t ts = type_size(dtype);
   uint64_t n = g.n;
   double eb_t;
@@ -994,15 +1031,19 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
     goto done;
   }
   /* Algorithm 1: predict + quantize every point (adaptive: each level's
-     predictor chosen first) */
+     predictor chosen first; Lorenzo: in flat order) */
   uint8_t lp[64];
-  level_predictors(x, dtype, &g, predictor, eb_t, radius, lp);
-  if (dtype == SZO_F32)
-    rc = predict_quantize_f32((const float*)x, &g, lp, (float)eb_t, radius, codes,
-                              (float*)recon);
-  else
-    rc = predict_quantize_f64((const double*)x, &g, lp, eb_t, radius, codes, (double*)recon);
-  if (rc) goto done;
+  if (predictor == SZO_LORENZO) {
+    lorenzo_quantize(x, dtype, &g, eb_t, radius, codes, recon);
+  } else {
+    level_predictors(x, dtype, &g, predictor, eb_t, radius, lp);
+    if (dtype == SZO_F32)
+      rc = predict_quantize_f32((const float*)x, &g, lp, (float)eb_t, radius, codes,
+                                (float*)recon);
+    else
+      rc = predict_quantize_f64((const double*)x, &g, lp, eb_t, radius, codes, (double*)recon);
+    if (rc) goto done;
+  }
   /* Huffman: frequencies -> lengths -> canonical codebook */
   if ((rc = szo_histogram(codes, n, nsym, hist))) goto done;
   rc = szo_huffman_lengths(hist, nsym, lens);
@@ -1091,7 +1132,7 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
   if (memcmp(s, "SZG1", 4) != 0 || get_u16(s + 4) != 1) return SZO_ERR_CORRUPT;
   if (s[45] == SZO_PWREL) return decompress_pwrel(s, size, outp, out_bytes, codes_out);
   int dtype = s[6], ndim = s[7], predictor = s[40], eb_mode = s[45];
-  if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 2 || eb_mode > 1)
+  if (dtype > 1 || ndim < 1 || ndim > 4 || predictor > 3 || eb_mode > 1)
     return SZO_ERR_CORRUPT;
   uint64_t dims[4];
   uint8_t order[4];
@@ -1102,6 +1143,7 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
   }
   struct szo_grid g;
   if (grid_init(&g, ndim, dims, order)) return SZO_ERR_CORRUPT;
+  if (predictor == SZO_LORENZO && !identity_order(&g)) return SZO_ERR_CORRUPT;
   double eb_t = get_f64(s + 56);
   uint32_t radius = get_u32(s + 64), chunk = get_u32(s + 68);
   uint64_t n_unpred = get_u64(s + 72);
@@ -1198,8 +1240,13 @@ int szo_decompress(const uint8_t* s, uint64_t size, void* outp,
       rc = SZO_ERR_CORRUPT;
       goto done;
     }
+    if (predictor == SZO_LORENZO) {
+      rc = lorenzo_reconstruct(codes, unpred, n_unpred, dtype, &g, eb_t, radius, outp);
+      goto codes_out;
+    }
     rc = reconstruct_levels(codes, unpred, n_unpred, dtype, &g, lp, eb_t, radius, outp);
   }
+codes_out:
   if (!rc && codes_out) memcpy(codes_out, codes, sizeof(uint16_t) * n);
 done:
   free(lens);

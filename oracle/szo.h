@@ -45,7 +45,7 @@ extern "C" {
 
 enum { SZO_F32 = 0, SZO_F64 = 1 };
 enum { SZO_ABS = 0, SZO_REL = 1, SZO_PWREL = 2 };
-enum { SZO_LINEAR = 0, SZO_CUBIC = 1, SZO_ADAPTIVE = 2 };
+enum { SZO_LINEAR = 0, SZO_CUBIC = 1, SZO_ADAPTIVE = 2, SZO_LORENZO = 3 };
 enum {
   SZO_OK = 0,
   SZO_ERR_ARG = -1,
