@@ -65,8 +65,20 @@ typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1, SZ_EB_PWREL = 2 } sz_eb_mode;
  * predicted both ways from the original values, its cost is the quantizer's
  * bin index |k| capped at the radius, and the level takes cubic unless its
  * linear cost sum is smaller.  The choice is stored in the stream (a bit per
- * level) and costs one extra read of the field and one host round trip. */
-typedef enum { SZ_INTERP_LINEAR = 0, SZ_INTERP_CUBIC = 1, SZ_INTERP_ADAPTIVE = 2 } sz_predictor;
+ * level) and costs one extra read of the field and one host round trip.
+ * SZ_LORENZO is the first-order Lorenzo predictor (Section 3.2 "Predictor",
+ * the predictor half of SZ3-LR): each point in flat order from the
+ * reconstructed values of its 2^N - 1 lower neighbours (sum over the nonempty
+ * sets S of dimensions of (-1)^(|S|+1) x'(q - e_S), outside the grid 0),
+ * through the same quantizer, encoder and stream format; it takes no
+ * dim_order.  Its points depend on each other through the quantizer, so it
+ * runs as wavefronts of blocks (one launch per block diagonal). */
+typedef enum {
+  SZ_INTERP_LINEAR = 0,
+  SZ_INTERP_CUBIC = 1,
+  SZ_INTERP_ADAPTIVE = 2,
+  SZ_LORENZO = 3
+} sz_predictor;
 
 typedef enum {
   SZ_OK = 0,

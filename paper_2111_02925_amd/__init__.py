@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libszg.so")
 
 F32, F64 = 0, 1
 ABS, REL, PWREL = 0, 1, 2
-LINEAR, CUBIC, ADAPTIVE = 0, 1, 2
+LINEAR, CUBIC, ADAPTIVE, LORENZO = 0, 1, 2, 3
 OK, ERR_ARG, ERR_DTYPE, ERR_CAPACITY, ERR_CORRUPT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7)
 STATUS_NAMES = {0: "SZ_OK", -1: "SZ_ERR_ARG", -2: "SZ_ERR_DTYPE", -3: "SZ_ERR_CAPACITY",
@@ -161,7 +161,7 @@ def _mode(v) -> int:
 
 def _pred(v) -> int:
     if isinstance(v, str):
-        return {"linear": LINEAR, "cubic": CUBIC, "adaptive": ADAPTIVE}[v.lower()]
+        return {"linear": LINEAR, "cubic": CUBIC, "adaptive": ADAPTIVE, "lorenzo": LORENZO}[v.lower()]
     return int(v)
 
 

@@ -289,7 +289,7 @@ int parse_header(const uint8_t* h, sz_info* info) {
   in.ndim = h[7];
   in.predictor = h[40];
   in.eb_mode = h[45];
-  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 2 || in.eb_mode > 2)
+  if (in.dtype > 1 || in.ndim < 1 || in.ndim > kMaxDims || in.predictor > 3 || in.eb_mode > 2)
     return SZ_ERR_CORRUPT;
   // adaptive interpolation: bit l - 1 of the level mask set = level l cubic
   in.level_mask = (uint32_t)get_le(h + 124, 4);
@@ -318,6 +318,9 @@ int parse_header(const uint8_t* h, sz_info* info) {
     if (d < in.ndim && in.dims[d] == 0) empty = true;
   }
   if (!valid_order(in.ndim, in.dim_order)) return SZ_ERR_CORRUPT;
+  if (in.predictor == SZ_LORENZO)  // (flat order: no dimension order)
+    for (int j = 0; j < in.ndim; j++)
+      if (in.dim_order[j] != j) return SZ_ERR_CORRUPT;
   if (empty) {
     n = 0;
   } else {
@@ -547,7 +550,7 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   *out_size = 0;
   if (eb_mode != SZ_EB_ABS && eb_mode != SZ_EB_REL) return fail(ctx, SZ_ERR_ARG, "bad eb_mode");
   if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
-      predictor != SZ_INTERP_ADAPTIVE)
+      predictor != SZ_INTERP_ADAPTIVE && predictor != SZ_LORENZO)
     return fail(ctx, SZ_ERR_ARG, "bad predictor");
   if (!(eb >= 0.0) || !__builtin_isfinite(eb)) return fail(ctx, SZ_ERR_ARG, "eb must be finite and >= 0");
   if (eb_mode == SZ_EB_ABS && dtype == SZ_F32 && !__builtin_isfinite((float)eb))
@@ -555,6 +558,9 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
   if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
     return fail(ctx, SZ_ERR_ARG, "d_in must be 16-byte and d_out 8-byte aligned");
+  if (predictor == SZ_LORENZO)
+    for (int j = 0; j < s.ndim; j++)
+      if (s.order[j] != j) return fail(ctx, SZ_ERR_ARG, "the Lorenzo predictor takes no dim_order");
   CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   if ((rc = ensure_sized(ctx, s, true))) return rc;
@@ -594,7 +600,12 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     put_le(hdr + 124, mask, 4);
   }
   auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
-  if (s.n) {
+  if (s.n && predictor == SZ_LORENZO) {
+    CHECK_HIP(timed(ctx, "interp", st, [&] {
+                return launch_lorenzo_compress(d_in, dtype, ctx->rec.p, codes, s.ndim, s.dims,
+                                               ctx->meta, s.radius, st);
+              }), "lorenzo");
+  } else if (s.n) {
     // the origin and every level, timed as one region
     CHECK_HIP(timed(ctx, "interp", st, [&] {
                 hipError_t e =
@@ -665,7 +676,7 @@ static int compress_pwrel(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
   if (!(delta > 0.0))
     return fail(ctx, SZ_ERR_ARG, "point-wise relative bound must be in (0, 1) and above the type's precision");
   if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
-      predictor != SZ_INTERP_ADAPTIVE)
+      predictor != SZ_INTERP_ADAPTIVE && predictor != SZ_LORENZO)
     return fail(ctx, SZ_ERR_ARG, "bad predictor");
   if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
   if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
@@ -779,6 +790,9 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                                                                     : SZ_INTERP_LINEAR;
     auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
     CHECK_HIP(timed(ctx, "recon", st, [&] {
+                if (in.predictor == SZ_LORENZO)
+                  return launch_lorenzo_recon(codes, s.dtype, d_out, s.ndim, s.dims, in.eb,
+                                              s.radius, st);
                 hipError_t e = launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
                 std::vector<LevelGeom> levels;
                 if (ctx->fused_levels &&

@@ -144,6 +144,13 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const PassGeom& g, const Meta* m,
                                 uint32_t radius, hipStream_t st);
+// the first-order Lorenzo predictor: every point, in wavefronts of blocks
+hipError_t launch_lorenzo_compress(const void* x, int dtype, void* rec, uint16_t* codes, int ndim,
+                                   const uint64_t* dims, const Meta* m, uint32_t radius,
+                                   hipStream_t st);
+hipError_t launch_lorenzo_recon(const uint16_t* codes, int dtype, void* out, int ndim,
+                                const uint64_t* dims, double eb_t, uint32_t radius,
+                                hipStream_t st);
 hipError_t launch_origin_recon(const uint16_t* codes, int dtype, void* out, double eb_t,
                                uint32_t radius, hipStream_t st);
 hipError_t launch_pass_recon(const uint16_t* codes, int dtype, int predictor, void* out,

@@ -156,8 +156,26 @@ ADAPT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES + FINE_CASES + PW_CASES + ADAPT_CASES,
-                         ids=[c[0] for c in CASES + FINE_CASES + PW_CASES + ADAPT_CASES])
+# The Lorenzo predictor: wavefronts of blocks (several block diagonals and
+# ragged blocks in every dimension), 1-D to 4-D, both dtypes, eb = 0, the
+# unpredictable path, special values and the point-wise relative mode.
+LOR_CASES = [
+    ("lor-lognormal-ragged", lambda: lognormal((97, 80, 71), 71), "rel", 1e-3, 3, 32768, 4096, None),
+    ("lor-f64-3d", lambda: synth.random_field((33, 40, 37), seed=72, dtype=np.float64), "rel", 1e-4, 3, 32768, 4096, None),
+    ("lor-climate-f32", lambda: synth.climate_2d((181, 362), seed=3, dtype=np.float32), "rel", 1e-4, 3, 32768, 4096, None),
+    ("lor-climate-f64", lambda: synth.climate_2d((181, 362), seed=73, dtype=np.float64), "rel", 1e-3, 3, 32768, 4096, None),
+    ("lor-1d", lambda: np.cumsum(np.random.default_rng(74).standard_normal(20003)).astype(np.float32), "rel", 1e-3, 3, 32768, 4096, None),
+    ("lor-4d", lambda: synth.random_field((9, 12, 7, 10), seed=75), "rel", 1e-3, 3, 32768, 512, None),
+    ("lor-4d-f64", lambda: synth.random_field((5, 20, 9, 18), seed=76, dtype=np.float64), "rel", 1e-3, 3, 32768, 512, None),
+    ("lor-eb0", lambda: synth.random_field((20, 30, 18), seed=77), "abs", 0.0, 3, 32768, 4096, None),
+    ("lor-R4-unpred", lambda: synth.random_field((30, 33, 40), seed=78), "rel", 1e-3, 3, 4, 1024, None),
+    ("lor-specials", lambda: specials((20, 22, 24), 79), "rel", 1e-2, 3, 32768, 4096, None),
+    ("lor-pwrel", lambda: mixed_signs((30, 28, 26), 80), "pwrel", 1e-3, 3, 32768, 4096, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES + FINE_CASES + PW_CASES + ADAPT_CASES + LOR_CASES,
+                         ids=[c[0] for c in CASES + FINE_CASES + PW_CASES + ADAPT_CASES + LOR_CASES])
 def test_parity(ctx, orc, case):
     label, gen, mode, eb, pred, radius, chunk, order = case
     x = gen()
@@ -232,6 +250,15 @@ def test_parity_special_values(ctx, orc):
 def test_parity_tiny_shapes(ctx, orc, shape):
     x = (np.arange(int(np.prod(shape)), dtype=np.float32) * 0.37 + 1).reshape(shape)
     check_case(ctx, orc, x, "rel", 1e-2, 1, chunk=64, label=f"tiny{shape}")
+    check_case(ctx, orc, x, "rel", 1e-2, 3, chunk=64, label=f"tiny-lorenzo{shape}")
+
+
+def test_lorenzo_rejects_dim_order(ctx):
+    import paper_2111_02925_amd as szg
+
+    xt = torch.from_numpy(synth.random_field((10, 12), seed=3)).cuda()
+    with pytest.raises(szg.SzError):
+        ctx.compress(xt, "rel", 1e-3, "lorenzo", dim_order=(1, 0))
 
 
 def test_parity_degenerate_bounds(ctx, orc):
