@@ -137,6 +137,34 @@ def adaptive_measurement(szg, torch, ctx, xt, in_bytes, rel, chunk, reps=3):
             "max_abs_err_over_eb": err / info["eb"] if info["eb"] > 0 else 0.0}
 
 
+def lorenzo_measurement(szg, torch, ctx, xt, in_bytes, rel, chunk, reps=3):
+    """The Lorenzo predictor on the same field and bound, outside the timed
+    region: throughput of compress and decompress (wavefronts of blocks),
+    ratio, and the largest error over the bound."""
+    cap = szg.compress_bound(tuple(xt.shape), szg.F32, 32768, chunk)
+    out = torch.empty(cap, dtype=torch.uint8, device=xt.device)
+    rec = torch.empty_like(xt)
+    s = ctx.compress(xt, "rel", rel, "lorenzo", chunk=chunk, out=out)
+    ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s = ctx.compress(xt, "rel", rel, "lorenzo", chunk=chunk, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.decompress(s, out=rec)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = szg.inspect(s[:128].cpu())
+    err = float((xt.double() - rec.double()).abs().max().item())
+    return {"workload": "the same field and bound, first-order Lorenzo predictor",
+            "ratio": round(in_bytes / s.numel(), 4),
+            "compress_GBps": round(in_bytes * reps / (t1 - t0) / 1e9, 3),
+            "decompress_GBps": round(in_bytes * reps / (t2 - t1) / 1e9, 3),
+            "max_abs_err_over_eb": err / info["eb"] if info["eb"] > 0 else 0.0}
+
+
 def lossless_measurement(szg, s, in_bytes, level=1):
     """The host lossless stage (zlib standing in for zstd) on the step's
     stream, outside the timed region: one thread of the host, the stream
@@ -343,11 +371,12 @@ def main():
 
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
-    lossless = pwrel = adaptive = None
+    lossless = pwrel = adaptive = lorenzo = None
     if not args.no_extras:
         lossless = lossless_measurement(szg, s, in_bytes)
         pwrel = pwrel_measurement(szg, torch, np, ctx, xt, in_bytes)
         adaptive = adaptive_measurement(szg, torch, ctx, xt, in_bytes, args.rel, args.chunk)
+        lorenzo = lorenzo_measurement(szg, torch, ctx, xt, in_bytes, args.rel, args.chunk)
 
     cpu = None
     parity = None
@@ -372,6 +401,14 @@ def main():
             pwrel["parity_with_oracle_128cubed"] = (
                 bytes(sc.cpu().numpy().tobytes()) == pref
                 and pback.cpu().numpy().tobytes() == oracle.decompress(pref).tobytes())
+        if lorenzo is not None:
+            lref = oracle.compress(corner, oracle.REL, args.rel, oracle.LORENZO, 32768, args.chunk)
+            sl = ctx.compress(torch.from_numpy(corner).to(dev), "rel", args.rel, "lorenzo",
+                              chunk=args.chunk)
+            lback = ctx.decompress(sl)
+            lorenzo["parity_with_oracle_128cubed"] = (
+                bytes(sl.cpu().numpy().tobytes()) == lref
+                and lback.cpu().numpy().tobytes() == oracle.decompress(lref).tobytes())
         if adaptive is not None:
             aref = oracle.compress(corner, oracle.REL, args.rel, oracle.ADAPTIVE, 32768, args.chunk)
             sa = ctx.compress(torch.from_numpy(corner).to(dev), "rel", args.rel, "adaptive",
@@ -417,6 +454,7 @@ def main():
         "lossless": lossless,
         "pwrel": pwrel,
         "adaptive": adaptive,
+        "lorenzo": lorenzo,
         "parity_with_oracle": parity,
     }
     print(json.dumps(res), flush=True)

@@ -38,14 +38,14 @@ struct LorGeom {
   uint32_t has_prev;
 };
 
-// Block shapes: (16, 16, 16) for 3-D and 4-D f32, (8, 16, 16) for f64;
+// Block shapes: (16, 16, 16) for 3-D f32, (8, 16, 16) for 4-D and f64;
 // (1, 256, 16) and (1, 128, 16) for 2-D; (1, 1, 1024) for 1-D.  LDS stays
 // within 64 KB.
 template <typename T, int N>
 struct LorShape;
 template <int N>
 struct LorShape<float, N> {
-  static constexpr int BA = N >= 3 ? 16 : 1, BB = N >= 3 ? 16 : N == 2 ? 256 : 1,
+  static constexpr int BA = N == 3 ? 16 : N == 4 ? 8 : 1, BB = N >= 3 ? 16 : N == 2 ? 256 : 1,
                        BC = N >= 2 ? 16 : 1024;
 };
 template <int N>
@@ -65,7 +65,9 @@ k_lorenzo(const T* __restrict__ x, const uint16_t* __restrict__ codes_in, uint16
           T* rec, LorGeom g, const Meta* __restrict__ m, T twoeb_dec, uint32_t R) {
   constexpr int BA = LorShape<T, N>::BA, BB = LorShape<T, N>::BB, BC = LorShape<T, N>::BC;
   constexpr int NT = LorThreads<BA, BB>::value;
-  constexpr int HA = BA + 1, HB = BB + 1, HC = BC + 1;  // with the halo
+  // LDS box with the halo; rows padded to BC + 2 so that the lanes of a step
+  // (c = t - a - b) fall in different banks
+  constexpr int HA = BA + 1, HB = BB + 1, HC = BC + 2;
   constexpr int NP = N == 4 ? HA * HB * HC : 1;
   __shared__ T Rs[HA * HB * HC];  // reconstructions, halo at index 0 of each dimension
   __shared__ T Ps[NP];            // 4-D: the previous hyperplane, same layout
@@ -81,24 +83,48 @@ k_lorenzo(const T* __restrict__ x, const uint16_t* __restrict__ codes_in, uint16
   const int tid = threadIdx.x;
   const T* __restrict__ hp = rec + g.off;  // this hyperplane's reconstructions
 
-  // halo of the reconstructions (and the previous hyperplane's box)
-  for (int i = tid; i < (ea + 1) * (eb + 1) * (ec + 1); i += NT) {
-    const int ic = i % (ec + 1), r = i / (ec + 1), ib = r % (eb + 1), ia = r / (eb + 1);
-    const int64_t ga = (int64_t)a0 + ia - 1, gb = (int64_t)b0 + ib - 1, gc = (int64_t)c0 + ic - 1;
-    const bool inside = ga >= 0 && gb >= 0 && gc >= 0;
-    const uint64_t f = inside ? (uint64_t)ga * g.sA + (uint64_t)gb * g.sB + (uint64_t)gc : 0;
-    const int li = (ia * HB + ib) * HC + ic;
-    if (ia == 0 || ib == 0 || ic == 0) Rs[li] = inside ? hp[f] : T(0);
-    if (N == 4) Ps[li] = inside && g.has_prev ? rec[g.prev + f] : T(0);
-  }
-  // the block's inputs
-  for (int i = tid; i < ea * eb * ec; i += NT) {
-    const int c = i % ec, r = i / ec, b = r % eb, a = r / eb;
-    const uint64_t f =
-        g.off + (uint64_t)(a0 + a) * g.sA + (uint64_t)(b0 + b) * g.sB + (uint64_t)(c0 + c);
-    const int li = (a * BB + b) * BC + c;
-    Xs[li] = DEC ? rec[f] : x[f];
-    if (DEC) Ks[li] = codes_in[f];
+  // Fill: every position (ia, ib, ic) of the box with the halo, index 0 for
+  // one step back.  A position with a 0 index is halo (the finished
+  // neighbour's value, or 0 outside the grid); the others are the block's
+  // points (input, or verbatim value and code).  Taken kUnroll positions a
+  // lane at a time, loads first, so that they are in flight together.
+  constexpr int WB = BB + 1, WC = BC + 1, BOX = (BA + 1) * WB * WC;
+  constexpr int kUnroll = 8;
+  for (int i0 = 0; i0 < BOX; i0 += kUnroll * NT) {
+    T vr[kUnroll], vp[kUnroll];
+    uint16_t vk[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; k++) {
+      const int i = i0 + k * NT + tid;
+      const int ic = i % WC, ib = (i / WC) % WB, ia = i / (WC * WB);
+      const bool in_box = i < BOX && ia <= ea && ib <= eb && ic <= ec;
+      const int64_t ga = (int64_t)a0 + ia - 1, gb = (int64_t)b0 + ib - 1,
+                    gc = (int64_t)c0 + ic - 1;
+      const bool inside = in_box && ga >= 0 && gb >= 0 && gc >= 0;
+      const uint64_t f = inside ? (uint64_t)ga * g.sA + (uint64_t)gb * g.sB + (uint64_t)gc : 0;
+      const bool halo = ia == 0 || ib == 0 || ic == 0;
+      vr[k] = T(0);
+      vk[k] = 0;
+      if (inside) vr[k] = halo ? hp[f] : (DEC ? hp[f] : x[g.off + f]);
+      if (DEC && inside && !halo) vk[k] = codes_in[g.off + f];
+      vp[k] = T(0);
+      if (N == 4 && inside && g.has_prev) vp[k] = rec[g.prev + f];
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; k++) {
+      const int i = i0 + k * NT + tid;
+      const int ic = i % WC, ib = (i / WC) % WB, ia = i / (WC * WB);
+      if (!(i < BOX && ia <= ea && ib <= eb && ic <= ec)) continue;
+      const int li = (ia * HB + ib) * HC + ic;
+      if (ia == 0 || ib == 0 || ic == 0) {
+        Rs[li] = vr[k];
+      } else {
+        const int xi = ((ia - 1) * BB + (ib - 1)) * BC + (ic - 1);
+        Xs[xi] = vr[k];
+        if (DEC) Ks[xi] = vk[k];
+      }
+      if (N == 4) Ps[li] = vp[k];
+    }
   }
   __syncthreads();
 
@@ -150,12 +176,13 @@ k_lorenzo(const T* __restrict__ x, const uint16_t* __restrict__ codes_in, uint16
   }
 
   // the block's codes and reconstructions
-  for (int i = tid; i < ea * eb * ec; i += NT) {
-    const int c = i % ec, r = i / ec, b = r % eb, a = r / eb;
+  for (int i = tid; i < BA * BB * BC; i += NT) {
+    const int c = i % BC, b = (i / BC) % BB, a = i / (BC * BB);
+    if (a >= ea || b >= eb || c >= ec) continue;
     const uint64_t f =
         g.off + (uint64_t)(a0 + a) * g.sA + (uint64_t)(b0 + b) * g.sB + (uint64_t)(c0 + c);
     rec[f] = Rs[((a + 1) * HB + (b + 1)) * HC + (c + 1)];
-    if (!DEC) codes_out[f] = Ks[(a * BB + b) * BC + c];
+    if (!DEC) codes_out[f] = Ks[i];
   }
 }
 
