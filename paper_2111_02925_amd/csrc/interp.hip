@@ -291,7 +291,9 @@ hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t*
 //  - the even column is on level 1 along d_row when t_row = 0, and on a
 //    coarser level otherwise (a quarter of the rows in 3-D: 1/8 of the
 //    points), where each lane finds its own level and dimension.
-// So 7/8 of the points take a path with block-uniform geometry.  Blocks of
+// Both columns' stencils are fetched (every load issued before any is used;
+// idle lanes read their row's first point) and evaluated by the same code.
+// Blocks of
 // one XCD (dealt round-robin, block b on XCD b mod 8) share one contiguous
 // eighth of the units and step through it together, neighbouring blocks on
 // neighbouring rows, so the rows and planes the stencils reach are read by
@@ -306,33 +308,45 @@ __device__ __forceinline__ uint32_t est_cost(T d, T eb, T inv2eb, uint32_t R) {
   return k < (T)R ? (uint32_t)k : R;  // (NaN: R)
 }
 
-// Both costs of the point at flat index f predicted along a dimension with
-// flat step sd (= s x stride), position i and extent nd.  Where the whole
-// wave is away from the ends (both neighbours on each side), the two
-// interior rules alone are evaluated.
+// The stencil of the point at flat index f along a dimension with flat step
+// sd (= s x stride), position i and extent nd: which neighbours exist and
+// their values (absent ones read the point itself).
 template <typename T>
-__device__ __forceinline__ void est_point(const T* __restrict__ x, uint32_t f, uint32_t i,
-                                          uint32_t nd, uint32_t s, uint32_t sd, T eb, T inv2eb,
-                                          uint32_t R, uint32_t& cl, uint32_t& cc) {
+struct EstStencil {
+  T x, a, b, c, e;
+  bool ha, hc, he;
+};
+template <typename T>
+__device__ __forceinline__ EstStencil<T> est_fetch(const T* __restrict__ x, uint32_t f, uint32_t i,
+                                                   uint32_t nd, uint32_t s, uint32_t sd) {
+  EstStencil<T> st;
   // i >= s and i < nd; the comparisons avoid 32-bit overflow
-  const bool ha = ((i - s) >> 1) >= s;                 // i >= 3s
-  const bool hc = nd - i > s;                          // i + s < nd
-  const bool he = hc && ((nd - i - s - 1) >> 1) >= s;  // i + 3s < nd
-  const T xv = x[f];
-  const T vb = x[f - sd];
-  const T vc = x[hc ? f + sd : f];
-  const T va = x[ha ? f - 3 * sd : f];
-  const T ve = x[he ? f + 3 * sd : f];
+  st.ha = ((i - s) >> 1) >= s;                    // i >= 3s
+  st.hc = nd - i > s;                             // i + s < nd
+  st.he = st.hc && ((nd - i - s - 1) >> 1) >= s;  // i + 3s < nd
+  st.x = x[f];
+  st.b = x[f - sd];
+  st.c = x[st.hc ? f + sd : f];
+  st.a = x[st.ha ? f - 3 * sd : f];
+  st.e = x[st.he ? f + 3 * sd : f];
+  return st;
+}
+// Both costs from a fetched stencil.  Where the whole wave is away from the
+// ends (both neighbours on each side), the two interior rules alone are
+// evaluated.
+template <typename T>
+__device__ __forceinline__ void est_eval(const EstStencil<T>& st, T eb, T inv2eb, uint32_t R,
+                                         uint32_t& cl, uint32_t& cc) {
   T pl, pc;
-  if (__builtin_amdgcn_ballot_w64(!(ha && he)) == 0) {
-    pl = (vb + vc) * T(0.5);
-    pc = (T(9) * (vb + vc) - (va + ve)) * T(0.0625);
+  if (__builtin_amdgcn_ballot_w64(!(st.ha && st.he)) == 0) {
+    pl = (st.b + st.c) * T(0.5);
+    pc = (T(9) * (st.b + st.c) - (st.a + st.e)) * T(0.0625);
   } else {
-    pl = interp_predict_sel<T, SZ_INTERP_LINEAR>(va, vb, vc, ve, ha, hc, he);
-    pc = interp_predict_sel<T, SZ_INTERP_CUBIC>(va, vb, vc, ve, ha, hc, he);
+    pl = interp_predict_sel<T, SZ_INTERP_LINEAR>(st.a, st.b, st.c, st.e, st.ha, st.hc, st.he);
+    pc = interp_predict_sel<T, SZ_INTERP_CUBIC>(st.a, st.b, st.c, st.e, st.ha, st.hc, st.he);
   }
-  cl = est_cost(xv - pl, eb, inv2eb, R);
-  cc = est_cost(xv - pc, eb, inv2eb, R);
+  cl = est_cost(st.x - pl, eb, inv2eb, R);
+  cc = est_cost(st.x - pc, eb, inv2eb, R);
 }
 
 template <typename T, int J>
@@ -409,87 +423,44 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
     const uint32_t c0 = seg * kSeg;
     const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
     const bool odd_along_row = trow > 0 || pos_last > prow;
-    // the unit's first point and, for the level-1 passes along d_row (rows
-    // with t_row = 0, s = 1), the neighbouring rows and which exist
-    const T* __restrict__ pu = x + base + c0;
-    const uint64_t rs = srow;
-    const bool da = trow == 0 && qrow >= 3, dc = trow == 0 && nrow - qrow > 1,
-               de = dc && nrow - qrow > 3;
+    // the odd column's pass (level 1): along the row, or along d_row
+    const uint32_t sd_odd = odd_along_row ? 1u : srow, nd_odd = odd_along_row ? ncol : nrow;
     uint32_t s1l = 0, s1c = 0, s2l = 0, s2c = 0;
 #pragma unroll
     for (int j = 0; j < J; j++) {
-      // the even column c0 + o (o signed: the stencil reaches o - 2)
-      const int o = 2 * (int)(threadIdx.x + j * kEstThreads);
-      const uint64_t ce64 = (uint64_t)c0 + (uint32_t)o;
-      // (wave-uniform) the wave's first even column, and whether every pair
-      // of the wave is whole and its odd column has both neighbours on each
-      // side along the row
-      const uint64_t cw = __builtin_amdgcn_readfirstlane((uint32_t)o) + (uint64_t)c0;
-      const bool interior = cw >= 2 && cw + 130 < ncol && cw + 127 < c1;
+      const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
+      const uint64_t ce64 = (uint64_t)c0 + o;
+      const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
+      const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
+      // the even column: level 1 along d_row when t_row = 0, else level
+      // t + 1 along the row or d_row (t = 64: the origin)
+      const int tc = ce ? __builtin_ctz(ce) : 64;
+      const int t = trow == 0 ? 0 : (tc < trow ? tc : trow);
+      const bool e_row = trow != 0 && (tc < trow || (tc == trow && pos_last > prow));
+      const bool e_ok = has_even && t != 64;
+      const uint32_t sp = e_ok ? 1u << t : 0u;
+      // stencils of both columns, every load issued before any is used
+      const EstStencil<T> so = est_fetch(x, base + co, odd_along_row ? co : qrow, nd_odd,
+                                         has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
+      const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
+                                         e_row ? sp : sp * srow);
       uint32_t cl, cc;
-      if (ce64 < c1) {
-        const uint32_t ce = (uint32_t)ce64;
-        const bool has_odd = ce + 1 < c1;
-        const T xe = pu[o];
-        const T xo = pu[has_odd ? o + 1 : o];
-        if (odd_along_row) {  // the odd column along the row: level 1
-          T pl, pc;
-          if (interior) {
-            const T va = pu[o - 2], vc = pu[o + 2], ve = pu[o + 4];
-            pl = (xe + vc) * T(0.5);
-            pc = (T(9) * (xe + vc) - (va + ve)) * T(0.0625);
-          } else {
-            const bool ha = ce >= 2, hc = ncol - ce > 2, he = ncol - ce > 4;
-            const T va = pu[ha ? o - 2 : o], vc = pu[hc ? o + 2 : o], ve = pu[he ? o + 4 : o];
-            pl = interp_predict_sel<T, SZ_INTERP_LINEAR>(va, xe, vc, ve, ha, hc, he);
-            pc = interp_predict_sel<T, SZ_INTERP_CUBIC>(va, xe, vc, ve, ha, hc, he);
-          }
-          if (has_odd) {
-            s1l += est_cost(xo - pl, eb, inv2eb, R);
-            s1c += est_cost(xo - pc, eb, inv2eb, R);
-          }
-        }
-        if (trow == 0) {
-          // level 1 along d_row: the even column, and the odd one unless it
-          // went along the row (flags uniform: one rule each)
-          const T* __restrict__ pe = pu + o;
-          const T bE = pe[-(int64_t)rs];
-          const T cE = dc ? pe[rs] : T(0);
-          const T aE = da ? pe[-3 * (int64_t)rs] : T(0);
-          const T eE = de ? pe[3 * rs] : T(0);
-          s1l += est_cost(xe - interp_predict<T, SZ_INTERP_LINEAR>(aE, bE, cE, eE, da, dc, de), eb,
-                          inv2eb, R);
-          s1c += est_cost(xe - interp_predict<T, SZ_INTERP_CUBIC>(aE, bE, cE, eE, da, dc, de), eb,
-                          inv2eb, R);
-          if (!odd_along_row && has_odd) {
-            const T bO = pe[1 - (int64_t)rs];
-            const T cO = dc ? pe[1 + rs] : T(0);
-            const T aO = da ? pe[1 - 3 * (int64_t)rs] : T(0);
-            const T eO = de ? pe[1 + 3 * rs] : T(0);
-            s1l += est_cost(xo - interp_predict<T, SZ_INTERP_LINEAR>(aO, bO, cO, eO, da, dc, de),
-                            eb, inv2eb, R);
-            s1c += est_cost(xo - interp_predict<T, SZ_INTERP_CUBIC>(aO, bO, cO, eO, da, dc, de),
-                            eb, inv2eb, R);
-          }
+      est_eval(so, eb, inv2eb, R, cl, cc);
+      if (has_odd) {
+        s1l += cl;
+        s1c += cc;
+      }
+      est_eval(se, eb, inv2eb, R, cl, cc);
+      if (e_ok) {
+        if (t == 0) {
+          s1l += cl;
+          s1c += cc;
+        } else if (t == 1) {
+          s2l += cl;
+          s2c += cc;
         } else {
-          // the even column on a coarser level (each lane its own)
-          const int tc = ce ? __builtin_ctz(ce) : 64;
-          const int t = tc < trow ? tc : trow;
-          if (t != 64) {  // (t = 64: the origin)
-            const bool along_row = tc < trow || (tc == trow && pos_last > prow);
-            const uint32_t sp = 1u << t;
-            if (along_row)
-              est_point(x, base + ce, ce, ncol, sp, sp, eb, inv2eb, R, cl, cc);
-            else
-              est_point(x, base + ce, qrow, nrow, sp, sp * srow, eb, inv2eb, R, cl, cc);
-            if (t == 1) {
-              s2l += cl;
-              s2c += cc;
-            } else {
-              atomicAdd(&sh[2 * t], (unsigned long long)cl);
-              atomicAdd(&sh[2 * t + 1], (unsigned long long)cc);
-            }
-          }
+          atomicAdd(&sh[2 * t], (unsigned long long)cl);
+          atomicAdd(&sh[2 * t + 1], (unsigned long long)cc);
         }
       }
     }
