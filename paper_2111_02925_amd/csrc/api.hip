@@ -215,6 +215,14 @@ int level_count(int ndim, const uint64_t* dims) {
   return L;
 }
 
+// bit l - 1 set: level l takes the cubic predictor
+uint32_t cubic_mask(const int* lvl_pred) {
+  uint32_t m = 0;
+  for (int l = 1; l <= kMaxLevels; l++)
+    if (lvl_pred[l] == SZ_INTERP_CUBIC) m |= 1u << (l - 1);
+  return m;
+}
+
 // The (level, dimension) passes of the multilevel traversal in execution
 // order: levels L..1 with stride s = 2^(l-1), and inside a level the
 // dimensions in `order`.  The origin is handled separately.
@@ -606,23 +614,32 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                                                ctx->meta, s.radius, st);
               }), "lorenzo");
   } else if (s.n) {
-    // the origin and every level, timed as one region
+    // the origin and every level, timed as one region; with the fused
+    // kernels, the origin and the coarsest levels (strides >= s_small) in one
+    // workgroup first
+    const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
+                                           cubic_mask(lvl_pred), (int)s.tsize());
+    const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
     CHECK_HIP(timed(ctx, "interp", st, [&] {
                 hipError_t e =
-                    launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta, s.radius, st);
+                    ctx->fused_levels
+                        ? launch_small_levels_compress(d_in, dtype, ctx->rec.p, codes, sg,
+                                                       ctx->meta, s.radius, st)
+                        : launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta,
+                                                 s.radius, st);
                 std::vector<LevelGeom> levels;
                 if (ctx->fused_levels &&
                     plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
                   // the finest level's reconstruction is not read by anything later
                   for (const LevelGeom& g : levels)
-                    if (e == hipSuccess)
+                    if (e == hipSuccess && g.s < s_small)
                       e = launch_level_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
                                                 ctx->meta, s.radius, g.s > 1, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);
                   for (const PassGeom& g : passes)
-                    if (e == hipSuccess)
+                    if (e == hipSuccess && g.s < s_small)
                       e = launch_pass_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
                                                ctx->meta, s.radius, st);
                 }
@@ -789,23 +806,29 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                     : l >= 1 && ((in.level_mask >> (l - 1)) & 1u) ? SZ_INTERP_CUBIC
                                                                     : SZ_INTERP_LINEAR;
     auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
+    const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
+                                           cubic_mask(lvl_pred), (int)s.tsize());
+    const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
     CHECK_HIP(timed(ctx, "recon", st, [&] {
                 if (in.predictor == SZ_LORENZO)
                   return launch_lorenzo_recon(codes, s.dtype, d_out, s.ndim, s.dims, in.eb,
                                               s.radius, st);
-                hipError_t e = launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
+                hipError_t e =
+                    ctx->fused_levels
+                        ? launch_small_levels_recon(codes, s.dtype, d_out, sg, in.eb, s.radius, st)
+                        : launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
                 std::vector<LevelGeom> levels;
                 if (ctx->fused_levels &&
                     plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
                   for (const LevelGeom& g : levels)
-                    if (e == hipSuccess)
+                    if (e == hipSuccess && g.s < s_small)
                       e = launch_level_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                              s.radius, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);
                   for (const PassGeom& g : passes)
-                    if (e == hipSuccess)
+                    if (e == hipSuccess && g.s < s_small)
                       e = launch_pass_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                             s.radius, st);
                 }

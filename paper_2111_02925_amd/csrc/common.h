@@ -144,6 +144,26 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const PassGeom& g, const Meta* m,
                                 uint32_t radius, hipStream_t st);
+// the origin and the coarsest levels (L .. l_stop) in one workgroup, their
+// lattice in LDS (values and u16 codes within kSmallBytes)
+constexpr uint32_t kSmallBytes = 48 * 1024;
+struct SmallGeom {
+  int ndim;
+  int L, l_stop;
+  uint32_t cubic;  // bit l - 1: level l cubic
+  uint64_t dims[kMaxDims];
+  uint64_t stride[kMaxDims];
+  uint8_t order[kMaxDims];
+  uint8_t pos[kMaxDims];
+};
+SmallGeom plan_small_levels(int ndim, const uint64_t* dims, const uint8_t* order, int L,
+                            uint32_t cubic_mask, int tsize);
+hipError_t launch_small_levels_compress(const void* x, int dtype, void* rec, uint16_t* codes,
+                                        const SmallGeom& sg, const Meta* m, uint32_t radius,
+                                        hipStream_t st);
+hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out,
+                                     const SmallGeom& sg, double eb_t, uint32_t radius,
+                                     hipStream_t st);
 // the first-order Lorenzo predictor: every point, in wavefronts of blocks
 hipError_t launch_lorenzo_compress(const void* x, int dtype, void* rec, uint16_t* codes, int ndim,
                                    const uint64_t* dims, const Meta* m, uint32_t radius,

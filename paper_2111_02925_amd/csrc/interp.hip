@@ -270,6 +270,183 @@ hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t*
   return hipGetLastError();
 }
 
+// The coarsest levels in one workgroup.  Every point of levels L .. l_stop
+// lies on the lattice of stride S = 2^(l_stop - 1) (all coordinates
+// multiples of S), which is small (at most kSmallBytes of values and
+// codes); as separate launches each level would cost a launch and a few
+// dependent round trips to memory for a handful of points.  One workgroup
+// loads the lattice into LDS, takes the origin and then the levels' passes
+// in the traversal order on the lattice (a barrier after each pass), and
+// stores the lattice's codes and values.  On the lattice, stride s becomes
+// s / S and extent n_d becomes ceil(n_d / S); every neighbour test
+// (i >= 3s, i + s < n_d, i + 3s < n_d) holds on the lattice exactly when it
+// holds on the grid, so the per-pass kernels' arithmetic (pass_point,
+// pass_predict, quantize / recover) gives their results.  Bit l - 1 of
+// `cubic` selects cubic for level l.
+constexpr uint32_t kSmallThreads = 1024;
+
+template <typename T, bool RECON>
+__global__ __launch_bounds__(kSmallThreads) void k_small_levels(
+    const T* __restrict__ x, T* v, uint16_t* codes, SmallGeom sg, const Meta* __restrict__ m,
+    T twoeb_dec, uint32_t R) {
+  constexpr uint32_t kCap = kSmallBytes / (sizeof(T) + 2);
+  __shared__ T lv[kCap];
+  __shared__ uint16_t lc[kCap];
+  __shared__ PassGeom pg;
+  const uint64_t S = 1ull << (sg.l_stop - 1);
+  // lattice extents and strides; flat grid index of lattice point k
+  // (loops unrolled over kMaxDims so that these stay in registers)
+  uint64_t me[kMaxDims] = {1, 1, 1, 1}, ls[kMaxDims] = {0, 0, 0, 0};
+  uint64_t np = 1;
+#pragma unroll
+  for (int e = kMaxDims - 1; e >= 0; e--) {
+    if (e < sg.ndim) {
+      me[e] = (sg.dims[e] + S - 1) / S;
+      ls[e] = np;
+      np *= me[e];
+    }
+  }
+  auto grid_index = [&](uint64_t k) {
+    uint64_t f = 0;
+#pragma unroll
+    for (int e = kMaxDims - 1; e >= 0; e--) {
+      if (e < sg.ndim) {
+        f += (k % me[e]) * S * sg.stride[e];
+        k /= me[e];
+      }
+    }
+    return f;
+  };
+  for (uint64_t k = threadIdx.x; k < np; k += kSmallThreads) {
+    const uint64_t f = grid_index(k);
+    lv[k] = RECON ? v[f] : x[f];  // (reconstruction: the verbatim values of code-0 points)
+    if (RECON) lc[k] = codes[f];
+  }
+  __syncthreads();
+  QuantParams<T> q{};
+  if (!RECON) q = QuantParams<T>::from_meta(m, R);
+  if (threadIdx.x == 0) {  // the origin, predicted as 0
+    if (RECON) {
+      const uint32_t code = lc[0];
+      if (code) lv[0] = recover(T(0), twoeb_dec, code, R);
+    } else {
+      T r;
+      lc[0] = (uint16_t)quantize(lv[0], T(0), q, r);
+      lv[0] = r;
+    }
+  }
+  // (compression: lv holds x until a point is visited, then its
+  // reconstruction; the stencil reads only visited points)
+  for (int l = sg.L; l >= sg.l_stop; l--) {
+    const uint64_t sp = (1ull << (l - 1)) / S;
+    const bool cubic = (sg.cubic >> (l - 1)) & 1u;
+    for (int j = 0; j < sg.ndim; j++) {
+      __syncthreads();  // the previous pass (or the origin) is complete; pg is free
+      if (threadIdx.x == 0) {
+        PassGeom g{};
+        g.ndim = sg.ndim;
+        g.d = sg.order[j];
+        g.s = (uint32_t)sp;
+        g.total = 1;
+#pragma unroll
+        for (int e = 0; e < kMaxDims; e++) {
+          if (e >= sg.ndim) continue;
+          uint64_t start = 0, step = 2 * sp;
+          if (e == g.d) {
+            start = sp;
+            g.nd = (uint32_t)me[e];
+          } else if (sg.pos[e] < j) {
+            step = sp;
+          }
+          g.start[e] = start;
+          g.step[e] = step;
+          g.cnt[e] = start < me[e] ? (uint32_t)((me[e] - start + step - 1) / step) : 0;
+          g.stride[e] = ls[e];
+          g.total *= g.cnt[e];
+        }
+        pg = g;
+      }
+      __syncthreads();
+      const PassGeom& g = pg;
+      for (uint64_t idx = threadIdx.x; idx < g.total; idx += kSmallThreads) {
+        const PassPoint pt = pass_point(g, (uint32_t)idx);
+        const T pred = cubic ? pass_predict<T, SZ_INTERP_CUBIC>(lv, g, pt)
+                             : pass_predict<T, SZ_INTERP_LINEAR>(lv, g, pt);
+        if (RECON) {
+          const uint32_t code = lc[pt.f];
+          if (code) lv[pt.f] = recover(pred, twoeb_dec, code, R);
+        } else {
+          T r;
+          lc[pt.f] = (uint16_t)quantize(lv[pt.f], pred, q, r);
+          lv[pt.f] = r;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (uint64_t k = threadIdx.x; k < np; k += kSmallThreads) {
+    const uint64_t f = grid_index(k);
+    v[f] = lv[k];
+    if (!RECON) codes[f] = lc[k];
+  }
+}
+
+// The levels the workgroup takes: from L down to the one with the smallest
+// stride S >= 2 whose lattice fits kSmallBytes (l_stop = L + 1: the origin
+// only).
+SmallGeom plan_small_levels(int ndim, const uint64_t* dims, const uint8_t* order, int L,
+                            uint32_t cubic_mask, int tsize) {
+  SmallGeom sg{};
+  sg.ndim = ndim;
+  sg.L = L;
+  sg.cubic = cubic_mask;
+  uint64_t st = 1;
+  for (int e = ndim - 1; e >= 0; e--) {
+    sg.dims[e] = dims[e];
+    sg.stride[e] = st;
+    st *= dims[e];
+  }
+  for (int j = 0; j < ndim; j++) {
+    sg.order[j] = order[j];
+    sg.pos[order[j]] = (uint8_t)j;
+  }
+  const uint64_t cap = kSmallBytes / (uint64_t)(tsize + 2);
+  sg.l_stop = L + 1;
+  for (int l = L; l >= 2; l--) {
+    const uint64_t s = 1ull << (l - 1);
+    uint64_t pts = 1;
+    for (int e = 0; e < ndim; e++) pts *= (dims[e] + s - 1) / s;
+    if (pts > cap) break;
+    sg.l_stop = l;
+  }
+  return sg;
+}
+
+hipError_t launch_small_levels_compress(const void* x, int dtype, void* rec, uint16_t* codes,
+                                        const SmallGeom& sg, const Meta* m, uint32_t radius,
+                                        hipStream_t st) {
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL((k_small_levels<float, false>), dim3(1), dim3(kSmallThreads), 0, st,
+                       (const float*)x, (float*)rec, codes, sg, m, 0.0f, radius);
+  else
+    hipLaunchKernelGGL((k_small_levels<double, false>), dim3(1), dim3(kSmallThreads), 0, st,
+                       (const double*)x, (double*)rec, codes, sg, m, 0.0, radius);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out,
+                                     const SmallGeom& sg, double eb_t, uint32_t radius,
+                                     hipStream_t st) {
+  uint16_t* c = const_cast<uint16_t*>(codes);  // (read only in reconstruction)
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL((k_small_levels<float, true>), dim3(1), dim3(kSmallThreads), 0, st,
+                       nullptr, (float*)out, c, sg, nullptr, 2.0f * (float)eb_t, radius);
+  else
+    hipLaunchKernelGGL((k_small_levels<double, true>), dim3(1), dim3(kSmallThreads), 0, st,
+                       nullptr, (double*)out, c, sg, nullptr, 2.0 * eb_t, radius);
+  return hipGetLastError();
+}
+
 // Adaptive interpolation: every level's cost under both predictors, from the
 // ORIGINAL values at the stencil points (the level's choice is made on the
 // host from these sums).  A point's cost under a predictor is the quantizer's
