@@ -461,7 +461,7 @@ void ctx_trim(sz_ctx* ctx) {
 
 size_t ctx_fixed_bytes() {
   return sizeof(Meta) + sizeof(uint32_t) * kMaxSym * 2 + histogram_scratch_bytes() +
-         (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 +
+         (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 + sizeof(uint64_t) * 2 * kMaxLevels +
          sizeof(uint64_t) * kMaxSym * 2 + sizeof(uint32_t) * kMaxSym * 9 + sizeof(uint16_t) * kMaxSym +
          (sizeof(uint32_t) << kLutBits) + (sizeof(uint64_t) << kLutBits) + sizeof(LongCodes) + 16 * (kMaxCodeLen + 2) +
          sizeof(uint16_t) * kMaxSym;
@@ -493,7 +493,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
                  &ctx->unpred_off, &ctx->block_sums})
     if (b->p) (void)hipFree(b->p);
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
-
+                   ctx->lvl_cost,
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
                    ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lut2, ctx->dt.lc,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
