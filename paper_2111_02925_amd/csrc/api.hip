@@ -53,6 +53,7 @@ struct sz_ctx {
   // size-dependent scratch
   Buf rec, codes, chunk_words, chunk_unpred, word_off, unpred_off, block_sums;
   Buf ylog, signs;  // point-wise relative mode: the log field and the sign words
+  Buf coarse;       // the stride-2 lattice for the strip kernel of the stride-1 level
   // fixed scratch
   Meta* meta = nullptr;
   uint32_t* hist = nullptr;
@@ -213,6 +214,22 @@ int level_count(int ndim, const uint64_t* dims) {
     L = l > L ? l : L;
   }
   return L;
+}
+
+// The stride-2 level stores its lattice compactly for the strip kernel when
+// both run: the stride-1 level takes the strip kernel and the stride-2 level
+// the fixed-pitch kernel (not the coarsest-levels workgroup).  Returns the
+// lattice's bytes, 0 if not.
+uint64_t compact_bytes(const std::vector<LevelGeom>& levels, int dtype, const void* x,
+                       const void* v, uint64_t s_small, size_t tsize) {
+  const LevelGeom* g1 = nullptr;
+  const LevelGeom* g2 = nullptr;
+  for (const LevelGeom& g : levels) {
+    if (g.s == 1) g1 = &g;
+    if (g.s == 2) g2 = &g;
+  }
+  if (!g1 || !g2 || s_small <= 2 || !g2->pitch64 || !fine_usable(*g1, dtype, x, v)) return 0;
+  return (uint64_t)g2->ext[0] * g2->ext[1] * g2->ext[2] * tsize;
 }
 
 // bit l - 1 set: level l takes the cubic predictor
@@ -437,6 +454,9 @@ size_t scratch_need(uint64_t n, size_t tsize, uint32_t chunk, bool compress) {
   uint64_t total = grown(((n + 7) & ~7ull) * 2) + 2 * grown(nch * 4) + 2 * grown(nch * 8) +
                    grown((2 * ((nch + 1023) / 1024) + 1) * 8);
   if (compress) total += grown(n * tsize);
+  // the stride-2 lattice of a field the strip kernel takes: below n / 3 points
+  // (extents >= 2, 2 and 4)
+  total += grown((n / 3 + 1) * tsize);
   return (size_t)total;
 }
 
@@ -444,7 +464,7 @@ size_t ctx_scratch_bytes(const sz_ctx* ctx) {
   size_t t = 0;
   for (const Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred,
                        &ctx->word_off, &ctx->unpred_off, &ctx->block_sums, &ctx->ylog,
-                       &ctx->signs})
+                       &ctx->signs, &ctx->coarse})
     t += b->cap;
   return t;
 }
@@ -452,7 +472,7 @@ size_t ctx_scratch_bytes(const sz_ctx* ctx) {
 void ctx_trim(sz_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
-                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs}) {
+                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->cap = 0;
@@ -490,7 +510,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
-                 &ctx->unpred_off, &ctx->block_sums})
+                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse})
     if (b->p) (void)hipFree(b->p);
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
                    ctx->lvl_cost,
@@ -620,6 +640,12 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
                                            cubic_mask(lvl_pred), (int)s.tsize());
     const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
+    std::vector<LevelGeom> levels;
+    const bool fused =
+        ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels);
+    const uint64_t cb = fused ? compact_bytes(levels, dtype, d_in, ctx->rec.p, s_small, s.tsize()) : 0;
+    if (cb) CHECK_HIP(ensure(ctx->coarse, cb), "hipMalloc(coarse)");
+    void* cmp = cb ? ctx->coarse.p : nullptr;
     CHECK_HIP(timed(ctx, "interp", st, [&] {
                 hipError_t e =
                     ctx->fused_levels
@@ -627,14 +653,12 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                                                        ctx->meta, s.radius, st)
                         : launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta,
                                                  s.radius, st);
-                std::vector<LevelGeom> levels;
-                if (ctx->fused_levels &&
-                    plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+                if (fused) {
                   // the finest level's reconstruction is not read by anything later
                   for (const LevelGeom& g : levels)
                     if (e == hipSuccess && g.s < s_small)
                       e = launch_level_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
-                                                ctx->meta, s.radius, g.s > 1, st);
+                                                ctx->meta, s.radius, g.s > 1, cmp, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);
@@ -809,6 +833,12 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
     const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
                                            cubic_mask(lvl_pred), (int)s.tsize());
     const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
+    std::vector<LevelGeom> levels;
+    const bool fused = in.predictor != SZ_LORENZO && ctx->fused_levels &&
+                       plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels);
+    const uint64_t cb = fused ? compact_bytes(levels, s.dtype, d_out, d_out, s_small, s.tsize()) : 0;
+    if (cb) CHECK_HIP(ensure(ctx->coarse, cb), "hipMalloc(coarse)");
+    void* cmp = cb ? ctx->coarse.p : nullptr;
     CHECK_HIP(timed(ctx, "recon", st, [&] {
                 if (in.predictor == SZ_LORENZO)
                   return launch_lorenzo_recon(codes, s.dtype, d_out, s.ndim, s.dims, in.eb,
@@ -817,13 +847,11 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                     ctx->fused_levels
                         ? launch_small_levels_recon(codes, s.dtype, d_out, sg, in.eb, s.radius, st)
                         : launch_origin_recon(codes, s.dtype, d_out, in.eb, s.radius, st);
-                std::vector<LevelGeom> levels;
-                if (ctx->fused_levels &&
-                    plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels)) {
+                if (fused) {
                   for (const LevelGeom& g : levels)
                     if (e == hipSuccess && g.s < s_small)
                       e = launch_level_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
-                                             s.radius, st);
+                                             s.radius, cmp, st);
                 } else {
                   std::vector<PassGeom> passes;
                   build_passes(s, passes);

@@ -213,15 +213,23 @@ struct LevelTuning {
   uint32_t fine_rows;      // rows per run of the strip kernel (0: chosen from the shape)
 };
 constexpr uint32_t kLevelStoreValues = 1u << 0;   // store reconstructed values of the tile
+// the stride-2 level also stores its whole lattice (coarser points included)
+// compactly, in lattice order, for the strip kernel of the stride-1 level;
+// reconstruction then stores no values in the field (the strip kernel
+// stores every point)
+constexpr uint32_t kLevelStoreCompact = 1u << 1;
 
 // Plans the levels L..1 (coarsest first); false for four dimensions.
 bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize,
                  const LevelTuning* tune, std::vector<LevelGeom>& out);
+// cmp: the stride-2 lattice, written by the stride-2 level and read by the
+// strip kernel (nullptr: neither; the strip kernel reads the field)
 hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* rec,
                                  uint16_t* codes, const LevelGeom& g, const Meta* m,
-                                 uint32_t radius, bool store_rec, hipStream_t st);
+                                 uint32_t radius, bool store_rec, void* cmp, hipStream_t st);
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
-                              const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+                              const LevelGeom& g, double eb_t, uint32_t radius, void* cmp,
+                              hipStream_t st);
 // The strip kernel of the stride-1 level (fine.hip): planned by plan_fine
 // (sets g.fine), launched when fine_usable (the field's pointers hold whole
 // column pairs).
@@ -229,9 +237,10 @@ bool plan_fine(LevelGeom& g, int tsize, uint32_t rows);
 bool fine_usable(const LevelGeom& g, int dtype, const void* x, const void* v);
 hipError_t launch_fine_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const LevelGeom& g, const Meta* m,
-                                uint32_t radius, hipStream_t st);
+                                uint32_t radius, const void* cmp, hipStream_t st);
 hipError_t launch_fine_recon(const uint16_t* codes, int dtype, int predictor, void* out,
-                             const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st);
+                             const LevelGeom& g, double eb_t, uint32_t radius, const void* cmp,
+                             hipStream_t st);
 
 // Point-wise relative mode (pwrel.hip): the log field's absolute bound, and
 // the transforms before and after the pipeline.

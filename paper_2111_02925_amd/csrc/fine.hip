@@ -143,7 +143,7 @@ template <typename T, int PRED, bool RECON, int A>
 __global__ __launch_bounds__(kFineMaxWaves * 64) void k_fine(const T* __restrict__ x, T* v,
                                                             uint16_t* codes, LevelGeom g,
                                                             const Meta* __restrict__ m, T twoeb,
-                                                            uint32_t R) {
+                                                            uint32_t R, const T* __restrict__ cmp) {
   static_assert(A % 2 == 0, "plane groups start on even planes");
   constexpr int NC = A / 2 + 3;  // coarse planes A0 - 2, A0, ..., A0 + A + 2
   using P = typename PairOf<T>::type;
@@ -211,11 +211,22 @@ __global__ __launch_bounds__(kFineMaxWaves * 64) void k_fine(const T* __restrict
   // Rows whose values are not needed still issue their loads (the waits count
   // alike on every path), at an address read by the same step: no traffic.
   // Even rows outside the run feed only the pass along a of odd planes.
+  // Coarse points come from the compact stride-2 lattice when the stride-2
+  // level stored one (cmp; lattice extents ceil(E/2), the lanes' even columns
+  // adjacent there), else from the field (every other column of a line).
+  const uint32_t M1 = (E1 + 1) / 2, M2 = (E2 + 1) / 2;
+  const T* __restrict__ csrc = cmp ? cmp : v;
   auto issue_even = [&](int32_t e) {
-    const uint32_t r = clamp_row(e) * fb + ce;
+    const uint32_t er = clamp_row(e);
+    const uint32_t r = er * fb + ce;
     const bool own = e >= (int32_t)B0 && e < (int32_t)B1;
 #pragma unroll
-    for (int k = 0; k < NC; k++) cv[k] = v[clamp_plane((int32_t)A0 - 2 + 2 * k) * fa + r];
+    for (int k = 0; k < NC; k++) {
+      const uint32_t a = clamp_plane((int32_t)A0 - 2 + 2 * k);
+      const size_t ci = cmp ? ((size_t)(a >> 1) * M1 + (er >> 1)) * M2 + (ce >> 1)
+                            : (size_t)(a * fa + r);
+      cv[k] = csrc[ci];
+    }
 #pragma unroll
     for (int j = 0; j < A; j++) {
       const int jj = (j % 2 == 0 && !own) ? j + 1 : j;
@@ -464,15 +475,15 @@ bool plan_fine(LevelGeom& g, int tsize, uint32_t rows) {
 template <typename T, bool RECON, int A>
 static hipError_t launch_fine_t(const void* x, int predictor, void* v, uint16_t* codes,
                                 const LevelGeom& g, const Meta* m, double eb_t, uint32_t R,
-                                hipStream_t st) {
+                                const void* cmp, hipStream_t st) {
   dim3 grid(g.f_items), block(64 * g.f_waves);
   const T twoeb = RECON ? (T)2 * (T)eb_t : T(0);
   if (predictor == SZ_INTERP_CUBIC)
     hipLaunchKernelGGL((k_fine<T, SZ_INTERP_CUBIC, RECON, A>), grid, block, 0, st, (const T*)x,
-                       (T*)v, codes, g, m, twoeb, R);
+                       (T*)v, codes, g, m, twoeb, R, (const T*)cmp);
   else
     hipLaunchKernelGGL((k_fine<T, SZ_INTERP_LINEAR, RECON, A>), grid, block, 0, st, (const T*)x,
-                       (T*)v, codes, g, m, twoeb, R);
+                       (T*)v, codes, g, m, twoeb, R, (const T*)cmp);
   return hipGetLastError();
 }
 
@@ -484,20 +495,23 @@ bool fine_usable(const LevelGeom& g, int dtype, const void* x, const void* v) {
 
 hipError_t launch_fine_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const LevelGeom& g, const Meta* m,
-                                uint32_t radius, hipStream_t st) {
+                                uint32_t radius, const void* cmp, hipStream_t st) {
   if (g.f_items == 0) return hipSuccess;
   if (dtype == SZ_F32)
-    return launch_fine_t<float, false, 8>(x, predictor, rec, codes, g, m, 0.0, radius, st);
-  return launch_fine_t<double, false, 4>(x, predictor, rec, codes, g, m, 0.0, radius, st);
+    return launch_fine_t<float, false, 8>(x, predictor, rec, codes, g, m, 0.0, radius, cmp, st);
+  return launch_fine_t<double, false, 4>(x, predictor, rec, codes, g, m, 0.0, radius, cmp, st);
 }
 
 hipError_t launch_fine_recon(const uint16_t* codes, int dtype, int predictor, void* out,
-                             const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st) {
+                             const LevelGeom& g, double eb_t, uint32_t radius, const void* cmp,
+                             hipStream_t st) {
   if (g.f_items == 0) return hipSuccess;
   uint16_t* c = const_cast<uint16_t*>(codes);  // only read when reconstructing
   if (dtype == SZ_F32)
-    return launch_fine_t<float, true, 8>(nullptr, predictor, out, c, g, nullptr, eb_t, radius, st);
-  return launch_fine_t<double, true, 4>(nullptr, predictor, out, c, g, nullptr, eb_t, radius, st);
+    return launch_fine_t<float, true, 8>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
+                                         cmp, st);
+  return launch_fine_t<double, true, 4>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
+                                        cmp, st);
 }
 
 }  // namespace szg

@@ -399,7 +399,7 @@ template <typename T, int PRED, bool RECON>
 __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_level64(const T* __restrict__ x, T* v,
                                                            uint16_t* codes, LevelGeom g,
                                                            const Meta* __restrict__ m, T twoeb,
-                                                           uint32_t R, uint32_t flags) {
+                                                           uint32_t R, uint32_t flags, T* cmp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* box = reinterpret_cast<T*>(smem_raw);
   T* ring = reinterpret_cast<T*>(smem_raw + g.box_bytes);
@@ -408,7 +408,8 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(5
   const uint32_t ring_slot = g.ring_b * kRingPitch;  // entries per coarse grid
   const uint32_t fa = (uint32_t)g.fs[0], fb = (uint32_t)g.fs[1], fc = (uint32_t)g.fs[2];
   const uint32_t ea = g.ext[0];
-  const bool store_v = (flags & kLevelStoreValues) != 0;
+  const bool store_c = (flags & kLevelStoreCompact) != 0;
+  const bool store_v = (flags & kLevelStoreValues) != 0 || (RECON && !store_c);
   QuantParams<T> q;
   if (RECON) {
     q.eb = T(0);
@@ -621,7 +622,8 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(5
           const uint32_t f = p * fa + qb * fb + colt;
           const uint32_t bk = bk0 + r * kPitch;
           if (!RECON && !(even_pc && (qb & 1u) == 0)) codes[f] = lcode[bk];
-          if (RECON || store_v) v[f] = box[bk];
+          if (store_v) v[f] = box[bk];
+          if (store_c) cmp[((size_t)p * g.ext[1] + qb) * g.ext[2] + qc] = box[bk];
         }
       }
     }
@@ -722,7 +724,7 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
 template <typename T, bool RECON>
 static hipError_t launch_level_t(const void* x, int predictor, void* v, uint16_t* codes,
                                  const LevelGeom& g, const Meta* m, double eb_t, uint32_t R,
-                                 uint32_t flags, hipStream_t st) {
+                                 uint32_t flags, void* cmp, hipStream_t st) {
   if (g.nitems == 0) return hipSuccess;
   dim3 grid((unsigned)g.nitems), block(kLevelThreads);
   const T twoeb = RECON ? (T)2 * (T)eb_t : T(0);
@@ -730,10 +732,10 @@ static hipError_t launch_level_t(const void* x, int predictor, void* v, uint16_t
   if (g.pitch64) {
     if (predictor == SZ_INTERP_CUBIC)
       hipLaunchKernelGGL((k_level64<T, SZ_INTERP_CUBIC, RECON>), grid, block, lds, st,
-                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags, (T*)cmp);
     else
       hipLaunchKernelGGL((k_level64<T, SZ_INTERP_LINEAR, RECON>), grid, block, lds, st,
-                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags);
+                         (const T*)x, (T*)v, codes, g, m, twoeb, R, flags, (T*)cmp);
   } else if (predictor == SZ_INTERP_CUBIC) {
     hipLaunchKernelGGL((k_level<T, SZ_INTERP_CUBIC, RECON>), grid, block, lds, st, (const T*)x,
                        (T*)v, codes, g, m, twoeb, R, flags);
@@ -746,28 +748,36 @@ static hipError_t launch_level_t(const void* x, int predictor, void* v, uint16_t
 
 hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* rec,
                                  uint16_t* codes, const LevelGeom& g, const Meta* m,
-                                 uint32_t radius, bool store_rec, hipStream_t st) {
-  const uint32_t flags = store_rec ? kLevelStoreValues : 0u;
+                                 uint32_t radius, bool store_rec, void* cmp, hipStream_t st) {
   // (the strip kernel stores no reconstruction: it runs the last level only)
   if (!store_rec && fine_usable(g, dtype, x, rec))
-    return launch_fine_compress(x, dtype, predictor, rec, codes, g, m, radius, st);
+    return launch_fine_compress(x, dtype, predictor, rec, codes, g, m, radius, cmp, st);
+  // the stride-2 level with a compact lattice: stored there instead of the field
+  const bool compact = cmp && g.s == 2 && g.pitch64;
+  const uint32_t flags =
+      compact ? kLevelStoreCompact : (store_rec ? kLevelStoreValues : 0u);
   if (dtype == SZ_F32)
-    return launch_level_t<float, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags, st);
-  return launch_level_t<double, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags, st);
+    return launch_level_t<float, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags,
+                                        compact ? cmp : nullptr, st);
+  return launch_level_t<double, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags,
+                                       compact ? cmp : nullptr, st);
 }
 
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
-                              const LevelGeom& g, double eb_t, uint32_t radius, hipStream_t st) {
+                              const LevelGeom& g, double eb_t, uint32_t radius, void* cmp,
+                              hipStream_t st) {
   // the tile is stored whole (its coarse points too, unchanged), so that the
   // output rows are written by one workgroup
   if (fine_usable(g, dtype, out, out))
-    return launch_fine_recon(codes, dtype, predictor, out, g, eb_t, radius, st);
+    return launch_fine_recon(codes, dtype, predictor, out, g, eb_t, radius, cmp, st);
+  const bool compact = cmp && g.s == 2 && g.pitch64;
+  const uint32_t flags = compact ? kLevelStoreCompact : kLevelStoreValues;
   uint16_t* c = const_cast<uint16_t*>(codes);  // only read when reconstructing
   if (dtype == SZ_F32)
     return launch_level_t<float, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
-                                       kLevelStoreValues, st);
+                                       flags, compact ? cmp : nullptr, st);
   return launch_level_t<double, true>(nullptr, predictor, out, c, g, nullptr, eb_t, radius,
-                                      kLevelStoreValues, st);
+                                      flags, compact ? cmp : nullptr, st);
 }
 
 }  // namespace szg
