@@ -292,35 +292,51 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_levels(
   constexpr uint32_t kCap = kSmallBytes / (sizeof(T) + 2);
   __shared__ T lv[kCap];
   __shared__ uint16_t lc[kCap];
-  __shared__ PassGeom pg;
   const uint64_t S = 1ull << (sg.l_stop - 1);
-  // lattice extents and strides; flat grid index of lattice point k
-  // (loops unrolled over kMaxDims so that these stay in registers)
-  uint64_t me[kMaxDims] = {1, 1, 1, 1}, ls[kMaxDims] = {0, 0, 0, 0};
-  uint64_t np = 1;
+  const int nd = sg.ndim;
+  // lattice extents and strides (at most kCap points: 32-bit arithmetic);
+  // loops unrolled over kMaxDims so that all of this stays in registers
+  uint32_t me[kMaxDims] = {1, 1, 1, 1}, ls[kMaxDims] = {0, 0, 0, 0};
+  uint32_t np = 1;
 #pragma unroll
   for (int e = kMaxDims - 1; e >= 0; e--) {
-    if (e < sg.ndim) {
-      me[e] = (sg.dims[e] + S - 1) / S;
+    if (e < nd) {
+      me[e] = (uint32_t)((sg.dims[e] + S - 1) / S);
       ls[e] = np;
       np *= me[e];
     }
   }
-  auto grid_index = [&](uint64_t k) {
+  auto grid_index = [&](uint32_t k) {
     uint64_t f = 0;
 #pragma unroll
     for (int e = kMaxDims - 1; e >= 0; e--) {
-      if (e < sg.ndim) {
-        f += (k % me[e]) * S * sg.stride[e];
+      if (e < nd) {
+        f += (uint64_t)(k % me[e]) * S * sg.stride[e];
         k /= me[e];
       }
     }
     return f;
   };
-  for (uint64_t k = threadIdx.x; k < np; k += kSmallThreads) {
-    const uint64_t f = grid_index(k);
-    lv[k] = RECON ? v[f] : x[f];  // (reconstruction: the verbatim values of code-0 points)
-    if (RECON) lc[k] = codes[f];
+  // the lattice into LDS, eight loads a lane in flight
+  constexpr int kU = 8;
+  for (uint32_t k0 = 0; k0 < np; k0 += kU * kSmallThreads) {
+    T vv[kU];
+    uint16_t cc[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint32_t k = k0 + u * kSmallThreads + threadIdx.x;
+      const uint64_t f = k < np ? grid_index(k) : 0;
+      vv[u] = RECON ? v[f] : x[f];  // (reconstruction: the verbatim values of code-0 points)
+      cc[u] = RECON ? codes[f] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint32_t k = k0 + u * kSmallThreads + threadIdx.x;
+      if (k < np) {
+        lv[k] = vv[u];
+        if (RECON) lc[k] = cc[u];
+      }
+    }
   }
   __syncthreads();
   QuantParams<T> q{};
@@ -338,53 +354,62 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_levels(
   // (compression: lv holds x until a point is visited, then its
   // reconstruction; the stencil reads only visited points)
   for (int l = sg.L; l >= sg.l_stop; l--) {
-    const uint64_t sp = (1ull << (l - 1)) / S;
+    const uint32_t sp = (uint32_t)((1ull << (l - 1)) / S);
     const bool cubic = (sg.cubic >> (l - 1)) & 1u;
-    for (int j = 0; j < sg.ndim; j++) {
-      __syncthreads();  // the previous pass (or the origin) is complete; pg is free
-      if (threadIdx.x == 0) {
-        PassGeom g{};
-        g.ndim = sg.ndim;
-        g.d = sg.order[j];
-        g.s = (uint32_t)sp;
-        g.total = 1;
+    for (int j = 0; j < nd; j++) {
+      __syncthreads();  // the previous pass (or the origin) is complete
+      // the pass along d = order[j] (every lane computes its geometry): d an
+      // odd multiple of sp, earlier dimensions of the order multiples of sp,
+      // later ones multiples of 2 sp
+      const int d = sg.order[j];
+      uint32_t cnt[kMaxDims] = {1, 1, 1, 1}, start[kMaxDims] = {0, 0, 0, 0},
+               step[kMaxDims] = {1, 1, 1, 1};
+      uint32_t total = 1, ext_d = 1, str_d = 0;
 #pragma unroll
-        for (int e = 0; e < kMaxDims; e++) {
-          if (e >= sg.ndim) continue;
-          uint64_t start = 0, step = 2 * sp;
-          if (e == g.d) {
-            start = sp;
-            g.nd = (uint32_t)me[e];
-          } else if (sg.pos[e] < j) {
-            step = sp;
-          }
-          g.start[e] = start;
-          g.step[e] = step;
-          g.cnt[e] = start < me[e] ? (uint32_t)((me[e] - start + step - 1) / step) : 0;
-          g.stride[e] = ls[e];
-          g.total *= g.cnt[e];
+      for (int e = 0; e < kMaxDims; e++) {
+        if (e >= nd) continue;
+        start[e] = e == d ? sp : 0u;
+        step[e] = (e == d || sg.pos[e] > j) ? 2 * sp : sp;
+        cnt[e] = start[e] < me[e] ? (me[e] - start[e] + step[e] - 1) / step[e] : 0u;
+        total *= cnt[e];
+        if (e == d) {
+          ext_d = me[e];
+          str_d = ls[e];
         }
-        pg = g;
       }
-      __syncthreads();
-      const PassGeom& g = pg;
-      for (uint64_t idx = threadIdx.x; idx < g.total; idx += kSmallThreads) {
-        const PassPoint pt = pass_point(g, (uint32_t)idx);
-        const T pred = cubic ? pass_predict<T, SZ_INTERP_CUBIC>(lv, g, pt)
-                             : pass_predict<T, SZ_INTERP_LINEAR>(lv, g, pt);
+      const uint32_t sd = sp * str_d;
+      for (uint32_t idx = threadIdx.x; idx < total; idx += kSmallThreads) {
+        uint32_t rem = idx, f = 0, i = 0;
+#pragma unroll
+        for (int e = kMaxDims - 1; e >= 0; e--) {
+          if (e < nd) {
+            const uint32_t qe = start[e] + (rem % cnt[e]) * step[e];
+            rem /= cnt[e];
+            f += qe * ls[e];
+            if (e == d) i = qe;
+          }
+        }
+        // the stencil as in the per-pass kernels
+        const bool has_a = i >= 3 * sp, has_c = i + sp < ext_d, has_e = i + 3 * sp < ext_d;
+        const T b = lv[f - sd];
+        const T c = has_c ? lv[f + sd] : T(0);
+        const T a = has_a && (!has_c || cubic) ? lv[f - 3 * sd] : T(0);
+        const T e = cubic && has_e ? lv[f + 3 * sd] : T(0);
+        const T pred = cubic ? interp_predict<T, SZ_INTERP_CUBIC>(a, b, c, e, has_a, has_c, has_e)
+                             : interp_predict<T, SZ_INTERP_LINEAR>(a, b, c, e, has_a, has_c, has_e);
         if (RECON) {
-          const uint32_t code = lc[pt.f];
-          if (code) lv[pt.f] = recover(pred, twoeb_dec, code, R);
+          const uint32_t code = lc[f];
+          if (code) lv[f] = recover(pred, twoeb_dec, code, R);
         } else {
           T r;
-          lc[pt.f] = (uint16_t)quantize(lv[pt.f], pred, q, r);
-          lv[pt.f] = r;
+          lc[f] = (uint16_t)quantize(lv[f], pred, q, r);
+          lv[f] = r;
         }
       }
     }
   }
   __syncthreads();
-  for (uint64_t k = threadIdx.x; k < np; k += kSmallThreads) {
+  for (uint32_t k = threadIdx.x; k < np; k += kSmallThreads) {
     const uint64_t f = grid_index(k);
     v[f] = lv[k];
     if (!RECON) codes[f] = lc[k];
