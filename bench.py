@@ -251,7 +251,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs per-field measurement")
-    ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the lossless, point-wise relative and adaptive measurements "
                          "(for profiler runs that count the step's kernels)")
