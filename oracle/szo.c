@@ -160,6 +160,12 @@ static uint64_t pass_point_next(const struct szo_grid* g,
 /* Typed arithmetic                                                    */
 /* ------------------------------------------------------------------ */
 
+/* The rows (along the last dimension) that price adaptive interpolation's
+ * dimension orders: row index r is taken when the top three bits of
+ * (r mod 2^32) * 0x9E3779B1 (Fibonacci hashing) are zero, about one row in
+ * eight, spread evenly over the rows. */
+static int row_sampled(uint64_t r) { return (((uint32_t)r * 0x9E3779B1u) >> 29) == 0; }
+
 #define T float
 #define FN(name) name##_f32
 #define FABS fabsf
@@ -1014,6 +1020,16 @@ int szo_compress(const void* x, int dtype, int ndim, const uint64_t* dims,
   uint64_t n = g.n;
   double eb_t;
   if ((rc = szo_resolve_eb(x, n, dtype, eb_mode, eb, &eb_t))) return rc;
+  /* adaptive interpolation with the default (identity) order: the
+     dimension order is chosen first */
+  if (predictor == SZO_ADAPTIVE && identity_order(&g) && ndim > 1 && n > 0) {
+    uint8_t ord[SZO_MAXD];
+    if (dtype == SZO_F32)
+      choose_order_f32((const float*)x, ndim, g.dims, (float)eb_t, radius, ord);
+    else
+      choose_order_f64((const double*)x, ndim, g.dims, eb_t, radius, ord);
+    if ((rc = grid_init(&g, ndim, dims, ord))) return rc;
+  }
 
   uint32_t nsym = 2 * radius;
   uint16_t* codes = (uint16_t*)malloc(sizeof(uint16_t) * (n ? n : 1));

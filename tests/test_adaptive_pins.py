@@ -22,8 +22,10 @@ def test_polynomials_take_cubic(orc, shape):
         x = x.astype(np.float64)
         s = orc.compress(x, orc.ABS, 1e-6, orc.ADAPTIVE)
         assert _mask(orc, s) == (1 << L) - 1
-        # then the stream equals the cubic one apart from the predictor byte and the mask
-        c = orc.compress(x, orc.ABS, 1e-6, orc.CUBIC)
+        # then the stream equals the cubic one (in the chosen dimension order)
+        # apart from the predictor byte and the mask
+        order = tuple(s[41:41 + x.ndim])
+        c = orc.compress(x, orc.ABS, 1e-6, orc.CUBIC, order=order)
         a = bytearray(s)
         a[40] = orc.CUBIC
         a[124:128] = b"\0\0\0\0"
@@ -104,3 +106,85 @@ def test_bad_masks_rejected(orc):
     fixed[124] = 1  # a mask on a fixed-predictor stream
     with pytest.raises(Exception):
         orc.decompress(bytes(fixed))
+
+
+def _row_sampled(r):
+    return ((r * 0x9E3779B1) & 0xFFFFFFFF) >> 29 == 0
+
+
+def _ctz(v):
+    return 64 if v == 0 else (v & -v).bit_length() - 1
+
+
+def _predict(xf, q, d, s, dims, strides, cubic):
+    """The interpolation rules written out (Section 6.2 stencils, the edge
+    cases of the cubic and linear rules), in float32."""
+    i, nd = q[d], dims[d]
+    f = sum(qe * st for qe, st in zip(q, strides))
+    sd = s * strides[d]
+    b = xf[f - sd]
+    has_a, has_c, has_e = i >= 3 * s, i + s < nd, i + 3 * s < nd
+    h = np.float32
+    if not has_c:
+        return (h(3) * b - xf[f - 3 * sd]) * h(0.5) if has_a else b
+    c = xf[f + sd]
+    if not cubic:
+        return (b + c) * h(0.5)
+    if has_a and has_e:
+        return (h(9) * (b + c) - (xf[f - 3 * sd] + xf[f + 3 * sd])) * h(0.0625)
+    if has_e:
+        return ((h(3) * b + h(6) * c) - xf[f + 3 * sd]) * h(0.125)
+    if has_a:
+        return ((h(6) * b + h(3) * c) - xf[f - 3 * sd]) * h(0.125)
+    return (b + c) * h(0.5)
+
+
+def _order_total(x, order, eb, R):
+    """Sampled price of one dimension order: per level, the cheaper of the
+    two cost sums over the points of sampled rows; every point's level and
+    pass found from its coordinates (fewest trailing zeros, last dimension
+    of the order with that many)."""
+    dims = x.shape
+    strides = [int(np.prod(dims[e + 1:])) for e in range(len(dims))]
+    xf = x.reshape(-1).astype(np.float32)
+    pos = {e: j for j, e in enumerate(order)}
+    inv = np.float32(1) / (np.float32(2) * np.float32(eb))
+    cost = {}
+    for q in np.ndindex(*dims):
+        t = min(_ctz(v) for v in q)
+        if t == 64:
+            continue
+        f = sum(qe * st for qe, st in zip(q, strides))
+        if not _row_sampled(f // dims[-1]):
+            continue
+        d = max((e for e in range(len(dims)) if _ctz(q[e]) == t), key=lambda e: pos[e])
+        for k in (0, 1):
+            p = _predict(xf, q, d, 1 << t, dims, strides, k == 1)
+            kf = np.rint(np.abs(np.float32(xf[f] - p)) * inv)
+            cost.setdefault(t, [0, 0])[k] += int(kf) if kf < R else R
+    return sum(min(c) for c in cost.values())
+
+
+@pytest.mark.parametrize("shape,seed", [((24, 40), 1), ((9, 11, 14), 2), ((30, 7, 12), 3),
+                                        ((5, 6, 4, 7), 4)])
+def test_order_is_the_cheapest_by_brute_force(orc, shape, seed):
+    import itertools
+
+    x = synth.random_field(shape, seed=seed)
+    x = x + np.linspace(0, 3, shape[-1], dtype=np.float32)  # a trend along the last axis
+    eb = 1e-2
+    s = orc.compress(x, orc.ABS, eb, orc.ADAPTIVE)
+    chosen = tuple(s[41:41 + x.ndim])
+    totals = {p: _order_total(x, p, eb, 32768) for p in itertools.permutations(range(x.ndim))}
+    best = min(totals.values())
+    first = next(p for p in sorted(totals) if totals[p] == best)
+    assert chosen == first, (chosen, first, totals)
+    # the stream decodes in that order within the bound
+    back = orc.decompress(s)
+    assert np.abs(back.astype(np.float64) - x).max() <= orc.parse_header(s)["eb"]
+
+
+def test_given_order_is_kept(orc):
+    x = synth.random_field((20, 30), seed=5)
+    s = orc.compress(x, orc.REL, 1e-3, orc.ADAPTIVE, order=(1, 0))
+    assert tuple(s[41:43]) == (1, 0)
