@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -62,7 +63,7 @@ struct sz_ctx {
   uint8_t* enc_len = nullptr;
   uint32_t* symtab = nullptr;
   uint64_t* totals = nullptr;
-  uint64_t* lvl_cost = nullptr;  // adaptive interpolation: [level][linear, cubic] cost sums
+  uint64_t* lvl_cost = nullptr;  // adaptive interpolation: [order][level][linear, cubic] cost sums
   CodebookScratch cb{};
   DecodeTables dt{};
   Meta* h_meta = nullptr;       // pinned
@@ -400,7 +401,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->enc_len, kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->symtab, sizeof(uint32_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->totals, sizeof(uint64_t) * 4), "hipMalloc");
-  CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * 2 * kMaxLevels), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * 2 * kMaxLevels * kMaxOrders), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_a, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_b, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.w, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
@@ -481,7 +482,7 @@ void ctx_trim(sz_ctx* ctx) {
 
 size_t ctx_fixed_bytes() {
   return sizeof(Meta) + sizeof(uint32_t) * kMaxSym * 2 + histogram_scratch_bytes() +
-         (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 + sizeof(uint64_t) * 2 * kMaxLevels +
+         (sizeof(uint64_t) + 1) * kMaxSym + sizeof(uint64_t) * 4 + sizeof(uint64_t) * 2 * kMaxLevels * kMaxOrders +
          sizeof(uint64_t) * kMaxSym * 2 + sizeof(uint32_t) * kMaxSym * 9 + sizeof(uint16_t) * kMaxSym +
          (sizeof(uint32_t) << kLutBits) + (sizeof(uint64_t) << kLutBits) + sizeof(LongCodes) + 16 * (kMaxCodeLen + 2) +
          sizeof(uint16_t) * kMaxSym;
@@ -610,6 +611,52 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   for (int l = 0; l <= kMaxLevels; l++)
     lvl_pred[l] = predictor == SZ_INTERP_ADAPTIVE ? SZ_INTERP_CUBIC : predictor;
   if (predictor == SZ_INTERP_ADAPTIVE && s.n) {
+    // the dimension order first (the default order only): every order priced
+    // on the sampled rows as the sum over levels of the cheaper cost sum,
+    // the cheapest first in lexicographic order
+    bool identity = true;
+    for (int j = 0; j < s.ndim; j++) identity = identity && s.order[j] == j;
+    if (identity && s.ndim > 1) {
+      std::vector<std::array<uint8_t, kMaxDims>> perms;
+      std::array<uint8_t, kMaxDims> pm{0, 1, 2, 3};
+      do perms.push_back(pm);
+      while (std::next_permutation(pm.begin(), pm.begin() + s.ndim));
+      const size_t per = 2 * kMaxLevels;
+      CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0,
+                                2 * per * perms.size(), st), "fill");
+      CHECK_HIP(timed(ctx, "estimate", st, [&] {
+                  hipError_t e = hipSuccess;
+                  for (size_t i = 0; i < perms.size() && e == hipSuccess; i++) {
+                    EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[i].data());
+                    eg.sampled = 1;
+                    e = launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, ctx->lvl_cost + per * i,
+                                        st);
+                  }
+                  return e;
+                }), "estimate");
+      std::vector<uint64_t> cost(per * perms.size());
+      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * cost.size(),
+                               hipMemcpyDeviceToHost, st), "memcpy");
+      CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+      const int L = level_count(s.ndim, s.dims);
+      uint64_t best = ~0ull;
+      size_t bi = 0;
+      for (size_t i = 0; i < perms.size(); i++) {
+        uint64_t total = 0;
+        for (int l = 1; l <= L; l++) {
+          const uint64_t lin = cost[per * i + 2 * (l - 1)], cub = cost[per * i + 2 * (l - 1) + 1];
+          total += cub < lin ? cub : lin;
+        }
+        if (total < best) {
+          best = total;
+          bi = i;
+        }
+      }
+      for (int j = 0; j < s.ndim; j++) {
+        s.order[j] = perms[bi][j];
+        hdr[41 + j] = perms[bi][j];
+      }
+    }
     CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0, 4 * kMaxLevels, st),
               "fill");
     const EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);

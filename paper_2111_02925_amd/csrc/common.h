@@ -92,7 +92,8 @@ constexpr uint32_t kStatusCountMismatch = 1u << 3;
 // points whose coordinate along `d` is an odd multiple of s, whose coordinates
 // along dimensions visited earlier in the level are multiples of s, and later
 // ones multiples of 2s.
-constexpr int kMaxLevels = 32;  // levels of a field of fewer than 2^32 points per dimension
+constexpr int kMaxLevels = 32;
+constexpr int kMaxOrders = 24;  // orders of at most four dimensions  // levels of a field of fewer than 2^32 points per dimension
 
 struct PassGeom {
   int ndim;
@@ -137,8 +138,15 @@ struct EstGeom {
   uint32_t pairs;         // column pairs a lane takes per unit (1, 2 or 4)
   uint64_t segs;          // units per row along the last dimension
   uint64_t units;         // rows x segs
+  uint32_t sampled;       // 1: only the rows est_row_sampled takes
 };
 EstGeom make_estimate_geom(int ndim, const uint64_t* dims, const uint8_t* order);
+// The rows that price the dimension orders: row index r when the top three
+// bits of (r mod 2^32) * 0x9E3779B1 (Fibonacci hashing) are zero, about one
+// row in eight.
+__host__ __device__ inline bool est_row_sampled(uint64_t r) {
+  return (((uint32_t)r * 0x9E3779B1u) >> 29) == 0;
+}
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st);
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,

@@ -446,6 +446,10 @@ bool plan_fine(LevelGeom& g, int tsize, uint32_t rows) {
   g.fine = 0;
   const uint32_t E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
   if (g.s != 1 || g.fs[2] != 1 || E0 < 2 || E1 < 2 || E2 < 4 || (E2 & 1u)) return false;
+  // a plane group's stores are addressed from its first plane: the planes
+  // (axis a) must be the field's outer dimension, each plane holding its
+  // rows (orders that swap the two outer dimensions take k_level64)
+  if (g.fs[1] * (uint64_t)E1 > g.fs[0]) return false;
   // a plane group's stores span less than 2^31 bytes (buffer offsets)
   if ((uint64_t)fine_planes(tsize) * g.fs[0] * (uint64_t)tsize >= 0x7FFF0000ull) return false;
   const uint32_t nw = std::min<uint32_t>(kFineMaxWaves, cdiv(E2, kFineCols));

@@ -609,6 +609,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
 #pragma unroll
     for (int e = 0; e < kMaxDims - 1; e++)
       if (e < last) base += q[e] * (uint32_t)g.stride[e];
+    if (g.sampled && !est_row_sampled(base / ncol)) continue;
     int trow = 64, prow = -1;
     uint32_t qrow = 0, srow = 0, nrow = 0;
 #pragma unroll

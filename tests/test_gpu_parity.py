@@ -98,6 +98,9 @@ FINE_CASES = [
     ("fine-unpred", lambda: synth.random_field((16, 40, 300), seed=37), "rel", 1e-6, 1, 32768, 4096, None),
     ("fine-unpred-R2", lambda: synth.random_field((10, 33, 140), seed=38), "rel", 1e-3, 0, 2, 1024, None),
     ("fine-4col", lambda: lognormal((12, 10, 4), 39), "rel", 1e-3, 1, 32768, 256, None),
+    # an order that swaps the outer dimensions keeps the contiguous pass last
+    # but not the planes outermost: the fixed-pitch kernel takes it
+    ("fine-swapped-order", lambda: lognormal((20, 37, 600), 31), "rel", 1e-3, 1, 32768, 4096, (1, 0, 2)),
 ]
 
 
