@@ -132,6 +132,7 @@ def adaptive_measurement(szg, torch, ctx, xt, in_bytes, rel, chunk, reps=3):
     return {"workload": "the same field and bound, adaptive linear/cubic per level",
             "ratio": round(in_bytes / s.numel(), 4),
             "level_mask": bin(info["level_mask"]),
+            "dim_order": list(info["dim_order"]),
             "compress_GBps": round(in_bytes * reps / (t1 - t0) / 1e9, 3),
             "decompress_GBps": round(in_bytes * reps / (t2 - t1) / 1e9, 3),
             "max_abs_err_over_eb": err / info["eb"] if info["eb"] > 0 else 0.0}
