@@ -140,7 +140,7 @@ __host__ __device__ inline Window fine_window(uint32_t win, uint32_t nwin, uint3
 }
 
 template <typename T, int PRED, bool RECON, int A>
-__global__ __launch_bounds__(kFineMaxWaves * 64) void k_fine(const T* __restrict__ x, T* v,
+__global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_fine(const T* __restrict__ x, T* v,
                                                             uint16_t* codes, LevelGeom g,
                                                             const Meta* __restrict__ m, T twoeb,
                                                             uint32_t R, const T* __restrict__ cmp) {
