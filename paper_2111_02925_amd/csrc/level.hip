@@ -396,7 +396,7 @@ struct RowIn {
 };
 
 template <typename T, int PRED, bool RECON>
-__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_level64(const T* __restrict__ x, T* v,
+__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_level64(const T* __restrict__ x, T* v,
                                                            uint16_t* codes, LevelGeom g,
                                                            const Meta* __restrict__ m, T twoeb,
                                                            uint32_t R, uint32_t flags, T* cmp) {
