@@ -2,8 +2,9 @@
 
 Bit-exact on everything: quantization codes, stream bytes (hence the
 compression ratio), and reconstructed values.  Cases span several chunks and
-levels with ragged extents, 1-D to 4-D, both predictors and dtypes, small
-radii (unpredictable path), dimension orders, chunk sizes, special values and
+levels with ragged extents, 1-D to 4-D, every predictor (linear, cubic,
+adaptive, Lorenzo) and both dtypes, the three error-bound modes, small radii
+(unpredictable path), dimension orders, chunk sizes, special values and
 degenerate shapes."""
 import os
 
