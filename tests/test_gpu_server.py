@@ -26,11 +26,14 @@ def fields():
         ("1d", np.cumsum(np.random.default_rng(33).standard_normal(20011)).astype(np.float32), "abs", 0.05, "cubic", 2048),
         ("tiny", synth.random_field((5, 7), seed=34), "rel", 1e-2, "cubic", 64),
         ("lognormal-2", synth.lognormal_grf((33, 70, 45), seed=35), "rel", 1e-4, "linear", 4096),
+        ("adaptive", synth.lognormal_grf((40, 36, 46), seed=36), "rel", 1e-3, "adaptive", 4096),
+        ("lorenzo-f64", synth.climate_2d((61, 90), seed=37, dtype=np.float64), "rel", 1e-3, "lorenzo", 1024),
+        ("pwrel", synth.lognormal_grf((30, 28, 26), seed=38), "pwrel", 1e-3, "cubic", 4096),
     ]
 
 
 def test_server_outputs_equal_calls_alone(szg):
-    print("[case] server: 5 fields x 3 repeats, 3 workers", flush=True)
+    print("[case] server: 8 fields x 3 repeats, 3 workers", flush=True)
     ctx = szg.Context(0)
     cases = []
     for label, x, mode, eb, pred, chunk in fields():
