@@ -595,7 +595,9 @@ __device__ __forceinline__ RunResult decode_run(
           const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
           uint32_t dd = ld(w2), f = ld(w2 + 1);
           asm volatile("" : "+v"(dd), "+v"(f));
-          buf = (((uint64_t)dd << 32) | f) & (~0ull << o2);
+          // the window restarts left-aligned at bit `used`: drop the o2 bits of
+          // word w2 already consumed
+          buf = (((uint64_t)dd << 32) | f) << o2;
           nb = 64 - o2;
           rd = w2 + 2;
         }

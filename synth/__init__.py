@@ -185,3 +185,35 @@ def random_field(shape, seed: int, alpha: float = -3.0, dtype=np.float32) -> np.
     """A plain seeded GRF of any shape (used for parity cases)."""
     rng = np.random.default_rng(seed)
     return grf(shape, alpha, rng).astype(dtype)
+
+
+def fibonacci_counts(m: int) -> list[int]:
+    """The first m Fibonacci numbers 1, 1, 2, 3, 5, ..."""
+    f = [1, 1]
+    while len(f) < m:
+        f.append(f[-1] + f[-2])
+    return f[:m]
+
+
+def fibonacci_steps_field(shape=(256, 256, 256), nsym: int = 34, seed: int = 41):
+    """An integer-valued float64 field whose mixed differences are steps with
+    Fibonacci frequencies.
+
+    The steps take the nsym integer values -nsym/2 .. nsym/2 - 1 (assigned to
+    the Fibonacci counts 1, 1, 2, 3, ... in a seeded order; the most frequent
+    value also takes the points left over), are placed at seeded random
+    positions, and are summed along every axis.  Returns (field, steps): the
+    steps array has the field's shape and int64 values."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    counts = fibonacci_counts(nsym)
+    if sum(counts) > n:
+        raise ValueError("field too small for the Fibonacci counts")
+    counts[-1] += n - sum(counts)
+    vals = np.arange(-(nsym // 2), nsym - nsym // 2, dtype=np.int64)
+    rng.shuffle(vals)
+    steps = np.repeat(vals, counts)[rng.permutation(n)].reshape(shape)
+    x = steps
+    for ax in range(len(shape)):
+        x = np.cumsum(x, axis=ax)
+    return x.astype(np.float64), steps

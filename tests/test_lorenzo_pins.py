@@ -95,3 +95,28 @@ def test_rejected_forms(orc):
     bad[40] = 4
     with pytest.raises(Exception):
         orc.decompress(bytes(bad))
+
+
+def test_fibonacci_steps_give_33_bit_codes(orc):
+    """Codes longer than 32 bits, fixed from outside.  On the integer field of
+    synth.fibonacci_steps_field at eb = 1/2 the codes are R plus the steps
+    (the mixed difference of a triple cumulative sum is the summand).  The
+    steps' counts are the Fibonacci numbers F1..F34, the last raised, so the
+    two-queue Huffman merge joins the running internal node with the next
+    leaf at every step (the sum of F1..Fk is F(k+2) - 1, below the leaf after
+    next): a caterpillar tree whose leaves, by increasing count, have depths
+    33, 33, 32, ..., 2, 1.  Round trip exact."""
+    x, steps = synth.fibonacci_steps_field((256, 256, 256), nsym=34, seed=41)
+    s, codes, rec = orc.compress(x, orc.ABS, 0.5, orc.LORENZO, want_debug=True)
+    assert np.array_equal(codes.astype(np.int64), 32768 + steps)
+    hist = np.bincount(codes.ravel(), minlength=65536)
+    lens = orc.huffman_lengths(hist)
+    used = np.flatnonzero(hist)
+    by_count = used[np.lexsort((used, hist[used]))]
+    m = len(used)
+    want = np.array([m - 1] + [m - k for k in range(1, m)])
+    assert np.array_equal(lens[by_count], want)
+    h = orc.parse_header(s)
+    table = np.frombuffer(s[128:128 + 4 * h["nsym"]], np.uint32)
+    assert int((table >> 16).max()) == 33
+    assert orc.decompress(s).tobytes() == x.tobytes()

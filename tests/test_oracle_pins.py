@@ -566,3 +566,23 @@ def test_bad_arguments(orc):
         args.update(kw)
         with pytest.raises(Exception):
             orc.compress(x, orc.ABS, 0.1, **args)
+
+
+@pytest.mark.parametrize("n,nsym,seed", [(1, 2, 0), (7, 8, 1), (4099, 65536, 2), (100000, 17, 3)])
+def test_histogram_is_a_direct_count(orc, n, nsym, seed):
+    """The histogram against an independent count (numpy's bincount), with
+    symbol 0 at the first position, the largest symbol nsym - 1 at the last
+    and a symbol that occurs only there, so that a skipped first or last
+    element or an off-by-one in the symbol index changes the counts."""
+    rng = np.random.default_rng(seed)
+    codes = rng.integers(1, max(nsym - 1, 2), size=n).astype(np.uint16)
+    codes[0] = 0
+    codes[-1] = nsym - 1
+    codes[1:-1][codes[1:-1] == nsym - 1] = 1
+    h = orc.histogram(codes, nsym)
+    want = np.bincount(codes, minlength=nsym)
+    assert h.dtype == np.uint64 and h.shape == (nsym,)
+    assert np.array_equal(h.astype(np.int64), want)
+    assert int(h.sum()) == n
+    with pytest.raises(Exception):
+        orc.histogram(np.array([nsym], dtype=np.uint16), nsym)
