@@ -790,12 +790,24 @@ double szo_exp2(double y) {
   return ldexp(p, (int)k);
 }
 
+/* The log field's absolute bound.  Relative margins: 4u for the exponential
+ * series and the final rounding to T (u the unit roundoff of T), and the
+ * factor (1 - 2^-20) for the series of the logarithm of the ratio.  Absolute
+ * margins: y = log2|x| is rounded to within half an ulp of |y| (plus far
+ * less for the series), and |y| < 2048 for every normal double (< 256 for
+ * every normal float), so the computed y is within 2^-42 (2^-45) of the true
+ * logarithm; the ratio (1 + eps)/(1 + 4u) takes two roundings in double,
+ * which move its logarithm by less than 2^-50.  Both are subtracted.  A
+ * bound too small to leave delta > 0 is rejected (for doubles, eps below
+ * about 1.6e-13). */
 double szo_pwrel_delta(double eps, int dtype) {
   if (!(eps > 0.0) || !(eps < 1.0)) return -1.0;
   const double u = dtype == SZO_F64 ? 0x1p-53 : 0x1p-24;
+  const double e_abs = (dtype == SZO_F64 ? 0x1p-42 : 0x1p-45) + 0x1p-50;
   const double r = (1.0 + eps) / (1.0 + 4.0 * u);
   if (!(r > 1.0)) return -1.0;
-  return szo_log2(r) * (1.0 - 0x1p-20);
+  const double d = szo_log2(r) * (1.0 - 0x1p-20) - e_abs;
+  return d > 0.0 ? d : -1.0;
 }
 
 /* the log-domain value of one field value (widened to double) */

@@ -7,15 +7,19 @@
 //
 // Forward: y = log2|x| as a double field, compressed by the interpolation
 // pipeline with the absolute bound delta = log2((1 + eps)/(1 + 4u)) (1 -
-// 2^-20), u the unit roundoff of the field type; the sign bits are kept, a
+// 2^-20) - E, u the unit roundoff of the field type and E the largest
+// rounding error of y over the type's normal values (2^-42 for doubles,
+// 2^-45 for floats) plus 2^-50 for the rounding of the ratio; the sign bits
+// are kept, a
 // bit per value, when any is set.  Zeros and values below the smallest
 // normal of T go to a level far below every normal value's logarithm and
 // come back as signed zeros; infinities map to +inf and NaN to NaN (both
 // unpredictable in the log field, hence stored verbatim).  Inverse: x' = +-
 // 2^y', clamped to the largest finite T.  With |y - y'| <= delta the bound
 // |x - x'| <= eps |x| holds for every normal x: the series below are within
-// about one unit in the last place, and the margins in delta cover them and
-// the final rounding to T.
+// about one unit in the last place, and the margins in delta cover them, the
+// absolute rounding of y at the largest exponents, and the final rounding to
+// T.
 //
 // The two maps are evaluated from their series in a fixed order (no
 // contraction), so that every implementation of the same definitions,
@@ -87,12 +91,20 @@ __host__ __device__ inline double pw_exp2(double y) {
   return ldexp(p, (int)k);
 }
 
+// The log field's absolute bound: relative margins for the exponential and
+// the rounding to T (4u) and for the series of the ratio's logarithm
+// (1 - 2^-20); absolute margins for the rounding of y = log2|x| itself, half
+// an ulp of |y| with |y| < 2048 for normal doubles (< 256 for floats): 2^-42
+// (2^-45), and for the ratio's two roundings in double (below 2^-50).
+// Bounds that leave no positive delta are rejected.
 double pwrel_delta(double eps, int dtype) {
   if (!(eps > 0.0) || !(eps < 1.0)) return -1.0;
   const double u = dtype == SZ_F64 ? 0x1p-53 : 0x1p-24;
+  const double e_abs = (dtype == SZ_F64 ? 0x1p-42 : 0x1p-45) + 0x1p-50;
   const double r = (1.0 + eps) / (1.0 + 4.0 * u);
   if (!(r > 1.0)) return -1.0;
-  return pw_log2(r) * (1.0 - 0x1p-20);
+  const double d = pw_log2(r) * (1.0 - 0x1p-20) - e_abs;
+  return d > 0.0 ? d : -1.0;
 }
 
 template <typename T>

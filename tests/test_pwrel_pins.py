@@ -46,19 +46,25 @@ def test_exp2_series_within_two_ulps(orc):
         assert orc.exp2(float(k)) == math.ldexp(1.0, k)
 
 
-@pytest.mark.parametrize("dtype,u", [(0, 2.0 ** -24), (1, 2.0 ** -53)])
-def test_delta_formula(orc, dtype, u):
-    for eps in (0.5, 1e-1, 1e-3, 1e-6):
+@pytest.mark.parametrize("dtype,u,e_log", [(0, 2.0 ** -24, 2.0 ** -45), (1, 2.0 ** -53, 2.0 ** -42)])
+def test_delta_formula(orc, dtype, u, e_log):
+    for eps in (0.5, 1e-1, 1e-3, 1e-6) + ((1e-9, 1e-12) if dtype == 1 else ()):
         d = orc.pwrel_delta(eps, dtype)
         # the definition's double roundings (1 + eps, its quotient), then the
-        # logarithm to 60 digits and the margin factor
+        # logarithm to 60 digits, the margin factor and the absolute margin
         r = (1.0 + eps) / (1.0 + 4.0 * u)
-        ref = Decimal(r).ln() / Decimal(2).ln() * (1 - Decimal(2) ** -20)
+        ref = (Decimal(r).ln() / Decimal(2).ln() * (1 - Decimal(2) ** -20)
+               - Decimal(e_log) - Decimal(2) ** -50)
         assert abs(Decimal(d) - ref) <= 2 * Decimal(math.ulp(float(ref)))
-        # and the margin is real: 2^d (1 + 4u) stays below 1 + eps
-        assert Decimal(2) ** Decimal(d) * (1 + 4 * Decimal(u)) < 1 + Decimal(eps)
-    # unusable bounds: too small for the type, or outside (0, 1)
+        # and the margins are real: with the log's largest rounding error E
+        # added back, 2^(d + E) (1 + 4u) stays below 1 + eps (the exact
+        # 1 + eps, not its double)
+        assert Decimal(2) ** (Decimal(d) + Decimal(e_log)) * (1 + 4 * Decimal(u)) < 1 + Decimal(eps)
+    # unusable bounds: too small for the type (the absolute margin alone
+    # needs eps above about 2^-42 ln 2 = 1.6e-13 for doubles), or outside (0, 1)
     assert orc.pwrel_delta(1e-9 if dtype == 0 else 1e-18, dtype) <= 0
+    if dtype == 1:
+        assert orc.pwrel_delta(1e-13, dtype) <= 0 and orc.pwrel_delta(1e-14, dtype) <= 0
     for bad in (0.0, -1e-3, 1.0, 2.0, float("nan")):
         assert orc.pwrel_delta(bad, dtype) <= 0
 
@@ -143,3 +149,35 @@ def test_corrupt_extension_rejected(orc):
             orc.decompress(bytes(bad))
     with pytest.raises(Exception):
         orc.decompress(bytes(s[:-8]))
+
+
+def _extreme(dtype, mag, seed):
+    """A positive field spanning a factor e^6 around `mag`, with both signs."""
+    x = synth.random_field((14, 12, 10), seed=seed, dtype=np.float64)
+    v = mag * np.exp(x) * np.where(x > 0, 1.0, -1.0)
+    return v.astype(dtype)
+
+
+@pytest.mark.parametrize("dtype,mag,eps", [
+    (np.float64, 1e300, 1e-12), (np.float64, 1e-300, 1e-12), (np.float64, 1e100, 2e-13),
+    (np.float64, 1e-300, 2e-13), (np.float64, 1e300, 1e-6), (np.float32, 1e36, 1e-6),
+    (np.float32, 1e-36, 1e-6), (np.float32, 1e36, 3e-7),
+])
+def test_pointwise_bound_at_extreme_exponents(orc, dtype, mag, eps):
+    """Near the ends of the exponent range |log2|x|| approaches 1024 (128),
+    where the rounding of the logarithm is largest: the bound still holds at
+    every point, in exact rationals, down to the smallest accepted eps."""
+    x = _extreme(dtype, mag, seed=int(abs(math.log10(mag))))
+    assert np.all(np.isfinite(x)) and np.all(np.abs(x) >= np.finfo(dtype).tiny)
+    back = orc.decompress(orc.compress(x, orc.PWREL, eps, orc.CUBIC))
+    _check_pointwise(x, back, eps)
+
+
+@pytest.mark.parametrize("eps", [1e-13, 1e-14])
+def test_too_small_bound_rejected_for_doubles(orc, eps):
+    """A double field of values near 1e300 at eps = 1e-14 would break the
+    bound (the rounding of log2|x| alone is about 4e-14 relative there), so
+    bounds below the absolute margin are refused."""
+    x = _extreme(np.float64, 1e300, seed=300)
+    with pytest.raises(Exception):
+        orc.compress(x, orc.PWREL, eps, orc.CUBIC)
