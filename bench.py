@@ -185,6 +185,77 @@ def lossless_measurement(szg, s, in_bytes, level=1):
             "restored": back == host}
 
 
+def copy_ceiling(torch, xt, reps=5):
+    """The practical streaming ceiling of the box: plain device-to-device
+    copies of the input, timed with HIP events on the current stream.  Two
+    copies: the HIP runtime's (hipMemcpyDtoDAsync) and torch's elementwise
+    kernel.  GB/s counts the bytes read plus the bytes written."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyDtoDAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p]
+    st = torch.cuda.current_stream()
+    nbytes = xt.numel() * xt.element_size()
+    dst = torch.empty_like(xt)
+    out = {}
+    for name in ("hipMemcpyDtoD", "torch_copy"):
+        ms = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            if name == "hipMemcpyDtoD":
+                rc = hip.hipMemcpyDtoDAsync(dst.data_ptr(), xt.data_ptr(), nbytes, st.cuda_stream)
+                if rc != 0:
+                    raise RuntimeError(f"hipMemcpyDtoDAsync failed ({rc})")
+            else:
+                dst.copy_(xt)
+            b.record(st)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        out[name] = round(2 * nbytes / (min(ms[1:]) * 1e-3) / 1e9, 1)
+    del dst
+    return out
+
+
+def bound_measurement(szg, torch, ctx, xt, rels, chunk, flush, reps=3):
+    """The same field at other range-relative bounds (cubic): event-timed
+    compress and decompress (the Infinity Cache flushed before each), the
+    ratio, and the streams and reconstructions kept for the oracle check."""
+    st = torch.cuda.current_stream()
+    in_bytes = xt.numel() * xt.element_size()
+    cap = szg.compress_bound(tuple(xt.shape), szg.F32, 32768, chunk)
+    out = torch.empty(cap, dtype=torch.uint8, device=xt.device)
+    rec = torch.empty_like(xt)
+    res = {}
+    for rel in rels:
+        s = ctx.compress(xt, "rel", rel, "cubic", chunk=chunk, out=out)
+        ctx.decompress(s, out=rec)
+        mc, md = [], []
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            flush()
+            e[0].record(st)
+            s = ctx.compress(xt, "rel", rel, "cubic", chunk=chunk, out=out)
+            e[1].record(st)
+            flush()
+            e[2].record(st)
+            ctx.decompress(s, out=rec)
+            e[3].record(st)
+            torch.cuda.synchronize()
+            mc.append(e[0].elapsed_time(e[1]))
+            md.append(e[2].elapsed_time(e[3]))
+        mc.sort()
+        md.sort()
+        res[f"{rel:g}"] = {
+            "compress_GBps": round(in_bytes / (mc[len(mc) // 2] * 1e-3) / 1e9, 3),
+            "decompress_GBps": round(in_bytes / (md[len(md) // 2] * 1e-3) / 1e9, 3),
+            "ratio": round(in_bytes / s.numel(), 4),
+            "_stream": bytes(s.cpu().numpy().tobytes()),
+            "_rec": rec.cpu().numpy().tobytes(),
+        }
+    return res
+
+
 def batch_measurement(szg, torch, np, synth, workers, reps=3):
     """Batched vs per-field compression of a mixed set of fields at rel eb
     1e-3: a loop of sz_compress calls on one stream, against the request
@@ -310,29 +381,46 @@ def main():
     per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in fam.items()}
     dom = max(per_step, key=lambda k: per_step[k][0])
 
-    # timed region: HIP events around the dominant family only
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # Infinity Cache flush: a 512 MiB write between the phases, so that no
+    # phase reads what the previous one left in the 256 MB cache (the stream
+    # the compression just wrote, in particular)
+    flush_buf = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+
+    def flush():
+        flush_buf.fill_(0)
+
+    # timed region: every step's compress and decompress between HIP events,
+    # the cache flushed before each (outside the events); HIP events around
+    # the dominant family as well
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
+          for _ in range(args.steps)]
     ctx.timing_reset()
     ctx.set_timing(True)
     ctx.set_timing_family(dom)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
+        flush()
         ev[i][0].record(st)
         s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk,
                          subchunks=args.subchunks, out=out)
         ev[i][1].record(st)
-        ctx.decompress(s, out=rec)
+        flush()
         ev[i][2].record(st)
+        ctx.decompress(s, out=rec)
+        ev[i][3].record(st)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ctx.set_timing(False)
     dom_ms_live, dom_regions = ctx.timing(dom)
     ctx.set_timing_family(None)
-    ms_c = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
-    ms_d = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
-    ms_step = t_total * 1e3 / args.steps
+    comp = [a.elapsed_time(b) for a, b, _, _ in ev]
+    decomp = [c.elapsed_time(d) for _, _, c, d in ev]
+    ms_c = float(np.median(comp))
+    ms_d = float(np.median(decomp))
+    # a step: one compress and one decompress, the flushes between them left out
+    ms_step = float(np.mean([a + b for a, b in zip(comp, decomp)]))
+    wall_ms_step = t_total * 1e3 / args.steps
     size = int(s.numel())
 
     # quality (measurement only, after the timed region)
@@ -370,6 +458,21 @@ def main():
                 "ms_per_step": round(dom_ms, 4),
                 "alg_bytes_per_step": alg[dom]}
 
+    # the whole step's algorithmic bytes: compression reads the field twice
+    # (range, then prediction), writes and reads the codes, writes the
+    # stream; decompression reads the stream, writes and reads the codes,
+    # writes the field
+    b_c = 2 * n * 4 + 4 * n + size
+    b_d = size + 4 * n + n * 4
+    step_alg = {"compress_bytes": b_c, "decompress_bytes": b_d,
+                "GBps": round((b_c + b_d) / (ms_step * 1e-3) / 1e9, 1),
+                "frac": round((b_c + b_d) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "compress_frac": round(b_c / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "decompress_frac": round(b_d / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    copy = copy_ceiling(torch, xt)
+    bounds = None if args.no_extras else bound_measurement(
+        szg, torch, ctx, xt, [1e-2, 1e-4], args.chunk, flush)
+
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
     lossless = pwrel = adaptive = lorenzo = None
@@ -393,6 +496,14 @@ def main():
         t3 = time.perf_counter()
         parity = (ref == bytes(s.cpu().numpy().tobytes())) and (
             back.tobytes() == rec.cpu().numpy().tobytes())
+        # the other bounds of the same field, byte for byte (streams and
+        # reconstructions kept from their GPU runs)
+        if bounds is not None:
+            for key, b in bounds.items():
+                bref = oracle.compress(x, oracle.REL, float(key), oracle.CUBIC, 32768, args.chunk,
+                                       sub=info["sub"])
+                b["parity_with_oracle"] = (bref == b["_stream"]) and (
+                    oracle.decompress(bref).tobytes() == b["_rec"])
         # the point-wise relative and adaptive modes on a 128^3 corner, byte for byte
         corner = np.ascontiguousarray(x[:128, :128, :128])
         if pwrel is not None:
@@ -450,6 +561,14 @@ def main():
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items()},
         "kernel_ms_note": "per family, from a separate run of the same steps with events around every family",
         "roofline": roofline,
+        "step_algorithmic": step_alg,
+        "copy_GBps": copy,
+        "timing_note": "ms_per_step and the compress/decompress rates are event-timed per phase "
+                       "with a 512 MiB Infinity Cache flush before each phase, outside the events; "
+                       "wall_ms_per_step includes the flushes",
+        "wall_ms_per_step": round(wall_ms_step, 4),
+        "bounds": None if bounds is None else {
+            k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in bounds.items()},
         "cpu_baseline": cpu,
         "batched": batched,
         "lossless": lossless,

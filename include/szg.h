@@ -254,6 +254,11 @@ typedef struct {
   sz_options options;
   void* d_out;            /* the stream (compress) or the field (decompress) */
   size_t out_capacity;
+  void* wait_event;       /* a hipEvent_t recorded where d_in was produced (and
+                             where d_out was last used), or NULL: the request's
+                             work waits for it on the device before it reads
+                             or writes either buffer. The event must stay
+                             valid until the request is done. */
 } sz_request;
 typedef struct sz_server sz_server;
 

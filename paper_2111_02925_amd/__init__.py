@@ -71,7 +71,7 @@ class Request(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_uint64 * 4),
                 ("eb_mode", ctypes.c_int), ("eb", ctypes.c_double), ("predictor", ctypes.c_int),
                 ("has_options", ctypes.c_int), ("options", Options), ("d_out", ctypes.c_void_p),
-                ("out_capacity", ctypes.c_size_t)]
+                ("out_capacity", ctypes.c_size_t), ("wait_event", ctypes.c_void_p)]
 
 
 REQ_COMPRESS, REQ_DECOMPRESS = 0, 1
@@ -465,11 +465,18 @@ class Server:
         return self._submit(r, (stream_t, out))
 
     def _submit(self, r, keep) -> int:
+        # the request's work waits, on the device, for what torch's current
+        # stream has queued so far: the input's producer and the output's
+        # earlier users
+        torch = _torch()
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        r.wait_event = ev.cuda_event
         t = ctypes.c_uint64(0)
         rc = self._lib.sz_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
         if rc:
             raise SzError(rc, "sz_server_submit")
-        self._keep[t.value] = keep
+        self._keep[t.value] = keep + (ev,)
         return t.value
 
     def poll(self, ticket: int):
@@ -491,7 +498,7 @@ class Server:
         return self._finish(ticket, st.value, sz.value)
 
     def _finish(self, ticket, status, size):
-        x, out = self._keep.pop(ticket)
+        x, out, _ev = self._keep.pop(ticket)
         if status:
             return status, None
         if out.dtype == _torch().uint8:

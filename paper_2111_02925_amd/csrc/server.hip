@@ -105,8 +105,13 @@ void worker_loop(sz_server* s, size_t me) {
     lk.unlock();
     const sz_request& r = job.req;
     size_t out_size = 0;
-    int rc;
-    if (r.kind == SZ_REQ_COMPRESS) {
+    int rc = SZ_OK;
+    // the caller's producer of the input (and last user of the output)
+    // finishes first, in device order
+    if (r.wait_event && hipStreamWaitEvent(w.stream, (hipEvent_t)r.wait_event, 0) != hipSuccess)
+      rc = SZ_ERR_DEVICE;
+    if (rc != SZ_OK) {
+    } else if (r.kind == SZ_REQ_COMPRESS) {
       rc = sz_compress(w.ctx, r.d_in, r.dtype, r.ndim, r.dims, r.eb_mode, r.eb, r.predictor,
                        r.has_options ? &r.options : nullptr, r.d_out, r.out_capacity, &out_size,
                        w.stream);
@@ -177,9 +182,18 @@ int sz_server_submit(sz_server* s, const sz_request* r, uint64_t* ticket) {
               : scratch_need(n, r->dtype == SZ_F64 ? 8 : 4, o.chunk, true);
   } else if (r->kind == SZ_REQ_DECOMPRESS) {
     if (!r->d_in || r->in_size < kHeaderBytes) return SZ_ERR_ARG;
+    // the header is read here, to size the request: after the caller's
+    // producer of the stream (wait_event), on a stream of the submitting
+    // thread's own
     uint8_t h[kHeaderBytes];
     (void)hipSetDevice(s->device);
-    if (hipMemcpy(h, r->d_in, kHeaderBytes, hipMemcpyDeviceToHost) != hipSuccess) return SZ_ERR_DEVICE;
+    hipStream_t hs = nullptr;
+    if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) return SZ_ERR_DEVICE;
+    hipError_t e = r->wait_event ? hipStreamWaitEvent(hs, (hipEvent_t)r->wait_event, 0) : hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(h, r->d_in, kHeaderBytes, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    (void)hipStreamDestroy(hs);
+    if (e != hipSuccess) return SZ_ERR_DEVICE;
     sz_info info;
     if (sz_inspect(h, kHeaderBytes, &info) != SZ_OK) return SZ_ERR_CORRUPT;
     need = scratch_need(info.n, info.coded_dtype == SZ_F64 ? 8 : 4, info.chunk, false);
@@ -217,8 +231,13 @@ int sz_server_wait(sz_server* s, uint64_t ticket, int* status, size_t* out_size)
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->results.find(ticket);
   if (it == s->results.end()) return SZ_ERR_ARG;
-  s->cv_done.wait(lk, [&] { return s->results[ticket].done; });
+  // (another thread may poll the same ticket meanwhile and forget it)
+  s->cv_done.wait(lk, [&] {
+    auto f = s->results.find(ticket);
+    return f == s->results.end() || f->second.done;
+  });
   it = s->results.find(ticket);
+  if (it == s->results.end()) return SZ_ERR_ARG;
   if (status) *status = it->second.status;
   if (out_size) *out_size = it->second.out_size;
   s->results.erase(it);

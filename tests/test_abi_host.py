@@ -121,7 +121,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "sz_options": (szg.Options, ["radius", "chunk", "dim_order", "subchunks"]),
         "sz_info": (szg.Info, ["dtype", "dims", "n", "eb", "chunk", "sub", "n_unpred", "stream_bytes"]),
         "sz_request": (szg.Request, ["kind", "d_in", "in_size", "dims", "eb", "options", "d_out",
-                                     "out_capacity"]),
+                                     "out_capacity", "wait_event"]),
         "sz_field": (szg.Field, ["d_in", "dims", "eb", "d_out", "out_size", "status"]),
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "szg.h"', "int main(void) {"]

@@ -101,3 +101,33 @@ def test_server_budget_respected_and_enforced(szg):
         assert ei.value.status == szg.ERR_ARG
     finally:
         srv.close()
+
+
+def test_server_waits_for_the_callers_stream(szg):
+    """A request submitted while torch's stream is still producing its input:
+    the server's work waits for that stream on the device, so the stream is
+    the one of the finished input."""
+    print("[case] server: input produced asynchronously just before submit", flush=True)
+    base = torch.from_numpy(synth.lognormal_grf((96, 96, 96), seed=39)).cuda()
+
+    def produce(out):
+        out.copy_(base)
+        for _ in range(300):  # a queue of kernels still running at submit time
+            out.mul_(1.0001)
+        return out
+
+    ctx = szg.Context(0)
+    ref_in = produce(torch.empty_like(base))
+    torch.cuda.synchronize()
+    ref = bytes(ctx.compress(ref_in, "rel", 1e-3, "cubic").cpu().numpy().tobytes())
+    ctx.close()
+    srv = szg.Server(0, budget_bytes=2 << 30, workers=2)
+    try:
+        for _ in range(3):
+            x = produce(torch.empty_like(base))
+            t = srv.submit_compress(x, "rel", 1e-3, "cubic")
+            st, out = srv.wait(t)
+            assert st == 0
+            assert bytes(out.cpu().numpy().tobytes()) == ref
+    finally:
+        srv.close()
