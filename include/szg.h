@@ -169,6 +169,31 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
                 const sz_options* opts, void* d_out, size_t out_capacity,
                 size_t* out_size, void* stream);
 
+/* sz_compress for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, stream bytes and status codes as sz_compress, except:
+ * - the size-dependent scratch (reconstruction n*sizeof(dtype), codes 2n,
+ *   four chunk tables of 24 bytes per chunk in all, and for three-dimensional
+ *   fields room for the stride-2 lattice, ceil(n0/2)*ceil(n1/2)*ceil(n2/2)
+ *   values; each piece rounded up to 256 bytes) lives in one static device
+ *   array of SZ_NOALLOC_SCRATCH_BYTES per GPU, held from library load until
+ *   the process ends.  A field that needs more returns SZ_ERR_NOMEM before
+ *   any work is enqueued (fields of up to about 10M f32 or 6M f64 values fit);
+ * - the context's fixed tables come from sz_ctx_create, so the call itself
+ *   makes no hipMalloc, hipFree or other allocating call;
+ * - SZ_EB_PWREL returns SZ_ERR_UNSUPPORTED, and timing (sz_set_timing) is
+ *   not recorded.
+ * Every call on a GPU shares that GPU's array, and the context's tables, and
+ * the array keeps the last call's contents: calls that overlap on one GPU
+ * (on any context or stream) race and must be serialised by the caller.
+ * sz_debug_codes after this call reads the codes from the array.
+ * Synchronises `stream`. */
+#define SZ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sz_compress_noalloc(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
+                        const uint64_t* dims, int eb_mode, double eb,
+                        int predictor, const sz_options* opts, void* d_out,
+                        size_t out_capacity, size_t* out_size, void* stream);
+
 /* Decompress a stream (device, stream_size bytes) into d_out (device,
  * out_capacity bytes, n values of the stream's dtype): parse and validate
  * the header, decode the Huffman chunks, scatter the unpredictable values,

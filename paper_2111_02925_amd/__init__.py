@@ -36,7 +36,11 @@ EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_last_error", "sz_default_optio
            "sz_timing_reset",
            "sz_debug_codes", "sz_server_create", "sz_server_submit", "sz_server_poll",
            "sz_server_wait", "sz_server_used_bytes", "sz_server_destroy",
-           "sz_lossless_bound", "sz_lossless_pack", "sz_lossless_unpack")
+           "sz_lossless_bound", "sz_lossless_pack", "sz_lossless_unpack",
+           "sz_compress_noalloc")
+
+# the static scratch of sz_compress_noalloc (SZ_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class SzLibraryMissing(ImportError):
@@ -114,6 +118,8 @@ def lib():
     L.sz_compress.argtypes = [P, P, I, I, U64P, I, D, I, ctypes.POINTER(Options), P, SZ,
                               ctypes.POINTER(SZ), P]
     L.sz_compress.restype = I
+    L.sz_compress_noalloc.argtypes = L.sz_compress.argtypes
+    L.sz_compress_noalloc.restype = I
     L.sz_decompress.argtypes = [P, P, SZ, P, SZ, P]
     L.sz_decompress.restype = I
     L.sz_inspect.argtypes = [P, SZ, ctypes.POINTER(Info)]
@@ -296,6 +302,21 @@ class Context:
                  out=None, stream=None):
         """Compress a contiguous float32/float64 CUDA tensor; returns a uint8
         CUDA tensor holding the stream (a view of `out` if given)."""
+        return self._compress("sz_compress", x, eb_mode, eb, predictor, radius, chunk,
+                              dim_order, subchunks, out, stream)
+
+    def compress_noalloc(self, x, out, eb_mode="rel", eb: float = 1e-3, predictor="cubic",
+                         radius: int = 32768, chunk: int = 4096, dim_order=None,
+                         subchunks: int = 0, stream=None):
+        """sz_compress_noalloc: as compress, into the caller's `out` (uint8
+        CUDA tensor); the library allocates no device memory for the call."""
+        if out is None:
+            raise ValueError("compress_noalloc needs the output buffer")
+        return self._compress("sz_compress_noalloc", x, eb_mode, eb, predictor, radius, chunk,
+                              dim_order, subchunks, out, stream)
+
+    def _compress(self, entry, x, eb_mode, eb, predictor, radius, chunk, dim_order, subchunks,
+                  out, stream):
         torch = _torch()
         if not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous CUDA tensor")
@@ -306,13 +327,15 @@ class Context:
                   else self._lib.sz_compress_bound)
             cap = int(fn(_dtype_code(x), x.dim(), dims, ctypes.byref(opts)))
             out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+        elif not out.is_cuda or out.dtype != torch.uint8 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 CUDA tensor")
         size = ctypes.c_size_t(0)
-        rc = self._lib.sz_compress(self._h, ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
-                                   dims, _mode(eb_mode), float(eb), _pred(predictor),
-                                   ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
-                                   out.numel(), ctypes.byref(size), self._stream(stream))
+        rc = getattr(self._lib, entry)(self._h, ctypes.c_void_p(x.data_ptr()), _dtype_code(x),
+                                       x.dim(), dims, _mode(eb_mode), float(eb), _pred(predictor),
+                                       ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
+                                       out.numel(), ctypes.byref(size), self._stream(stream))
         if rc:
-            err = self._err(rc, "sz_compress")
+            err = self._err(rc, entry)
             err.required = size.value
             raise err
         return out[: size.value]

@@ -22,12 +22,20 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.h"
 
 using namespace szg;
+
+// The size-dependent scratch of sz_compress_noalloc, for callers that cannot
+// allocate device memory.  Host code never uses this name as a device address:
+// each device's copy is reached through the address hipGetSymbolAddress gives
+// for it, taken once per device when the first context on it is created.
+constexpr size_t kNoAllocScratchBytes = SZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -69,6 +77,16 @@ struct sz_ctx {
   Meta* h_meta = nullptr;       // pinned
   uint8_t* h_header = nullptr;  // pinned
   uint64_t last_n = 0;
+  const uint16_t* last_codes = nullptr;  // the codes of the last compression
+  // plans of the levels and passes, reserved at creation so that planning a
+  // call allocates nothing
+  std::vector<LevelGeom> levels;
+  std::vector<PassGeom> passes;
+  // sz_compress_noalloc: this device's static scratch (its device address),
+  // or the reason it is unavailable; that entry point records no events
+  void* noalloc_scratch = nullptr;
+  std::string noalloc_err;
+  bool no_timing = false;
   // one launch per level (fields of up to three dimensions) instead of one
   // per (level, dimension) pass; SZG_FUSED_LEVELS=0 selects the pass kernels
   bool fused_levels = true;
@@ -122,7 +140,8 @@ hipEvent_t get_event(sz_ctx* c) {
 
 template <class F>
 hipError_t timed(sz_ctx* c, const char* name, hipStream_t st, F&& f) {
-  if (!c->timing || (!c->timing_family.empty() && c->timing_family != name)) return f();
+  if (!c->timing || c->no_timing || (!c->timing_family.empty() && c->timing_family != name))
+    return f();
   hipEvent_t a = get_event(c), b = get_event(c);
   (void)hipEventRecord(a, st);
   hipError_t e = f();
@@ -438,6 +457,96 @@ int ensure_sized(sz_ctx* ctx, const Shape& s, bool need_rec) {
   return SZ_OK;
 }
 
+// The size-dependent scratch of one compression.
+struct Work {
+  void* rec = nullptr;
+  uint16_t* codes = nullptr;
+  uint32_t* chunk_words = nullptr;
+  uint32_t* chunk_unpred = nullptr;
+  uint64_t* word_off = nullptr;
+  uint64_t* unpred_off = nullptr;
+  uint64_t* block_sums = nullptr;
+  void* coarse = nullptr;  // the stride-2 lattice, when taken from the static scratch
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// Lays the pieces of Work out from `base` (each 256-byte aligned) and returns
+// their bytes: reconstruction, codes (whole 8-code vectors), the four chunk
+// tables, the scan's block sums, and room for the stride-2 lattice of a
+// three-dimensional field (the product of ceil(n_d / 2), whatever the order).
+uint64_t carve_work(const Shape& s, uint8_t* base, Work* w) {
+  const uint64_t nch = s.nchunks();
+  uint64_t lattice = 0;
+  if (s.ndim == 3)
+    lattice = ((s.dims[0] + 1) / 2) * ((s.dims[1] + 1) / 2) * ((s.dims[2] + 1) / 2) * s.tsize();
+  const uint64_t bytes[8] = {s.n * s.tsize(), ((s.n + 7) & ~7ull) * 2, nch * 4, nch * 4, nch * 8,
+                             nch * 8, (2 * ((nch + 1023) / 1024) + 1) * 8, lattice};
+  void** slot[8] = {&w->rec, (void**)&w->codes, (void**)&w->chunk_words, (void**)&w->chunk_unpred,
+                    (void**)&w->word_off, (void**)&w->unpred_off, (void**)&w->block_sums,
+                    &w->coarse};
+  uint64_t off = 0;
+  for (int i = 0; i < 8; i++) {
+    *slot[i] = base ? base + off : nullptr;
+    off += align256(bytes[i] ? bytes[i] : 8);
+  }
+  return off;
+}
+
+// Work from the context's buffers (grown on demand), or for the
+// no-allocation entry point from this device's static scratch.
+int acquire_work(sz_ctx* ctx, const Shape& s, bool noalloc, Work* w) {
+  if (noalloc) {
+    if (!ctx->noalloc_scratch)
+      return fail(ctx, SZ_ERR_DEVICE, "static scratch unavailable: " + ctx->noalloc_err);
+    const uint64_t need = carve_work(s, nullptr, w);
+    if (need > kNoAllocScratchBytes)
+      return fail(ctx, SZ_ERR_NOMEM,
+                  "sz_compress_noalloc: the field needs " + std::to_string(need) +
+                      " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
+                      " its static buffer holds");
+    carve_work(s, static_cast<uint8_t*>(ctx->noalloc_scratch), w);
+    return SZ_OK;
+  }
+  int rc = ensure_sized(ctx, s, true);
+  if (rc) return rc;
+  w->rec = ctx->rec.p;
+  w->codes = static_cast<uint16_t*>(ctx->codes.p);
+  w->chunk_words = static_cast<uint32_t*>(ctx->chunk_words.p);
+  w->chunk_unpred = static_cast<uint32_t*>(ctx->chunk_unpred.p);
+  w->word_off = static_cast<uint64_t*>(ctx->word_off.p);
+  w->unpred_off = static_cast<uint64_t*>(ctx->unpred_off.p);
+  w->block_sums = static_cast<uint64_t*>(ctx->block_sums.p);
+  w->coarse = nullptr;
+  return SZ_OK;
+}
+
+// Each device's static scratch, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Called with `device` current.
+void bind_static_scratch(sz_ctx* ctx, int device) {
+  if (device >= kMaxDevices) {
+    ctx->noalloc_err = "device index above " + std::to_string(kMaxDevices - 1);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_tried[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_tried[device] = true;
+  }
+  ctx->noalloc_scratch = g_scratch_ptr[device];
+  if (!ctx->noalloc_scratch)
+    ctx->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(g_scratch_err[device]);
+}
+
 }  // namespace
 
 // ---- scratch accounting for the server (server.hip)
@@ -503,6 +612,9 @@ sz_ctx* sz_ctx_create(int device) {
     sz_ctx_destroy(ctx);
     return nullptr;
   }
+  ctx->levels.reserve(kMaxLevels);
+  ctx->passes.reserve(kMaxLevels * kMaxDims);
+  bind_static_scratch(ctx, device);
   return ctx;
 }
 
@@ -570,7 +682,8 @@ int sz_inspect(const void* h_stream, size_t len, sz_info* info) {
 
 static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
                          int eb_mode, double eb, int predictor, const sz_options* opts,
-                         void* d_out, size_t out_capacity, size_t* out_size, void* stream) {
+                         void* d_out, size_t out_capacity, size_t* out_size, void* stream,
+                         bool noalloc = false) {
   if (!ctx) return SZ_ERR_ARG;
   Shape s;
   int rc = make_shape(ctx, dtype, ndim, dims, opts, &s);
@@ -592,9 +705,10 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
       if (s.order[j] != j) return fail(ctx, SZ_ERR_ARG, "the Lorenzo predictor takes no dim_order");
   CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if ((rc = ensure_sized(ctx, s, true))) return rc;
+  Work w;
+  if ((rc = acquire_work(ctx, s, noalloc, &w))) return rc;
   uint8_t* out = static_cast<uint8_t*>(d_out);
-  uint16_t* codes = static_cast<uint16_t*>(ctx->codes.p);
+  uint16_t* codes = w.codes;
   const uint32_t nsym = 2 * s.radius;
   const uint64_t nch = s.nchunks();
   uint8_t hdr[kHeaderBytes];
@@ -617,16 +731,17 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     bool identity = true;
     for (int j = 0; j < s.ndim; j++) identity = identity && s.order[j] == j;
     if (identity && s.ndim > 1) {
-      std::vector<std::array<uint8_t, kMaxDims>> perms;
+      std::array<std::array<uint8_t, kMaxDims>, kMaxOrders> perms;
+      size_t nperm = 0;
       std::array<uint8_t, kMaxDims> pm{0, 1, 2, 3};
-      do perms.push_back(pm);
+      do perms[nperm++] = pm;
       while (std::next_permutation(pm.begin(), pm.begin() + s.ndim));
       const size_t per = 2 * kMaxLevels;
       CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0,
-                                2 * per * perms.size(), st), "fill");
+                                2 * per * nperm, st), "fill");
       CHECK_HIP(timed(ctx, "estimate", st, [&] {
                   hipError_t e = hipSuccess;
-                  for (size_t i = 0; i < perms.size() && e == hipSuccess; i++) {
+                  for (size_t i = 0; i < nperm && e == hipSuccess; i++) {
                     EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[i].data());
                     eg.sampled = 1;
                     e = launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, ctx->lvl_cost + per * i,
@@ -634,14 +749,14 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                   }
                   return e;
                 }), "estimate");
-      std::vector<uint64_t> cost(per * perms.size());
-      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * cost.size(),
+      std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
+      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * per * nperm,
                                hipMemcpyDeviceToHost, st), "memcpy");
       CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
       const int L = level_count(s.ndim, s.dims);
       uint64_t best = ~0ull;
       size_t bi = 0;
-      for (size_t i = 0; i < perms.size(); i++) {
+      for (size_t i = 0; i < nperm; i++) {
         uint64_t total = 0;
         for (int l = 1; l <= L; l++) {
           const uint64_t lin = cost[per * i + 2 * (l - 1)], cub = cost[per * i + 2 * (l - 1) + 1];
@@ -677,7 +792,7 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   auto pred_of = [&](uint32_t stride) { return lvl_pred[1 + __builtin_ctz(stride)]; };
   if (s.n && predictor == SZ_LORENZO) {
     CHECK_HIP(timed(ctx, "interp", st, [&] {
-                return launch_lorenzo_compress(d_in, dtype, ctx->rec.p, codes, s.ndim, s.dims,
+                return launch_lorenzo_compress(d_in, dtype, w.rec, codes, s.ndim, s.dims,
                                                ctx->meta, s.radius, st);
               }), "lorenzo");
   } else if (s.n) {
@@ -687,31 +802,34 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
                                            cubic_mask(lvl_pred), (int)s.tsize());
     const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
-    std::vector<LevelGeom> levels;
+    std::vector<LevelGeom>& levels = ctx->levels;
     const bool fused =
         ctx->fused_levels && plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels);
-    const uint64_t cb = fused ? compact_bytes(levels, dtype, d_in, ctx->rec.p, s_small, s.tsize()) : 0;
-    if (cb) CHECK_HIP(ensure(ctx->coarse, cb), "hipMalloc(coarse)");
-    void* cmp = cb ? ctx->coarse.p : nullptr;
+    const uint64_t cb = fused ? compact_bytes(levels, dtype, d_in, w.rec, s_small, s.tsize()) : 0;
+    // (the static scratch always holds room for the lattice of a 3-D field)
+    if (cb && !noalloc) {
+      CHECK_HIP(ensure(ctx->coarse, cb), "hipMalloc(coarse)");
+      w.coarse = ctx->coarse.p;
+    }
+    void* cmp = cb ? w.coarse : nullptr;
     CHECK_HIP(timed(ctx, "interp", st, [&] {
                 hipError_t e =
                     ctx->fused_levels
-                        ? launch_small_levels_compress(d_in, dtype, ctx->rec.p, codes, sg,
+                        ? launch_small_levels_compress(d_in, dtype, w.rec, codes, sg,
                                                        ctx->meta, s.radius, st)
-                        : launch_origin_compress(d_in, dtype, ctx->rec.p, codes, ctx->meta,
+                        : launch_origin_compress(d_in, dtype, w.rec, codes, ctx->meta,
                                                  s.radius, st);
                 if (fused) {
                   // the finest level's reconstruction is not read by anything later
                   for (const LevelGeom& g : levels)
                     if (e == hipSuccess && g.s < s_small)
-                      e = launch_level_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
+                      e = launch_level_compress(d_in, dtype, pred_of(g.s), w.rec, codes, g,
                                                 ctx->meta, s.radius, g.s > 1, cmp, st);
                 } else {
-                  std::vector<PassGeom> passes;
-                  build_passes(s, passes);
-                  for (const PassGeom& g : passes)
+                  build_passes(s, ctx->passes);
+                  for (const PassGeom& g : ctx->passes)
                     if (e == hipSuccess && g.s < s_small)
-                      e = launch_pass_compress(d_in, dtype, pred_of(g.s), ctx->rec.p, codes, g,
+                      e = launch_pass_compress(d_in, dtype, pred_of(g.s), w.rec, codes, g,
                                                ctx->meta, s.radius, st);
                 }
                 return e;
@@ -726,9 +844,8 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
               return launch_codebook(ctx->hist, nsym, ctx->cb, ctx->enc_code, ctx->enc_len,
                                      ctx->symtab, ctx->meta, st);
             }), "codebook");
-  EncodeScratch es{static_cast<uint32_t*>(ctx->chunk_words.p), static_cast<uint32_t*>(ctx->chunk_unpred.p),
-                   static_cast<uint64_t*>(ctx->word_off.p), static_cast<uint64_t*>(ctx->unpred_off.p),
-                   static_cast<uint64_t*>(ctx->block_sums.p), ctx->totals};
+  EncodeScratch es{w.chunk_words, w.chunk_unpred, w.word_off, w.unpred_off, w.block_sums,
+                   ctx->totals};
   CHECK_HIP(timed(ctx, "encode", st, [&] {
               return launch_encode(codes, d_in, dtype, s.n, s.chunk, s.sub, s.radius, ctx->enc_code,
                                    ctx->enc_len, es, out, out_capacity, ctx->meta, st);
@@ -739,6 +856,7 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
   ctx->last_n = s.n;
+  ctx->last_codes = codes;
   const Meta& m = *ctx->h_meta;
   if (m.status & kStatusEbNotFinite) return fail(ctx, SZ_ERR_ARG, "resolved error bound is not finite");
   if (m.status & kStatusCodeTooLong) return fail(ctx, SZ_ERR_UNSUPPORTED, "Huffman code longer than 64 bits");
@@ -805,6 +923,19 @@ int sz_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64
                           out_size, stream);
   return compress_core(ctx, d_in, dtype, ndim, dims, eb_mode, eb, predictor, opts, d_out,
                        out_capacity, out_size, stream);
+}
+
+int sz_compress_noalloc(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
+                        int eb_mode, double eb, int predictor, const sz_options* opts, void* d_out,
+                        size_t out_capacity, size_t* out_size, void* stream) {
+  if (!ctx) return SZ_ERR_ARG;
+  if (eb_mode == SZ_EB_PWREL)
+    return fail(ctx, SZ_ERR_UNSUPPORTED, "sz_compress_noalloc takes absolute and relative bounds only");
+  ctx->no_timing = true;
+  const int rc = compress_core(ctx, d_in, dtype, ndim, dims, eb_mode, eb, predictor, opts, d_out,
+                               out_capacity, out_size, stream, true);
+  ctx->no_timing = false;
+  return rc;
 }
 
 int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d_out,
@@ -880,7 +1011,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
     const SmallGeom sg = plan_small_levels(s.ndim, s.dims, s.order, level_count(s.ndim, s.dims),
                                            cubic_mask(lvl_pred), (int)s.tsize());
     const uint64_t s_small = ctx->fused_levels ? 1ull << (sg.l_stop - 1) : ~0ull;
-    std::vector<LevelGeom> levels;
+    std::vector<LevelGeom>& levels = ctx->levels;
     const bool fused = in.predictor != SZ_LORENZO && ctx->fused_levels &&
                        plan_levels(s.ndim, s.dims, s.order, (int)s.tsize(), nullptr, levels);
     const uint64_t cb = fused ? compact_bytes(levels, s.dtype, d_out, d_out, s_small, s.tsize()) : 0;
@@ -900,9 +1031,8 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                       e = launch_level_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                              s.radius, cmp, st);
                 } else {
-                  std::vector<PassGeom> passes;
-                  build_passes(s, passes);
-                  for (const PassGeom& g : passes)
+                  build_passes(s, ctx->passes);
+                  for (const PassGeom& g : ctx->passes)
                     if (e == hipSuccess && g.s < s_small)
                       e = launch_pass_recon(codes, s.dtype, pred_of(g.s), d_out, g, in.eb,
                                             s.radius, st);
@@ -970,7 +1100,8 @@ int sz_debug_codes(sz_ctx* ctx, void* d_codes, size_t capacity, void* stream) {
   if (capacity < ctx->last_n * 2) return fail(ctx, SZ_ERR_CAPACITY, "capacity too small");
   if (ctx->last_n == 0) return SZ_OK;
   hipStream_t st = (hipStream_t)stream;
-  CHECK_HIP(hipMemcpyAsync(d_codes, ctx->codes.p, ctx->last_n * 2, hipMemcpyDeviceToDevice, st), "memcpy");
+  CHECK_HIP(hipMemcpyAsync(d_codes, ctx->last_codes, ctx->last_n * 2, hipMemcpyDeviceToDevice, st),
+            "memcpy");
   CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
   return SZ_OK;
 }
