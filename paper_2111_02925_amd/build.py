@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["interp.hip", "level.hip", "fine.hip", "pwrel.hip", "lorenzo.hip", "huffman.hip", "encode.hip", "decode.hip", "api.hip",
-           "server.hip", "lossless.cpp"]
+           "batch.hip", "server.hip", "lossless.cpp"]
 HEADERS = ["common.h", "device_math.h", "block_ops.h"]
 
 FLAGS = [

@@ -87,6 +87,7 @@ struct sz_ctx {
   void* noalloc_scratch = nullptr;
   std::string noalloc_err;
   bool no_timing = false;
+  BatchPlan* batch = nullptr;  // sz_compress_batch's plan for the last batch shapes
   // one launch per level (fields of up to three dimensions) instead of one
   // per (level, dimension) pass; SZG_FUSED_LEVELS=0 selects the pass kernels
   bool fused_levels = true;
@@ -223,41 +224,6 @@ int make_shape(sz_ctx* c, int dtype, int ndim, const uint64_t* dims, const sz_op
     return fail(c, SZ_ERR_ARG, "subchunks must be 1, or 2, 4 or 8 splitting chunk into whole encoder runs");
   if (!valid_order(ndim, s->order)) return fail(c, SZ_ERR_ARG, "dim_order must be a permutation");
   return SZ_OK;
-}
-
-// The number of levels: L = max over dimensions of ceil(log2 n_d).
-int level_count(int ndim, const uint64_t* dims) {
-  int L = 0;
-  for (int d = 0; d < ndim; d++) {
-    int l = 0;
-    while (l < 63 && (1ull << l) < dims[d]) l++;
-    L = l > L ? l : L;
-  }
-  return L;
-}
-
-// The stride-2 level stores its lattice compactly for the strip kernel when
-// both run: the stride-1 level takes the strip kernel and the stride-2 level
-// the fixed-pitch kernel (not the coarsest-levels workgroup).  Returns the
-// lattice's bytes, 0 if not.
-uint64_t compact_bytes(const std::vector<LevelGeom>& levels, int dtype, const void* x,
-                       const void* v, uint64_t s_small, size_t tsize) {
-  const LevelGeom* g1 = nullptr;
-  const LevelGeom* g2 = nullptr;
-  for (const LevelGeom& g : levels) {
-    if (g.s == 1) g1 = &g;
-    if (g.s == 2) g2 = &g;
-  }
-  if (!g1 || !g2 || s_small <= 2 || !g2->pitch64 || !fine_usable(*g1, dtype, x, v)) return 0;
-  return (uint64_t)g2->ext[0] * g2->ext[1] * g2->ext[2] * tsize;
-}
-
-// bit l - 1 set: level l takes the cubic predictor
-uint32_t cubic_mask(const int* lvl_pred) {
-  uint32_t m = 0;
-  for (int l = 1; l <= kMaxLevels; l++)
-    if (lvl_pred[l] == SZ_INTERP_CUBIC) m |= 1u << (l - 1);
-  return m;
 }
 
 // The (level, dimension) passes of the multilevel traversal in execution
@@ -553,6 +519,41 @@ void bind_static_scratch(sz_ctx* ctx, int device) {
 
 namespace szg {
 
+// The number of levels: L = max over dimensions of ceil(log2 n_d).
+int level_count(int ndim, const uint64_t* dims) {
+  int L = 0;
+  for (int d = 0; d < ndim; d++) {
+    int l = 0;
+    while (l < 63 && (1ull << l) < dims[d]) l++;
+    L = l > L ? l : L;
+  }
+  return L;
+}
+
+// The stride-2 level stores its lattice compactly for the strip kernel when
+// both run: the stride-1 level takes the strip kernel and the stride-2 level
+// the fixed-pitch kernel (not the coarsest-levels workgroup).  Returns the
+// lattice's bytes, 0 if not.
+uint64_t compact_bytes(const std::vector<LevelGeom>& levels, int dtype, const void* x,
+                       const void* v, uint64_t s_small, size_t tsize) {
+  const LevelGeom* g1 = nullptr;
+  const LevelGeom* g2 = nullptr;
+  for (const LevelGeom& g : levels) {
+    if (g.s == 1) g1 = &g;
+    if (g.s == 2) g2 = &g;
+  }
+  if (!g1 || !g2 || s_small <= 2 || !g2->pitch64 || !fine_usable(*g1, dtype, x, v)) return 0;
+  return (uint64_t)g2->ext[0] * g2->ext[1] * g2->ext[2] * tsize;
+}
+
+// bit l - 1 set: level l takes the cubic predictor
+uint32_t cubic_mask(const int* lvl_pred) {
+  uint32_t m = 0;
+  for (int l = 1; l <= kMaxLevels; l++)
+    if (lvl_pred[l] == SZ_INTERP_CUBIC) m |= 1u << (l - 1);
+  return m;
+}
+
 size_t pwrel_scratch_need(uint64_t n, bool compress) {
   auto grown = [](uint64_t b) { return b + b / 8; };
   return (size_t)(grown(n * 8) + (compress ? grown(((n + 63) / 64) * 8) : 0));
@@ -622,6 +623,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  batch_plan_free(ctx->batch);
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
                  &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse})
     if (b->p) (void)hipFree(b->p);
@@ -680,6 +682,29 @@ int sz_inspect(const void* h_stream, size_t len, sz_info* info) {
   return parse_header(static_cast<const uint8_t*>(h_stream), info);
 }
 
+// The arguments of a compression with an absolute or range-relative bound:
+// shape and options (into *s), bound, predictor, buffers and alignment.
+static int check_compress(sz_ctx* ctx, const void* d_in, int dtype, int ndim,
+                          const uint64_t* dims, int eb_mode, double eb, int predictor,
+                          const sz_options* opts, const void* d_out, Shape* s) {
+  int rc = make_shape(ctx, dtype, ndim, dims, opts, s);
+  if (rc) return rc;
+  if (eb_mode != SZ_EB_ABS && eb_mode != SZ_EB_REL) return fail(ctx, SZ_ERR_ARG, "bad eb_mode");
+  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
+      predictor != SZ_INTERP_ADAPTIVE && predictor != SZ_LORENZO)
+    return fail(ctx, SZ_ERR_ARG, "bad predictor");
+  if (!(eb >= 0.0) || !__builtin_isfinite(eb)) return fail(ctx, SZ_ERR_ARG, "eb must be finite and >= 0");
+  if (eb_mode == SZ_EB_ABS && dtype == SZ_F32 && !__builtin_isfinite((float)eb))
+    return fail(ctx, SZ_ERR_ARG, "eb not representable in float");
+  if ((s->n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
+  if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
+    return fail(ctx, SZ_ERR_ARG, "d_in must be 16-byte and d_out 8-byte aligned");
+  if (predictor == SZ_LORENZO)
+    for (int j = 0; j < s->ndim; j++)
+      if (s->order[j] != j) return fail(ctx, SZ_ERR_ARG, "the Lorenzo predictor takes no dim_order");
+  return SZ_OK;
+}
+
 static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, const uint64_t* dims,
                          int eb_mode, double eb, int predictor, const sz_options* opts,
                          void* d_out, size_t out_capacity, size_t* out_size, void* stream,
@@ -690,19 +715,8 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   if (rc) return rc;
   if (!out_size) return fail(ctx, SZ_ERR_ARG, "out_size is NULL");
   *out_size = 0;
-  if (eb_mode != SZ_EB_ABS && eb_mode != SZ_EB_REL) return fail(ctx, SZ_ERR_ARG, "bad eb_mode");
-  if (predictor != SZ_INTERP_LINEAR && predictor != SZ_INTERP_CUBIC &&
-      predictor != SZ_INTERP_ADAPTIVE && predictor != SZ_LORENZO)
-    return fail(ctx, SZ_ERR_ARG, "bad predictor");
-  if (!(eb >= 0.0) || !__builtin_isfinite(eb)) return fail(ctx, SZ_ERR_ARG, "eb must be finite and >= 0");
-  if (eb_mode == SZ_EB_ABS && dtype == SZ_F32 && !__builtin_isfinite((float)eb))
-    return fail(ctx, SZ_ERR_ARG, "eb not representable in float");
-  if ((s.n && !d_in) || !d_out) return fail(ctx, SZ_ERR_ARG, "null buffer");
-  if (((uintptr_t)d_in % 16) || ((uintptr_t)d_out % 8))
-    return fail(ctx, SZ_ERR_ARG, "d_in must be 16-byte and d_out 8-byte aligned");
-  if (predictor == SZ_LORENZO)
-    for (int j = 0; j < s.ndim; j++)
-      if (s.order[j] != j) return fail(ctx, SZ_ERR_ARG, "the Lorenzo predictor takes no dim_order");
+  if ((rc = check_compress(ctx, d_in, dtype, ndim, dims, eb_mode, eb, predictor, opts, d_out, &s)))
+    return rc;
   CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   Work w;
@@ -1055,16 +1069,66 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
 int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields, const sz_options* opts,
                       void* stream) {
   if (!ctx || (nfields > 0 && !fields) || nfields < 0) return SZ_ERR_ARG;
-  int first = SZ_OK;
+  CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  // the fields the shared launches cover go to the batched path; the rest
+  // (other predictors and bounds, four dimensions, empty or invalid fields)
+  // take sz_compress one by one
+  std::vector<BatchItem> items;
+  std::vector<int> where, single;
+  const bool batched = !(getenv("SZG_BATCH") && strcmp(getenv("SZG_BATCH"), "0") == 0);
   for (int i = 0; i < nfields; i++) {
+    sz_field& f = fields[i];
+    f.out_size = 0;
+    Shape s;
+    if (!batched || f.eb_mode == SZ_EB_PWREL ||
+        check_compress(ctx, f.d_in, f.dtype, f.ndim, f.dims, f.eb_mode, f.eb, f.predictor, opts,
+                       f.d_out, &s) != SZ_OK) {
+      single.push_back(i);
+      continue;
+    }
+    BatchItem it{};
+    it.x = f.d_in;
+    it.out = f.d_out;
+    it.cap = f.out_capacity;
+    it.dtype = s.dtype;
+    it.ndim = s.ndim;
+    for (int d = 0; d < kMaxDims; d++) {
+      it.dims[d] = s.dims[d];
+      it.order[d] = s.order[d];
+    }
+    it.eb_mode = f.eb_mode;
+    it.eb = f.eb;
+    it.pred = f.predictor;
+    it.R = s.radius;
+    it.chunk = s.chunk;
+    it.sub = s.sub;
+    header_template(s, f.predictor, f.eb_mode, f.eb, it.hdr);
+    if (batch_item_supported(it)) {
+      items.push_back(it);
+      where.push_back(i);
+    } else {
+      single.push_back(i);
+    }
+  }
+  std::string err;
+  const int rc = batch_compress(ctx->device, &ctx->batch, items, st, err);
+  for (size_t k = 0; k < items.size(); k++) {
+    sz_field& f = fields[where[k]];
+    f.status = rc ? rc : items[k].status;
+    f.out_size = rc ? 0 : items[k].out_size;
+  }
+  if (rc) fail(ctx, rc, err);
+  for (int i : single) {
     sz_field& f = fields[i];
     size_t sz = 0;
     f.status = sz_compress(ctx, f.d_in, f.dtype, f.ndim, f.dims, f.eb_mode, f.eb, f.predictor, opts,
                            f.d_out, f.out_capacity, &sz, stream);
     f.out_size = sz;
-    if (f.status != SZ_OK && first == SZ_OK) first = f.status;
   }
-  return first;
+  for (int i = 0; i < nfields; i++)
+    if (fields[i].status != SZ_OK) return fields[i].status;
+  return SZ_OK;
 }
 
 int sz_set_timing(sz_ctx* ctx, int enable) {

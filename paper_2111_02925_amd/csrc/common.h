@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "szg.h"
@@ -238,6 +239,15 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
                               const LevelGeom& g, double eb_t, uint32_t radius, void* cmp,
                               hipStream_t st);
+// The number of levels, L = max over dimensions of ceil(log2 n_d); the
+// cubic-level mask of per-level predictors; the bytes of the compact stride-2
+// lattice when both the stride-2 level (fixed-pitch kernel) and the strip
+// kernel run, else 0 (api.hip).
+int level_count(int ndim, const uint64_t* dims);
+uint32_t cubic_mask(const int* lvl_pred);
+uint64_t compact_bytes(const std::vector<LevelGeom>& levels, int dtype, const void* x,
+                       const void* v, uint64_t s_small, size_t tsize);
+
 // The strip kernel of the stride-1 level (fine.hip): planned by plan_fine
 // (sets g.fine), launched when fine_usable (the field's pointers hold whole
 // column pairs).
@@ -304,6 +314,111 @@ hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
                                uint64_t nchunks, uint32_t sub, const uint8_t* header_template,
                                int dtype, Meta* m, hipStream_t st);
+
+// ---- batches (batch.hip): the fields of a batch share every launch.
+// A launch covers a list of jobs (a field, and for the level kernels one of
+// its levels); its workgroups map to jobs through a per-workgroup table of job
+// indices.  Every job starts on a multiple of 8 workgroups (the padding maps
+// to kNoJob and exits at once), so that a job's workgroups are dealt to the
+// eight XCDs exactly as a launch of the job alone would deal them.
+constexpr uint32_t kNoJob = 0xFFFFFFFFu;
+
+struct BField {
+  // written for every call
+  const void* x;
+  uint8_t* out;
+  uint64_t cap;
+  double eb_value;
+  // fixed by the plan
+  int32_t eb_mode, dtype;
+  uint64_t n, nchunks;
+  uint32_t R, chunk, sub, pad;
+  void* rec;
+  uint16_t* codes;
+  void* cmp;           // the stride-2 lattice, or null
+  Meta* m;
+  uint32_t* hist;      // 2R bins
+  uint64_t* enc_code;  // 2R
+  uint8_t* enc_len;    // 2R
+  uint32_t* symtab;    // 2R
+  CodebookScratch cb;
+  uint32_t* chunk_words;  // the field's slices of the batch's chunk tables
+  uint32_t* chunk_zeros;
+  uint64_t* word_off;     // exclusive scans over the whole batch
+  uint64_t* zero_off;
+  uint64_t* lword_off;    // the same, from the field's first chunk
+  uint64_t* lzero_off;
+  SmallGeom sg;
+  uint32_t hdr[kHeaderBytes / 4];  // header template (patched on the device)
+};
+
+struct BJob {
+  uint32_t field, first, nblk, flags;  // flags: kLevelStore* (level kernels)
+  LevelGeom g;                         // level kernels only
+};
+
+// A launch's tables, as the kernels see them.
+struct BLaunch {
+  const BField* __restrict__ f;
+  const BJob* __restrict__ jobs;
+  const uint32_t* __restrict__ wg;  // job of each workgroup
+};
+
+// The job of this workgroup and its index inside the job; false for padding.
+__device__ __forceinline__ bool batch_job(const BLaunch& L, BJob& j, uint32_t& local) {
+  const uint32_t k = __builtin_amdgcn_readfirstlane(L.wg[blockIdx.x]);
+  if (k == kNoJob) return false;
+  j = L.jobs[k];
+  local = blockIdx.x - j.first;
+  return true;
+}
+
+// One field as sz_compress_batch hands it to the batched path.
+struct BatchItem {
+  const void* x;
+  void* out;
+  size_t cap;
+  int dtype, ndim;
+  uint64_t dims[kMaxDims];
+  uint8_t order[kMaxDims];
+  int eb_mode;
+  double eb;
+  int pred;
+  uint32_t R, chunk, sub;
+  uint8_t hdr[kHeaderBytes];  // header template
+  int status;                 // written
+  size_t out_size;            // written
+};
+struct BatchPlan;
+void batch_plan_free(BatchPlan* p);
+// Whether the batched launches cover a field: 1 to 3 dimensions, linear or
+// cubic interpolation, an absolute or range-relative bound, and every level
+// on the fixed-pitch or strip kernel.
+bool batch_item_supported(const BatchItem& it);
+// Compresses the items (validated, one radius, chunk and sub-chunk count) with
+// shared launches; *plan is the cached plan (rebuilt when the shapes or
+// options change).  Returns SZ_OK with each item's status and size set, or an
+// error for all of them (err says why).
+int batch_compress(int device, BatchPlan** plan, std::vector<BatchItem>& items, hipStream_t st,
+                   std::string& err);
+
+hipError_t launch_b_meta_init(const BField* f, uint32_t nf, hipStream_t st);
+hipError_t launch_b_minmax(int dtype, BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_resolve_eb(const BField* f, uint32_t nf, hipStream_t st);
+hipError_t launch_b_small_levels(int dtype, BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_level(int dtype, int predictor, BLaunch L, uint32_t nwg, uint32_t lds,
+                          hipStream_t st);
+hipError_t launch_b_fine(int dtype, int predictor, uint32_t waves, BLaunch L, uint32_t nwg,
+                         hipStream_t st);
+hipError_t launch_b_histogram(BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_codebook(BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_encode_size(BLaunch L, uint32_t nwg, hipStream_t st);
+// field-local chunk offsets from the batch-wide scans, and each field's totals
+hipError_t launch_b_rebase(BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_encode_pack(int dtype, BLaunch L, uint32_t nwg, hipStream_t st);
+hipError_t launch_b_write_tables(BLaunch L, uint32_t nwg, hipStream_t st);
+// each field's (stream bytes, status bits) into res[2 i], res[2 i + 1]
+hipError_t launch_b_results(const BField* f, uint32_t nf, uint64_t* res, hipStream_t st);
 
 // Codes longer than the lookup table: with canonical codes the left-justified
 // end of each length's code range grows with the length, and comparing the

@@ -223,11 +223,11 @@ __device__ __forceinline__ void wave_step() { asm volatile("" ::: "memory"); }
 __device__ __forceinline__ void size_fast(const uint16_t* __restrict__ codes, uint64_t n,
                                           uint32_t chunk, uint64_t nchunks, const FastLds& f,
                                           uint32_t lo, uint32_t* chunk_words,
-                                          uint32_t* chunk_zeros) {
+                                          uint32_t* chunk_zeros, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
   const uint64_t last8 = (n - 1) & ~7ull;
-  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
        c += wstride) {
     const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
     const uint32_t clen = (uint32_t)(cend - cbeg);
@@ -259,13 +259,13 @@ __device__ __forceinline__ void pack_fast(
     uint32_t sub, uint64_t nchunks, FastLds& f, uint32_t lo,
     const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
     const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
-    const Layout& l, uint8_t* out, uint64_t cap) {
+    const Layout& l, uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   uint32_t* buf = f.buf[threadIdx.x >> 6];
   const uint32_t span = chunk / sub;
-  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
+  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
   const uint64_t last8 = (n - 1) & ~7ull;
-  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
        c += wstride) {
     const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
     const uint32_t clen = (uint32_t)(cend - cbeg);
@@ -370,10 +370,11 @@ __device__ __forceinline__ void size_chunks(const uint16_t* __restrict__ codes, 
                                             const EncWindow& w,
                                             const uint64_t* __restrict__ enc_code,
                                             const uint8_t* __restrict__ enc_len,
-                                            uint32_t* chunk_words, uint32_t* chunk_zeros) {
+                                            uint32_t* chunk_words, uint32_t* chunk_zeros,
+                                            uint32_t bid, uint32_t nblk) {
   const int lane = threadIdx.x & 63;
-  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
-  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
+  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
        c += wstride) {
     const LaneRun r = lane_run(c, chunk, n, lane);
     uint32_t bits = 0, zeros = 0;
@@ -401,25 +402,47 @@ __device__ __forceinline__ void size_chunks(const uint16_t* __restrict__ codes, 
   }
 }
 
-__global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
-    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks, uint32_t R,
-    uint32_t nsym, const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
-    uint32_t* chunk_words, uint32_t* chunk_zeros, const Meta* __restrict__ m) {
-  __shared__ EncLds u;
+__device__ __forceinline__ void encode_size_body(
+    EncLds& u, const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks,
+    uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, uint32_t* chunk_words, uint32_t* chunk_zeros,
+    const Meta* __restrict__ m, uint32_t bid, uint32_t nblk) {
   EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   if (fast_path(w)) {
     load_fast(u.f, w, enc_code, enc_len);
     __syncthreads();
-    size_fast(codes, n, chunk, nchunks, u.f, w.lo, chunk_words, chunk_zeros);
+    size_fast(codes, n, chunk, nchunks, u.f, w.lo, chunk_words, chunk_zeros, bid, nblk);
     return;
   }
   load_tables(t, w, nsym, enc_code, enc_len, !w.lds_only);
   __syncthreads();
   if (w.lds_only)
-    size_chunks<true>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros);
+    size_chunks<true>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros,
+                      bid, nblk);
   else
-    size_chunks<false>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros);
+    size_chunks<false>(codes, n, chunk, nchunks, t, w, enc_code, enc_len, chunk_words, chunk_zeros,
+                       bid, nblk);
+}
+
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks, uint32_t R,
+    uint32_t nsym, const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
+    uint32_t* chunk_words, uint32_t* chunk_zeros, const Meta* __restrict__ m) {
+  __shared__ EncLds u;
+  encode_size_body(u, codes, n, chunk, nchunks, R, nsym, enc_code, enc_len, chunk_words,
+                   chunk_zeros, m, blockIdx.x, gridDim.x);
+}
+
+// the chunk sizes of every field of a batch
+__global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_size(BLaunch L) {
+  __shared__ EncLds u;
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  encode_size_body(u, f.codes, f.n, f.chunk, f.nchunks, f.R, 2 * f.R, f.enc_code, f.enc_len,
+                   f.chunk_words, f.chunk_zeros, f.m, local, j.nblk);
 }
 
 // ------------------------------------------------------------------ packing
@@ -431,10 +454,10 @@ __device__ __forceinline__ void pack_chunks(
     const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
     const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
     const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
-    const Layout& l, uint8_t* out, uint64_t cap) {
+    const Layout& l, uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
   const int lane = threadIdx.x & 63;
-  const uint64_t wstride = (uint64_t)gridDim.x * kEncWaves;
-  for (uint64_t c = blockIdx.x * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
+  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
        c += wstride) {
     const LaneRun r = lane_run(c, chunk, n, lane);
     const bool cached = r.m <= kSeg;
@@ -539,14 +562,13 @@ __device__ __forceinline__ void pack_chunks(
 }
 
 template <typename T>
-__global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
-    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
-    uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
-    const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
-    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
-    const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
-    const Meta* __restrict__ m) {
-  __shared__ EncLds u;
+__device__ __forceinline__ void encode_pack_body(
+    EncLds& u, const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n,
+    uint32_t chunk, uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym,
+    const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
+    const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
+    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off, uint8_t* out,
+    uint64_t cap, const Meta* __restrict__ m, uint32_t bid, uint32_t nblk) {
   EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   const Layout l =
@@ -555,17 +577,43 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
     load_fast(u.f, w, enc_code, enc_len);
     __syncthreads();
     pack_fast<T>(codes, x, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros, word_off,
-                 zero_off, l, out, cap);
+                 zero_off, l, out, cap, bid, nblk);
     return;
   }
   load_tables(t, w, nsym, enc_code, enc_len, true);
   __syncthreads();
   if (w.lds_only)
     pack_chunks<T, true>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
-                         chunk_zeros, word_off, zero_off, l, out, cap);
+                         chunk_zeros, word_off, zero_off, l, out, cap, bid, nblk);
   else
     pack_chunks<T, false>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
-                          chunk_zeros, word_off, zero_off, l, out, cap);
+                          chunk_zeros, word_off, zero_off, l, out, cap, bid, nblk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
+    const Meta* __restrict__ m) {
+  __shared__ EncLds u;
+  encode_pack_body<T>(u, codes, x, n, chunk, sub, nchunks, R, nsym, enc_code, enc_len, chunk_words,
+                      chunk_zeros, word_off, zero_off, out, cap, m, blockIdx.x, gridDim.x);
+}
+
+// the packing of every field of a batch, with the field-local chunk offsets
+template <typename T>
+__global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_pack(BLaunch L) {
+  __shared__ EncLds u;
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  encode_pack_body<T>(u, f.codes, static_cast<const T*>(f.x), f.n, f.chunk, f.sub, f.nchunks, f.R,
+                      2 * f.R, f.enc_code, f.enc_len, f.chunk_words, f.chunk_zeros, f.lword_off,
+                      f.lzero_off, f.out, f.cap, f.m, local, j.nblk);
 }
 
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
@@ -601,14 +649,15 @@ struct HeaderBytes {
   uint32_t w[kHeaderBytes / 4];
 };
 
-__global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap,
-                                                      const uint32_t* __restrict__ symtab,
-                                                      uint64_t nchunks, uint32_t sub,
-                                                      HeaderBytes hdr, uint32_t tsize, Meta* m) {
+__device__ __forceinline__ void write_tables_body(uint8_t* out, uint64_t cap,
+                                                  const uint32_t* __restrict__ symtab,
+                                                  uint64_t nchunks, uint32_t sub,
+                                                  const uint32_t* hdr, uint32_t tsize, Meta* m,
+                                                  uint32_t bid, uint32_t nblk) {
   const uint64_t K = m->nsym_used;
   const Layout l = stream_layout(K, nchunks, sub, m->n_unpred, tsize, m->total_words);
-  const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = bid * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t gs = (uint64_t)nblk * blockDim.x;
   if (gid < kHeaderBytes / 4) {
     // header word gid; the device-side fields are 8-byte values at 56, 72,
     // 80 (K, then the sub-chunk count from the template), 88 and 96
@@ -622,7 +671,7 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
     } else if (at == 72) {
       v64 = m->n_unpred;
     } else if (at == 80) {
-      v64 = K | ((uint64_t)hdr.w[84 / 4] << 32);
+      v64 = K | ((uint64_t)hdr[84 / 4] << 32);
     } else if (at == 88) {
       v64 = m->total_words;
     } else if (at == 96) {
@@ -630,7 +679,7 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
     } else {
       patched = false;
     }
-    const uint32_t word = patched ? (uint32_t)(v64 >> ((byte & 4) ? 32 : 0)) : hdr.w[gid];
+    const uint32_t word = patched ? (uint32_t)(v64 >> ((byte & 4) ? 32 : 0)) : hdr[gid];
     guarded_store_u32(out, cap, byte, word);
   }
   if (gid == 0) {
@@ -641,6 +690,82 @@ __global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap
     m->stream_bytes = l.size;
   }
   for (uint64_t i = gid; i < K; i += gs) guarded_store_u32(out, cap, l.off_sym + 4 * i, symtab[i]);
+}
+
+__global__ __launch_bounds__(256) void k_write_tables(uint8_t* out, uint64_t cap,
+                                                      const uint32_t* __restrict__ symtab,
+                                                      uint64_t nchunks, uint32_t sub,
+                                                      HeaderBytes hdr, uint32_t tsize, Meta* m) {
+  write_tables_body(out, cap, symtab, nchunks, sub, hdr.w, tsize, m, blockIdx.x, gridDim.x);
+}
+
+// the header and symbol table of every field of a batch
+__global__ __launch_bounds__(256) void k_b_write_tables(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  write_tables_body(f.out, f.cap, f.symtab, f.nchunks, f.sub, f.hdr, f.dtype == SZ_F32 ? 4u : 8u,
+                    f.m, local, j.nblk);
+}
+
+hipError_t launch_b_write_tables(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_write_tables, dim3(nwg), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_encode_size(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_encode_size, dim3(nwg), dim3(kEncWaves * 64), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_encode_pack(int dtype, BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL(k_b_encode_pack<float>, dim3(nwg), dim3(kEncWaves * 64), 0, st, L);
+  else
+    hipLaunchKernelGGL(k_b_encode_pack<double>, dim3(nwg), dim3(kEncWaves * 64), 0, st, L);
+  return hipGetLastError();
+}
+
+// Field-local chunk offsets: the batch-wide exclusive scans minus the value
+// at the field's first chunk; the field's totals (bitstream words) from its
+// last chunk.  One job per field.
+__global__ __launch_bounds__(256) void k_b_rebase(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  const uint64_t wb = f.word_off[0], zb = f.zero_off[0];
+  for (uint64_t c = local * (uint64_t)blockDim.x + threadIdx.x; c < f.nchunks;
+       c += (uint64_t)j.nblk * blockDim.x) {
+    f.lword_off[c] = f.word_off[c] - wb;
+    f.lzero_off[c] = f.zero_off[c] - zb;
+  }
+  if (local == 0 && threadIdx.x == 0 && f.nchunks)
+    f.m->total_words = f.word_off[f.nchunks - 1] + f.chunk_words[f.nchunks - 1] - wb;
+}
+
+hipError_t launch_b_rebase(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_rebase, dim3(nwg), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+// (stream bytes, status) of every field, gathered for one copy to the host
+__global__ void k_b_results(const BField* __restrict__ f, uint32_t nf, uint64_t* res) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  res[2 * i] = f[i].m->stream_bytes;
+  res[2 * i + 1] = f[i].m->status;
+}
+
+hipError_t launch_b_results(const BField* f, uint32_t nf, uint64_t* res, hipStream_t st) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_results, dim3((nf + 255) / 256), dim3(256), 0, st, f, nf, res);
+  return hipGetLastError();
 }
 
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,

@@ -140,10 +140,9 @@ __host__ __device__ inline Window fine_window(uint32_t win, uint32_t nwin, uint3
 }
 
 template <typename T, int PRED, bool RECON, int A>
-__global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_fine(const T* __restrict__ x, T* v,
-                                                            uint16_t* codes, LevelGeom g,
-                                                            const Meta* __restrict__ m, T twoeb,
-                                                            uint32_t R, const T* __restrict__ cmp) {
+__device__ __forceinline__ void fine_body(const T* __restrict__ x, T* v, uint16_t* codes,
+                                          const LevelGeom& g, const Meta* __restrict__ m, T twoeb,
+                                          uint32_t R, const T* __restrict__ cmp, uint32_t bid) {
   static_assert(A % 2 == 0, "plane groups start on even planes");
   constexpr int NC = A / 2 + 3;  // coarse planes A0 - 2, A0, ..., A0 + A + 2
   using P = typename PairOf<T>::type;
@@ -169,7 +168,7 @@ __global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per
   // round-robin; each die takes a contiguous range of items).  Plane groups
   // vary fastest: neighbouring groups read three coarse planes in common, at
   // the same rows at about the same time, so the second read hits the die's L2
-  uint32_t t = blockIdx.x;
+  uint32_t t = bid;
   {
     const uint32_t full = g.f_items & ~7u;
     if (t < full) t = (t & 7) * (full >> 3) + (t >> 3);
@@ -434,6 +433,26 @@ __global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per
   }
 }
 
+template <typename T, int PRED, bool RECON, int A>
+__global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_fine(
+    const T* __restrict__ x, T* v, uint16_t* codes, LevelGeom g, const Meta* __restrict__ m,
+    T twoeb, uint32_t R, const T* __restrict__ cmp) {
+  fine_body<T, PRED, RECON, A>(x, v, codes, g, m, twoeb, R, cmp, blockIdx.x);
+}
+
+// The stride-1 level of several fields (a batch) with the same number of
+// waves per workgroup: each job is a field's stride-1 level.
+template <typename T, int PRED, int A>
+__global__ __launch_bounds__(kFineMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_b_fine(
+    BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  fine_body<T, PRED, false, A>(static_cast<const T*>(f.x), static_cast<T*>(f.rec), f.codes, j.g,
+                               f.m, T(0), f.R, static_cast<const T*>(f.cmp), local);
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -504,6 +523,24 @@ hipError_t launch_fine_compress(const void* x, int dtype, int predictor, void* r
   if (dtype == SZ_F32)
     return launch_fine_t<float, false, 8>(x, predictor, rec, codes, g, m, 0.0, radius, cmp, st);
   return launch_fine_t<double, false, 4>(x, predictor, rec, codes, g, m, 0.0, radius, cmp, st);
+}
+
+hipError_t launch_b_fine(int dtype, int predictor, uint32_t waves, BLaunch L, uint32_t nwg,
+                         hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  dim3 grid(nwg), block(64 * waves);
+  if (dtype == SZ_F32) {
+    if (predictor == SZ_INTERP_CUBIC)
+      hipLaunchKernelGGL((k_b_fine<float, SZ_INTERP_CUBIC, 8>), grid, block, 0, st, L);
+    else
+      hipLaunchKernelGGL((k_b_fine<float, SZ_INTERP_LINEAR, 8>), grid, block, 0, st, L);
+  } else {
+    if (predictor == SZ_INTERP_CUBIC)
+      hipLaunchKernelGGL((k_b_fine<double, SZ_INTERP_CUBIC, 4>), grid, block, 0, st, L);
+    else
+      hipLaunchKernelGGL((k_b_fine<double, SZ_INTERP_LINEAR, 4>), grid, block, 0, st, L);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fine_recon(const uint16_t* codes, int dtype, int predictor, void* out,

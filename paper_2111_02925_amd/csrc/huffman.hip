@@ -53,10 +53,13 @@ __device__ __forceinline__ uint32_t hist_slot(uint32_t c, uint32_t slo) {
   return c == 0 ? kHistShared + 2 : (uint32_t)v;
 }
 
-__global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __restrict__ codes,
-                                                            uint64_t n, uint32_t R,
-                                                            uint32_t* __restrict__ part,
-                                                            uint32_t* hist, Meta* m) {
+// part != nullptr: the workgroup's counts go to its row of partial
+// histograms (bid = its row); otherwise they are added to hist with global
+// atomics (the batched launch, whose workgroups span many fields).
+__device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ codes, uint64_t n,
+                                               uint32_t R, uint32_t* __restrict__ part,
+                                               uint32_t* hist, Meta* m, uint32_t bid,
+                                               uint32_t nblk) {
   __shared__ uint32_t lane_cnt[kHistLane * kHistThreads];
   __shared__ uint32_t shared_cnt[kHistSlots];
   const uint32_t t = threadIdx.x;
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
   const uint64_t nvec = n / 8;
   const uint4* v4 = reinterpret_cast<const uint4*>(codes);
   const uint64_t ntiles = (nvec + kHistTile - 1) / kHistTile;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (uint64_t tile = bid; tile < ntiles; tile += nblk) {
     const uint64_t base = tile * kHistTile + t;
     uint4 v[kHistVecs];
 #pragma unroll
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
       }
     }
   }
-  if (blockIdx.x == 0 && t < (n & 7)) count(codes[nvec * 8 + t]);
+  if (bid == 0 && t < (n & 7)) count(codes[nvec * 8 + t]);
   __syncthreads();
   // per-lane bins into the workgroup's window (rotated reads: distinct banks)
   {
@@ -104,8 +107,21 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
     if (sum) atomicAdd(&shared_cnt[hist_slot(hw.plo + b, hw.slo)], sum);
   }
   __syncthreads();
-  uint32_t* row = part + (uint64_t)blockIdx.x * kHistSlots;
-  for (uint32_t i = t; i < kHistSlots; i += kHistThreads) row[i] = shared_cnt[i];
+  if (part) {
+    uint32_t* row = part + (uint64_t)bid * kHistSlots;
+    for (uint32_t i = t; i < kHistSlots; i += kHistThreads) row[i] = shared_cnt[i];
+  } else {
+    // the window's slots (and code 0) straight into the histogram
+    for (uint32_t i = t; i < kHistSlots; i += kHistThreads) {
+      const uint32_t c = shared_cnt[i];
+      uint32_t sym = 0xFFFFFFFFu;
+      if (i == kHistShared + 2)
+        sym = 0;
+      else if (i >= 1 && i <= kHistShared && hw.slo + i - 1 < 2 * R)
+        sym = hw.slo + i - 1;
+      if (c && sym != 0xFFFFFFFFu) atomicAdd(&hist[sym], c);
+    }
+  }
   // far codes (rare): re-read this workgroup's codes, global atomics
   if (shared_cnt[0] | shared_cnt[kHistShared + 1]) {
     if (t == 0) atomicOr(&m->hist_far, 1u);
@@ -113,7 +129,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
       const uint32_t sl = hist_slot(c, hw.slo);
       if (sl == 0 || sl == kHistShared + 1) atomicAdd(&hist[c], 1u);
     };
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    for (uint64_t tile = bid; tile < ntiles; tile += nblk)
       for (uint32_t j = 0; j < kHistVecs; j++) {
         const uint64_t i = tile * kHistTile + t + (uint64_t)j * kHistThreads;
         if (i < nvec) {
@@ -125,8 +141,31 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
           }
         }
       }
-    if (blockIdx.x == 0 && t < (n & 7)) far(codes[nvec * 8 + t]);
+    if (bid == 0 && t < (n & 7)) far(codes[nvec * 8 + t]);
   }
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __restrict__ codes,
+                                                            uint64_t n, uint32_t R,
+                                                            uint32_t* __restrict__ part,
+                                                            uint32_t* hist, Meta* m) {
+  histogram_body(codes, n, R, part, hist, m, blockIdx.x, gridDim.x);
+}
+
+// every field of a batch: each job is a field's codes, its counts added to
+// the field's (zeroed) histogram
+__global__ __launch_bounds__(kHistThreads) void k_b_histogram(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  histogram_body(f.codes, f.n, f.R, nullptr, f.hist, f.m, local, j.nblk);
+}
+
+hipError_t launch_b_histogram(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_histogram, dim3(nwg), dim3(kHistThreads), 0, st, L);
+  return hipGetLastError();
 }
 
 // Sums the partial rows: a workgroup takes 64 slots of 32 rows (a wave per
@@ -645,10 +684,9 @@ __device__ __forceinline__ void codebook_wave(uint32_t K, uint64_t* enc_code, ui
 
 // The used symbols are found by scanning the histogram: only the window the
 // histogram kernel counts in (and symbol 0) when no code fell outside it.
-__global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restrict__ hist,
-                                                          uint32_t nsym, CodebookScratch s,
-                                                          uint64_t* enc_code, uint8_t* enc_len,
-                                                          uint32_t* symtab, Meta* m) {
+__device__ __forceinline__ void codebook_body(const uint32_t* __restrict__ hist, uint32_t nsym,
+                                              const CodebookScratch& s, uint64_t* enc_code,
+                                              uint8_t* enc_len, uint32_t* symtab, Meta* m) {
   __shared__ union {
     uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
     CbLds lds;
@@ -726,6 +764,28 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restr
   lds_barrier();
   if (K > 1) rank_leaves(K, L);
   if (t < 64) codebook_wave(K, enc_code, enc_len, symtab, m, L);
+}
+
+__global__ __launch_bounds__(kCbThreads) void k_codebook(const uint32_t* __restrict__ hist,
+                                                          uint32_t nsym, CodebookScratch s,
+                                                          uint64_t* enc_code, uint8_t* enc_len,
+                                                          uint32_t* symtab, Meta* m) {
+  codebook_body(hist, nsym, s, enc_code, enc_len, symtab, m);
+}
+
+// one workgroup per field of a batch
+__global__ __launch_bounds__(kCbThreads) void k_b_codebook(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  codebook_body(f.hist, 2 * f.R, f.cb, f.enc_code, f.enc_len, f.symtab, f.m);
+}
+
+hipError_t launch_b_codebook(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_codebook, dim3(nwg), dim3(kCbThreads), 0, st, L);
+  return hipGetLastError();
 }
 
 hipError_t launch_codebook(const uint32_t* hist, uint32_t nsym, CodebookScratch s,

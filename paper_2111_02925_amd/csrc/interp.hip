@@ -34,7 +34,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) 
   return hipGetLastError();
 }
 
-__global__ void k_meta_init(Meta* m) {
+__device__ __forceinline__ void meta_init(Meta* m) {
   m->key_min = ~0ull;
   m->key_max = 0;
   m->eb = 0;
@@ -50,6 +50,8 @@ __global__ void k_meta_init(Meta* m) {
   m->status = 0;
   m->hist_far = 0;
 }
+
+__global__ void k_meta_init(Meta* m) { meta_init(m); }
 
 hipError_t launch_meta_init(Meta* m, hipStream_t st) {
   hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(1), 0, st, m);
@@ -106,15 +108,17 @@ __device__ __forceinline__ void fold_minmax(T v, uint64_t& lo, uint64_t& hi) {
 }
 
 // Grid-stride reduction with 16-byte loads; one 64-bit atomic pair per block.
+// (bid, nblk): this workgroup among the nblk that share the field.
 template <typename T>
-__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_t n, Meta* m) {
+__device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n, Meta* m,
+                                            uint32_t bid, uint32_t nblk) {
   constexpr int V = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(V)));
   uint64_t lo = ~0ull, hi = 0;
   const uint64_t nv = n / V;
   const vec_t* xv = reinterpret_cast<const vec_t*>(x);
-  const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t gs = (uint64_t)nblk * blockDim.x;
+  uint64_t i = bid * (uint64_t)blockDim.x + threadIdx.x;
   for (; i + 3 * gs < nv; i += 4 * gs) {
     vec_t a = __builtin_nontemporal_load(xv + i);
     vec_t b = __builtin_nontemporal_load(xv + i + gs);
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_
 #pragma unroll
     for (int k = 0; k < V; k++) fold_minmax<T>(a[k], lo, hi);
   }
-  for (uint64_t t = nv * V + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += gs)
+  for (uint64_t t = nv * V + bid * (uint64_t)blockDim.x + threadIdx.x; t < n; t += gs)
     fold_minmax<T>(x[t], lo, hi);
   lo = wave_min_u64(lo);
   hi = wave_max_u64(hi);
@@ -156,6 +160,11 @@ __global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_t n, Meta* m) {
+  minmax_body<T>(x, n, m, blockIdx.x, gridDim.x);
+}
+
 hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, hipStream_t st) {
   if (n == 0) return hipSuccess;
   uint64_t blocks = (n + 256 * 64 - 1) / (256 * 64);
@@ -173,7 +182,7 @@ hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, hipStrea
 // eb in the field type; twoeb and 1/twoeb are derived from it in T.  REL:
 // value * (max - min) in double, then rounded to T.
 template <typename T>
-__global__ void k_resolve_eb(int mode, double value, Meta* m) {
+__device__ __forceinline__ void resolve_eb(int mode, double value, Meta* m) {
   T eb;
   if (mode == SZ_EB_ABS) {
     eb = (T)value;
@@ -190,6 +199,11 @@ __global__ void k_resolve_eb(int mode, double value, Meta* m) {
   m->eb = (double)eb;
   m->twoeb = (double)twoeb;
   m->inv2eb = (double)inv;
+}
+
+template <typename T>
+__global__ void k_resolve_eb(int mode, double value, Meta* m) {
+  resolve_eb<T>(mode, value, m);
 }
 
 hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st) {
@@ -286,9 +300,9 @@ hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t*
 constexpr uint32_t kSmallThreads = 1024;
 
 template <typename T, bool RECON>
-__global__ __launch_bounds__(kSmallThreads) void k_small_levels(
-    const T* __restrict__ x, T* v, uint16_t* codes, SmallGeom sg, const Meta* __restrict__ m,
-    T twoeb_dec, uint32_t R) {
+__device__ __forceinline__ void small_levels_body(const T* __restrict__ x, T* v, uint16_t* codes,
+                                                  const SmallGeom& sg, const Meta* __restrict__ m,
+                                                  T twoeb_dec, uint32_t R) {
   constexpr uint32_t kCap = kSmallBytes / (sizeof(T) + 2);
   __shared__ T lv[kCap];
   __shared__ uint16_t lc[kCap];
@@ -414,6 +428,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_levels(
     v[f] = lv[k];
     if (!RECON) codes[f] = lc[k];
   }
+}
+
+template <typename T, bool RECON>
+__global__ __launch_bounds__(kSmallThreads) void k_small_levels(
+    const T* __restrict__ x, T* v, uint16_t* codes, SmallGeom sg, const Meta* __restrict__ m,
+    T twoeb_dec, uint32_t R) {
+  small_levels_body<T, RECON>(x, v, codes, sg, m, twoeb_dec, R);
 }
 
 // The levels the workgroup takes: from L down to the one with the smallest
@@ -805,6 +826,74 @@ hipError_t launch_pass_recon(const uint16_t* codes, int dtype, int predictor, vo
       hipLaunchKernelGGL((k_pass_recon<double, SZ_INTERP_LINEAR>), grid, block, 0, st, codes,
                          (double*)out, g, twoeb, radius);
   }
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------ batches
+// The same stages for every field of a batch in one launch (batch.hip).
+
+__global__ void k_b_meta_init(const BField* __restrict__ f, uint32_t nf) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nf) meta_init(f[i].m);
+}
+
+hipError_t launch_b_meta_init(const BField* f, uint32_t nf, hipStream_t st) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_meta_init, dim3((nf + 255) / 256), dim3(256), 0, st, f, nf);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_b_minmax(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  minmax_body<T>(static_cast<const T*>(f.x), f.n, f.m, local, j.nblk);
+}
+
+hipError_t launch_b_minmax(int dtype, BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL(k_b_minmax<float>, dim3(nwg), dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL(k_b_minmax<double>, dim3(nwg), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+__global__ void k_b_resolve_eb(const BField* __restrict__ f, uint32_t nf) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  if (f[i].dtype == SZ_F32)
+    resolve_eb<float>(f[i].eb_mode, f[i].eb_value, f[i].m);
+  else
+    resolve_eb<double>(f[i].eb_mode, f[i].eb_value, f[i].m);
+}
+
+hipError_t launch_b_resolve_eb(const BField* f, uint32_t nf, hipStream_t st) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_resolve_eb, dim3((nf + 255) / 256), dim3(256), 0, st, f, nf);
+  return hipGetLastError();
+}
+
+// one workgroup per field: the origin and the coarsest levels
+template <typename T>
+__global__ __launch_bounds__(kSmallThreads) void k_b_small_levels(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  small_levels_body<T, false>(static_cast<const T*>(f.x), static_cast<T*>(f.rec), f.codes, f.sg,
+                              f.m, T(0), f.R);
+}
+
+hipError_t launch_b_small_levels(int dtype, BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL(k_b_small_levels<float>, dim3(nwg), dim3(kSmallThreads), 0, st, L);
+  else
+    hipLaunchKernelGGL(k_b_small_levels<double>, dim3(nwg), dim3(kSmallThreads), 0, st, L);
   return hipGetLastError();
 }
 

@@ -396,15 +396,15 @@ struct RowIn {
 };
 
 template <typename T, int PRED, bool RECON>
-__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_level64(const T* __restrict__ x, T* v,
-                                                           uint16_t* codes, LevelGeom g,
-                                                           const Meta* __restrict__ m, T twoeb,
-                                                           uint32_t R, uint32_t flags, T* cmp) {
+__device__ __forceinline__ void level64_body(const T* __restrict__ x, T* v, uint16_t* codes,
+                                             const LevelGeom& g, const Meta* __restrict__ m,
+                                             T twoeb, uint32_t R, uint32_t flags, T* cmp,
+                                             uint32_t bid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* box = reinterpret_cast<T*>(smem_raw);
   T* ring = reinterpret_cast<T*>(smem_raw + g.box_bytes);
   uint16_t* lcode = reinterpret_cast<uint16_t*>(smem_raw + g.box_bytes + g.ring_bytes);
-  const Item I = item_of(g, blockIdx.x);
+  const Item I = item_of(g, bid);
   const uint32_t ring_slot = g.ring_b * kRingPitch;  // entries per coarse grid
   const uint32_t fa = (uint32_t)g.fs[0], fb = (uint32_t)g.fs[1], fc = (uint32_t)g.fs[2];
   const uint32_t ea = g.ext[0];
@@ -631,6 +631,26 @@ __global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
+template <typename T, int PRED, bool RECON>
+__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_level64(
+    const T* __restrict__ x, T* v, uint16_t* codes, LevelGeom g, const Meta* __restrict__ m,
+    T twoeb, uint32_t R, uint32_t flags, T* cmp) {
+  level64_body<T, PRED, RECON>(x, v, codes, g, m, twoeb, R, flags, cmp, blockIdx.x);
+}
+
+// Compression of one level of several fields (a batch): each job is a field's
+// level, with its geometry and store flags.
+template <typename T, int PRED>
+__global__ __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_b_level64(
+    BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  level64_body<T, PRED, false>(static_cast<const T*>(f.x), static_cast<T*>(f.rec), f.codes, j.g,
+                               f.m, T(0), f.R, j.flags, static_cast<T*>(f.cmp), local);
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -761,6 +781,27 @@ hipError_t launch_level_compress(const void* x, int dtype, int predictor, void* 
                                         compact ? cmp : nullptr, st);
   return launch_level_t<double, false>(x, predictor, rec, codes, g, m, 0.0, radius, flags,
                                        compact ? cmp : nullptr, st);
+}
+
+hipError_t launch_b_level(int dtype, int predictor, BLaunch L, uint32_t nwg, uint32_t lds,
+                          hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  if (dtype == SZ_F32) {
+    if (predictor == SZ_INTERP_CUBIC)
+      hipLaunchKernelGGL((k_b_level64<float, SZ_INTERP_CUBIC>), dim3(nwg), dim3(kLevelThreads), lds,
+                         st, L);
+    else
+      hipLaunchKernelGGL((k_b_level64<float, SZ_INTERP_LINEAR>), dim3(nwg), dim3(kLevelThreads),
+                         lds, st, L);
+  } else {
+    if (predictor == SZ_INTERP_CUBIC)
+      hipLaunchKernelGGL((k_b_level64<double, SZ_INTERP_CUBIC>), dim3(nwg), dim3(kLevelThreads),
+                         lds, st, L);
+    else
+      hipLaunchKernelGGL((k_b_level64<double, SZ_INTERP_LINEAR>), dim3(nwg), dim3(kLevelThreads),
+                         lds, st, L);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_level_recon(const uint16_t* codes, int dtype, int predictor, void* out,
