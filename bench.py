@@ -256,58 +256,125 @@ def bound_measurement(szg, torch, ctx, xt, rels, chunk, flush, reps=3):
     return res
 
 
-def batch_measurement(szg, torch, np, synth, workers, reps=3):
-    """Batched vs per-field compression of a mixed set of fields at rel eb
-    1e-3: a loop of sz_compress calls on one stream, against the request
-    server (workers with their own contexts and streams).  Outputs must be
-    byte-identical."""
-    n_large = 4
-    flds = synth.batch_fields(seed=4, n_large=n_large)
+def batch_measurement(szg, torch, np, synth, workers, reps=5):
+    """The batching workload (13 x 100x500x500 f32 plus 64 fields of dims
+    U{16..96}^3): sz_compress_batch (shared launches, graph replay) against a
+    loop of sz_compress calls on one stream and against the request server,
+    once with each field's drawn rel eb (log-uniform over 1e-5..1e-2) and once
+    with every field at rel 1e-3.  All three must write the same bytes (the
+    oracle checks them in the CPU-baseline leg: every field of the drawn
+    bounds, a seeded sample at 1e-3).  Times are medians over `reps` runs,
+    each preceded by an Infinity Cache flush."""
+    flds = synth.batch_fields(seed=4, n_large=13)
     dev = torch.device("cuda:0")
     xs = [torch.from_numpy(f).to(dev) for f, _ in flds]
     total = sum(x.numel() * x.element_size() for x in xs)
+    npts = [x.numel() for x in xs]
     outs = [torch.empty(szg.compress_bound(tuple(x.shape), szg.F32), dtype=torch.uint8, device=dev)
             for x in xs]
+    flush_buf = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
     ctx = szg.Context(0)
-
-    def per_field():
-        sizes = []
-        for x, o in zip(xs, outs):
-            sizes.append(int(ctx.compress(x, "rel", 1e-3, "cubic", out=o).numel()))
-        torch.cuda.synchronize()
-        return sizes
-
-    ref_sizes = per_field()
-    ref = [bytes(o[:n].cpu().numpy().tobytes()) for o, n in zip(outs, ref_sizes)]
-    t_pf = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        per_field()
-        t_pf.append(time.perf_counter() - t0)
     srv = szg.Server(0, budget_bytes=64 << 30, workers=workers)
     souts = [torch.empty_like(o) for o in outs]
+    rng = np.random.default_rng(12)
+    sample = sorted(set([0] + [13 + int(k) for k in rng.choice(64, size=6, replace=False)]))
 
-    def served():
-        ts = [srv.submit_compress(x, "rel", 1e-3, "cubic", out=o) for x, o in zip(xs, souts)]
-        return [srv.wait(t) for t in ts]
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            flush_buf.fill_(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
 
-    res = served()
-    identical = all(st == 0 and bytes(v.cpu().numpy().tobytes()) == r
-                    for (st, v), r in zip(res, ref))
-    t_sv = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        served()
-        t_sv.append(time.perf_counter() - t0)
+    res = {"workload": "13 x 100x500x500 + 64 fields of dims U{16..96}^3 f32, offset + scale * "
+                       "GRF (slope U[-4,-2], offset and scale log-uniform over 1e-3..1e6), cubic",
+           "fields": len(xs), "input_bytes": total, "server_workers": workers}
+    for label, ebs in (("drawn_eb", [e for _, e in flds]), ("rel_1e-3", [1e-3] * len(flds))):
+        def per_field():
+            return [int(ctx.compress(x, "rel", e, "cubic", out=o).numel())
+                    for x, o, e in zip(xs, outs, ebs)]
+
+        sizes = per_field()
+        torch.cuda.synchronize()
+        ref = [bytes(o[:n].cpu().numpy().tobytes()) for o, n in zip(outs, sizes)]
+        batch_in = [(x, "rel", e, "cubic") for x, e in zip(xs, ebs)]
+        t_first = time.perf_counter()
+        got = ctx.compress_batch(batch_in)  # builds the plan, tunes the tiles, captures the graph
+        t_first = time.perf_counter() - t_first
+        same_batch = all(bytes(g.cpu().numpy().tobytes()) == r for g, r in zip(got, ref))
+        del got
+
+        def served():
+            ts = [srv.submit_compress(x, "rel", e, "cubic", out=o) for x, o, e in zip(xs, souts, ebs)]
+            return [srv.wait(t) for t in ts]
+
+        sres = served()
+        same_server = all(st == 0 and bytes(v.cpu().numpy().tobytes()) == r
+                          for (st, v), r in zip(sres, ref))
+        t_b = timed(lambda: ctx.compress_batch(batch_in))
+        t_pf = timed(per_field)
+        t_sv = timed(served)
+        stream_bytes = sum(len(r) for r in ref)
+        # compress: read x twice (range, then prediction), write and read the
+        # u16 codes, write the stream
+        alg = sum(n * 4 * 2 + 4 * n for n in npts) + stream_bytes
+        res[label] = {
+            "batched_GBps": round(total / t_b / 1e9, 2), "batched_ms": round(t_b * 1e3, 3),
+            "per_field_GBps": round(total / t_pf / 1e9, 2), "per_field_ms": round(t_pf * 1e3, 3),
+            "server_GBps": round(total / t_sv / 1e9, 2), "server_ms": round(t_sv * 1e3, 3),
+            "batched_over_per_field": round(t_pf / t_b, 2),
+            "batched_alg_bytes": alg, "batched_alg_GBps": round(alg / t_b / 1e9, 1),
+            "batched_frac": round(alg / t_b / 1e9 / HBM_PEAK_GBPS, 4),
+            "ratio": round(total / stream_bytes, 3),
+            "first_call_ms": round(t_first * 1e3, 1),
+            "batch_identical_to_per_field": same_batch,
+            "server_identical_to_per_field": same_server,
+            "_streams": ref if label == "drawn_eb" else {k: ref[k] for k in sample},
+            "_ebs": ebs,
+        }
     srv.close()
     ctx.close()
-    pf, sv = float(np.median(t_pf)), float(np.median(t_sv))
-    return {"workload": f"{n_large} x 100x500x500 + 64 fields of dims U{{16..96}}^3 f32, offset + "
-                        f"scale * GRF (slope U[-4,-2]), cubic, rel eb 1e-3",
-            "fields": len(xs), "input_bytes": total,
-            "per_field_GBps": round(total / pf / 1e9, 3), "per_field_ms": round(pf * 1e3, 3),
-            "server_GBps": round(total / sv / 1e9, 3), "server_ms": round(sv * 1e3, 3),
-            "server_workers": workers, "outputs_identical": identical}
+    res["_fields"] = [f for f, _ in flds]
+    res["_sample"] = sample
+    return res
+
+
+def strip_private(d):
+    """The object without its private (underscore) entries, recursively."""
+    if not isinstance(d, dict):
+        return d
+    return {k: strip_private(v) for k, v in d.items() if not k.startswith("_")}
+
+
+def batch_oracle_leg(orc, batched, threads):
+    """The oracle on the batching workload: every field at its drawn bound,
+    one field per thread (the oracle is reentrant C; ctypes releases the
+    interpreter lock) across `threads` host threads, checked byte for byte
+    against the GPU's streams, timed as the CPU baseline of that workload; and
+    the seeded sample at rel 1e-3."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    fields = batched["_fields"]
+    d = batched["drawn_eb"]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        streams = list(ex.map(lambda k: orc.compress(fields[k], orc.REL, d["_ebs"][k], orc.CUBIC),
+                              range(len(fields))))
+    wall = time.perf_counter() - t0
+    d["parity_with_oracle_all_fields"] = all(a == b for a, b in zip(streams, d["_streams"]))
+    e = batched["rel_1e-3"]
+    e["parity_with_oracle_sample"] = all(
+        orc.compress(fields[k], orc.REL, 1e-3, orc.CUBIC) == v for k, v in e["_streams"].items())
+    e["oracle_sample_fields"] = batched["_sample"]
+    batched["cpu_baseline"] = {
+        "value": round(batched["input_bytes"] / wall / 1e9, 4), "unit": "GB/s (compress)",
+        "cores": threads, "kind": "oracle",
+        "sample": f"all {len(fields)} fields at their drawn bounds, compress only, one field per "
+                  f"thread on {threads} host threads ({wall:.1f}s wall)"}
 
 
 def main():
@@ -498,6 +565,8 @@ def main():
             back.tobytes() == rec.cpu().numpy().tobytes())
         # the other bounds of the same field, byte for byte (streams and
         # reconstructions kept from their GPU runs)
+        if batched is not None:
+            batch_oracle_leg(oracle, batched, min(16, os.cpu_count() or 1))
         if bounds is not None:
             for key, b in bounds.items():
                 bref = oracle.compress(x, oracle.REL, float(key), oracle.CUBIC, 32768, args.chunk,
@@ -570,7 +639,7 @@ def main():
         "bounds": None if bounds is None else {
             k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in bounds.items()},
         "cpu_baseline": cpu,
-        "batched": batched,
+        "batched": strip_private(batched),
         "lossless": lossless,
         "pwrel": pwrel,
         "adaptive": adaptive,
