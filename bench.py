@@ -301,9 +301,9 @@ def batch_measurement(szg, torch, np, synth, workers, reps=5):
         sizes = per_field()
         torch.cuda.synchronize()
         ref = [bytes(o[:n].cpu().numpy().tobytes()) for o, n in zip(outs, sizes)]
-        batch_in = [(x, "rel", e, "cubic") for x, e in zip(xs, ebs)]
+        call = ctx.prepare_batch([(x, "rel", e, "cubic") for x, e in zip(xs, ebs)])
         t_first = time.perf_counter()
-        got = ctx.compress_batch(batch_in)  # builds the plan, tunes the tiles, captures the graph
+        got = call.run()  # builds the plan, tunes the tiles, captures the graph
         t_first = time.perf_counter() - t_first
         same_batch = all(bytes(g.cpu().numpy().tobytes()) == r for g, r in zip(got, ref))
         del got
@@ -315,7 +315,7 @@ def batch_measurement(szg, torch, np, synth, workers, reps=5):
         sres = served()
         same_server = all(st == 0 and bytes(v.cpu().numpy().tobytes()) == r
                           for (st, v), r in zip(sres, ref))
-        t_b = timed(lambda: ctx.compress_batch(batch_in))
+        t_b = timed(call.run)
         t_pf = timed(per_field)
         t_sv = timed(served)
         stream_bytes = sum(len(r) for r in ref)
@@ -341,6 +341,151 @@ def batch_measurement(szg, torch, np, synth, workers, reps=5):
     res["_fields"] = [f for f, _ in flds]
     res["_sample"] = sample
     return res
+
+
+def serving_measurement(szg, torch, np, synth, workers, n_req, budget=200 << 30, window=32,
+                        loads=(0.5, 0.8, 1.2), n_sample=100):
+    """The serving workload: ``n_req`` compression requests (synth.serving_requests:
+    sizes log-uniform over 16^3..256x512x512 points, random aspect ratios,
+    slopes U[-4,-2], rel eb log-uniform over 1e-5..1e-2), each a crop of a
+    device-resident base field, served by the request server under an HBM
+    budget.
+
+    1. saturated rate: a closed loop keeping ``window`` requests outstanding;
+    2. at each offered load, Poisson arrivals at load x the saturated rate;
+       a request's latency runs from its scheduled arrival to the client's
+       observation that it is done (the client polls the oldest 64
+       outstanding tickets between arrivals; the server starts requests in
+       arrival order, so later ones cannot be done first unless those are);
+    3. every request is served again in a mix (closed loop) and compared on
+       the device with the same request compressed alone; a seeded sample
+       keeps its bytes for the oracle (CPU-baseline leg)."""
+    pool = synth.serving_pool(seed=5)
+    reqs = synth.serving_requests(n_req, seed=6)
+    dev = torch.device("cuda:0")
+    bases = [torch.from_numpy(f).to(dev) for f, _ in pool]
+    srv = szg.Server(0, budget_bytes=budget, workers=workers)
+    caps = [szg.compress_bound(r["shape"], szg.F32) for r in reqs]
+    nbytes = [4 * int(np.prod(r["shape"])) for r in reqs]
+    total = sum(nbytes)
+
+    def crop(k):
+        r = reqs[k]
+        (a, b, c), (na, nb, nc) = r["origin"], r["shape"]
+        return bases[r["base"]][a:a + na, b:b + nb, c:c + nc].contiguous()
+
+    def issue(k):
+        out = torch.empty(caps[k], dtype=torch.uint8, device=dev)
+        return srv.submit_compress(crop(k), "rel", reqs[k]["rel_eb"], "cubic", out=out)
+
+    def sweep(outstanding, on_done, limit=64):
+        done = []
+        for t in list(outstanding)[:limit]:
+            res = srv.poll(t)
+            if res is not None:
+                done.append((t, res))
+        for t, res in done:
+            on_done(outstanding.pop(t), res)
+
+    # 1. saturated rate
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outstanding, nxt = {}, 0
+    while nxt < n_req or outstanding:
+        while nxt < n_req and len(outstanding) < window:
+            outstanding[issue(nxt)] = nxt
+            nxt += 1
+        sweep(outstanding, lambda k, res: None)
+    t_sat = time.perf_counter() - t0
+    sat_rate = n_req / t_sat
+    res = {"workload": f"{n_req} compression requests, 3-D f32 crops of {len(pool)} base GRFs "
+                       "of 256x512x512 (slopes -4..-2), sizes log-uniform 16^3..256x512x512, "
+                       "random aspect ratios, rel eb log-uniform 1e-5..1e-2, cubic",
+           "requests": n_req, "input_bytes": total, "budget_bytes": budget, "workers": workers,
+           "saturated": {"req_per_s": round(sat_rate, 1), "GBps": round(total / t_sat / 1e9, 2),
+                         "window": window, "seconds": round(t_sat, 3)}}
+    # 2. Poisson arrivals at each offered load
+    rng = np.random.default_rng(7)
+    for load in loads:
+        lam = load * sat_rate
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+        lat = np.zeros(n_req)
+        last = [0.0]
+        outstanding, i = {}, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+
+        def on_done(k, r):
+            now = time.perf_counter() - t0
+            lat[k] = now - arr[k]
+            last[0] = now
+            if r[0] != 0:
+                raise RuntimeError(f"request {k} failed with status {r[0]}")
+
+        while i < n_req or outstanding:
+            now = time.perf_counter() - t0
+            while i < n_req and arr[i] <= now:
+                outstanding[issue(i)] = i
+                i += 1
+            sweep(outstanding, on_done)
+        span = last[0] - arr[0]
+        res[f"load_{load:g}"] = {
+            "offered_req_per_s": round(lam, 1),
+            "achieved_GBps": round(total / span / 1e9, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "mean_ms": round(float(lat.mean()) * 1e3, 3),
+        }
+    # 3. in a mix (closed loop) against alone, every request
+    ctx = szg.Context(0)
+    sample = sorted(int(k) for k in np.random.default_rng(8).choice(n_req, size=min(n_sample, n_req),
+                                                                    replace=False))
+    keep = {}
+    bad = []
+
+    def check(k, r):
+        alone = ctx.compress(crop(k), "rel", reqs[k]["rel_eb"], "cubic")
+        if r[0] != 0 or r[1].numel() != alone.numel() or not torch.equal(r[1], alone):
+            bad.append(k)
+        if k in sample_set:
+            keep[k] = bytes(r[1].cpu().numpy().tobytes())
+
+    sample_set = set(sample)
+    outstanding, nxt = {}, 0
+    while nxt < n_req or outstanding:
+        while nxt < n_req and len(outstanding) < window:
+            outstanding[issue(nxt)] = nxt
+            nxt += 1
+        sweep(outstanding, check)
+    srv.close()
+    ctx.close()
+    res["alone_equals_in_mix"] = {"requests": n_req, "mismatches": len(bad)}
+    res["_sample"] = keep
+    res["_reqs"] = reqs
+    res["_pool"] = [f for f, _ in pool]
+    return res
+
+
+def serving_oracle_leg(orc, serving, threads):
+    """The oracle on a seeded sample of the serving requests (host crops of
+    the same base fields), byte for byte against the served streams."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    reqs, pool, sample = serving["_reqs"], serving["_pool"], serving["_sample"]
+
+    def one(k):
+        r = reqs[k]
+        (a, b, c), (na, nb, nc) = r["origin"], r["shape"]
+        x = np.ascontiguousarray(pool[r["base"]][a:a + na, b:b + nb, c:c + nc])
+        return orc.compress(x, orc.REL, r["rel_eb"], orc.CUBIC) == sample[k]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        ok = list(ex.map(one, sorted(sample)))
+    serving["parity_with_oracle_sample"] = {"requests": len(ok), "identical": all(ok),
+                                            "seconds": round(time.perf_counter() - t0, 2)}
 
 
 def strip_private(d):
@@ -391,6 +536,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs per-field measurement")
     ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving measurement (Poisson arrivals, p50/p99)")
+    ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the lossless, point-wise relative and adaptive measurements "
                          "(for profiler runs that count the step's kernels)")
@@ -542,6 +690,8 @@ def main():
 
     batched = None if args.no_batch else batch_measurement(szg, torch, np, synth,
                                                            args.batch_workers)
+    serving = None if args.no_serving else serving_measurement(
+        szg, torch, np, synth, args.batch_workers, args.serving_requests)
     lossless = pwrel = adaptive = lorenzo = None
     if not args.no_extras:
         lossless = lossless_measurement(szg, s, in_bytes)
@@ -567,6 +717,8 @@ def main():
         # reconstructions kept from their GPU runs)
         if batched is not None:
             batch_oracle_leg(oracle, batched, min(16, os.cpu_count() or 1))
+        if serving is not None:
+            serving_oracle_leg(oracle, serving, min(16, os.cpu_count() or 1))
         if bounds is not None:
             for key, b in bounds.items():
                 bref = oracle.compress(x, oracle.REL, float(key), oracle.CUBIC, 32768, args.chunk,
@@ -640,6 +792,7 @@ def main():
             k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in bounds.items()},
         "cpu_baseline": cpu,
         "batched": strip_private(batched),
+        "serving": strip_private(serving),
         "lossless": lossless,
         "pwrel": pwrel,
         "adaptive": adaptive,

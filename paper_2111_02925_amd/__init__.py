@@ -362,33 +362,12 @@ class Context:
                        stream=None):
         """fields: list of (tensor, eb_mode, eb, predictor).  Returns the list
         of stream tensors (views of per-field output buffers)."""
-        torch = _torch()
-        arr = (Field * len(fields))()
-        outs = []
-        opts = make_options(radius, chunk, None, 4, subchunks)
-        for i, (x, mode, eb, pred) in enumerate(fields):
-            o1 = make_options(radius, chunk, None, x.dim(), subchunks)
-            fn = (self._lib.sz_compress_bound_pwrel if _mode(mode) == PWREL
-                  else self._lib.sz_compress_bound)
-            cap = int(fn(_dtype_code(x), x.dim(), _dims(x.shape), ctypes.byref(o1)))
-            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
-            outs.append(out)
-            f = arr[i]
-            f.d_in = x.data_ptr()
-            f.dtype = _dtype_code(x)
-            f.ndim = x.dim()
-            for d in range(4):
-                f.dims[d] = int(x.shape[d]) if d < x.dim() else 1
-            f.eb_mode = _mode(mode)
-            f.eb = float(eb)
-            f.predictor = _pred(pred)
-            f.d_out = out.data_ptr()
-            f.out_capacity = out.numel()
-        rc = self._lib.sz_compress_batch(self._h, arr, len(fields), ctypes.byref(opts),
-                                         self._stream(stream))
-        if rc:
-            raise self._err(rc, "sz_compress_batch")
-        return [outs[i][: arr[i].out_size] for i in range(len(fields))]
+        return self.prepare_batch(fields, radius, chunk, subchunks).run(stream)
+
+    def prepare_batch(self, fields, radius: int = 32768, chunk: int = 4096, subchunks: int = 0):
+        """A batch whose argument array and output buffers are built once, for
+        calls repeated on the same inputs (BatchCall.run)."""
+        return BatchCall(self, fields, radius, chunk, subchunks)
 
     def debug_codes(self, n: int, device="cuda"):
         torch = _torch()
@@ -414,6 +393,47 @@ class Context:
         cnt = ctypes.c_uint64(0)
         self._lib.sz_timing_get(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt))
         return ms.value, cnt.value
+
+
+class BatchCall:
+    """The arguments of one sz_compress_batch call (field array, options,
+    output buffers sized by the compression bound), kept for repeated runs."""
+
+    def __init__(self, ctx: "Context", fields, radius: int, chunk: int, subchunks: int):
+        torch = _torch()
+        self._ctx = ctx
+        self._arr = (Field * len(fields))()
+        self._opts = make_options(radius, chunk, None, 4, subchunks)
+        self.outs = []
+        for i, (x, mode, eb, pred) in enumerate(fields):
+            if not x.is_cuda or not x.is_contiguous():
+                raise ValueError("fields must be contiguous CUDA tensors")
+            o1 = make_options(radius, chunk, None, x.dim(), subchunks)
+            fn = (ctx._lib.sz_compress_bound_pwrel if _mode(mode) == PWREL
+                  else ctx._lib.sz_compress_bound)
+            cap = int(fn(_dtype_code(x), x.dim(), _dims(x.shape), ctypes.byref(o1)))
+            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+            self.outs.append(out)
+            f = self._arr[i]
+            f.d_in = x.data_ptr()
+            f.dtype = _dtype_code(x)
+            f.ndim = x.dim()
+            for d in range(4):
+                f.dims[d] = int(x.shape[d]) if d < x.dim() else 1
+            f.eb_mode = _mode(mode)
+            f.eb = float(eb)
+            f.predictor = _pred(pred)
+            f.d_out = out.data_ptr()
+            f.out_capacity = out.numel()
+        self._keep = [x for x, *_ in fields]  # the inputs stay alive with the call
+
+    def run(self, stream=None):
+        ctx = self._ctx
+        rc = ctx._lib.sz_compress_batch(ctx._h, self._arr, len(self.outs), ctypes.byref(self._opts),
+                                        ctx._stream(stream))
+        if rc:
+            raise ctx._err(rc, "sz_compress_batch")
+        return [self.outs[i][: self._arr[i].out_size] for i in range(len(self.outs))]
 
 
 _default_ctx = {}

@@ -1104,12 +1104,24 @@ int sz_compress_batch(sz_ctx* ctx, sz_field* fields, int nfields, const sz_optio
     it.chunk = s.chunk;
     it.sub = s.sub;
     header_template(s, f.predictor, f.eb_mode, f.eb, it.hdr);
-    if (batch_item_supported(it)) {
-      items.push_back(it);
-      where.push_back(i);
-    } else {
-      single.push_back(i);
+    items.push_back(it);
+    where.push_back(i);
+  }
+  // the cached plan covers exactly these fields, or each field is checked
+  if (!batch_plan_covers(ctx->batch, items)) {
+    size_t k = 0;
+    for (size_t j = 0; j < items.size(); j++) {
+      if (batch_item_supported(items[j])) {
+        items[k] = items[j];
+        where[k] = where[j];
+        k++;
+      } else {
+        single.push_back(where[j]);
+      }
     }
+    items.resize(k);
+    where.resize(k);
+    std::sort(single.begin(), single.end());
   }
   std::string err;
   const int rc = batch_compress(ctx->device, &ctx->batch, items, st, err);

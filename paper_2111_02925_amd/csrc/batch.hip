@@ -169,6 +169,10 @@ bool batch_item_supported(const BatchItem& it) {
   return true;
 }
 
+bool batch_plan_covers(const BatchPlan* plan, const std::vector<BatchItem>& items) {
+  return plan && !items.empty() && plan->key == plan_key(items);
+}
+
 namespace {
 
 hipError_t dev_alloc(void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 8); }
@@ -414,7 +418,7 @@ void build_steps(BatchPlan& P, const std::vector<BatchItem>& items, const std::v
   {
     std::vector<BJob> js;
     for (uint32_t i = 0; i < nf; i++)
-      js.push_back(field_job(i, std::min<uint32_t>(1024, std::max<uint32_t>(1, cdiv32(P.fields[i].n, 16384)))));
+      js.push_back(field_job(i, std::min<uint32_t>(256, std::max<uint32_t>(1, cdiv32(P.fields[i].n, 65536)))));
     Step m{};
     m.op = Op::Hist;
     add_step(P, m, js, false);

@@ -395,6 +395,9 @@ void batch_plan_free(BatchPlan* p);
 // cubic interpolation, an absolute or range-relative bound, and every level
 // on the fixed-pitch or strip kernel.
 bool batch_item_supported(const BatchItem& it);
+// The plan was built for exactly these fields' shapes and options (so each
+// of them is supported).
+bool batch_plan_covers(const BatchPlan* plan, const std::vector<BatchItem>& items);
 // Compresses the items (validated, one radius, chunk and sub-chunk count) with
 // shared launches; *plan is the cached plan (rebuilt when the shapes or
 // options change).  Returns SZ_OK with each item's status and size set, or an

@@ -15,7 +15,10 @@ comparable value distribution:
                           spikes (ATM stand-in).
 * ``batch_fields``    -- 13 offset/scaled GRFs of 100x500x500 plus 64 small
                           fields (Hurricane-like variables).
-* ``serving_requests``-- request shapes / bounds for the serving loop.
+* ``serving_pool``    -- base fields (GRFs of 256x512x512, slopes spread over
+                          [-4, -2]) that serving requests crop.
+* ``serving_requests``-- the serving workload's requests: size, aspect ratio,
+                          base field, crop origin and bound of each.
 """
 from __future__ import annotations
 
@@ -178,6 +181,57 @@ def batch_fields(seed: int = 4, n_large: int = 13, large_shape=(100, 500, 500),
         g = grf(shp, alpha, rng, dtype=np.float32 if int(np.prod(shp)) >= (1 << 24) else np.float64)
         f = (off + scale * g.astype(np.float64)).astype(np.float32)
         out.append((f, rel))
+    return out
+
+
+def serving_pool(seed: int = 5, n_base: int = 5, shape=(256, 512, 512)):
+    """The base fields serving requests are cropped from: ``n_base`` float32
+    GRFs of ``shape`` whose spectral slopes are spread evenly over [-4, -2].
+    Returns a list of (field, slope)."""
+    rng = np.random.default_rng(seed)
+    slopes = np.linspace(-4.0, -2.0, n_base)
+    return [(grf(shape, float(a), rng, dtype=np.float32).astype(np.float32, copy=False), float(a))
+            for a in slopes]
+
+
+def serving_requests(n: int = 10000, seed: int = 6, base_shape=(256, 512, 512), n_base: int = 5,
+                     lo: int = 16 ** 3, hi: int = 256 * 512 * 512):
+    """The serving workload: ``n`` compression requests, each a crop of a
+    base field of ``serving_pool``.
+
+    * size N log-uniform over [lo, hi] points;
+    * aspect ratio: log n_d = w_d log N with w ~ Dirichlet(2, 2, 2); an
+      extent above the base field's is clipped and its excess exponent shared
+      among the other dimensions (extents at least 4);
+    * spectral slope U[-4, -2], served by the base field of nearest slope;
+    * crop origin uniform over the positions that fit;
+    * range-relative bound log-uniform over [1e-5, 1e-2].
+
+    Returns a list of dicts: shape, base, origin, slope, rel_eb."""
+    rng = np.random.default_rng(seed)
+    slopes = np.linspace(-4.0, -2.0, n_base)
+    cap = np.log(np.asarray(base_shape, dtype=np.float64))
+    out = []
+    for _ in range(n):
+        logn = rng.uniform(math.log(lo), math.log(hi))
+        w = rng.dirichlet([2.0, 2.0, 2.0])
+        ld = w * logn
+        free = np.ones(3, dtype=bool)
+        for _ in range(3):  # clip and share the excess among the others
+            over = free & (ld > cap)
+            if not over.any():
+                break
+            excess = float((ld[over] - cap[over]).sum())
+            ld[over] = cap[over]
+            free &= ~over
+            if free.any():
+                ld[free] += excess * w[free] / w[free].sum()
+        dims = tuple(int(min(base_shape[d], max(4, round(math.exp(ld[d]))))) for d in range(3))
+        slope = float(rng.uniform(-4.0, -2.0))
+        base = int(np.argmin(np.abs(slopes - slope)))
+        origin = tuple(int(rng.integers(0, base_shape[d] - dims[d] + 1)) for d in range(3))
+        rel = float(10.0 ** rng.uniform(-5.0, -2.0))
+        out.append({"shape": dims, "base": base, "origin": origin, "slope": slope, "rel_eb": rel})
     return out
 
 
