@@ -861,8 +861,11 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   EncodeScratch es{w.chunk_words, w.chunk_unpred, w.word_off, w.unpred_off, w.block_sums,
                    ctx->totals};
   CHECK_HIP(timed(ctx, "encode", st, [&] {
+              // (the reconstruction is dead once the levels are done: the
+              // encoder packs its chunks there)
               return launch_encode(codes, d_in, dtype, s.n, s.chunk, s.sub, s.radius, ctx->enc_code,
-                                   ctx->enc_len, es, out, out_capacity, ctx->meta, st);
+                                   ctx->enc_len, es, static_cast<uint32_t*>(w.rec), out,
+                                   out_capacity, ctx->meta, st);
             }), "encode");
   CHECK_HIP(timed(ctx, "other", st, [&] {
               return launch_write_tables(out, out_capacity, ctx->symtab, nch, s.sub, hdr, dtype, ctx->meta, st);

@@ -307,10 +307,12 @@ struct EncodeScratch {
   uint64_t* block_sums;
   uint64_t* totals;
 };
+// slots: at least n words of scratch (the reconstruction buffer, dead by
+// then), where the lane-parallel path packs each chunk before one copy.
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
                          uint32_t chunk, uint32_t sub, uint32_t radius, const uint64_t* enc_code,
-                         const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
-                         Meta* m, hipStream_t st);
+                         const uint8_t* enc_len, EncodeScratch es, uint32_t* slots, uint8_t* out,
+                         uint64_t cap, Meta* m, hipStream_t st);
 hipError_t launch_write_tables(uint8_t* out, uint64_t capacity, const uint32_t* symtab,
                                uint64_t nchunks, uint32_t sub, const uint8_t* header_template,
                                int dtype, Meta* m, hipStream_t st);

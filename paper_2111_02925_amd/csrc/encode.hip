@@ -220,46 +220,20 @@ __device__ __forceinline__ Sym8 lookup8(const FastLds& f, uint32_t lo, uint4 v, 
 
 __device__ __forceinline__ void wave_step() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ void size_fast(const uint16_t* __restrict__ codes, uint64_t n,
-                                          uint32_t chunk, uint64_t nchunks, const FastLds& f,
-                                          uint32_t lo, uint32_t* chunk_words,
-                                          uint32_t* chunk_zeros, uint32_t bid, uint32_t nblk) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
-  const uint64_t last8 = (n - 1) & ~7ull;
-  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
-       c += wstride) {
-    const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
-    const uint32_t clen = (uint32_t)(cend - cbeg);
-    uint32_t bits = 0, zeros = 0;
-    uint4 nxt = load8(codes, cbeg + 8 * lane, last8);
-    for (uint64_t g = cbeg; g < cend; g += kStep) {
-      const uint4 cur = nxt;
-      const uint64_t i0 = g + 8 * lane;
-      nxt = load8(codes, i0 + kStep, last8);
-      const uint32_t off = (uint32_t)(i0 - cbeg);
-      const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
-      const Sym8 r = lookup8(f, lo, cur, nv);
-#pragma unroll
-      for (int j = 0; j < 8; j++) bits += r.len[j];
-      zeros += r.zeros;
-    }
-    bits = wave_sum_u32(bits);
-    zeros = wave_sum_u32(zeros);
-    if (lane == 0) {
-      chunk_words[c] = (bits + 31) / 32;
-      chunk_zeros[c] = zeros;
-    }
-  }
-}
+// ------------------------------------------------ single read of the codes
+// On the lane-parallel path the codes are read once: the first pass packs
+// each chunk exactly as pack_fast does, but into a slot of its own (chunk c's
+// words at word c * chunk of `slots`: a chunk of clen symbols of at most 32
+// bits each fills at most clen words, so the slots of a field of n symbols
+// fit n words), writing its chunk-table and sub-chunk entries (chunk-local
+// values) and its sizes for the scans; the second pass copies every slot to
+// its place in the bitstream and scatters the unpredictable values of the
+// chunks that have some (ranked by ballots over the chunk's codes).
 
-template <typename T>
-__device__ __forceinline__ void pack_fast(
-    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
-    uint32_t sub, uint64_t nchunks, FastLds& f, uint32_t lo,
-    const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
-    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
-    const Layout& l, uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void pack_fast_slots(
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint32_t sub,
+    uint64_t nchunks, FastLds& f, uint32_t lo, uint32_t* chunk_words, uint32_t* chunk_zeros,
+    uint32_t* slots, const Layout& l, uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   uint32_t* buf = f.buf[threadIdx.x >> 6];
   const uint32_t span = chunk / sub;
@@ -269,14 +243,9 @@ __device__ __forceinline__ void pack_fast(
        c += wstride) {
     const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
     const uint32_t clen = (uint32_t)(cend - cbeg);
-    const uint64_t wbyte = l.off_bits + 4 * word_off[c];
-    uint64_t zr = zero_off[c];
-    if (lane == 0) {
-      guarded_store_u32(out, cap, l.off_chunk + 8 * c, chunk_words[c]);
-      guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, chunk_zeros[c]);
-    }
-    uint32_t have = 0, done = 0, written = 0;  // bits in buf, chunk bits so far, words stored
-    uint32_t next_sub = span, k_sub = 1;         // start of the next sub-chunk, its number
+    uint32_t* slot = slots + cbeg;
+    uint32_t have = 0, done = 0, written = 0, zeros = 0;
+    uint32_t next_sub = span, k_sub = 1;
     uint4 nxt = load8(codes, cbeg + 8 * lane, last8);
     for (uint64_t g = cbeg; g < cend; g += kStep) {
       const uint4 cur = nxt;
@@ -286,19 +255,17 @@ __device__ __forceinline__ void pack_fast(
       const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
       const Sym8 r = lookup8(f, lo, cur, nv);
       uint32_t pre[8], t = 0;
-      uint64_t acc = 0;  // the lane's bits, right-aligned (exact while t <= 64)
+      uint64_t acc = 0;
 #pragma unroll
       for (int j = 0; j < 8; j++) {
         pre[j] = t;
         t += r.len[j];
         acc = (acc << r.len[j]) | r.code[j];
       }
-      const uint32_t z = r.zeros;
-      const uint32_t mine = t | (z << 16);  // t <= 256, z <= 8
+      const uint32_t mine = t | (r.zeros << 16);
       const uint32_t incl = wave_incl_scan_dpp(mine);
       const uint32_t tot = __builtin_amdgcn_readlane(incl, 63), excl = incl - mine;
       const uint32_t e = excl & 0xFFFFu;
-      // sub-chunks starting in this step (their starts are multiples of 8)
       const uint32_t step0 = (uint32_t)(g - cbeg);
       while (k_sub < sub && next_sub < clen && next_sub < step0 + kStep) {
         if (off == next_sub)
@@ -308,7 +275,7 @@ __device__ __forceinline__ void pack_fast(
       }
       const uint32_t o = have + e;
       if (t <= 64) {
-        acc = t ? acc << (64 - t) : 0ull;  // left-aligned
+        acc = t ? acc << (64 - t) : 0ull;
         const uint32_t sh = o & 31, wd = o >> 5;
         atomicOr(&buf[wd], (uint32_t)(acc >> (32 + sh)));
         atomicOr(&buf[wd + 1], (uint32_t)(acc >> sh));
@@ -322,24 +289,13 @@ __device__ __forceinline__ void pack_fast(
           atomicOr(&buf[(pos >> 5) + 1], (uint32_t)v);
         }
       }
-      if (z) {  // unpredictable values, verbatim, flat order
-        uint64_t rk = zr + (excl >> 16);
-#pragma unroll
-        for (int j = 0; j < 8; j++)
-          if ((r.zmask >> j) & 1u) {
-            const uint64_t off = l.off_unpred + rk * sizeof(T);
-            if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[i0 + j];
-            rk++;
-          }
-      }
       have += tot & 0xFFFFu;
       done += tot & 0xFFFFu;
-      zr += tot >> 16;
-      if (have > (kBufWords - kStep - 1) * 32) {  // the next step might not fit: store
+      zeros += tot >> 16;
+      if (have > (kBufWords - kStep - 1) * 32) {
         wave_step();
         const uint32_t full = have >> 5;
-        for (uint32_t k = lane; k < full; k += 64)
-          guarded_store_u32(out, cap, wbyte + 4 * (uint64_t)(written + k), buf[k]);
+        for (uint32_t k = lane; k < full; k += 64) slot[written + k] = buf[k];
         const uint32_t last = buf[full];
         wave_step();
         for (uint32_t k = lane; k <= full + 2; k += 64) buf[k] = k == 0 ? last : 0u;
@@ -350,15 +306,61 @@ __device__ __forceinline__ void pack_fast(
     }
     wave_step();
     const uint32_t nw = (have + 31) >> 5;
-    for (uint32_t k = lane; k < nw; k += 64)
-      guarded_store_u32(out, cap, wbyte + 4 * (uint64_t)(written + k), buf[k]);
+    for (uint32_t k = lane; k < nw; k += 64) slot[written + k] = buf[k];
     wave_step();
     for (uint32_t k = lane; k < nw + 2; k += 64) buf[k] = 0u;
     wave_step();
-    // sub-chunks that start at or past the chunk's last symbol start at its end
     for (uint32_t k = lane + 1; k < sub; k += 64)
       if ((uint64_t)k * span >= clen)
         guarded_store_u32(out, cap, l.off_sub + 4 * (c * (sub - 1) + k - 1), done);
+    if (lane == 0) {
+      const uint32_t words = (done + 31) / 32;
+      chunk_words[c] = words;
+      chunk_zeros[c] = zeros;
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c, words);
+      guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, zeros);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_slots(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint64_t nchunks, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, const uint32_t* __restrict__ slots, const Layout& l,
+    uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wstride = (uint64_t)nblk * kEncWaves;
+  for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
+       c += wstride) {
+    const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
+    const uint32_t nw = chunk_words[c];
+    const uint32_t* src = slots + cbeg;
+    const uint64_t dst = l.off_bits + 4 * word_off[c];
+    uint32_t k = lane;
+    for (; k + 192 < nw; k += 256) {  // four loads in flight
+      const uint32_t a = src[k], b = src[k + 64], d = src[k + 128], e = src[k + 192];
+      guarded_store_u32(out, cap, dst + 4 * (uint64_t)k, a);
+      guarded_store_u32(out, cap, dst + 4 * (uint64_t)(k + 64), b);
+      guarded_store_u32(out, cap, dst + 4 * (uint64_t)(k + 128), d);
+      guarded_store_u32(out, cap, dst + 4 * (uint64_t)(k + 192), e);
+    }
+    for (; k < nw; k += 64) guarded_store_u32(out, cap, dst + 4 * (uint64_t)k, src[k]);
+    if (chunk_zeros[c]) {  // unpredictable values, verbatim, flat order
+      uint64_t rk = zero_off[c];
+      for (uint64_t i0 = cbeg; i0 < cend; i0 += 64) {
+        const uint64_t i = i0 + lane;
+        const bool z = i < cend && codes[i] == 0;
+        const uint64_t bal = __ballot(z);
+        if (z) {
+          const uint64_t off =
+              l.off_unpred + (rk + (uint64_t)__popcll(bal & ((1ull << lane) - 1))) * sizeof(T);
+          if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[i];
+        }
+        rk += (uint64_t)__popcll(bal);
+      }
+    }
   }
 }
 
@@ -402,17 +404,23 @@ __device__ __forceinline__ void size_chunks(const uint16_t* __restrict__ codes, 
   }
 }
 
+// The first pass: the chunks' sizes, and on the lane-parallel path their
+// bits packed into the slots (with their chunk-table and sub-chunk entries).
 __device__ __forceinline__ void encode_size_body(
-    EncLds& u, const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks,
-    uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    EncLds& u, const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint32_t sub,
+    uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
     const uint8_t* __restrict__ enc_len, uint32_t* chunk_words, uint32_t* chunk_zeros,
-    const Meta* __restrict__ m, uint32_t bid, uint32_t nblk) {
+    uint32_t* slots, uint8_t* out, uint64_t cap, const Meta* __restrict__ m, uint32_t bid,
+    uint32_t nblk) {
   EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   if (fast_path(w)) {
     load_fast(u.f, w, enc_code, enc_len);
     __syncthreads();
-    size_fast(codes, n, chunk, nchunks, u.f, w.lo, chunk_words, chunk_zeros, bid, nblk);
+    // (the chunk-table and sub-chunk sections do not depend on the totals)
+    const Layout l = stream_layout(m->nsym_used, nchunks, sub, 0, 4, 0);
+    pack_fast_slots(codes, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros, slots, l,
+                    out, cap, bid, nblk);
     return;
   }
   load_tables(t, w, nsym, enc_code, enc_len, !w.lds_only);
@@ -426,12 +434,13 @@ __device__ __forceinline__ void encode_size_body(
 }
 
 __global__ __launch_bounds__(kEncWaves * 64) void k_encode_size(
-    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint64_t nchunks, uint32_t R,
-    uint32_t nsym, const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
-    uint32_t* chunk_words, uint32_t* chunk_zeros, const Meta* __restrict__ m) {
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint32_t sub, uint64_t nchunks,
+    uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, uint32_t* chunk_words, uint32_t* chunk_zeros,
+    uint32_t* slots, uint8_t* out, uint64_t cap, const Meta* __restrict__ m) {
   __shared__ EncLds u;
-  encode_size_body(u, codes, n, chunk, nchunks, R, nsym, enc_code, enc_len, chunk_words,
-                   chunk_zeros, m, blockIdx.x, gridDim.x);
+  encode_size_body(u, codes, n, chunk, sub, nchunks, R, nsym, enc_code, enc_len, chunk_words,
+                   chunk_zeros, slots, out, cap, m, blockIdx.x, gridDim.x);
 }
 
 // the chunk sizes of every field of a batch
@@ -441,8 +450,9 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_size(BLaunch L) {
   uint32_t local;
   if (!batch_job(L, j, local)) return;
   const BField& f = L.f[j.field];
-  encode_size_body(u, f.codes, f.n, f.chunk, f.nchunks, f.R, 2 * f.R, f.enc_code, f.enc_len,
-                   f.chunk_words, f.chunk_zeros, f.m, local, j.nblk);
+  encode_size_body(u, f.codes, f.n, f.chunk, f.sub, f.nchunks, f.R, 2 * f.R, f.enc_code,
+                   f.enc_len, f.chunk_words, f.chunk_zeros, static_cast<uint32_t*>(f.rec), f.out,
+                   f.cap, f.m, local, j.nblk);
 }
 
 // ------------------------------------------------------------------ packing
@@ -561,23 +571,24 @@ __device__ __forceinline__ void pack_chunks(
   }
 }
 
+// The second pass: on the lane-parallel path the slots to their places (and
+// the unpredictable values); otherwise the codes packed from scratch.
 template <typename T>
 __device__ __forceinline__ void encode_pack_body(
     EncLds& u, const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n,
     uint32_t chunk, uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym,
     const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
     const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
-    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off, uint8_t* out,
-    uint64_t cap, const Meta* __restrict__ m, uint32_t bid, uint32_t nblk) {
+    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
+    const uint32_t* __restrict__ slots, uint8_t* out, uint64_t cap, const Meta* __restrict__ m,
+    uint32_t bid, uint32_t nblk) {
   EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   const Layout l =
       stream_layout(m->nsym_used, nchunks, sub, m->n_unpred, sizeof(T), m->total_words);
   if (fast_path(w)) {
-    load_fast(u.f, w, enc_code, enc_len);
-    __syncthreads();
-    pack_fast<T>(codes, x, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros, word_off,
-                 zero_off, l, out, cap, bid, nblk);
+    copy_slots<T>(codes, x, n, chunk, nchunks, chunk_words, chunk_zeros, word_off, zero_off, slots,
+                  l, out, cap, bid, nblk);
     return;
   }
   load_tables(t, w, nsym, enc_code, enc_len, true);
@@ -596,11 +607,11 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode_pack(
     uint32_t sub, uint64_t nchunks, uint32_t R, uint32_t nsym, const uint64_t* __restrict__ enc_code,
     const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
-    const uint64_t* __restrict__ zero_off, uint8_t* out, uint64_t cap,
-    const Meta* __restrict__ m) {
+    const uint64_t* __restrict__ zero_off, const uint32_t* __restrict__ slots, uint8_t* out,
+    uint64_t cap, const Meta* __restrict__ m) {
   __shared__ EncLds u;
   encode_pack_body<T>(u, codes, x, n, chunk, sub, nchunks, R, nsym, enc_code, enc_len, chunk_words,
-                      chunk_zeros, word_off, zero_off, out, cap, m, blockIdx.x, gridDim.x);
+                      chunk_zeros, word_off, zero_off, slots, out, cap, m, blockIdx.x, gridDim.x);
 }
 
 // the packing of every field of a batch, with the field-local chunk offsets
@@ -613,32 +624,33 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_pack(BLaunch L) {
   const BField& f = L.f[j.field];
   encode_pack_body<T>(u, f.codes, static_cast<const T*>(f.x), f.n, f.chunk, f.sub, f.nchunks, f.R,
                       2 * f.R, f.enc_code, f.enc_len, f.chunk_words, f.chunk_zeros, f.lword_off,
-                      f.lzero_off, f.out, f.cap, f.m, local, j.nblk);
+                      f.lzero_off, static_cast<const uint32_t*>(f.rec), f.out, f.cap, f.m, local,
+                      j.nblk);
 }
 
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
                          uint32_t chunk, uint32_t sub, uint32_t radius, const uint64_t* enc_code,
-                         const uint8_t* enc_len, EncodeScratch es, uint8_t* out, uint64_t cap,
-                         Meta* m, hipStream_t st) {
+                         const uint8_t* enc_len, EncodeScratch es, uint32_t* slots, uint8_t* out,
+                         uint64_t cap, Meta* m, hipStream_t st) {
   const uint64_t nchunks = (n + chunk - 1) / chunk;
   if (nchunks == 0) return hipSuccess;
   const uint32_t nsym = 2 * radius;
   uint64_t blocks = (nchunks + kEncWaves - 1) / kEncWaves;
   if (blocks > 2048) blocks = 2048;
   dim3 grid((unsigned)blocks), block(kEncWaves * 64);
-  hipLaunchKernelGGL(k_encode_size, grid, block, 0, st, codes, n, chunk, nchunks, radius, nsym,
-                     enc_code, enc_len, es.chunk_words, es.chunk_zeros, m);
+  hipLaunchKernelGGL(k_encode_size, grid, block, 0, st, codes, n, chunk, sub, nchunks, radius,
+                     nsym, enc_code, enc_len, es.chunk_words, es.chunk_zeros, slots, out, cap, m);
   hipError_t e = launch_scan_pair(es.chunk_words, es.chunk_zeros, nchunks, es.word_off,
                                   es.zero_off, es.block_sums, &m->total_words, es.totals, st);
   if (e != hipSuccess) return e;
   if (dtype == SZ_F32)
     hipLaunchKernelGGL(k_encode_pack<float>, grid, block, 0, st, codes, (const float*)x, n, chunk,
                        sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
-                       es.chunk_zeros, es.word_off, es.zero_off, out, cap, m);
+                       es.chunk_zeros, es.word_off, es.zero_off, slots, out, cap, m);
   else
     hipLaunchKernelGGL(k_encode_pack<double>, grid, block, 0, st, codes, (const double*)x, n,
                        chunk, sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
-                       es.chunk_zeros, es.word_off, es.zero_off, out, cap, m);
+                       es.chunk_zeros, es.word_off, es.zero_off, slots, out, cap, m);
   return hipGetLastError();
 }
 
