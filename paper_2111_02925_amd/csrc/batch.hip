@@ -39,8 +39,8 @@ namespace szg {
 namespace {
 
 enum class Op : uint8_t {
-  MetaInit, Minmax, Resolve, Small, Level, Fine, FillHist, Hist, Codebook, EncSize, Scan, Rebase,
-  Pack, Tables, Results
+  MetaInit, Minmax, Resolve, Small, Level, Fine, FillHist, Hist, HistReduce, Codebook, EncSize,
+  Scan, Rebase, Pack, Tables, Results
 };
 
 struct Step {
@@ -53,6 +53,10 @@ struct Step {
 
 uint64_t up256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 uint32_t cdiv32(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+// histogram workgroups (and partial rows) of a field of n points
+uint32_t hist_blocks(uint64_t n) {
+  return std::min<uint32_t>(256, std::max<uint32_t>(1, cdiv32(n, 65536)));
+}
 
 // The tilings the first call of a plan tries for each level stride.
 const LevelTuning kTunings[] = {
@@ -187,7 +191,8 @@ int build_plan(BatchPlan& P, const std::vector<BatchItem>& items, std::string& e
   // sizes, in arena order: per field rec, codes, cmp, meta, enc tables,
   // codebook scratch; then the batch's histograms and chunk tables
   uint64_t total = 0, nch_all = 0;
-  std::vector<uint64_t> off(P.nf * 16, 0), c0s(P.nf, 0);
+  std::vector<uint64_t> off(P.nf * 16, 0), c0s(P.nf, 0), rows0(P.nf, 0);
+  uint64_t rows_all = 0;
   for (uint32_t i = 0; i < P.nf; i++) {
     const BatchItem& it = items[i];
     BField& f = P.fields[i];
@@ -225,12 +230,16 @@ int build_plan(BatchPlan& P, const std::vector<BatchItem>& items, std::string& e
     }
     c0s[i] = nch_all;
     nch_all += f.nchunks;
+    rows0[i] = rows_all;
+    rows_all += hist_blocks(n);
   }
   P.nchunks = nch_all;
   const uint64_t nsym = 2ull * items[0].R;  // one radius per batch
   P.hist_words = nsym * P.nf;
   const uint64_t off_hist = total;
   total += up256(4 * P.hist_words);
+  const uint64_t off_rows = total;
+  total += up256(4 * rows_all * hist_row_words());
   const uint64_t off_cw = total;
   total += up256(4 * (nch_all + 1));
   const uint64_t off_cz = total;
@@ -281,6 +290,7 @@ int build_plan(BatchPlan& P, const std::vector<BatchItem>& items, std::string& e
     f.cb.phase_end = reinterpret_cast<uint32_t*>(A + o[13]);
     f.cb.leaf_sym = reinterpret_cast<uint16_t*>(A + o[14]);
     f.hist = P.hist_all + (uint64_t)i * nsym;
+    f.hist_part = reinterpret_cast<uint32_t*>(A + off_rows) + rows0[i] * hist_row_words();
     f.chunk_words = P.cw_all + c0;
     f.chunk_zeros = P.cz_all + c0;
     f.word_off = P.wo_all + c0;
@@ -418,9 +428,20 @@ void build_steps(BatchPlan& P, const std::vector<BatchItem>& items, const std::v
   {
     std::vector<BJob> js;
     for (uint32_t i = 0; i < nf; i++)
-      js.push_back(field_job(i, std::min<uint32_t>(256, std::max<uint32_t>(1, cdiv32(P.fields[i].n, 65536)))));
+      js.push_back(field_job(i, hist_blocks(P.fields[i].n)));
     Step m{};
     m.op = Op::Hist;
+    add_step(P, m, js, false);
+  }
+  {
+    std::vector<BJob> js;
+    for (uint32_t i = 0; i < nf; i++) {
+      BJob j = field_job(i, hist_reduce_blocks());
+      j.flags = hist_blocks(P.fields[i].n);  // the rows to sum
+      js.push_back(j);
+    }
+    Step m{};
+    m.op = Op::HistReduce;
     add_step(P, m, js, false);
   }
   {
@@ -506,6 +527,7 @@ hipError_t run_step(BatchPlan& P, const Step& s, hipStream_t st) {
     case Op::Fine: return launch_b_fine(s.dtype, s.pred, s.waves, L, s.nwg, st);
     case Op::FillHist: return launch_fill_u32(P.hist_all, 0, P.hist_words, st);
     case Op::Hist: return launch_b_histogram(L, s.nwg, st);
+    case Op::HistReduce: return launch_b_hist_reduce(L, s.nwg, st);
     case Op::Codebook: return launch_b_codebook(L, s.nwg, st);
     case Op::EncSize: return launch_b_encode_size(L, s.nwg, st);
     case Op::Scan:

@@ -340,6 +340,7 @@ struct BField {
   void* cmp;           // the stride-2 lattice, or null
   Meta* m;
   uint32_t* hist;      // 2R bins
+  uint32_t* hist_part; // the histogram workgroups' partial rows
   uint64_t* enc_code;  // 2R
   uint8_t* enc_len;    // 2R
   uint32_t* symtab;    // 2R
@@ -416,6 +417,10 @@ hipError_t launch_b_level(int dtype, int predictor, BLaunch L, uint32_t nwg, uin
 hipError_t launch_b_fine(int dtype, int predictor, uint32_t waves, BLaunch L, uint32_t nwg,
                          hipStream_t st);
 hipError_t launch_b_histogram(BLaunch L, uint32_t nwg, hipStream_t st);
+// sums each field's partial rows (a job per field; flags = the field's rows)
+hipError_t launch_b_hist_reduce(BLaunch L, uint32_t nwg, hipStream_t st);
+uint32_t hist_reduce_blocks();  // workgroups of a field's reduction
+size_t hist_row_words();        // u32 words of one partial row
 hipError_t launch_b_codebook(BLaunch L, uint32_t nwg, hipStream_t st);
 hipError_t launch_b_encode_size(BLaunch L, uint32_t nwg, hipStream_t st);
 // field-local chunk offsets from the batch-wide scans, and each field's totals

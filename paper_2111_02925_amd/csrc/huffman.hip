@@ -23,13 +23,20 @@ namespace szg {
 // workgroup, code 0 (unpredictable) to a counter of its own, and codes
 // further out to two overflow counters.  Each workgroup writes its counts to
 // a row of partial histograms, which a second kernel sums into the
-// histogram; a workgroup whose overflow counters are not zero re-reads its
-// codes and adds those far codes with global atomics.
+// histogram.  A workgroup whose overflow counters are not zero re-reads its
+// codes and counts those far codes in a second window of kFarSlots counters
+// (kFarHalf symbols on each side of the first window, in the LDS of the
+// per-lane counters), stored in the far part of its row and flagged; codes
+// beyond it go to the histogram with global atomics.
 
 constexpr uint32_t kHistThreads = 256;
 constexpr uint32_t kHistLane = 32;          // per-lane bins around R
 constexpr uint32_t kHistShared = 4096;      // workgroup bins around R
 constexpr uint32_t kHistSlots = kHistShared + 3;  // below | window | above | code 0
+constexpr uint32_t kFarHalf = 4096;         // far-window symbols on each side
+constexpr uint32_t kFarSlots = 2 * kFarHalf;
+static_assert(kFarSlots <= kHistLane * kHistThreads, "the far window reuses the per-lane counters");
+constexpr uint32_t kHistRow = kHistSlots + kFarSlots + 1;  // window | far window | far flag
 constexpr uint32_t kHistVecs = 8;           // 8-code vectors per lane per tile
 constexpr uint32_t kHistTile = kHistThreads * kHistVecs;  // vectors per tile
 constexpr uint32_t kHistMaxBlocks = 768;
@@ -53,9 +60,36 @@ __device__ __forceinline__ uint32_t hist_slot(uint32_t c, uint32_t slo) {
   return c == 0 ? kHistShared + 2 : (uint32_t)v;
 }
 
-// part != nullptr: the workgroup's counts go to its row of partial
-// histograms (bid = its row); otherwise they are added to hist with global
-// atomics (the batched launch, whose workgroups span many fields).
+// The far window: kFarHalf symbols below the first window, then kFarHalf
+// above it.  Returns the slot of a far code, or kFarSlots beyond it.
+__host__ __device__ __forceinline__ uint32_t far_slot(uint32_t c, uint32_t slo) {
+  if (c < slo) return slo - c <= kFarHalf ? kFarHalf - (slo - c) : kFarSlots;
+  const uint32_t d = c - (slo + kHistShared);
+  return d < kFarHalf ? kFarHalf + d : kFarSlots;
+}
+// The symbol of a partial-row column, or 0xFFFFFFFF for none.
+__host__ __device__ __forceinline__ uint32_t column_symbol(uint32_t col, uint32_t R) {
+  const HistWindow hw = hist_window(R);
+  if (col == kHistShared + 2) return 0;
+  if (col >= 1 && col <= kHistShared) {
+    // (symbol 0 is counted in its own column, never in the window)
+    const uint32_t s = hw.slo + col - 1;
+    return s >= 1 && s < 2 * R ? s : 0xFFFFFFFFu;
+  }
+  if (col < kHistSlots || col >= kHistSlots + kFarSlots) return 0xFFFFFFFFu;
+  const uint32_t f = col - kHistSlots;
+  uint32_t s;
+  if (f < kFarHalf) {
+    if (hw.slo < kFarHalf - f) return 0xFFFFFFFFu;
+    s = hw.slo - (kFarHalf - f);
+  } else {
+    s = hw.slo + kHistShared + (f - kFarHalf);
+  }
+  return s >= 1 && s < 2 * R ? s : 0xFFFFFFFFu;
+}
+
+// The workgroup's counts go to its row of partial histograms, part + bid *
+// kHistRow; (bid, nblk): this workgroup among the nblk that share the codes.
 __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ codes, uint64_t n,
                                                uint32_t R, uint32_t* __restrict__ part,
                                                uint32_t* hist, Meta* m, uint32_t bid,
@@ -107,42 +141,42 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ code
     if (sum) atomicAdd(&shared_cnt[hist_slot(hw.plo + b, hw.slo)], sum);
   }
   __syncthreads();
-  if (part) {
-    uint32_t* row = part + (uint64_t)bid * kHistSlots;
-    for (uint32_t i = t; i < kHistSlots; i += kHistThreads) row[i] = shared_cnt[i];
-  } else {
-    // the window's slots (and code 0) straight into the histogram
-    for (uint32_t i = t; i < kHistSlots; i += kHistThreads) {
-      const uint32_t c = shared_cnt[i];
-      uint32_t sym = 0xFFFFFFFFu;
-      if (i == kHistShared + 2)
-        sym = 0;
-      else if (i >= 1 && i <= kHistShared && hw.slo + i - 1 < 2 * R)
-        sym = hw.slo + i - 1;
-      if (c && sym != 0xFFFFFFFFu) atomicAdd(&hist[sym], c);
+  uint32_t* row = part + (uint64_t)bid * kHistRow;
+  for (uint32_t i = t; i < kHistSlots; i += kHistThreads) row[i] = shared_cnt[i];
+  const bool far_codes = (shared_cnt[0] | shared_cnt[kHistShared + 1]) != 0;
+  if (t == 0) row[kHistRow - 1] = far_codes ? 1u : 0u;
+  if (!far_codes) return;
+  // far codes: re-read this workgroup's codes into the far window (the
+  // per-lane counters, summed above, are free again)
+  if (t == 0) atomicOr(&m->hist_far, 1u);
+  __syncthreads();
+  for (uint32_t i = t; i < kFarSlots; i += kHistThreads) lane_cnt[i] = 0;
+  __syncthreads();
+  auto far = [&](uint32_t c) {
+    const uint32_t sl = hist_slot(c, hw.slo);
+    if (sl == 0 || sl == kHistShared + 1) {
+      const uint32_t f = far_slot(c, hw.slo);
+      if (f < kFarSlots)
+        atomicAdd(&lane_cnt[f], 1u);
+      else
+        atomicAdd(&hist[c], 1u);
     }
-  }
-  // far codes (rare): re-read this workgroup's codes, global atomics
-  if (shared_cnt[0] | shared_cnt[kHistShared + 1]) {
-    if (t == 0) atomicOr(&m->hist_far, 1u);
-    auto far = [&](uint32_t c) {
-      const uint32_t sl = hist_slot(c, hw.slo);
-      if (sl == 0 || sl == kHistShared + 1) atomicAdd(&hist[c], 1u);
-    };
-    for (uint64_t tile = bid; tile < ntiles; tile += nblk)
-      for (uint32_t j = 0; j < kHistVecs; j++) {
-        const uint64_t i = tile * kHistTile + t + (uint64_t)j * kHistThreads;
-        if (i < nvec) {
-          const uint4 q = v4[i];
-          const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-          for (int h = 0; h < 4; h++) {
-            far(w[h] & 0xFFFFu);
-            far(w[h] >> 16);
-          }
+  };
+  for (uint64_t tile = bid; tile < ntiles; tile += nblk)
+    for (uint32_t j = 0; j < kHistVecs; j++) {
+      const uint64_t i = tile * kHistTile + t + (uint64_t)j * kHistThreads;
+      if (i < nvec) {
+        const uint4 q = v4[i];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        for (int h = 0; h < 4; h++) {
+          far(w[h] & 0xFFFFu);
+          far(w[h] >> 16);
         }
       }
-    if (bid == 0 && t < (n & 7)) far(codes[nvec * 8 + t]);
-  }
+    }
+  if (bid == 0 && t < (n & 7)) far(codes[nvec * 8 + t]);
+  __syncthreads();
+  for (uint32_t i = t; i < kFarSlots; i += kHistThreads) row[kHistSlots + i] = lane_cnt[i];
 }
 
 __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __restrict__ codes,
@@ -152,14 +186,13 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const uint16_t* __re
   histogram_body(codes, n, R, part, hist, m, blockIdx.x, gridDim.x);
 }
 
-// every field of a batch: each job is a field's codes, its counts added to
-// the field's (zeroed) histogram
+// every field of a batch: each job is a field's codes, into the field's rows
 __global__ __launch_bounds__(kHistThreads) void k_b_histogram(BLaunch L) {
   BJob j;
   uint32_t local;
   if (!batch_job(L, j, local)) return;
   const BField& f = L.f[j.field];
-  histogram_body(f.codes, f.n, f.R, nullptr, f.hist, f.m, local, j.nblk);
+  histogram_body(f.codes, f.n, f.R, f.hist_part, f.hist, f.m, local, j.nblk);
 }
 
 hipError_t launch_b_histogram(BLaunch L, uint32_t nwg, hipStream_t st) {
@@ -168,36 +201,74 @@ hipError_t launch_b_histogram(BLaunch L, uint32_t nwg, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Sums the partial rows: a workgroup takes 64 slots of 32 rows (a wave per
-// 8 rows, lanes on consecutive slots) and adds its column sums to the
-// histogram.
+// Sums the partial rows: a workgroup takes 64 columns of 32 rows (a wave per
+// 8 rows, lanes on consecutive columns) and adds its column sums to the
+// histogram; far columns count only the rows flagged for them.
 constexpr uint32_t kHistReduceRows = 32;
 
 __global__ __launch_bounds__(256) void k_hist_reduce(const uint32_t* __restrict__ part,
                                                      uint32_t rows, uint32_t R, uint32_t* hist) {
   __shared__ uint32_t colsum[4][64];
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t slot = blockIdx.x * 64 + lane;
+  const uint32_t col = blockIdx.x * 64 + lane;
+  const bool far_col = col >= kHistSlots;
   const uint32_t r0 = blockIdx.y * kHistReduceRows + wv * (kHistReduceRows / 4);
   uint32_t sum = 0;
-  if (slot < kHistSlots) {
 #pragma unroll
-    for (uint32_t j = 0; j < kHistReduceRows / 4; j++)
-      if (r0 + j < rows) sum += part[(uint64_t)(r0 + j) * kHistSlots + slot];
+  for (uint32_t j = 0; j < kHistReduceRows / 4; j++) {
+    const uint32_t r = r0 + j;
+    if (r < rows && (!far_col || part[(uint64_t)r * kHistRow + kHistRow - 1]) && col < kHistRow - 1)
+      sum += part[(uint64_t)r * kHistRow + col];
   }
   colsum[wv][lane] = sum;
   __syncthreads();
-  if (wv == 0 && slot < kHistSlots) {
+  if (wv == 0) {
     const uint32_t tot = colsum[0][lane] + colsum[1][lane] + colsum[2][lane] + colsum[3][lane];
-    const HistWindow hw = hist_window(R);
-    uint32_t sym = 0xFFFFFFFFu;
-    if (slot == kHistShared + 2)
-      sym = 0;
-    else if (slot >= 1 && slot <= kHistShared && hw.slo + slot - 1 < 2 * R)
-      sym = hw.slo + slot - 1;
+    const uint32_t sym = col < kHistRow - 1 ? column_symbol(col, R) : 0xFFFFFFFFu;
     if (tot && sym != 0xFFFFFFFFu) atomicAdd(&hist[sym], tot);
   }
 }
+
+// The batch's rows: a workgroup per (field, 64 columns) sums all of the
+// field's rows and stores the window's sums (no other writer touches those
+// symbols) or adds the far window's nonzero sums.
+__global__ __launch_bounds__(256) void k_b_hist_reduce(BLaunch L) {
+  __shared__ uint32_t colsum[4][64];
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t col = local * 64 + lane;
+  const bool far_col = col >= kHistSlots;
+  const uint32_t rows = j.flags;  // the field's histogram workgroups
+  uint32_t sum = 0;
+  if (col < kHistRow - 1)
+    for (uint32_t r = wv; r < rows; r += 4)
+      if (!far_col || f.hist_part[(uint64_t)r * kHistRow + kHistRow - 1])
+        sum += f.hist_part[(uint64_t)r * kHistRow + col];
+  colsum[wv][lane] = sum;
+  __syncthreads();
+  if (wv == 0) {
+    const uint32_t tot = colsum[0][lane] + colsum[1][lane] + colsum[2][lane] + colsum[3][lane];
+    const uint32_t sym = col < kHistRow - 1 ? column_symbol(col, f.R) : 0xFFFFFFFFu;
+    if (sym != 0xFFFFFFFFu) {
+      if (!far_col)
+        f.hist[sym] = tot;
+      else if (tot)
+        atomicAdd(&f.hist[sym], tot);
+    }
+  }
+}
+
+hipError_t launch_b_hist_reduce(BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_hist_reduce, dim3(nwg), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+uint32_t hist_reduce_blocks() { return (kHistRow - 1 + 63) / 64; }
+size_t hist_row_words() { return kHistRow; }
 
 hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, uint32_t* part,
                             uint32_t* hist, Meta* m, hipStream_t st) {
@@ -209,12 +280,12 @@ hipError_t launch_histogram(const uint16_t* codes, uint64_t n, uint32_t radius, 
   // stays far below 2^32 for any field of up to 2^32 - 1 points
   hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(kHistThreads), 0, st, codes, n, radius,
                      part, hist, m);
-  dim3 rgrid((kHistSlots + 63) / 64, (blocks + kHistReduceRows - 1) / kHistReduceRows);
+  dim3 rgrid(hist_reduce_blocks(), (blocks + kHistReduceRows - 1) / kHistReduceRows);
   hipLaunchKernelGGL(k_hist_reduce, rgrid, dim3(256), 0, st, part, blocks, radius, hist);
   return hipGetLastError();
 }
 
-size_t histogram_scratch_bytes() { return sizeof(uint32_t) * (size_t)kHistMaxBlocks * kHistSlots; }
+size_t histogram_scratch_bytes() { return sizeof(uint32_t) * (size_t)kHistMaxBlocks * kHistRow; }
 
 // --------------------------------------------------------------- codebook
 // Huffman code lengths by the two-queue greedy merge (leaves sorted by
@@ -251,24 +322,70 @@ __device__ __forceinline__ uint32_t upper_bound_w(const uint32_t* w, uint32_t lo
   return lo;
 }
 
-// Compact the symbols with nonzero `val` in ascending symbol order; returns K.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t x = __shfl_xor(v, o, 64);
+    v = x > v ? x : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t x = __shfl_xor(v, o, 64);
+    v = x < v ? x : v;
+  }
+  return v;
+}
+
+// Compact the symbols with nonzero count (hist) or length (lens) in ascending
+// symbol order; returns K.  Each wave takes a contiguous segment of the
+// symbols, its lanes consecutive symbols (coalesced loads, four steps of 64
+// in flight); a symbol's place is its wave's base (an exclusive scan of the
+// waves' counts) plus the nonzero symbols before it in its wave, counted by
+// ballots.
 __device__ uint32_t compact_used(const uint32_t* hist, const uint8_t* lens, uint32_t nsym,
                                  uint64_t* keys, uint32_t* symtab, uint32_t* sh16) {
-  const uint32_t T = blockDim.x, t = threadIdx.x;
-  const uint32_t seg = (nsym + T - 1) / T;
-  const uint32_t beg = t * seg < nsym ? t * seg : nsym;
+  const uint32_t T = blockDim.x, t = threadIdx.x, lane = t & 63, nw = T >> 6;
+  const uint32_t seg = ((nsym + nw - 1) / nw + 255) & ~255u;
+  const uint32_t beg = (t >> 6) * seg < nsym ? (t >> 6) * seg : nsym;
   const uint32_t end = beg + seg < nsym ? beg + seg : nsym;
+  const uint64_t below = (1ull << lane) - 1;
+  auto load4 = [&](uint32_t b, uint32_t (&v)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t s = b + 64 * k + lane;
+      v[k] = s < end ? (hist ? hist[s] : (uint32_t)lens[s]) : 0u;
+    }
+  };
   uint32_t c = 0;
-  for (uint32_t s = beg; s < end; s++) c += hist ? (hist[s] != 0) : (lens[s] != 0);
+  for (uint32_t b = beg; b < end; b += 256) {
+    uint32_t v[4];
+    load4(b, v);
+#pragma unroll
+    for (int k = 0; k < 4; k++) c += (uint32_t)__popcll(__ballot(v[k] != 0));
+  }
   uint32_t K;
-  uint32_t pos = block_excl_scan_u32(c, sh16, &K);
-  for (uint32_t s = beg; s < end; s++) {
-    if (hist) {
-      if (hist[s]) keys[pos++] = ((uint64_t)hist[s] << 32) | s;
-    } else if (lens[s]) {
-      keys[pos] = ((uint64_t)lens[s] << 16) | s;
-      if (symtab) symtab[pos] = s | ((uint32_t)lens[s] << 16);
-      pos++;
+  const uint32_t ex = block_excl_scan_u32(lane == 0 ? c : 0u, sh16, &K);
+  uint32_t pos = __shfl(ex, 0, 64);  // the waves before this one
+  for (uint32_t b = beg; b < end; b += 256) {
+    uint32_t v[4];
+    load4(b, v);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint64_t bal = __ballot(v[k] != 0);
+      if (v[k]) {
+        const uint32_t p = pos + (uint32_t)__popcll(bal & below);
+        const uint32_t s = b + 64 * k + lane;
+        if (hist) {
+          keys[p] = ((uint64_t)v[k] << 32) | s;
+        } else {
+          keys[p] = ((uint64_t)v[k] << 16) | s;
+          if (symtab) symtab[p] = s | (v[k] << 16);
+        }
+      }
+      pos += (uint32_t)__popcll(bal);
     }
   }
   __syncthreads();
@@ -317,7 +434,15 @@ __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym
     }
     return;
   }
-  for (uint32_t i = t; i < K; i += T) atomicMax(&sh_maxw, (uint32_t)(s.keys_a[i] >> 32));
+  {  // the largest count: a wave reduction, then one LDS atomic per wave
+    uint32_t mw = 0;
+    for (uint32_t i = t; i < K; i += T) {
+      const uint32_t c = (uint32_t)(s.keys_a[i] >> 32);
+      mw = c > mw ? c : mw;
+    }
+    mw = wave_max_u32(mw);
+    if ((t & 63) == 0) atomicMax(&sh_maxw, mw);
+  }
   __syncthreads();
   int wbits = 32 - __clz(sh_maxw);
   int hi_bit = 32 + ((wbits + 3) & ~3);
@@ -411,21 +536,31 @@ __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym
       if (i != root) s.depth[i] = s.depth[s.parent[i]] + 1;
     __syncthreads();
   }
-  for (uint32_t i = t; i < K; i += T) {
-    uint32_t d = s.depth[s.parent[i]] + 1;
-    if (d > kMaxCodeLen) {
-      atomicOr(&m->status, kStatusCodeTooLong);
-      d = kMaxCodeLen;
+  {
+    uint32_t ml = 0;
+    for (uint32_t i = t; i < K; i += T) {
+      uint32_t d = s.depth[s.parent[i]] + 1;
+      if (d > kMaxCodeLen) {
+        atomicOr(&m->status, kStatusCodeTooLong);
+        d = kMaxCodeLen;
+      }
+      enc_len[s.leaf_sym[i]] = (uint8_t)d;
+      ml = d > ml ? d : ml;
     }
-    enc_len[s.leaf_sym[i]] = (uint8_t)d;
-    atomicMax(&sh_maxlen, d);
+    ml = wave_max_u32(ml);
+    if ((t & 63) == 0) atomicMax(&sh_maxlen, ml);
   }
   __syncthreads();
 
   // 5. canonical codes: (length, symbol) order
   compact_used(nullptr, enc_len, nsym, s.keys_a, symtab, sh16);
   uint64_t* bylen = block_radix_sort(s.keys_a, s.keys_b, K, 16, 24, cnt, sh16);
-  for (uint32_t i = t; i < K; i += T) atomicAdd(&bl_count[(bylen[i] >> 16) & 0xFF], 1u);
+  // lengths per code length from the boundaries of the sorted runs
+  for (uint32_t i = t; i < K; i += T) {
+    const uint32_t l = (uint32_t)(bylen[i] >> 16) & 0xFF;
+    if (i + 1 == K || ((uint32_t)(bylen[i + 1] >> 16) & 0xFF) != l) atomicAdd(&bl_count[l], i + 1);
+    if (i > 0 && ((uint32_t)(bylen[i - 1] >> 16) & 0xFF) != l) atomicSub(&bl_count[l], i);
+  }
   __syncthreads();
   if (t == 0) {
     uint64_t code = 0;
@@ -440,14 +575,32 @@ __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym
     m->max_len = sh_maxlen;
   }
   __syncthreads();
+  __shared__ uint32_t sh_lo, sh_hi;
+  if (t == 0) {
+    sh_lo = 0xFFFFFFFFu;
+    sh_hi = 0;
+  }
+  __syncthreads();
+  uint32_t lo = 0xFFFFFFFFu, hi = 0;
   for (uint32_t j = t; j < K; j += T) {
     uint64_t key = bylen[j];
     uint32_t l = (uint32_t)(key >> 16) & 0xFF, sym = (uint32_t)(key & 0xFFFF);
     enc_code[sym] = first_code[l] + (j - len_offset[l]);
     if (sym) {
-      atomicMin(&m->sym_lo, sym);
-      atomicMax(&m->sym_hi, sym);
+      lo = sym < lo ? sym : lo;
+      hi = sym > hi ? sym : hi;
     }
+  }
+  lo = wave_min_u32(lo);
+  hi = wave_max_u32(hi);
+  if ((t & 63) == 0) {
+    atomicMin(&sh_lo, lo);
+    atomicMax(&sh_hi, hi);
+  }
+  __syncthreads();
+  if (t == 0 && sh_lo != 0xFFFFFFFFu) {
+    atomicMin(&m->sym_lo, sh_lo);
+    atomicMax(&m->sym_hi, sh_hi);
   }
 }
 
@@ -495,15 +648,6 @@ __device__ __forceinline__ uint32_t wave_count_le(const uint32_t* w, uint32_t lo
   i = b + lane;
   const uint32_t c2 = (uint32_t)__popcll(__ballot(lane < step && i < hi && (uint64_t)w[i] <= v));
   return c1 * step + c2;
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t x = __shfl_xor(v, o, 64);
-    v = x > v ? x : v;
-  }
-  return v;
 }
 
 // Leaves by rank: a bitonic network over P = 2^k >= K keys by the whole
