@@ -40,7 +40,7 @@ namespace {
 
 enum class Op : uint8_t {
   MetaInit, Minmax, Resolve, Small, Level, Fine, FillHist, Hist, HistReduce, Codebook, EncSize,
-  Scan, Rebase, Pack, Tables, Results
+  Scan, Rebase, Pack, Copy, Tables, Results
 };
 
 struct Step {
@@ -472,13 +472,18 @@ void build_steps(BatchPlan& P, const std::vector<BatchItem>& items, const std::v
     add_step(P, m, js, false);
   }
   for (int dt : {SZ_F32, SZ_F64}) {
-    std::vector<BJob> js;
+    std::vector<BJob> js, jc;
     for (uint32_t i = 0; i < nf; i++)
-      if (P.fields[i].dtype == dt) js.push_back(field_job(i, enc_blocks(i)));
+      if (P.fields[i].dtype == dt) {
+        js.push_back(field_job(i, encode_pack_blocks(P.fields[i].nchunks)));
+        jc.push_back(field_job(i, encode_copy_blocks(P.fields[i].nchunks)));
+      }
     Step m{};
     m.op = Op::Pack;
     m.dtype = dt;
     add_step(P, m, js, false);
+    m.op = Op::Copy;
+    add_step(P, m, jc, false);
   }
   {
     std::vector<BJob> js;
@@ -535,6 +540,7 @@ hipError_t run_step(BatchPlan& P, const Step& s, hipStream_t st) {
                               P.totals, P.totals + 1, st);
     case Op::Rebase: return launch_b_rebase(L, s.nwg, st);
     case Op::Pack: return launch_b_encode_pack(s.dtype, L, s.nwg, st);
+    case Op::Copy: return launch_b_encode_copy(s.dtype, L, s.nwg, st);
     case Op::Tables: return launch_b_write_tables(L, s.nwg, st);
     case Op::Results: return launch_b_results(P.d_fields, P.nf, P.d_res, st);
   }

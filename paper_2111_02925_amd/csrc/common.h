@@ -426,6 +426,10 @@ hipError_t launch_b_encode_size(BLaunch L, uint32_t nwg, hipStream_t st);
 // field-local chunk offsets from the batch-wide scans, and each field's totals
 hipError_t launch_b_rebase(BLaunch L, uint32_t nwg, hipStream_t st);
 hipError_t launch_b_encode_pack(int dtype, BLaunch L, uint32_t nwg, hipStream_t st);
+// the lane-parallel path's second pass (the slots' copy), a wave per chunk
+hipError_t launch_b_encode_copy(int dtype, BLaunch L, uint32_t nwg, hipStream_t st);
+uint32_t encode_copy_blocks(uint64_t nchunks);
+uint32_t encode_pack_blocks(uint64_t nchunks);  // the second pass of codes over 32 bits
 hipError_t launch_b_write_tables(BLaunch L, uint32_t nwg, hipStream_t st);
 // each field's (stream bytes, status bits) into res[2 i], res[2 i + 1]
 hipError_t launch_b_results(const BField* f, uint32_t nf, uint64_t* res, hipStream_t st);

@@ -23,7 +23,7 @@
 
 namespace szg {
 
-constexpr uint32_t kEncWindow = 8192;  // LDS codebook entries
+constexpr uint32_t kEncWindow = 7168;  // LDS codebook entries
 constexpr int kEncWaves = 4;
 constexpr int kSeg = 64;  // symbols of a lane's run held in registers at once
 
@@ -43,6 +43,7 @@ struct EncWindow {
   bool lds_only;     // every coded symbol other than 0 is in the window, codes <= 32 bits
   uint64_t code0;    // codeword of symbol 0
   uint32_t len0;
+  uint32_t max_len;
 };
 
 __device__ __forceinline__ EncWindow enc_window(const Meta* m, uint32_t R,
@@ -56,6 +57,7 @@ __device__ __forceinline__ EncWindow enc_window(const Meta* m, uint32_t R,
   w.span = w.lds_only ? (none ? 0u : shi - slo + 1) : kEncWindow;
   w.code0 = enc_code[0];
   w.len0 = enc_len[0];
+  w.max_len = m->max_len;
   return w;
 }
 
@@ -154,14 +156,22 @@ __device__ __forceinline__ LaneRun lane_run(uint64_t c, uint32_t chunk, uint64_t
 // make every prefetch of the next step's codes wait for them to complete.
 
 constexpr uint32_t kStep = 512;                // symbols per wave step, 8 per lane
-constexpr uint32_t kBufWords = 1024;           // bit buffer words per wave
+constexpr uint32_t kBufWords = 768;            // bit buffer words per wave (a step needs at most 512)
 constexpr uint32_t kBufAlloc = kBufWords + 3;  // plus the words a last step may touch
 constexpr uint32_t kFastWindow = 3064;         // LDS codebook entries of the lane-parallel path
+// with codes of at most 27 bits an entry takes 32 bits (code | len << 27), so
+// the same LDS holds twice the window
+constexpr uint32_t kFastWindow32 = 2 * (kFastWindow + 1) - 1;
+constexpr uint32_t kLen32 = 27;
 
 struct FastLds {
-  // code | len << 32 by symbol - lo; the last entry is symbol 0's, with bit 40
-  // set so that summing entries >> 40 counts unpredictable values
-  uint64_t ent[kFastWindow + 1];
+  union {
+    // code | len << 32 by symbol - lo; the last entry is symbol 0's, with bit
+    // 40 set so that summing entries >> 40 counts unpredictable values
+    uint64_t ent[kFastWindow + 1];
+    // code | len << 27 by symbol - lo; the last entry is symbol 0's
+    uint32_t ent32[kFastWindow32 + 1];
+  };
   uint32_t buf[kEncWaves][kBufAlloc];
 };
 union EncLds {
@@ -169,17 +179,28 @@ union EncLds {
   FastLds f;
 };
 
-__device__ __forceinline__ bool fast_path(const EncWindow& w) {
-  return w.lds_only && w.span <= kFastWindow;
+// 0: the per-lane-run path; 1: the lane-parallel path with 64-bit entries;
+// 2: with 32-bit entries (codes of at most kLen32 bits)
+__device__ __forceinline__ int fast_path(const EncWindow& w) {
+  if (!w.lds_only) return 0;
+  if (w.max_len <= kLen32 && w.span <= kFastWindow32) return 2;
+  return w.span <= kFastWindow ? 1 : 0;
 }
 
+template <bool E32>
 __device__ __forceinline__ void load_fast(FastLds& f, const EncWindow& w,
                                           const uint64_t* __restrict__ enc_code,
                                           const uint8_t* __restrict__ enc_len) {
-  for (uint32_t i = threadIdx.x; i < w.span; i += blockDim.x)
-    f.ent[i] = ((uint64_t)enc_len[w.lo + i] << 32) | (uint32_t)enc_code[w.lo + i];
-  if (threadIdx.x == 0)
-    f.ent[kFastWindow] = (1ull << 40) | ((uint64_t)w.len0 << 32) | (uint32_t)w.code0;
+  if (E32) {
+    for (uint32_t i = threadIdx.x; i < w.span; i += blockDim.x)
+      f.ent32[i] = ((uint32_t)enc_len[w.lo + i] << kLen32) | (uint32_t)enc_code[w.lo + i];
+    if (threadIdx.x == 0) f.ent32[kFastWindow32] = (w.len0 << kLen32) | (uint32_t)w.code0;
+  } else {
+    for (uint32_t i = threadIdx.x; i < w.span; i += blockDim.x)
+      f.ent[i] = ((uint64_t)enc_len[w.lo + i] << 32) | (uint32_t)enc_code[w.lo + i];
+    if (threadIdx.x == 0)
+      f.ent[kFastWindow] = (1ull << 40) | ((uint64_t)w.len0 << 32) | (uint32_t)w.code0;
+  }
   for (uint32_t i = threadIdx.x; i < kEncWaves * kBufAlloc; i += blockDim.x)
     (&f.buf[0][0])[i] = 0;
 }
@@ -196,24 +217,34 @@ __device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ codes, uint6
 
 // Table entries of the 8 symbols; symbols at or past nv get an empty entry.
 struct Sym8 {
-  uint32_t code[8], len[8], zeros, zmask;  // zmask bit j: symbol j is 0
+  uint32_t code[8], len[8], zeros;
 };
+template <bool E32>
 __device__ __forceinline__ Sym8 lookup8(const FastLds& f, uint32_t lo, uint4 v, uint32_t nv) {
   Sym8 r;
   r.zeros = 0;
-  r.zmask = 0;
   const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int j = 0; j < 8; j++) {
     const uint32_t s = (wd[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-    // (clamped: symbols past the field's end may be anything)
-    const uint32_t k = s - lo < kFastWindow ? s - lo : kFastWindow;
-    uint64_t e = f.ent[s ? k : kFastWindow];
-    e = (uint32_t)j < nv ? e : 0ull;
-    r.code[j] = (uint32_t)e;
-    r.len[j] = (uint32_t)(e >> 32) & 0xFFu;
-    r.zeros += (uint32_t)(e >> 40);
-    r.zmask |= (uint32_t)(e >> 40) << j;
+    if (E32) {
+      // (clamped: symbols past the field's end may be anything; symbols
+      // below lo wrap to large offsets)
+      const uint32_t k = min(s - lo, kFastWindow32);
+      uint32_t e = f.ent32[s ? k : kFastWindow32];
+      const bool in = (uint32_t)j < nv;
+      e = in ? e : 0u;
+      r.code[j] = e & ((1u << kLen32) - 1u);
+      r.len[j] = e >> kLen32;
+      r.zeros += (in && s == 0) ? 1u : 0u;
+    } else {
+      const uint32_t k = s - lo < kFastWindow ? s - lo : kFastWindow;
+      uint64_t e = f.ent[s ? k : kFastWindow];
+      e = (uint32_t)j < nv ? e : 0ull;
+      r.code[j] = (uint32_t)e;
+      r.len[j] = (uint32_t)(e >> 32) & 0xFFu;
+      r.zeros += (uint32_t)(e >> 40);
+    }
   }
   return r;
 }
@@ -230,6 +261,7 @@ __device__ __forceinline__ void wave_step() { asm volatile("" ::: "memory"); }
 // its place in the bitstream and scatters the unpredictable values of the
 // chunks that have some (ranked by ballots over the chunk's codes).
 
+template <bool E32>
 __device__ __forceinline__ void pack_fast_slots(
     const uint16_t* __restrict__ codes, uint64_t n, uint32_t chunk, uint32_t sub,
     uint64_t nchunks, FastLds& f, uint32_t lo, uint32_t* chunk_words, uint32_t* chunk_zeros,
@@ -253,7 +285,7 @@ __device__ __forceinline__ void pack_fast_slots(
       nxt = load8(codes, i0 + kStep, last8);
       const uint32_t off = (uint32_t)(i0 - cbeg);
       const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
-      const Sym8 r = lookup8(f, lo, cur, nv);
+      const Sym8 r = lookup8<E32>(f, lo, cur, nv);
       uint32_t pre[8], t = 0;
       uint64_t acc = 0;
 #pragma unroll
@@ -332,6 +364,7 @@ __device__ __forceinline__ void copy_slots(
     uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t wstride = (uint64_t)nblk * kEncWaves;
+  const uint64_t last8 = (n - 1) & ~7ull;
   for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
        c += wstride) {
     const uint64_t cbeg = c * chunk, cend = cbeg + chunk < n ? cbeg + chunk : n;
@@ -348,17 +381,33 @@ __device__ __forceinline__ void copy_slots(
     }
     for (; k < nw; k += 64) guarded_store_u32(out, cap, dst + 4 * (uint64_t)k, src[k]);
     if (chunk_zeros[c]) {  // unpredictable values, verbatim, flat order
+      // 8 codes a lane per step; a lane's code-0 symbols are ranked by a
+      // wave scan of the lanes' counts
       uint64_t rk = zero_off[c];
-      for (uint64_t i0 = cbeg; i0 < cend; i0 += 64) {
-        const uint64_t i = i0 + lane;
-        const bool z = i < cend && codes[i] == 0;
-        const uint64_t bal = __ballot(z);
-        if (z) {
-          const uint64_t off =
-              l.off_unpred + (rk + (uint64_t)__popcll(bal & ((1ull << lane) - 1))) * sizeof(T);
-          if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[i];
+      const uint32_t clen = (uint32_t)(cend - cbeg);
+      for (uint64_t g = cbeg; g < cend; g += kStep) {
+        const uint64_t i0 = g + 8 * lane;
+        const uint4 q = load8(codes, i0, last8);
+        const uint32_t off = (uint32_t)(i0 - cbeg);
+        const uint32_t nv = off < clen ? (clen - off < 8 ? clen - off : 8u) : 0u;
+        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+        uint32_t zm = 0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const uint32_t sym = (wd[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+          zm |= (sym == 0 && (uint32_t)j < nv) ? 1u << j : 0u;
         }
-        rk += (uint64_t)__popcll(bal);
+        const uint32_t cnt = (uint32_t)__popc(zm);
+        const uint32_t incl = wave_incl_scan_dpp(cnt);
+        const uint32_t tot = __builtin_amdgcn_readlane(incl, 63);
+        uint64_t r = rk + (incl - cnt);
+        for (int j = 0; j < 8; j++)
+          if ((zm >> j) & 1u) {
+            const uint64_t o = l.off_unpred + r * sizeof(T);
+            if (o + sizeof(T) <= cap) *reinterpret_cast<T*>(out + o) = x[i0 + j];
+            r++;
+          }
+        rk += tot;
       }
     }
   }
@@ -404,6 +453,15 @@ __device__ __forceinline__ void size_chunks(const uint16_t* __restrict__ codes, 
   }
 }
 
+template <typename T, bool LDS_ONLY, bool SLOTS>
+__device__ __forceinline__ void pack_chunks(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint32_t sub, uint64_t nchunks, const EncTables& t, const EncWindow& w,
+    const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
+    uint32_t* chunk_words, uint32_t* chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, uint32_t* slots, const Layout& l, uint8_t* out,
+    uint64_t cap, uint32_t bid, uint32_t nblk);
+
 // The first pass: the chunks' sizes, and on the lane-parallel path their
 // bits packed into the slots (with their chunk-table and sub-chunk entries).
 __device__ __forceinline__ void encode_size_body(
@@ -414,15 +472,37 @@ __device__ __forceinline__ void encode_size_body(
     uint32_t nblk) {
   EncTables& t = u.t;
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
-  if (fast_path(w)) {
-    load_fast(u.f, w, enc_code, enc_len);
-    __syncthreads();
+  if (const int fp = fast_path(w)) {
     // (the chunk-table and sub-chunk sections do not depend on the totals)
     const Layout l = stream_layout(m->nsym_used, nchunks, sub, 0, 4, 0);
-    pack_fast_slots(codes, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros, slots, l,
-                    out, cap, bid, nblk);
+    if (fp == 2) {
+      load_fast<true>(u.f, w, enc_code, enc_len);
+      __syncthreads();
+      pack_fast_slots<true>(codes, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros,
+                            slots, l, out, cap, bid, nblk);
+    } else {
+      load_fast<false>(u.f, w, enc_code, enc_len);
+      __syncthreads();
+      pack_fast_slots<false>(codes, n, chunk, sub, nchunks, u.f, w.lo, chunk_words, chunk_zeros,
+                             slots, l, out, cap, bid, nblk);
+    }
     return;
   }
+  if (w.max_len <= 32) {  // the per-lane-run path, into the slots
+    load_tables(t, w, nsym, enc_code, enc_len, true);
+    __syncthreads();
+    const Layout l = stream_layout(m->nsym_used, nchunks, sub, 0, 4, 0);
+    if (w.lds_only)
+      pack_chunks<float, true, true>(codes, nullptr, n, chunk, sub, nchunks, t, w, enc_code,
+                                     enc_len, chunk_words, chunk_zeros, nullptr, nullptr, slots, l,
+                                     out, cap, bid, nblk);
+    else
+      pack_chunks<float, false, true>(codes, nullptr, n, chunk, sub, nchunks, t, w, enc_code,
+                                      enc_len, chunk_words, chunk_zeros, nullptr, nullptr, slots, l,
+                                      out, cap, bid, nblk);
+    return;
+  }
+  // codes over 32 bits: the sizes here, the packing in the second pass
   load_tables(t, w, nsym, enc_code, enc_len, !w.lds_only);
   __syncthreads();
   if (w.lds_only)
@@ -457,14 +537,18 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_size(BLaunch L) {
 
 // ------------------------------------------------------------------ packing
 
-template <typename T, bool LDS_ONLY>
+// SLOTS (codes of at most 32 bits): the chunk is packed into its slot (as on
+// the lane-parallel path), its sizes and table entries written, and its
+// unpredictable values left to the copy pass; otherwise packed into place
+// from the scans' offsets.
+template <typename T, bool LDS_ONLY, bool SLOTS>
 __device__ __forceinline__ void pack_chunks(
     const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
     uint32_t sub, uint64_t nchunks, const EncTables& t, const EncWindow& w,
     const uint64_t* __restrict__ enc_code, const uint8_t* __restrict__ enc_len,
-    const uint32_t* __restrict__ chunk_words, const uint32_t* __restrict__ chunk_zeros,
-    const uint64_t* __restrict__ word_off, const uint64_t* __restrict__ zero_off,
-    const Layout& l, uint8_t* out, uint64_t cap, uint32_t bid, uint32_t nblk) {
+    uint32_t* chunk_words, uint32_t* chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, uint32_t* slots, const Layout& l, uint8_t* out,
+    uint64_t cap, uint32_t bid, uint32_t nblk) {
   const int lane = threadIdx.x & 63;
   const uint64_t wstride = (uint64_t)nblk * kEncWaves;
   for (uint64_t c = bid * (uint64_t)kEncWaves + (threadIdx.x >> 6); c < nchunks;
@@ -488,10 +572,22 @@ __device__ __forceinline__ void pack_chunks(
         }
       }
     }
-    const uint64_t bit0 = wave_incl_scan_u32(bits, lane) - bits;
-    uint64_t zrank = zero_off[c] + (wave_incl_scan_u32(zeros, lane) - zeros);
-    const uint64_t wbase = l.off_bits + 4 * word_off[c];
-    if (lane == 0) {
+    const uint32_t bits_incl = wave_incl_scan_u32(bits, lane);
+    const uint32_t zeros_incl = wave_incl_scan_u32(zeros, lane);
+    const uint64_t bit0 = bits_incl - bits;
+    uint64_t zrank = SLOTS ? 0 : zero_off[c] + (zeros_incl - zeros);
+    const uint64_t wbase = SLOTS ? 0 : l.off_bits + 4 * word_off[c];
+    uint32_t* slot = SLOTS ? slots + c * chunk : nullptr;
+    if (SLOTS) {
+      const uint32_t words = (__shfl(bits_incl, 63, 64) + 31) / 32;
+      const uint32_t zc = __shfl(zeros_incl, 63, 64);
+      if (lane == 0) {
+        chunk_words[c] = words;
+        chunk_zeros[c] = zc;
+        guarded_store_u32(out, cap, l.off_chunk + 8 * c, words);
+        guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, zc);
+      }
+    } else if (lane == 0) {
       guarded_store_u32(out, cap, l.off_chunk + 8 * c, chunk_words[c]);
       guarded_store_u32(out, cap, l.off_chunk + 8 * c + 4, chunk_zeros[c]);
     }
@@ -517,6 +613,8 @@ __device__ __forceinline__ void pack_chunks(
       if (first_pending) {
         first_contrib = word;
         first_pending = false;
+      } else if (SLOTS) {
+        slot[wi] = word;
       } else {
         guarded_store_u32(out, cap, wbase + 4 * wi, word);
       }
@@ -544,7 +642,7 @@ __device__ __forceinline__ void pack_chunks(
           acc |= cw << (64 - len - na);
           na += len;
           if (na >= 32) emit();
-          if (sym == 0) {  // unpredictable value, verbatim, flat order
+          if (!SLOTS && sym == 0) {  // unpredictable value, verbatim, flat order
             const uint64_t off = l.off_unpred + zrank * sizeof(T);
             if (off + sizeof(T) <= cap) *reinterpret_cast<T*>(out + off) = x[s0 + k];
             zrank++;
@@ -567,12 +665,17 @@ __device__ __forceinline__ void pack_chunks(
     }
     uint32_t next = __shfl_down(first_contrib, 1, 64);
     if (lane == 63) next = 0;
-    if (has_last) guarded_store_u32(out, cap, wbase + 4 * wi, last | next);
+    if (has_last) {
+      if (SLOTS)
+        slot[wi] = last | next;
+      else
+        guarded_store_u32(out, cap, wbase + 4 * wi, last | next);
+    }
   }
 }
 
-// The second pass: on the lane-parallel path the slots to their places (and
-// the unpredictable values); otherwise the codes packed from scratch.
+// The second pass for codes over 32 bits: packed from scratch into place.
+// (Otherwise k_encode_copy moves the slots instead.)
 template <typename T>
 __device__ __forceinline__ void encode_pack_body(
     EncLds& u, const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n,
@@ -586,19 +689,17 @@ __device__ __forceinline__ void encode_pack_body(
   const EncWindow w = enc_window(m, R, enc_code, enc_len);
   const Layout l =
       stream_layout(m->nsym_used, nchunks, sub, m->n_unpred, sizeof(T), m->total_words);
-  if (fast_path(w)) {
-    copy_slots<T>(codes, x, n, chunk, nchunks, chunk_words, chunk_zeros, word_off, zero_off, slots,
-                  l, out, cap, bid, nblk);
-    return;
-  }
+  if (fast_path(w) || w.max_len <= 32) return;
   load_tables(t, w, nsym, enc_code, enc_len, true);
   __syncthreads();
+  uint32_t* cw = const_cast<uint32_t*>(chunk_words);  // (read only without SLOTS)
+  uint32_t* cz = const_cast<uint32_t*>(chunk_zeros);
   if (w.lds_only)
-    pack_chunks<T, true>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
-                         chunk_zeros, word_off, zero_off, l, out, cap, bid, nblk);
+    pack_chunks<T, true, false>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, cw, cz,
+                                word_off, zero_off, nullptr, l, out, cap, bid, nblk);
   else
-    pack_chunks<T, false>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, chunk_words,
-                          chunk_zeros, word_off, zero_off, l, out, cap, bid, nblk);
+    pack_chunks<T, false, false>(codes, x, n, chunk, sub, nchunks, t, w, enc_code, enc_len, cw, cz,
+                                 word_off, zero_off, nullptr, l, out, cap, bid, nblk);
 }
 
 template <typename T>
@@ -628,6 +729,67 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_pack(BLaunch L) {
                       j.nblk);
 }
 
+// The second pass of the lane-parallel path: no LDS, a wave per chunk.
+template <typename T>
+__device__ __forceinline__ void encode_copy_body(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint32_t sub, uint64_t nchunks, uint32_t R, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, const uint32_t* __restrict__ slots, uint8_t* out,
+    uint64_t cap, const Meta* __restrict__ m, uint32_t bid, uint32_t nblk) {
+  const EncWindow w = enc_window(m, R, enc_code, enc_len);
+  if (!fast_path(w) && w.max_len > 32) return;
+  const Layout l =
+      stream_layout(m->nsym_used, nchunks, sub, m->n_unpred, sizeof(T), m->total_words);
+  copy_slots<T>(codes, x, n, chunk, nchunks, chunk_words, chunk_zeros, word_off, zero_off, slots, l,
+                out, cap, bid, nblk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode_copy(
+    const uint16_t* __restrict__ codes, const T* __restrict__ x, uint64_t n, uint32_t chunk,
+    uint32_t sub, uint64_t nchunks, uint32_t R, const uint64_t* __restrict__ enc_code,
+    const uint8_t* __restrict__ enc_len, const uint32_t* __restrict__ chunk_words,
+    const uint32_t* __restrict__ chunk_zeros, const uint64_t* __restrict__ word_off,
+    const uint64_t* __restrict__ zero_off, const uint32_t* __restrict__ slots, uint8_t* out,
+    uint64_t cap, const Meta* __restrict__ m) {
+  encode_copy_body<T>(codes, x, n, chunk, sub, nchunks, R, enc_code, enc_len, chunk_words,
+                      chunk_zeros, word_off, zero_off, slots, out, cap, m, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEncWaves * 64) void k_b_encode_copy(BLaunch L) {
+  BJob j;
+  uint32_t local;
+  if (!batch_job(L, j, local)) return;
+  const BField& f = L.f[j.field];
+  encode_copy_body<T>(f.codes, static_cast<const T*>(f.x), f.n, f.chunk, f.sub, f.nchunks, f.R,
+                      f.enc_code, f.enc_len, f.chunk_words, f.chunk_zeros, f.lword_off, f.lzero_off,
+                      static_cast<const uint32_t*>(f.rec), f.out, f.cap, f.m, local, j.nblk);
+}
+
+// workgroups of the second packing pass (codes over 32 bits only)
+uint32_t encode_pack_blocks(uint64_t nchunks) {
+  const uint64_t b = (nchunks + kEncWaves - 1) / kEncWaves;
+  return (uint32_t)(b < 64 ? (b ? b : 1) : 64);
+}
+
+// workgroups of the copy pass: a wave per chunk
+uint32_t encode_copy_blocks(uint64_t nchunks) {
+  const uint64_t b = (nchunks + kEncWaves - 1) / kEncWaves;
+  return (uint32_t)(b < 16384 ? (b ? b : 1) : 16384);
+}
+
+hipError_t launch_b_encode_copy(int dtype, BLaunch L, uint32_t nwg, hipStream_t st) {
+  if (nwg == 0) return hipSuccess;
+  if (dtype == SZ_F32)
+    hipLaunchKernelGGL(k_b_encode_copy<float>, dim3(nwg), dim3(kEncWaves * 64), 0, st, L);
+  else
+    hipLaunchKernelGGL(k_b_encode_copy<double>, dim3(nwg), dim3(kEncWaves * 64), 0, st, L);
+  return hipGetLastError();
+}
+
 hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64_t n,
                          uint32_t chunk, uint32_t sub, uint32_t radius, const uint64_t* enc_code,
                          const uint8_t* enc_len, EncodeScratch es, uint32_t* slots, uint8_t* out,
@@ -637,20 +799,32 @@ hipError_t launch_encode(const uint16_t* codes, const void* x, int dtype, uint64
   const uint32_t nsym = 2 * radius;
   uint64_t blocks = (nchunks + kEncWaves - 1) / kEncWaves;
   if (blocks > 2048) blocks = 2048;
-  dim3 grid((unsigned)blocks), block(kEncWaves * 64);
+  dim3 grid((unsigned)blocks);
+  const dim3 block(kEncWaves * 64);
   hipLaunchKernelGGL(k_encode_size, grid, block, 0, st, codes, n, chunk, sub, nchunks, radius,
                      nsym, enc_code, enc_len, es.chunk_words, es.chunk_zeros, slots, out, cap, m);
   hipError_t e = launch_scan_pair(es.chunk_words, es.chunk_zeros, nchunks, es.word_off,
                                   es.zero_off, es.block_sums, &m->total_words, es.totals, st);
   if (e != hipSuccess) return e;
-  if (dtype == SZ_F32)
+  // the second pass: the packing of codes over 32 bits (rare: a small grid),
+  // or the slots' copy (each kernel returns at once when the other applies)
+  const dim3 cgrid(encode_copy_blocks(nchunks));
+  grid = dim3(encode_pack_blocks(nchunks));
+  if (dtype == SZ_F32) {
     hipLaunchKernelGGL(k_encode_pack<float>, grid, block, 0, st, codes, (const float*)x, n, chunk,
                        sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
                        es.chunk_zeros, es.word_off, es.zero_off, slots, out, cap, m);
-  else
+    hipLaunchKernelGGL(k_encode_copy<float>, cgrid, block, 0, st, codes, (const float*)x, n, chunk,
+                       sub, nchunks, radius, enc_code, enc_len, es.chunk_words, es.chunk_zeros,
+                       es.word_off, es.zero_off, slots, out, cap, m);
+  } else {
     hipLaunchKernelGGL(k_encode_pack<double>, grid, block, 0, st, codes, (const double*)x, n,
                        chunk, sub, nchunks, radius, nsym, enc_code, enc_len, es.chunk_words,
                        es.chunk_zeros, es.word_off, es.zero_off, slots, out, cap, m);
+    hipLaunchKernelGGL(k_encode_copy<double>, cgrid, block, 0, st, codes, (const double*)x, n,
+                       chunk, sub, nchunks, radius, enc_code, enc_len, es.chunk_words,
+                       es.chunk_zeros, es.word_off, es.zero_off, slots, out, cap, m);
+  }
   return hipGetLastError();
 }
 
