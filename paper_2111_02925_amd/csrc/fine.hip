@@ -190,8 +190,12 @@ __device__ __forceinline__ void fine_body(const T* __restrict__ x, T* v, uint16_
   const bool c_has_a = ce >= 2, c_has_c = ce + 2 < E2, c_has_e = ce + 4 < E2;
   const bool c_int = wc0 >= 2 && wc0 + 130 < E2;  // every lane of the wave has all four
   const uint32_t wl = wave > 0 ? wave - 1 : 0u, wr = wave + 1 < nw ? wave + 1 : wave;
-  // stores of the plane group, relative to its first plane
-  const uint32_t g_bytes = min(E0 - min(A0, E0), (uint32_t)A) * fa * (uint32_t)(RECON ? sizeof(T) : 2);
+  // stores of the plane group, relative to its first plane: up to the end of
+  // its last plane's last row (a group's rows lie far apart when the planes
+  // are not the field's outer dimension)
+  const uint32_t g_na = min(E0 - min(A0, E0), (uint32_t)A);
+  const uint32_t g_elems = g_na ? (g_na - 1) * fa + (E1 - 1) * fb + E2 : 0u;
+  const uint32_t g_bytes = g_elems * (uint32_t)(RECON ? sizeof(T) : 2);
   const __amdgpu_buffer_rsrc_t out_buf =
       RECON ? buffer_of(v + (size_t)A0 * fa, g_bytes) : buffer_of(codes + (size_t)A0 * fa, g_bytes);
 
@@ -465,12 +469,11 @@ bool plan_fine(LevelGeom& g, int tsize, uint32_t rows) {
   g.fine = 0;
   const uint32_t E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
   if (g.s != 1 || g.fs[2] != 1 || E0 < 2 || E1 < 2 || E2 < 4 || (E2 & 1u)) return false;
-  // a plane group's stores are addressed from its first plane: the planes
-  // (axis a) must be the field's outer dimension, each plane holding its
-  // rows (orders that swap the two outer dimensions take k_level64)
-  if (g.fs[1] * (uint64_t)E1 > g.fs[0]) return false;
-  // a plane group's stores span less than 2^31 bytes (buffer offsets)
-  if ((uint64_t)fine_planes(tsize) * g.fs[0] * (uint64_t)tsize >= 0x7FFF0000ull) return false;
+  // a plane group's stores are addressed from its first plane and span less
+  // than 2^31 bytes (buffer offsets): from there to the end of its last
+  // plane's last row, whichever of the two outer dimensions the planes are
+  const uint64_t span = (uint64_t)(fine_planes(tsize) - 1) * g.fs[0] + (uint64_t)(E1 - 1) * g.fs[1] + E2;
+  if (span * (uint64_t)tsize >= 0x7FFF0000ull) return false;
   const uint32_t nw = std::min<uint32_t>(kFineMaxWaves, cdiv(E2, kFineCols));
   const uint32_t width = kFineCols * nw;
   uint32_t nwin = 1;

@@ -243,10 +243,16 @@ __global__ __launch_bounds__(256) void k_b_hist_reduce(BLaunch L) {
   const bool far_col = col >= kHistSlots;
   const uint32_t rows = j.flags;  // the field's histogram workgroups
   uint32_t sum = 0;
-  if (col < kHistRow - 1)
-    for (uint32_t r = wv; r < rows; r += 4)
-      if (!far_col || f.hist_part[(uint64_t)r * kHistRow + kHistRow - 1])
-        sum += f.hist_part[(uint64_t)r * kHistRow + col];
+  if (col < kHistRow - 1) {
+    const uint32_t* p = f.hist_part + col;
+    const uint32_t* flag = f.hist_part + kHistRow - 1;
+#pragma unroll 8
+    for (uint32_t r = wv; r < rows; r += 4) {
+      const uint32_t v = p[(uint64_t)r * kHistRow];
+      const bool use = !far_col || flag[(uint64_t)r * kHistRow] != 0;
+      sum += use ? v : 0u;
+    }
+  }
   colsum[wv][lane] = sum;
   __syncthreads();
   if (wv == 0) {
