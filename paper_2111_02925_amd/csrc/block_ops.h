@@ -94,41 +94,78 @@ __device__ inline uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_
 }
 
 // -------------------------------------------------- single-block radix sort
-// Stable LSD sort of 64-bit keys on bits [lo_bit, hi_bit), 4 bits per pass,
-// by one block.  cnt: LDS table of 16 * blockDim.x counters (digit-major, so
-// the exclusive scan of the table gives stable destinations).  Returns the
-// buffer holding the result.
-
+// Stable LSD sort of 64-bit keys on bits [lo_bit, hi_bit), 8 bits per pass,
+// by one block.  Each wave takes a contiguous segment of the keys and walks
+// it in tiles of 64 (coalesced loads); within a tile the lanes holding the
+// same digit are found with ballots over the digit's bits, so a key's rank
+// among equal digits of its tile is a population count.  A pass counts each
+// wave's keys per digit, scans the counts in (digit, wave) order (stable
+// destinations), then scatters.  cnt: LDS table of at least 256 * waves
+// counters.  Returns the buffer holding the result.
 __device__ inline uint64_t* block_radix_sort(uint64_t* a, uint64_t* b, uint32_t K, int lo_bit,
-                                      int hi_bit, uint32_t* cnt, uint32_t* sh16) {
-  const uint32_t T = blockDim.x, t = threadIdx.x;
-  const uint32_t seg = (K + T - 1) / T;
-  const uint32_t beg = t * seg < K ? t * seg : K;
+                                             int hi_bit, uint32_t* cnt, uint32_t* sh16) {
+  const uint32_t T = blockDim.x, t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = T >> 6;
+  const uint32_t seg = ((K + nw - 1) / nw + 63) & ~63u;
+  const uint32_t beg = wv * seg < K ? wv * seg : K;
   const uint32_t end = beg + seg < K ? beg + seg : K;
-  for (int bit = lo_bit; bit < hi_bit; bit += 4) {
-    for (int d = 0; d < 16; d++) cnt[d * T + t] = 0;
-    for (uint32_t i = beg; i < end; i++) cnt[((a[i] >> bit) & 15) * T + t]++;
-    __syncthreads();
-    // exclusive scan of the 16*T table: each thread owns 16 consecutive slots
-    uint32_t loc[16];
-    uint32_t sum = 0;
+  const uint64_t below = (1ull << lane) - 1;
+  // lanes whose digit equals this lane's (invalid lanes match each other only)
+  auto peers = [&](uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+    m = valid ? m : ~m;
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-      loc[k] = cnt[t * 16 + k];
-      sum += loc[k];
+    for (int k = 0; k < 8; k++) {
+      const uint64_t bk = __ballot((d >> k) & 1u);
+      m &= ((d >> k) & 1u) ? bk : ~bk;
     }
-    uint32_t tot;
-    uint32_t run = block_excl_scan_u32(sum, sh16, &tot);
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-      cnt[t * 16 + k] = run;
-      run += loc[k];
+    return m;
+  };
+  for (int bit = lo_bit; bit < hi_bit; bit += 8) {
+    const uint32_t width = hi_bit - bit < 8 ? (uint32_t)(hi_bit - bit) : 8u;
+    const uint64_t mask = (1ull << width) - 1;
+    for (uint32_t i = t; i < 256 * nw; i += T) cnt[i] = 0;
+    __syncthreads();
+    // counts per (digit, wave): one leader per digit adds its tile's count
+    for (uint32_t base = beg; base < end; base += 64) {
+      const uint32_t i = base + lane;
+      const bool valid = i < end;
+      const uint32_t d = valid ? (uint32_t)((a[i] >> bit) & mask) : 0u;
+      const uint64_t pm = peers(d, valid);
+      if (valid && (pm & below) == 0) cnt[d * nw + wv] += (uint32_t)__popcll(pm);
     }
     __syncthreads();
-    for (uint32_t i = beg; i < end; i++) {
-      uint64_t key = a[i];
-      uint32_t slot = ((key >> bit) & 15) * T + t;
-      b[cnt[slot]++] = key;
+    // exclusive scan of the table in (digit, wave) order: 4 entries a thread
+    {
+      const uint32_t per = (256 * nw + T - 1) / T;
+      uint32_t loc[8];
+      uint32_t sum = 0;
+      for (uint32_t k = 0; k < per; k++) {
+        const uint32_t i = t * per + k;
+        loc[k] = i < 256 * nw ? cnt[i] : 0u;
+        sum += loc[k];
+      }
+      uint32_t tot;
+      uint32_t run = block_excl_scan_u32(sum, sh16, &tot);
+      for (uint32_t k = 0; k < per; k++) {
+        const uint32_t i = t * per + k;
+        if (i < 256 * nw) cnt[i] = run;
+        run += loc[k];
+      }
+    }
+    __syncthreads();
+    // scatter: the digit's next slot for this wave, plus the rank in the tile
+    for (uint32_t base = beg; base < end; base += 64) {
+      const uint32_t i = base + lane;
+      const bool valid = i < end;
+      const uint64_t key = valid ? a[i] : 0ull;
+      const uint32_t d = (uint32_t)((key >> bit) & mask);
+      const uint64_t pm = peers(d, valid);
+      const uint32_t slot = d * nw + wv;
+      const uint32_t pos = valid ? cnt[slot] + (uint32_t)__popcll(pm & below) : 0u;
+      if (valid) b[pos] = key;
+      // (a wave's LDS accesses take effect in order: every lane has read the
+      // slot before its leader advances it)
+      if (valid && (pm & below) == 0) cnt[slot] += (uint32_t)__popcll(pm);
     }
     __syncthreads();
     uint64_t* tmp = a;

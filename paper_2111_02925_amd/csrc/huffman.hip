@@ -399,9 +399,15 @@ __device__ uint32_t compact_used(const uint32_t* hist, const uint8_t* lens, uint
 }
 
 // Any K: the tree arrays live in global scratch.
+// The node weights of the merge stay in LDS (w_lds, kCbWCap entries, sharing
+// the radix sort's table) when the tree fits, so that the merge phases'
+// binary searches read LDS.
+constexpr uint32_t kCbWCap = 36864;
+
 __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym,
                                 CodebookScratch s, uint64_t* enc_code, uint8_t* enc_len,
-                                uint32_t* symtab, Meta* m, uint32_t* cnt, uint32_t* sh16) {
+                                uint32_t* symtab, Meta* m, uint32_t* cnt, uint32_t* sh16,
+                                uint32_t* w_lds) {
   __shared__ uint32_t sh_li, sh_qi, sh_qn, sh_cl, sh_ci, sh_done, sh_nphase;
   __shared__ uint32_t sh_maxw, sh_maxlen;
   __shared__ uint32_t bl_count[kMaxCodeLen + 2];
@@ -455,9 +461,11 @@ __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym
 
   // 2. stable sort by count -> leaves ordered by (count, symbol)
   uint64_t* sorted = block_radix_sort(s.keys_a, s.keys_b, K, 32, hi_bit, cnt, sh16);
+  __syncthreads();  // (the sort's table and w_lds share LDS)
+  uint32_t* w = 2 * K <= kCbWCap ? w_lds : s.w;
   for (uint32_t i = t; i < K; i += T) {
     uint64_t key = sorted[i];
-    s.w[i] = (uint32_t)(key >> 32);
+    w[i] = (uint32_t)(key >> 32);
     s.leaf_sym[i] = (uint16_t)(key & 0xFFFF);
   }
   if (t == 0) {
@@ -470,7 +478,6 @@ __device__ void codebook_global(const uint32_t* __restrict__ hist, uint32_t nsym
   __syncthreads();
 
   // 3. phases of the two-queue merge
-  uint32_t* w = s.w;
   for (;;) {
     if (t == 0) {
       uint32_t li = sh_li, qi = sh_qi, qn = sh_qn;
@@ -839,6 +846,7 @@ __device__ __forceinline__ void codebook_body(const uint32_t* __restrict__ hist,
                                               uint8_t* enc_len, uint32_t* symtab, Meta* m) {
   __shared__ union {
     uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
+    uint32_t w[kCbWCap];            // its node weights, when they fit
     CbLds lds;
   } u;
   __shared__ uint32_t sh16[16];
@@ -884,7 +892,7 @@ __device__ __forceinline__ void codebook_body(const uint32_t* __restrict__ hist,
     return;
   }
   if (K > kCbLdsCap) {
-    codebook_global(hist, nsym, s, enc_code, enc_len, symtab, m, u.cnt, sh16);
+    codebook_global(hist, nsym, s, enc_code, enc_len, symtab, m, u.cnt, sh16, u.w);
     return;
   }
   // leaves in symbol order, at the scanned offsets
