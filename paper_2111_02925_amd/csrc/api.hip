@@ -397,6 +397,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->cb.leaf_sym, sizeof(uint16_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lut, sizeof(uint32_t) << kLutBits), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lut2, sizeof(uint64_t) << kLutBits), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->dt.l2, sizeof(uint32_t) * kL2Prefixes * kL2Entries), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.lc, sizeof(LongCodes)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.first, sizeof(uint64_t) * (kMaxCodeLen + 2)), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->dt.count, sizeof(uint32_t) * (kMaxCodeLen + 2)), "hipMalloc");
@@ -630,7 +631,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
                    ctx->lvl_cost,
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
-                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lut2, ctx->dt.lc,
+                   ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lut2, ctx->dt.l2, ctx->dt.lc,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
   for (void* p : fixed)
     if (p) (void)hipFree(p);
@@ -1006,13 +1007,10 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   if (s.n) {
     CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
-                return launch_decode_tables(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt, ctx->meta, st);
+                return launch_decode_front(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
+                                           l.off_chunk, nch, cwords, cunp, woff, uoff, bsum,
+                                           ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
               }), "decode_tables");
-    CHECK_HIP(timed(ctx, "chunk_scan", st, [&] {
-                return launch_chunk_table_scan(str, l.off_chunk, nch, cwords, cunp, woff, uoff,
-                                               bsum, ctx->totals, in.total_words, in.n_unpred,
-                                               ctx->meta, st);
-              }), "chunk_scan");
     CHECK_HIP(timed(ctx, "decode", st, [&] {
                 return launch_decode_chunks(str, stream_size, l.off_sub, l.off_unpred, l.off_bits,
                                             in.total_words, in.n_unpred, s.n, s.chunk, s.sub, in.nsym,

@@ -455,10 +455,17 @@ struct LongCodes {
   uint32_t pad;
 };
 
+// Second level of the lookup: the first kL2Prefixes table windows that begin
+// codes longer than the table each get kL2Entries entries, indexed by the
+// next kL2Bits bits: sym | len << 16 when the code is at most kLutBits +
+// kL2Bits long, else 0 (the window limits resolve it).
+constexpr uint32_t kL2Bits = 6, kL2Prefixes = 16, kL2Entries = 1u << kL2Bits;
 struct DecodeTables {
   LongCodes* lc;         // derived by the table kernel for the chunk decoder
   uint32_t* lut;         // 1 << kLutBits entries: sym | len << 16 (len 0 = longer code)
-  uint64_t* lut2;        // 1 << kLutBits entries: up to three whole codes of the window
+  uint64_t* lut2;        // 1 << kLutBits entries: up to three whole codes of the window,
+                         // or (count 0) the window's second-level block, 0xFFFF for none
+  uint32_t* l2;          // kL2Prefixes * kL2Entries second-level entries
   uint64_t* first;       // kMaxCodeLen + 1
   uint32_t* count;       // kMaxCodeLen + 1
   uint32_t* offset;      // kMaxCodeLen + 1
@@ -466,13 +473,14 @@ struct DecodeTables {
   uint64_t* keys_a;
   uint64_t* keys_b;
 };
-hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
-                                uint32_t nsym, DecodeTables t, Meta* m, hipStream_t st);
-hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
-                                   uint32_t* chunk_words, uint32_t* chunk_unpred,
-                                   uint64_t* word_off, uint64_t* unpred_off,
-                                   uint64_t* block_sums, uint64_t* totals, uint64_t total_words,
-                                   uint64_t n_unpred, Meta* m, hipStream_t st);
+// The decoding tables, and the chunk table's scans (word and unpredictable
+// offsets of every chunk, totals checked against the header): by a second
+// block of the same launch for short tables, else by launches of their own.
+hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
+                               uint32_t nsym, DecodeTables t, uint64_t off_chunk, uint64_t nchunks,
+                               uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
+                               uint64_t* unpred_off, uint64_t* block_sums, uint64_t* totals,
+                               uint64_t total_words, uint64_t n_unpred, Meta* m, hipStream_t st);
 hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_sub,
                                 uint64_t off_unpred, uint64_t off_bits, uint64_t total_words,
                                 uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,

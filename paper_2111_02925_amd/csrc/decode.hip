@@ -161,6 +161,51 @@ __global__ __launch_bounds__(256) void k_scan2_apply(PairScan p) {
   }
 }
 
+// Both scans in one block, in tiles of kOneBlockPer entries a thread with a
+// running carry: for short tables, run by a second block of the table kernel
+// beside its first block's work instead of three launches of their own.
+constexpr uint32_t kOneBlockPer = 16;
+constexpr uint64_t kOneBlockScanMax = 65536;  // longest table scanned this way
+__device__ void pair_scan_one_block(const PairScan& p, uint64_t* sh) {
+  const uint32_t T = blockDim.x, t = threadIdx.x;
+  uint64_t ca = 0, cb = 0;
+  for (uint64_t base = 0; base < p.n; base += (uint64_t)T * kOneBlockPer) {
+    const uint64_t i0 = base + (uint64_t)t * kOneBlockPer;
+    uint32_t la[kOneBlockPer], lb[kOneBlockPer];
+    uint64_t va = 0, vb = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kOneBlockPer; k++) {
+      const uint64_t i = i0 + k;
+      la[k] = i < p.n ? p.a[i * p.stride] : 0u;
+      lb[k] = i < p.n ? p.b[i * p.stride] : 0u;
+      va += la[k];
+      vb += lb[k];
+    }
+    uint64_t ta, tb;
+    uint64_t ra = block_excl_scan_u64(va, sh, &ta) + ca;
+    uint64_t rb = block_excl_scan_u64(vb, sh, &tb) + cb;
+#pragma unroll
+    for (uint32_t k = 0; k < kOneBlockPer; k++) {
+      const uint64_t i = i0 + k;
+      if (i < p.n) {
+        if (p.a_copy) p.a_copy[i] = la[k];
+        if (p.b_copy) p.b_copy[i] = lb[k];
+        p.a_off[i] = ra;
+        p.b_off[i] = rb;
+      }
+      ra += la[k];
+      rb += lb[k];
+    }
+    ca += ta;
+    cb += tb;
+  }
+  if (t == 0) {
+    if (p.a_total) *p.a_total = ca;
+    if (p.b_total) *p.b_total = cb;
+    if (p.m && (ca != p.want_a || cb != p.want_b)) atomicOr(&p.m->status, kStatusCorrupt);
+  }
+}
+
 static hipError_t launch_scan2(const PairScan& p, hipStream_t st) {
   uint64_t nb = (p.n + kScanPerBlock - 1) / kScanPerBlock;
   if (nb == 0) nb = 1;
@@ -265,8 +310,10 @@ __device__ __forceinline__ void long_codes(uint32_t K, const uint32_t* bl, const
 // Multi-symbol table: for every kLutBits-bit window, the whole codes it holds
 // from its start, up to three, with their symbols and the bits they end at
 // (each found by a lookup of the window shifted past the codes before it; a
-// code that fits the remaining bits is decided by them alone).  Count 0: the
-// first code is longer than the window.  Called by every thread.
+// code that fits the remaining bits is decided by them alone).  An entry
+// stops before a second or third code of symbol 0, so that only its first
+// symbol can be an unpredictable value.  Count 0: the first code is longer
+// than the window.  Called by every thread.
 constexpr uint32_t kMultiSyms = 3;
 __device__ __forceinline__ uint64_t multi_entry(uint32_t c, const uint32_t (&sym)[kMultiSyms],
                                                 const uint32_t (&end)[kMultiSyms]) {
@@ -281,7 +328,7 @@ __device__ void multi_symbol_table(DecodeTables d) {
     for (uint32_t j = 0; j < kMultiSyms; j++) {
       const uint32_t e = d.lut[(x << pos) & ((1u << kLutBits) - 1)];
       const uint32_t l = e >> 16;
-      if (l == 0 || pos + l > (uint32_t)kLutBits) break;
+      if (l == 0 || pos + l > (uint32_t)kLutBits || (j > 0 && (e & 0xFFFFu) == 0)) break;
       sym[j] = e & 0xFFFFu;
       pos += l;
       end[j] = pos;
@@ -291,10 +338,42 @@ __device__ void multi_symbol_table(DecodeTables d) {
   }
 }
 
+// Second level for the windows that begin long codes.  With canonical codes
+// the short codes fill the table windows [0, p0), p0 = first[kLutBits] +
+// count[kLutBits], and every later window begins codes longer than the table.
+// Block i serves window p0 + i: its entry y is the code that starts with that
+// window followed by the kL2Bits bits of y, found among the lengths up to
+// kLutBits + kL2Bits by its left-justified range.  The multi-symbol entries of
+// the long windows point to their blocks.  Called by every thread once the
+// single-code table has been read.
+__device__ void second_level(DecodeTables d, const uint32_t* bl, const uint64_t* firsts,
+                             const uint32_t* offs) {
+  __syncthreads();
+  const uint32_t p0 = (uint32_t)(firsts[kLutBits] + bl[kLutBits]);
+  for (uint32_t e = threadIdx.x; e < kL2Prefixes * kL2Entries; e += blockDim.x) {
+    const uint32_t p = p0 + e / kL2Entries;
+    uint32_t ent = 0;
+    if (p < (1u << kLutBits)) {
+      const uint64_t v = ((uint64_t)p << (32 - kLutBits)) |
+                         ((uint64_t)(e % kL2Entries) << (32 - kLutBits - kL2Bits));
+      for (uint32_t l = kLutBits + 1; l <= kLutBits + kL2Bits; l++) {
+        const uint64_t lo = firsts[l] << (32 - l), hi = (firsts[l] + bl[l]) << (32 - l);
+        if (bl[l] && v >= lo && v < hi) {
+          ent = (uint32_t)d.sorted_sym[offs[l] + (uint32_t)((v >> (32 - l)) - firsts[l])] | (l << 16);
+          break;
+        }
+      }
+    }
+    d.l2[e] = ent;
+  }
+  for (uint32_t p = p0 + threadIdx.x; p < (1u << kLutBits); p += blockDim.x)
+    d.lut2[p] = p - p0 < kL2Prefixes ? p - p0 : 0xFFFFu;
+}
+
 __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
                                                               uint64_t off_sym, uint32_t K,
                                                               uint32_t nsym, DecodeTables d,
-                                                              Meta* m) {
+                                                              Meta* m, PairScan scan) {
   __shared__ union {
     uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
     struct {
@@ -307,6 +386,11 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   __shared__ uint32_t bl[kMaxCodeLen + 2], run[kMaxCodeLen + 2], offs[kMaxCodeLen + 2];
   __shared__ uint64_t firsts[kMaxCodeLen + 2];
   __shared__ uint32_t bad;
+  __shared__ uint64_t sh64[16];
+  if (blockIdx.x == 1) {  // the chunk table's scans
+    pair_scan_one_block(scan, sh64);
+    return;
+  }
   const uint32_t T = blockDim.x, t = threadIdx.x;
   if (t <= kMaxCodeLen + 1) {
     bl[t] = 0;
@@ -364,6 +448,7 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
       }
     }
     multi_symbol_table(d);
+    second_level(d, bl, firsts, offs);
     return;
   }
   // (length, symbol) order, a wave of symbols at a time
@@ -415,27 +500,25 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
     }
   }
   multi_symbol_table(d);
+  second_level(d, bl, firsts, offs);
 }
 
-hipError_t launch_decode_tables(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
-                                uint32_t nsym, DecodeTables t, Meta* m, hipStream_t st) {
-  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kCbThreads), 0, st, stream, off_sym,
-                     nsym_used, nsym, t, m);
-  return hipGetLastError();
-}
-
-hipError_t launch_chunk_table_scan(const uint8_t* stream, uint64_t off_chunk, uint64_t nchunks,
-                                   uint32_t* chunk_words, uint32_t* chunk_unpred,
-                                   uint64_t* word_off, uint64_t* unpred_off,
-                                   uint64_t* block_sums, uint64_t* totals, uint64_t total_words,
-                                   uint64_t n_unpred, Meta* m, hipStream_t st) {
-  if (nchunks == 0) return hipSuccess;
-  // the table's (words, unpredictable) pairs read in place, copied out for
-  // the decoder, scanned, and their totals checked
+hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
+                               uint32_t nsym, DecodeTables t, uint64_t off_chunk, uint64_t nchunks,
+                               uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
+                               uint64_t* unpred_off, uint64_t* block_sums, uint64_t* totals,
+                               uint64_t total_words, uint64_t n_unpred, Meta* m, hipStream_t st) {
+  // the chunk table's (words, unpredictable) pairs are read in place, copied
+  // out for the decoder, scanned, and their totals checked
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
   PairScan p{tab, tab + 1, 2u, nchunks, chunk_words, chunk_unpred, word_off, unpred_off,
              block_sums, totals, totals + 1, total_words, n_unpred, m};
-  return launch_scan2(p, st);
+  const bool one_block = nchunks <= kOneBlockScanMax;
+  hipLaunchKernelGGL(k_decode_tables, dim3(one_block ? 2 : 1), dim3(kCbThreads), 0, st, stream,
+                     off_sym, nsym_used, nsym, t, m, p);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !one_block) e = launch_scan2(p, st);
+  return e;
 }
 
 __global__ void k_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
@@ -489,8 +572,8 @@ template <bool LONG_LDS>
 __device__ __forceinline__ RunResult decode_run(
     const uint32_t* __restrict__ words, uint32_t wlast, uint32_t nt, const uint64_t* lut2,
     const LongCodes& lc, const uint32_t l0, const uint32_t (&lim)[kWinLens], const uint16_t* long_sym,
-    const uint16_t* __restrict__ sorted_sym, uint16_t* stage, uint32_t* ring, uint64_t beg,
-    uint64_t end, uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
+    const uint16_t* __restrict__ sorted_sym, const uint32_t* l2, uint16_t* stage, uint32_t* ring,
+    uint64_t beg, uint64_t end, uint32_t start, uint32_t chunk, uint16_t* codes, uint32_t* zlist) {
   auto ld = [&](uint32_t i) { return words[i < wlast ? i : wlast]; };
   uint32_t zeros = 0;
   uint64_t used = start;
@@ -543,6 +626,9 @@ __device__ __forceinline__ RunResult decode_run(
     const uint32_t cnt = (uint32_t)(end - g < kGroup ? end - g : kGroup);
     uint32_t zmask = 0;  // positions of unpredictable values in this group
     for (uint32_t k = 0; k < cnt;) {
+      // the word after the window, read from the ring beside the lookup: the
+      // refill below takes it without a second wait
+      const uint32_t wr = ring[(rd & (kRing - 1)) * nt];
       // up to three whole codes of the next kLutBits bits at once; the
       // symbols past the group's end are written to the spare stage slots
       // and not counted
@@ -557,49 +643,61 @@ __device__ __forceinline__ RunResult decode_run(
         stage[k * nt] = (uint16_t)s0;
         stage[(k + 1) * nt] = (uint16_t)s1;
         stage[(k + 2) * nt] = (uint16_t)s2;
-        const uint32_t z = (s0 == 0 ? 1u : 0u) | (s1 == 0 ? 2u : 0u) | (s2 == 0 ? 4u : 0u);
-        zmask |= (z & ((1u << mm) - 1u)) << k;
+        zmask |= (s0 == 0 ? 1u : 0u) << k;  // a later code of an entry is never 0
         used += bits;
         buf <<= bits;
         nb -= bits;
         k += mm;
-      } else {  // a code longer than the table
+      } else {  // a code longer than the table: its window's second level
         uint32_t sym, len;
-        const uint32_t win = (uint32_t)(buf >> 32);
-        uint32_t l = l0;
-#pragma unroll
-        for (int qq = 0; qq < kWinLens; qq++) l += win > lim[qq] ? 1u : 0u;
-        if (l <= 32) {
-          const uint32_t idx = lc.base32[l] + (win >> (32 - l));
-          sym = LONG_LDS ? long_sym[idx] : sorted_sym[idx + lc.long_first];
-          len = l;
+        const uint32_t blk = (uint32_t)e2 & 0xFFFFu;
+        const uint32_t ent =
+            blk < kL2Prefixes
+                ? l2[blk * kL2Entries + ((uint32_t)(buf >> (64 - kLutBits - kL2Bits)) & (kL2Entries - 1))]
+                : 0u;
+        if (ent >> 16) {  // a code of at most kLutBits + kL2Bits bits
+          sym = ent & 0xFFFFu;
+          len = ent >> 16;
           used += len;
           buf <<= len;
           nb -= len;
-        } else {  // longer than 32 bits: exact read of the next 64 bits
-          const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
-          uint32_t a = ld(wi), b = ld(wi + 1), cc = ld(wi + 2);
-          asm volatile("" : "+v"(a), "+v"(b), "+v"(cc));
-          uint64_t w64 = ((uint64_t)a << 32) | b;
-          if (o) w64 = (w64 << o) | (cc >> (32 - o));
-          l = 33;
-          for (uint32_t qq = 33; qq < lc.max_len; qq++) l += w64 >= lc.end_lj[qq] ? 1u : 0u;
-          const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
-          // a 32-bit read, so that this rare load is never merged with the
-          // table reads above into one generic-address load
-          uint32_t pair = reinterpret_cast<const uint32_t*>(sorted_sym)[idx >> 1];
-          asm volatile("" : "+v"(pair));
-          sym = (pair >> (16 * (idx & 1))) & 0xFFFFu;
-          len = l;
-          used += len;
-          const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
-          uint32_t dd = ld(w2), f = ld(w2 + 1);
-          asm volatile("" : "+v"(dd), "+v"(f));
-          // the window restarts left-aligned at bit `used`: drop the o2 bits of
-          // word w2 already consumed
-          buf = (((uint64_t)dd << 32) | f) << o2;
-          nb = 64 - o2;
-          rd = w2 + 2;
+        } else {  // longer, or past the second level's windows: the window limits
+          const uint32_t win = (uint32_t)(buf >> 32);
+          uint32_t l = l0;
+#pragma unroll
+          for (int qq = 0; qq < kWinLens; qq++) l += win > lim[qq] ? 1u : 0u;
+          if (l <= 32) {
+            const uint32_t idx = lc.base32[l] + (win >> (32 - l));
+            sym = LONG_LDS ? long_sym[idx] : sorted_sym[idx + lc.long_first];
+            len = l;
+            used += len;
+            buf <<= len;
+            nb -= len;
+          } else {  // longer than 32 bits: exact read of the next 64 bits
+            const uint32_t wi = (uint32_t)(used >> 5), o = (uint32_t)(used & 31);
+            uint32_t a = ld(wi), b = ld(wi + 1), cc = ld(wi + 2);
+            asm volatile("" : "+v"(a), "+v"(b), "+v"(cc));
+            uint64_t w64 = ((uint64_t)a << 32) | b;
+            if (o) w64 = (w64 << o) | (cc >> (32 - o));
+            l = 33;
+            for (uint32_t qq = 33; qq < lc.max_len; qq++) l += w64 >= lc.end_lj[qq] ? 1u : 0u;
+            const uint32_t idx = (uint32_t)(lc.base[l] + (w64 >> (64 - l)));
+            // a 32-bit read, so that this rare load is never merged with the
+            // table reads above into one generic-address load
+            uint32_t pair = reinterpret_cast<const uint32_t*>(sorted_sym)[idx >> 1];
+            asm volatile("" : "+v"(pair));
+            sym = (pair >> (16 * (idx & 1))) & 0xFFFFu;
+            len = l;
+            used += len;
+            const uint32_t o2 = (uint32_t)(used & 31), w2 = (uint32_t)(used >> 5);
+            uint32_t dd = ld(w2), f = ld(w2 + 1);
+            asm volatile("" : "+v"(dd), "+v"(f));
+            // the window restarts left-aligned at bit `used`: drop the o2 bits of
+            // word w2 already consumed
+            buf = (((uint64_t)dd << 32) | f) << o2;
+            nb = 64 - o2;
+            rd = w2 + 2;
+          }
         }
         stage[k * nt] = (uint16_t)sym;
         zmask |= (sym == 0 ? 1u : 0u) << k;
@@ -608,7 +706,7 @@ __device__ __forceinline__ RunResult decode_run(
       if (nb < 32) {  // append the next word: from the ring, or read directly
         uint32_t wv;
         if (rd < avail) {
-          wv = ring[(rd & (kRing - 1)) * nt];
+          wv = wr;
         } else {
           wv = ld(rd);
           asm volatile("" : "+v"(wv));
@@ -653,6 +751,7 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   __shared__ uint16_t long_sym[kLongSymCap];
   __shared__ uint16_t stage_all[NT * (kGroup + 2)];  // two spare slots per lane
   __shared__ uint32_t ring_all[NT * kRing];
+  __shared__ uint32_t l2[kL2Prefixes * kL2Entries];
   uint16_t* stage = stage_all + threadIdx.x;
   uint32_t* ring = ring_all + threadIdx.x;
   {
@@ -670,12 +769,24 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
       const uint32_t i = threadIdx.x + j * NT;
       lw[j] = i < kLcWords ? reinterpret_cast<const uint32_t*>(d.lc)[i] : 0u;
     }
+    constexpr uint32_t kL2Words = kL2Prefixes * kL2Entries;
+    uint32_t l2w[(kL2Words + NT - 1) / NT];
+#pragma unroll
+    for (uint32_t j = 0; j < (kL2Words + NT - 1) / NT; j++) {
+      const uint32_t i = threadIdx.x + j * NT;
+      l2w[j] = i < kL2Words ? d.l2[i] : 0u;
+    }
 #pragma unroll
     for (uint32_t j = 0; j < kLutVecs; j++) reinterpret_cast<uint4*>(lut2)[threadIdx.x + j * NT] = v[j];
 #pragma unroll
     for (uint32_t j = 0; j < (kLcWords + NT - 1) / NT; j++) {
       const uint32_t i = threadIdx.x + j * NT;
       if (i < kLcWords) reinterpret_cast<uint32_t*>(&lc)[i] = lw[j];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < (kL2Words + NT - 1) / NT; j++) {
+      const uint32_t i = threadIdx.x + j * NT;
+      if (i < kL2Words) l2[i] = l2w[j];
     }
   }
   __syncthreads();
@@ -715,9 +826,9 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   uint32_t* zlist = reinterpret_cast<uint32_t*>(out + beg);
   const RunResult res =
       lc.long_in_lds
-          ? decode_run<true>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, stage,
+          ? decode_run<true>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, l2, stage,
                              ring, beg, end, start, chunk, codes, zlist)
-          : decode_run<false>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, stage,
+          : decode_run<false>(words, wlast, NT, lut2, lc, l0, lim, long_sym, d.sorted_sym, l2, stage,
                               ring, beg, end, start, chunk, codes, zlist);
   bool bad = k + 1 < sub ? res.used != next : (res.used + 31) / 32 != W;
   // exclusive scan of the code-0 counts over the chunk's S lanes
