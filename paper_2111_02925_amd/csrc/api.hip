@@ -1015,7 +1015,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                 return launch_decode_chunks(str, stream_size, l.off_sub, l.off_unpred, l.off_bits,
                                             in.total_words, in.n_unpred, s.n, s.chunk, s.sub, in.nsym,
                                             s.dtype, cwords, cunp,
-                                            woff, uoff, ctx->dt, codes, d_out, ctx->meta, st);
+                                            woff, uoff, bsum, ctx->dt, codes, d_out, ctx->meta, st);
               }), "decode");
     int lvl_pred[kMaxLevels + 1];
     for (int l = 0; l <= kMaxLevels; l++)

@@ -83,6 +83,8 @@ struct Meta {
   uint64_t stream_bytes;
   uint32_t status;     // error bits (kStatus*)
   uint32_t hist_far;   // some code was counted outside the histogram's window
+  uint32_t slices_done;  // blocks of the decoder's chunk-table scan that have finished
+  uint32_t pad;
 };
 constexpr uint32_t kStatusEbNotFinite = 1u << 0;
 constexpr uint32_t kStatusCodeTooLong = 1u << 1;
@@ -473,9 +475,10 @@ struct DecodeTables {
   uint64_t* keys_a;
   uint64_t* keys_b;
 };
-// The decoding tables, and the chunk table's scans (word and unpredictable
-// offsets of every chunk, totals checked against the header): by a second
-// block of the same launch for short tables, else by launches of their own.
+// The decoding tables (block 0) and the chunk table's scans (word and
+// unpredictable offsets of every chunk within its slice of kSliceEntries
+// chunks, the slices' carries in block_sums, totals checked against the
+// header) in one launch.
 hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
                                uint32_t nsym, DecodeTables t, uint64_t off_chunk, uint64_t nchunks,
                                uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
@@ -486,8 +489,8 @@ hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uin
                                 uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
                                 uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
                                 const uint32_t* chunk_unpred, const uint64_t* word_off,
-                                const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
-                                void* out, Meta* m, hipStream_t st);
+                                const uint64_t* unpred_off, const uint64_t* carry, DecodeTables t,
+                                uint16_t* codes, void* out, Meta* m, hipStream_t st);
 hipError_t launch_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
                                Meta* m, hipStream_t st);
 

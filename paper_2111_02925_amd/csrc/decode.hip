@@ -161,48 +161,72 @@ __global__ __launch_bounds__(256) void k_scan2_apply(PairScan p) {
   }
 }
 
-// Both scans in one block, in tiles of kOneBlockPer entries a thread with a
-// running carry: for short tables, run by a second block of the table kernel
-// beside its first block's work instead of three launches of their own.
-constexpr uint32_t kOneBlockPer = 16;
-constexpr uint64_t kOneBlockScanMax = 65536;  // longest table scanned this way
-__device__ void pair_scan_one_block(const PairScan& p, uint64_t* sh) {
-  const uint32_t T = blockDim.x, t = threadIdx.x;
-  uint64_t ca = 0, cb = 0;
-  for (uint64_t base = 0; base < p.n; base += (uint64_t)T * kOneBlockPer) {
-    const uint64_t i0 = base + (uint64_t)t * kOneBlockPer;
-    uint32_t la[kOneBlockPer], lb[kOneBlockPer];
-    uint64_t va = 0, vb = 0;
+// The chunk table's scans inside the table kernel: blocks 1, 2, ... take a
+// slice of kSliceEntries entries each (kSlicePer a thread, in order) and
+// write the slice's own exclusive offsets and its totals; the last slice
+// block to finish (counted in Meta) turns the slice totals into carries, the
+// exclusive offsets of the slices in sums[] (words, then unpredictable
+// values), which the chunk decoder adds, and checks the totals.
+constexpr uint32_t kSlicePer = 4;
+constexpr uint32_t kSliceEntries = kCbThreads * kSlicePer;
+__device__ void scan_slice(const PairScan& p, uint64_t sl, uint64_t nslices, uint64_t* sh) {
+  __shared__ uint32_t last;
+  const uint32_t t = threadIdx.x;
+  const uint64_t i0 = sl * kSliceEntries + (uint64_t)t * kSlicePer;
+  uint32_t la[kSlicePer], lb[kSlicePer];
+  uint64_t va = 0, vb = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kOneBlockPer; k++) {
-      const uint64_t i = i0 + k;
-      la[k] = i < p.n ? p.a[i * p.stride] : 0u;
-      lb[k] = i < p.n ? p.b[i * p.stride] : 0u;
-      va += la[k];
-      vb += lb[k];
-    }
-    uint64_t ta, tb;
-    uint64_t ra = block_excl_scan_u64(va, sh, &ta) + ca;
-    uint64_t rb = block_excl_scan_u64(vb, sh, &tb) + cb;
+  for (uint32_t k = 0; k < kSlicePer; k++) {
+    const uint64_t i = i0 + k;
+    la[k] = i < p.n ? p.a[i * p.stride] : 0u;
+    lb[k] = i < p.n ? p.b[i * p.stride] : 0u;
+    va += la[k];
+    vb += lb[k];
+  }
+  uint64_t ta, tb;
+  uint64_t ra = block_excl_scan_u64(va, sh, &ta);
+  uint64_t rb = block_excl_scan_u64(vb, sh, &tb);
 #pragma unroll
-    for (uint32_t k = 0; k < kOneBlockPer; k++) {
-      const uint64_t i = i0 + k;
-      if (i < p.n) {
-        if (p.a_copy) p.a_copy[i] = la[k];
-        if (p.b_copy) p.b_copy[i] = lb[k];
-        p.a_off[i] = ra;
-        p.b_off[i] = rb;
-      }
-      ra += la[k];
-      rb += lb[k];
+  for (uint32_t k = 0; k < kSlicePer; k++) {
+    const uint64_t i = i0 + k;
+    if (i < p.n) {
+      p.a_copy[i] = la[k];
+      p.b_copy[i] = lb[k];
+      p.a_off[i] = ra;
+      p.b_off[i] = rb;
     }
-    ca += ta;
-    cb += tb;
+    ra += la[k];
+    rb += lb[k];
   }
   if (t == 0) {
-    if (p.a_total) *p.a_total = ca;
-    if (p.b_total) *p.b_total = cb;
-    if (p.m && (ca != p.want_a || cb != p.want_b)) atomicOr(&p.m->status, kStatusCorrupt);
+    p.sums[sl] = ta;
+    p.sums[nslices + sl] = tb;
+    __threadfence();
+    last = atomicAdd(&p.m->slices_done, 1u) == nslices - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // the carries, in place (read past this CU's cache: other blocks wrote them)
+  const uint64_t per = (nslices + blockDim.x - 1) / blockDim.x;
+  const uint64_t b0 = t * per < nslices ? t * per : nslices;
+  const uint64_t b1 = b0 + per < nslices ? b0 + per : nslices;
+  uint64_t tot[2];
+  for (int h = 0; h < 2; h++) {
+    uint64_t* bs = p.sums + h * nslices;
+    uint64_t v = 0;
+    for (uint64_t i = b0; i < b1; i++) v += __hip_atomic_load(bs + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t run = block_excl_scan_u64(v, sh, &tot[h]);
+    for (uint64_t i = b0; i < b1; i++) {
+      const uint64_t x = __hip_atomic_load(bs + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bs[i] = run;
+      run += x;
+    }
+  }
+  if (t == 0) {
+    p.a_total[0] = tot[0];
+    p.b_total[0] = tot[1];
+    if (tot[0] != p.want_a || tot[1] != p.want_b) atomicOr(&p.m->status, kStatusCorrupt);
   }
 }
 
@@ -387,8 +411,8 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   __shared__ uint64_t firsts[kMaxCodeLen + 2];
   __shared__ uint32_t bad;
   __shared__ uint64_t sh64[16];
-  if (blockIdx.x == 1) {  // the chunk table's scans
-    pair_scan_one_block(scan, sh64);
+  if (blockIdx.x > 0) {  // a slice of the chunk table's scans
+    scan_slice(scan, blockIdx.x - 1, gridDim.x - 1, sh64);
     return;
   }
   const uint32_t T = blockDim.x, t = threadIdx.x;
@@ -513,12 +537,11 @@ hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
   PairScan p{tab, tab + 1, 2u, nchunks, chunk_words, chunk_unpred, word_off, unpred_off,
              block_sums, totals, totals + 1, total_words, n_unpred, m};
-  const bool one_block = nchunks <= kOneBlockScanMax;
-  hipLaunchKernelGGL(k_decode_tables, dim3(one_block ? 2 : 1), dim3(kCbThreads), 0, st, stream,
-                     off_sym, nsym_used, nsym, t, m, p);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && !one_block) e = launch_scan2(p, st);
-  return e;
+  const uint64_t nslices = (nchunks + kSliceEntries - 1) / kSliceEntries;
+  if (nslices >= (1u << 20)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_decode_tables, dim3((unsigned)(1 + nslices)), dim3(kCbThreads), 0, st,
+                     stream, off_sym, nsym_used, nsym, t, m, p);
+  return hipGetLastError();
 }
 
 __global__ void k_check_totals(const uint64_t* totals, uint64_t total_words, uint64_t n_unpred,
@@ -745,7 +768,8 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
     uint64_t total_words, uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
     uint64_t nchunks, uint32_t nsym_used, const uint32_t* __restrict__ chunk_words,
     const uint32_t* __restrict__ chunk_unpred, const uint64_t* __restrict__ word_off,
-    const uint64_t* __restrict__ unpred_off, DecodeTables d, uint16_t* codes, T* out, Meta* m) {
+    const uint64_t* __restrict__ unpred_off, const uint64_t* __restrict__ carry, uint64_t nslices,
+    DecodeTables d, uint16_t* codes, T* out, Meta* m) {
   __shared__ __align__(16) uint64_t lut2[1u << kLutBits];
   __shared__ LongCodes lc;
   __shared__ uint16_t long_sym[kLongSymCap];
@@ -805,8 +829,10 @@ __global__ __launch_bounds__(NT) void k_decode_chunks(
   const uint32_t k = (uint32_t)(tg & (sub - 1));
   // S divides the block size, so the lanes of a chunk leave together
   if (c >= nchunks || m->status) return;
-  const uint64_t W = chunk_words[c], wbase = word_off[c];
-  const uint64_t uexp = chunk_unpred[c], ubase = unpred_off[c];
+  // the offsets within the chunk's slice of the table plus the slice's carries
+  const uint64_t sl = c / kSliceEntries;
+  const uint64_t W = chunk_words[c], wbase = word_off[c] + carry[sl];
+  const uint64_t uexp = chunk_unpred[c], ubase = unpred_off[c] + carry[nslices + sl];
   // a non-empty chunk holds at least one bit; its words and unpredictable
   // values must lie inside their sections (the same verdict for all S lanes)
   if (W == 0 || wbase + W > total_words || ubase + uexp > n_unpred) {
@@ -857,10 +883,11 @@ hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uin
                                 uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,
                                 uint32_t nsym_used, int dtype, const uint32_t* chunk_words,
                                 const uint32_t* chunk_unpred, const uint64_t* word_off,
-                                const uint64_t* unpred_off, DecodeTables t, uint16_t* codes,
-                                void* out, Meta* m, hipStream_t st) {
+                                const uint64_t* unpred_off, const uint64_t* carry, DecodeTables t,
+                                uint16_t* codes, void* out, Meta* m, hipStream_t st) {
   (void)stream_size;
   const uint64_t nchunks = (n + chunk - 1) / chunk;
+  const uint64_t nslices = (nchunks + kSliceEntries - 1) / kSliceEntries;
   if (nchunks == 0) return hipSuccess;
   if (!valid_sub(chunk, sub)) return hipErrorInvalidValue;
   const uint64_t lanes = nchunks * sub;
@@ -871,7 +898,8 @@ hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uin
 #define SZG_DECODE_LAUNCH(TT, NTT)                                                               \
   hipLaunchKernelGGL((k_decode_chunks<TT, NTT>), grid, block, 0, st, stream, off_sub, off_unpred, \
                      off_bits, total_words, n_unpred, n, chunk, sub, nchunks, nsym_used,          \
-                     chunk_words, chunk_unpred, word_off, unpred_off, t, codes, (TT*)out, m)
+                     chunk_words, chunk_unpred, word_off, unpred_off, carry, nslices, t, codes, \
+                     (TT*)out, m)
   if (dtype == SZ_F32) {
     if (small)
       SZG_DECODE_LAUNCH(float, 64);

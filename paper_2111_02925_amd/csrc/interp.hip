@@ -48,6 +48,7 @@ __device__ __forceinline__ void meta_init(Meta* m) {
   m->total_words = 0;
   m->stream_bytes = 0;
   m->status = 0;
+  m->slices_done = 0;
   m->hist_far = 0;
 }
 
@@ -98,13 +99,16 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
+// A lane keeps its running minimum and maximum as values of T (non-finite
+// inputs replaced by the infinity that leaves them unchanged: two selects and
+// a min and a max per value); the keys are formed once, for the reductions.
+// Which zero is kept when both signs occur does not change max - min.
 template <typename T>
-__device__ __forceinline__ void fold_minmax(T v, uint64_t& lo, uint64_t& hi) {
-  if (finite_t(v)) {
-    uint64_t k = order_key(v);
-    lo = k < lo ? k : lo;
-    hi = k > hi ? k : hi;
-  }
+__device__ __forceinline__ void fold_minmax(T v, T& lo, T& hi) {
+  const bool fin = finite_t(v);
+  const T inf = __builtin_inf();
+  lo = __builtin_fmin(lo, fin ? v : inf);
+  hi = __builtin_fmax(hi, fin ? v : -inf);
 }
 
 // Grid-stride reduction with 16-byte loads; one 64-bit atomic pair per block.
@@ -114,7 +118,7 @@ __device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n,
                                             uint32_t bid, uint32_t nblk) {
   constexpr int V = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(V)));
-  uint64_t lo = ~0ull, hi = 0;
+  T vlo = __builtin_inf(), vhi = -__builtin_inf();
   const uint64_t nv = n / V;
   const vec_t* xv = reinterpret_cast<const vec_t*>(x);
   const uint64_t gs = (uint64_t)nblk * blockDim.x;
@@ -126,19 +130,22 @@ __device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n,
     vec_t d = __builtin_nontemporal_load(xv + i + 3 * gs);
 #pragma unroll
     for (int k = 0; k < V; k++) {
-      fold_minmax<T>(a[k], lo, hi);
-      fold_minmax<T>(b[k], lo, hi);
-      fold_minmax<T>(c[k], lo, hi);
-      fold_minmax<T>(d[k], lo, hi);
+      fold_minmax<T>(a[k], vlo, vhi);
+      fold_minmax<T>(b[k], vlo, vhi);
+      fold_minmax<T>(c[k], vlo, vhi);
+      fold_minmax<T>(d[k], vlo, vhi);
     }
   }
   for (; i < nv; i += gs) {
     vec_t a = xv[i];
 #pragma unroll
-    for (int k = 0; k < V; k++) fold_minmax<T>(a[k], lo, hi);
+    for (int k = 0; k < V; k++) fold_minmax<T>(a[k], vlo, vhi);
   }
   for (uint64_t t = nv * V + bid * (uint64_t)blockDim.x + threadIdx.x; t < n; t += gs)
-    fold_minmax<T>(x[t], lo, hi);
+    fold_minmax<T>(x[t], vlo, vhi);
+  // no finite value: the empty keys
+  uint64_t lo = vlo <= vhi ? order_key(vlo) : ~0ull;
+  uint64_t hi = vlo <= vhi ? order_key(vhi) : 0ull;
   lo = wave_min_u64(lo);
   hi = wave_max_u64(hi);
   __shared__ uint64_t slo[4], shi[4];
