@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <array>
 #include <map>
 #include <mutex>
@@ -97,6 +98,7 @@ struct sz_ctx {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, Stat> stats;
+  hipEvent_t done = nullptr;  // marks the end of a call's work for the host to wait on
 };
 
 namespace {
@@ -137,6 +139,27 @@ hipEvent_t get_event(sz_ctx* c) {
   hipEvent_t e = nullptr;
   (void)hipEventCreate(&e);
   return e;
+}
+
+// The host's waits for the device (the header of a stream, a call's sizes and
+// status): a marker on the stream, polled for up to kSpinMicros (the wait is
+// usually a few tens of microseconds, and a blocking wait adds its wake-up
+// time to every call), then waited for by blocking.
+constexpr int kSpinMicros = 500;
+hipError_t wait_stream(sz_ctx* c, hipStream_t st) {
+  if (!c->done) {
+    hipError_t e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(c->done, st);
+  if (e != hipSuccess) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    e = hipEventQuery(c->done);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros))
+      return hipEventSynchronize(c->done);
+  }
 }
 
 template <class F>
@@ -642,6 +665,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->done) (void)hipEventDestroy(ctx->done);
   delete ctx;
 }
 
@@ -872,7 +896,7 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
               return launch_write_tables(out, out_capacity, ctx->symtab, nch, s.sub, hdr, dtype, ctx->meta, st);
             }), "write_tables");
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
-  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  CHECK_HIP(wait_stream(ctx, st), "wait");
   ctx->last_n = s.n;
   ctx->last_codes = codes;
   const Meta& m = *ctx->h_meta;
@@ -965,8 +989,11 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   if (stream_size < kHeaderBytes) return fail(ctx, SZ_ERR_CORRUPT, "stream shorter than its header");
   CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  // (the per-call values are reset before the header is read: one launch less
+  // once the host has the header)
+  CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   CHECK_HIP(hipMemcpyAsync(ctx->h_header, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, st), "memcpy");
-  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  CHECK_HIP(wait_stream(ctx, st), "wait");
   sz_info in;
   if (parse_header(ctx->h_header, &in) != SZ_OK) return fail(ctx, SZ_ERR_CORRUPT, "invalid header");
   if (in.stream_bytes > stream_size) return fail(ctx, SZ_ERR_CORRUPT, "stream truncated");
@@ -1004,7 +1031,6 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   uint64_t* uoff = static_cast<uint64_t*>(ctx->unpred_off.p);
   uint64_t* bsum = static_cast<uint64_t*>(ctx->block_sums.p);
 
-  CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   if (s.n) {
     CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
                 return launch_decode_front(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
@@ -1062,7 +1088,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
                 "pwrel_inverse");
   }
   CHECK_HIP(hipMemcpyAsync(ctx->h_meta, ctx->meta, sizeof(Meta), hipMemcpyDeviceToHost, st), "memcpy");
-  CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  CHECK_HIP(wait_stream(ctx, st), "wait");
   if (ctx->h_meta->status & kStatusCorrupt) return fail(ctx, SZ_ERR_CORRUPT, "stream failed validation");
   return SZ_OK;
 }

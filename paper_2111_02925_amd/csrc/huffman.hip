@@ -347,39 +347,41 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 
 // Compact the symbols with nonzero count (hist) or length (lens) in ascending
 // symbol order; returns K.  Each wave takes a contiguous segment of the
-// symbols, its lanes consecutive symbols (coalesced loads, four steps of 64
-// in flight); a symbol's place is its wave's base (an exclusive scan of the
+// symbols, its lanes consecutive symbols (coalesced loads, kCompactLoads
+// steps of 64 in flight: each pass over a segment is bound by the round trips
+// to memory); a symbol's place is its wave's base (an exclusive scan of the
 // waves' counts) plus the nonzero symbols before it in its wave, counted by
 // ballots.
+constexpr uint32_t kCompactLoads = 16, kCompactStep = 64 * kCompactLoads;
 __device__ uint32_t compact_used(const uint32_t* hist, const uint8_t* lens, uint32_t nsym,
                                  uint64_t* keys, uint32_t* symtab, uint32_t* sh16) {
   const uint32_t T = blockDim.x, t = threadIdx.x, lane = t & 63, nw = T >> 6;
-  const uint32_t seg = ((nsym + nw - 1) / nw + 255) & ~255u;
+  const uint32_t seg = ((nsym + nw - 1) / nw + kCompactStep - 1) & ~(kCompactStep - 1);
   const uint32_t beg = (t >> 6) * seg < nsym ? (t >> 6) * seg : nsym;
   const uint32_t end = beg + seg < nsym ? beg + seg : nsym;
   const uint64_t below = (1ull << lane) - 1;
-  auto load4 = [&](uint32_t b, uint32_t (&v)[4]) {
+  auto load_step = [&](uint32_t b, uint32_t (&v)[kCompactLoads]) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < (int)kCompactLoads; k++) {
       const uint32_t s = b + 64 * k + lane;
       v[k] = s < end ? (hist ? hist[s] : (uint32_t)lens[s]) : 0u;
     }
   };
   uint32_t c = 0;
-  for (uint32_t b = beg; b < end; b += 256) {
-    uint32_t v[4];
-    load4(b, v);
+  for (uint32_t b = beg; b < end; b += kCompactStep) {
+    uint32_t v[kCompactLoads];
+    load_step(b, v);
 #pragma unroll
-    for (int k = 0; k < 4; k++) c += (uint32_t)__popcll(__ballot(v[k] != 0));
+    for (int k = 0; k < (int)kCompactLoads; k++) c += (uint32_t)__popcll(__ballot(v[k] != 0));
   }
   uint32_t K;
   const uint32_t ex = block_excl_scan_u32(lane == 0 ? c : 0u, sh16, &K);
   uint32_t pos = __shfl(ex, 0, 64);  // the waves before this one
-  for (uint32_t b = beg; b < end; b += 256) {
-    uint32_t v[4];
-    load4(b, v);
+  for (uint32_t b = beg; b < end; b += kCompactStep) {
+    uint32_t v[kCompactLoads];
+    load_step(b, v);
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < (int)kCompactLoads; k++) {
       const uint64_t bal = __ballot(v[k] != 0);
       if (v[k]) {
         const uint32_t p = pos + (uint32_t)__popcll(bal & below);
