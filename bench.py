@@ -282,7 +282,7 @@ def batch_measurement(szg, torch, np, synth, workers, reps=5):
     def timed(fn):
         ts = []
         for _ in range(reps):
-            flush_buf.fill_(1)
+            flush_buf.max()  # evict the cache with clean lines (see `flush` in main)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fn()
@@ -583,26 +583,32 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
+    # Infinity Cache flush between the phases, so that no phase reads what the
+    # previous one left in the 256 MB cache (the stream the compression just
+    # wrote, in particular): a read of 512 MiB, which leaves the cache holding
+    # clean lines (a write would leave 256 MB of dirty lines for the next
+    # phase to write back inside its timed region)
+    flush_buf = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+
+    def flush():
+        flush_buf.max()
+
     # per-family breakdown (HIP events around every family), outside the
-    # timed region: the events cost about a tenth of a step
+    # timed region (the events cost about a tenth of a step), flushed like it
     ctx.timing_reset()
     ctx.set_timing(True)
     ctx.set_timing_family(None)
     for _ in range(args.steps):
-        step()
+        flush()
+        s = ctx.compress(xt, "rel", args.rel, "cubic", chunk=args.chunk,
+                         subchunks=args.subchunks, out=out)
+        flush()
+        ctx.decompress(s, out=rec)
     torch.cuda.synchronize()
     ctx.set_timing(False)
     fam = {k: ctx.timing(k) for k in FAMILIES}
     per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in fam.items()}
     dom = max(per_step, key=lambda k: per_step[k][0])
-
-    # Infinity Cache flush: a 512 MiB write between the phases, so that no
-    # phase reads what the previous one left in the 256 MB cache (the stream
-    # the compression just wrote, in particular)
-    flush_buf = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
-
-    def flush():
-        flush_buf.fill_(0)
 
     # timed region: every step's compress and decompress between HIP events,
     # the cache flushed before each (outside the events); HIP events around
@@ -785,7 +791,7 @@ def main():
         "step_algorithmic": step_alg,
         "copy_GBps": copy,
         "timing_note": "ms_per_step and the compress/decompress rates are event-timed per phase "
-                       "with a 512 MiB Infinity Cache flush before each phase, outside the events; "
+                       "with a 512 MiB Infinity Cache flush (a read) before each phase, outside the events; "
                        "wall_ms_per_step includes the flushes",
         "wall_ms_per_step": round(wall_ms_step, 4),
         "bounds": None if bounds is None else {

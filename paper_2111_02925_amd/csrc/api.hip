@@ -99,6 +99,7 @@ struct sz_ctx {
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, Stat> stats;
   hipEvent_t done = nullptr;  // marks the end of a call's work for the host to wait on
+  hipEvent_t header = nullptr;  // marks a stream's header copied to the host
 };
 
 namespace {
@@ -146,20 +147,25 @@ hipEvent_t get_event(sz_ctx* c) {
 // usually a few tens of microseconds, and a blocking wait adds its wake-up
 // time to every call), then waited for by blocking.
 constexpr int kSpinMicros = 500;
-hipError_t wait_stream(sz_ctx* c, hipStream_t st) {
-  if (!c->done) {
-    hipError_t e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+hipError_t mark(hipEvent_t& ev, hipStream_t st) {
+  if (!ev) {
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = hipEventRecord(c->done, st);
-  if (e != hipSuccess) return e;
+  return hipEventRecord(ev, st);
+}
+hipError_t wait_mark(hipEvent_t ev) {
   const auto t0 = std::chrono::steady_clock::now();
   for (;;) {
-    e = hipEventQuery(c->done);
+    const hipError_t e = hipEventQuery(ev);
     if (e != hipErrorNotReady) return e;
     if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros))
-      return hipEventSynchronize(c->done);
+      return hipEventSynchronize(ev);
   }
+}
+hipError_t wait_stream(sz_ctx* c, hipStream_t st) {
+  hipError_t e = mark(c->done, st);
+  return e == hipSuccess ? wait_mark(c->done) : e;
 }
 
 template <class F>
@@ -666,6 +672,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   if (ctx->done) (void)hipEventDestroy(ctx->done);
+  if (ctx->header) (void)hipEventDestroy(ctx->header);
   delete ctx;
 }
 
@@ -989,11 +996,28 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   if (stream_size < kHeaderBytes) return fail(ctx, SZ_ERR_CORRUPT, "stream shorter than its header");
   CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  // (the per-call values are reset before the header is read: one launch less
-  // once the host has the header)
+  // The per-call values are reset and the header is copied out; then the
+  // decoding tables and the chunk table's scans start from the header in
+  // device memory while the host waits for its copy (when the chunk buffers
+  // hold the chunks; else, or when the buffers move below, the host launches
+  // them once it has parsed the header).
   CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   CHECK_HIP(hipMemcpyAsync(ctx->h_header, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, st), "memcpy");
-  CHECK_HIP(wait_stream(ctx, st), "wait");
+  CHECK_HIP(mark(ctx->header, st), "hipEventRecord");
+  uint64_t cap = std::min({ctx->chunk_words.cap / 4, ctx->chunk_unpred.cap / 4, ctx->word_off.cap / 8,
+                           ctx->unpred_off.cap / 8});
+  cap = std::min<uint64_t>(cap, ctx->block_sums.cap >= 24 ? (ctx->block_sums.cap / 8 - 1) / 2 * 1024 : 0);
+  const void* early_bufs[5] = {ctx->chunk_words.p, ctx->chunk_unpred.p, ctx->word_off.p,
+                               ctx->unpred_off.p, ctx->block_sums.p};
+  if (cap)
+    CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
+                return launch_decode_front_early(
+                    static_cast<const uint8_t*>(d_stream), stream_size, cap, ctx->dt,
+                    static_cast<uint32_t*>(ctx->chunk_words.p), static_cast<uint32_t*>(ctx->chunk_unpred.p),
+                    static_cast<uint64_t*>(ctx->word_off.p), static_cast<uint64_t*>(ctx->unpred_off.p),
+                    static_cast<uint64_t*>(ctx->block_sums.p), ctx->totals, ctx->meta, st);
+              }), "decode_tables");
+  CHECK_HIP(wait_mark(ctx->header), "wait");
   sz_info in;
   if (parse_header(ctx->h_header, &in) != SZ_OK) return fail(ctx, SZ_ERR_CORRUPT, "invalid header");
   if (in.stream_bytes > stream_size) return fail(ctx, SZ_ERR_CORRUPT, "stream truncated");
@@ -1032,11 +1056,17 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
   uint64_t* bsum = static_cast<uint64_t*>(ctx->block_sums.p);
 
   if (s.n) {
-    CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
-                return launch_decode_front(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
-                                           l.off_chunk, nch, cwords, cunp, woff, uoff, bsum,
-                                           ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
-              }), "decode_tables");
+    const void* bufs[5] = {cwords, cunp, woff, uoff, bsum};
+    const bool early = cap && nch <= cap && std::equal(bufs, bufs + 5, early_bufs);
+    if (!early) {
+      // (the early launch may have run with the header's values: start over)
+      CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
+      CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
+                  return launch_decode_front(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
+                                             l.off_chunk, nch, cwords, cunp, woff, uoff, bsum,
+                                             ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
+                }), "decode_tables");
+    }
     CHECK_HIP(timed(ctx, "decode", st, [&] {
                 return launch_decode_chunks(str, stream_size, l.off_sub, l.off_unpred, l.off_bits,
                                             in.total_words, in.n_unpred, s.n, s.chunk, s.sub, in.nsym,

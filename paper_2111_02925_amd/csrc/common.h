@@ -484,6 +484,14 @@ hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t
                                uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
                                uint64_t* unpred_off, uint64_t* block_sums, uint64_t* totals,
                                uint64_t total_words, uint64_t n_unpred, Meta* m, hipStream_t st);
+// The same before the host has the header: the kernel reads the fields it
+// needs from the stream's header in device memory and does nothing when they
+// fail the host's checks or the chunk buffers hold fewer than cap chunks.
+hipError_t launch_decode_front_early(const uint8_t* stream, uint64_t stream_size, uint64_t cap,
+                                     DecodeTables t, uint32_t* chunk_words, uint32_t* chunk_unpred,
+                                     uint64_t* word_off, uint64_t* unpred_off,
+                                     uint64_t* block_sums, uint64_t* totals, Meta* m,
+                                     hipStream_t st);
 hipError_t launch_decode_chunks(const uint8_t* stream, uint64_t stream_size, uint64_t off_sub,
                                 uint64_t off_unpred, uint64_t off_bits, uint64_t total_words,
                                 uint64_t n_unpred, uint64_t n, uint32_t chunk, uint32_t sub,

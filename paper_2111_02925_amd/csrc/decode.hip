@@ -161,51 +161,56 @@ __global__ __launch_bounds__(256) void k_scan2_apply(PairScan p) {
   }
 }
 
-// The chunk table's scans inside the table kernel: blocks 1, 2, ... take a
-// slice of kSliceEntries entries each (kSlicePer a thread, in order) and
-// write the slice's own exclusive offsets and its totals; the last slice
-// block to finish (counted in Meta) turns the slice totals into carries, the
-// exclusive offsets of the slices in sums[] (words, then unpredictable
-// values), which the chunk decoder adds, and checks the totals.
+// The chunk table's scans inside the table kernel: blocks 1, 2, ... take
+// slices of kSliceEntries entries (kSlicePer a thread, in order), each
+// writing the slice's own exclusive offsets and its totals; the block that
+// finishes the last slice (counted in Meta) turns the slice totals into
+// carries, the exclusive offsets of the slices in sums[] (words, then
+// unpredictable values), which the chunk decoder adds, and checks the totals.
 constexpr uint32_t kSlicePer = 4;
 constexpr uint32_t kSliceEntries = kCbThreads * kSlicePer;
-__device__ void scan_slice(const PairScan& p, uint64_t sl, uint64_t nslices, uint64_t* sh) {
+constexpr uint32_t kSliceBlocks = 256;  // most slice blocks of one launch
+__device__ void scan_slices(const PairScan& p, uint64_t* sh) {
   __shared__ uint32_t last;
   const uint32_t t = threadIdx.x;
-  const uint64_t i0 = sl * kSliceEntries + (uint64_t)t * kSlicePer;
-  uint32_t la[kSlicePer], lb[kSlicePer];
-  uint64_t va = 0, vb = 0;
+  const uint64_t nslices = (p.n + kSliceEntries - 1) / kSliceEntries;
+  for (uint64_t sl = blockIdx.x - 1; sl < nslices; sl += gridDim.x - 1) {
+    const uint64_t i0 = sl * kSliceEntries + (uint64_t)t * kSlicePer;
+    uint32_t la[kSlicePer], lb[kSlicePer];
+    uint64_t va = 0, vb = 0;
 #pragma unroll
-  for (uint32_t k = 0; k < kSlicePer; k++) {
-    const uint64_t i = i0 + k;
-    la[k] = i < p.n ? p.a[i * p.stride] : 0u;
-    lb[k] = i < p.n ? p.b[i * p.stride] : 0u;
-    va += la[k];
-    vb += lb[k];
-  }
-  uint64_t ta, tb;
-  uint64_t ra = block_excl_scan_u64(va, sh, &ta);
-  uint64_t rb = block_excl_scan_u64(vb, sh, &tb);
-#pragma unroll
-  for (uint32_t k = 0; k < kSlicePer; k++) {
-    const uint64_t i = i0 + k;
-    if (i < p.n) {
-      p.a_copy[i] = la[k];
-      p.b_copy[i] = lb[k];
-      p.a_off[i] = ra;
-      p.b_off[i] = rb;
+    for (uint32_t k = 0; k < kSlicePer; k++) {
+      const uint64_t i = i0 + k;
+      la[k] = i < p.n ? p.a[i * p.stride] : 0u;
+      lb[k] = i < p.n ? p.b[i * p.stride] : 0u;
+      va += la[k];
+      vb += lb[k];
     }
-    ra += la[k];
-    rb += lb[k];
+    uint64_t ta, tb;
+    uint64_t ra = block_excl_scan_u64(va, sh, &ta);
+    uint64_t rb = block_excl_scan_u64(vb, sh, &tb);
+#pragma unroll
+    for (uint32_t k = 0; k < kSlicePer; k++) {
+      const uint64_t i = i0 + k;
+      if (i < p.n) {
+        p.a_copy[i] = la[k];
+        p.b_copy[i] = lb[k];
+        p.a_off[i] = ra;
+        p.b_off[i] = rb;
+      }
+      ra += la[k];
+      rb += lb[k];
+    }
+    if (t == 0) {
+      p.sums[sl] = ta;
+      p.sums[nslices + sl] = tb;
+      __threadfence();
+      last = atomicAdd(&p.m->slices_done, 1u) == nslices - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (last) break;  // every slice is done (this block has no further one)
   }
-  if (t == 0) {
-    p.sums[sl] = ta;
-    p.sums[nslices + sl] = tb;
-    __threadfence();
-    last = atomicAdd(&p.m->slices_done, 1u) == nslices - 1 ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!last) return;
+  if (blockIdx.x - 1 >= nslices || !last) return;
   __threadfence();
   // the carries, in place (read past this CU's cache: other blocks wrote them)
   const uint64_t per = (nslices + blockDim.x - 1) / blockDim.x;
@@ -228,6 +233,38 @@ __device__ void scan_slice(const PairScan& p, uint64_t sl, uint64_t nslices, uin
     p.b_total[0] = tot[1];
     if (tot[0] != p.want_a || tot[1] != p.want_b) atomicOr(&p.m->status, kStatusCorrupt);
   }
+}
+
+// The header fields the table kernel needs, read on the device (the same
+// fields and checks as the host's parse, at the same offsets): coded
+// symbols, bins, chunk count, the chunk table's place and the totals.  False
+// when the header does not pass them or the chunk buffers hold fewer than
+// cap chunks; the host then launches the kernel itself once it has parsed
+// the header.
+__device__ bool front_from_header(const uint8_t* h, uint64_t stream_size, uint64_t cap,
+                                  uint32_t& K, uint32_t& nsym, uint64_t& off_chunk,
+                                  uint64_t& nch, uint64_t& words, uint64_t& unpred) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(h);
+  const uint64_t* d = reinterpret_cast<const uint64_t*>(h);
+  if (stream_size < kHeaderBytes || w[0] != 0x31475A53u /* "SZG1" */ || (w[1] & 0xFFFFu) != 1u)
+    return false;
+  const uint32_t ndim = h[7];
+  if (ndim < 1 || ndim > (uint32_t)kMaxDims) return false;
+  uint64_t n = 1;
+  for (uint32_t k = 0; k < ndim; k++) {
+    const uint64_t e = d[1 + k];
+    if (e == 0 || e > kMaxPoints || n > kMaxPoints / e) return false;
+    n *= e;
+  }
+  const uint32_t radius = w[16], chunk = w[17];
+  K = w[20];
+  unpred = d[9];
+  words = d[11];
+  if (radius < 1 || radius > kMaxRadius || chunk == 0 || K == 0 || K > 2 * radius) return false;
+  nsym = 2 * radius;
+  nch = (n + chunk - 1) / chunk;
+  off_chunk = kHeaderBytes + pad8(4ull * K);
+  return nch <= cap && off_chunk + 8 * nch <= stream_size;
 }
 
 static hipError_t launch_scan2(const PairScan& p, hipStream_t st) {
@@ -397,7 +434,8 @@ __device__ void second_level(DecodeTables d, const uint32_t* bl, const uint64_t*
 __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __restrict__ stream,
                                                               uint64_t off_sym, uint32_t K,
                                                               uint32_t nsym, DecodeTables d,
-                                                              Meta* m, PairScan scan) {
+                                                              Meta* m, PairScan scan,
+                                                              uint64_t hdr_size, uint64_t cap) {
   __shared__ union {
     uint32_t cnt[16 * kCbThreads];  // radix-sort table of the global path
     struct {
@@ -411,8 +449,34 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   __shared__ uint64_t firsts[kMaxCodeLen + 2];
   __shared__ uint32_t bad;
   __shared__ uint64_t sh64[16];
-  if (blockIdx.x > 0) {  // a slice of the chunk table's scans
-    scan_slice(scan, blockIdx.x - 1, gridDim.x - 1, sh64);
+  if (hdr_size) {  // the parameters from the header in device memory
+    __shared__ uint32_t sk, sn, sok;
+    __shared__ uint64_t soff, snch, swords, sunp;
+    if (threadIdx.x == 0) {
+      uint32_t k_ = 0, n_ = 0;
+      uint64_t off_ = 0, nch_ = 0, w_ = 0, u_ = 0;
+      sok = front_from_header(stream, hdr_size, cap, k_, n_, off_, nch_, w_, u_) ? 1u : 0u;
+      sk = k_;
+      sn = n_;
+      soff = off_;
+      snch = nch_;
+      swords = w_;
+      sunp = u_;
+    }
+    __syncthreads();
+    if (!sok) return;
+    K = sk;
+    nsym = sn;
+    off_sym = kHeaderBytes;
+    const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + soff);
+    scan.a = tab;
+    scan.b = tab + 1;
+    scan.n = snch;
+    scan.want_a = swords;
+    scan.want_b = sunp;
+  }
+  if (blockIdx.x > 0) {  // slices of the chunk table's scans
+    scan_slices(scan, sh64);
     return;
   }
   const uint32_t T = blockDim.x, t = threadIdx.x;
@@ -527,6 +591,11 @@ __global__ __launch_bounds__(kCbThreads) void k_decode_tables(const uint8_t* __r
   second_level(d, bl, firsts, offs);
 }
 
+static unsigned slice_grid(uint64_t nchunks) {
+  const uint64_t ns = (nchunks + kSliceEntries - 1) / kSliceEntries;
+  return 1u + (unsigned)(ns < kSliceBlocks ? ns : kSliceBlocks);
+}
+
 hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
                                uint32_t nsym, DecodeTables t, uint64_t off_chunk, uint64_t nchunks,
                                uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
@@ -537,10 +606,21 @@ hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(stream + off_chunk);
   PairScan p{tab, tab + 1, 2u, nchunks, chunk_words, chunk_unpred, word_off, unpred_off,
              block_sums, totals, totals + 1, total_words, n_unpred, m};
-  const uint64_t nslices = (nchunks + kSliceEntries - 1) / kSliceEntries;
-  if (nslices >= (1u << 20)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_decode_tables, dim3((unsigned)(1 + nslices)), dim3(kCbThreads), 0, st,
-                     stream, off_sym, nsym_used, nsym, t, m, p);
+  hipLaunchKernelGGL(k_decode_tables, dim3(slice_grid(nchunks)), dim3(kCbThreads), 0, st, stream,
+                     off_sym, nsym_used, nsym, t, m, p, 0ull, 0ull);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_front_early(const uint8_t* stream, uint64_t stream_size, uint64_t cap,
+                                     DecodeTables t, uint32_t* chunk_words, uint32_t* chunk_unpred,
+                                     uint64_t* word_off, uint64_t* unpred_off,
+                                     uint64_t* block_sums, uint64_t* totals, Meta* m,
+                                     hipStream_t st) {
+  if (cap == 0 || stream_size < kHeaderBytes) return hipErrorInvalidValue;
+  PairScan p{nullptr, nullptr, 2u, 0, chunk_words, chunk_unpred, word_off, unpred_off,
+             block_sums, totals, totals + 1, 0, 0, m};
+  hipLaunchKernelGGL(k_decode_tables, dim3(slice_grid(cap)), dim3(kCbThreads), 0, st, stream,
+                     kHeaderBytes, 0u, 0u, t, m, p, stream_size, cap);
   return hipGetLastError();
 }
 
