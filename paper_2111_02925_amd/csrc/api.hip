@@ -1062,7 +1062,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_stream, size_t stream_size, void* d
       // (the early launch may have run with the header's values: start over)
       CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
       CHECK_HIP(timed(ctx, "decode_tables", st, [&] {
-                  return launch_decode_front(str, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
+                  return launch_decode_front(str, in.stream_bytes, l.off_sym, in.nsym, 2 * s.radius, ctx->dt,
                                              l.off_chunk, nch, cwords, cunp, woff, uoff, bsum,
                                              ctx->totals, in.total_words, in.n_unpred, ctx->meta, st);
                 }), "decode_tables");

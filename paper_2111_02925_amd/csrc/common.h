@@ -475,11 +475,13 @@ struct DecodeTables {
   uint64_t* keys_a;
   uint64_t* keys_b;
 };
-// The decoding tables (block 0) and the chunk table's scans (word and
+// The decoding tables (block 0), the chunk table's scans (word and
 // unpredictable offsets of every chunk within its slice of kSliceEntries
 // chunks, the slices' carries in block_sums, totals checked against the
-// header) in one launch.
-hipError_t launch_decode_front(const uint8_t* stream, uint64_t off_sym, uint32_t nsym_used,
+// header) and a read of the stream's stream_bytes that brings it into the
+// Infinity Cache for the chunk decoder, in one launch.
+hipError_t launch_decode_front(const uint8_t* stream, uint64_t stream_bytes, uint64_t off_sym,
+                               uint32_t nsym_used,
                                uint32_t nsym, DecodeTables t, uint64_t off_chunk, uint64_t nchunks,
                                uint32_t* chunk_words, uint32_t* chunk_unpred, uint64_t* word_off,
                                uint64_t* unpred_off, uint64_t* block_sums, uint64_t* totals,
