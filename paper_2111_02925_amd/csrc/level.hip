@@ -677,10 +677,25 @@ bool plan_levels(int ndim, const uint64_t* dims, const uint8_t* order, int tsize
     while ((1ull << l) < dims[d]) l++;
     L = std::max(L, l);
   }
+  // Without a tuning, a level with few work items under the default tiling
+  // (a coarse level of a large field, or a small field) takes shorter (b, c)
+  // tiles: more workgroups, more halo work (measured per stride on 512^3:
+  // strides 16 and 8 gain a fifth, stride 4 and finer lose).  Tiles never
+  // change the bytes.
   const LevelTuning def{2048, 32, 58, 64 * 1024, 1, 0};
-  const LevelTuning& tu = tune ? *tune : def;
+  const LevelTuning few{4096, 16, 58, 64 * 1024, 1, 0};
+  const LevelTuning fewer{8192, 8, 58, 64 * 1024, 1, 0};
   for (int l = L; l >= 1; l--) {
     const uint64_t s = 1ull << (l - 1);
+    const LevelTuning* pick = tune ? tune : &def;
+    if (!tune && s >= 8) {
+      const uint64_t items32 = (uint64_t)ceil_div32((V[O[1]] - 1) / s + 1, 32) *
+                               ceil_div32((V[O[2]] - 1) / s + 1, 58) *
+                               ceil_div32((V[O[0]] - 1) / s + 1, 2);
+      if (items32 < 64) pick = &fewer;
+      else if (items32 < 256) pick = &few;
+    }
+    const LevelTuning& tu = *pick;
     LevelGeom g{};
     g.s = (uint32_t)s;
     for (int j = 0; j < 3; j++) {
