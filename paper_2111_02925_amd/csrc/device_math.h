@@ -80,12 +80,15 @@ __device__ __forceinline__ uint32_t quantize(T x, T pred, const QuantParams<T>& 
   }
   const T kf = rint_t(diff * q.inv2eb);
   const bool in_range = fabs_t(kf) < (T)q.R;  // false for NaN
-  const int k = (int)(in_range ? kf : T(0));
-  const T r = pred + q.twoeb * (T)k;
+  // k stays in T: an integer below R in magnitude, exact in T, so R + k is
+  // too and converts to the code exactly (one conversion instead of two);
+  // + 0 turns a rounded -0 into the +0 that an integer k would give
+  const T k = in_range ? kf + T(0) : T(0);
+  const T r = pred + q.twoeb * k;
   const bool holds = bound_holds(x, r, q.eb);  // evaluated for every lane: no branch on in_range
   const bool ok = in_range & holds;
   rec = ok ? r : x;
-  return ok ? (uint32_t)((int)q.R + k) : 0u;
+  return ok ? (uint32_t)(k + (T)q.R) : 0u;
 }
 
 template <typename T>
