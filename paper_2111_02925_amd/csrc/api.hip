@@ -100,6 +100,11 @@ struct sz_ctx {
   std::map<std::string, Stat> stats;
   hipEvent_t done = nullptr;  // marks the end of a call's work for the host to wait on
   hipEvent_t header = nullptr;  // marks a stream's header copied to the host
+  // the rows that price the dimension orders (est_row_sampled) for one shape
+  Buf est_rows;
+  uint64_t est_nrows = 0;
+  std::array<uint64_t, kMaxDims> est_dims{};
+  int est_ndim = 0;
 };
 
 namespace {
@@ -605,7 +610,7 @@ size_t ctx_scratch_bytes(const sz_ctx* ctx) {
   size_t t = 0;
   for (const Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred,
                        &ctx->word_off, &ctx->unpred_off, &ctx->block_sums, &ctx->ylog,
-                       &ctx->signs, &ctx->coarse})
+                       &ctx->signs, &ctx->coarse, &ctx->est_rows})
     t += b->cap;
   return t;
 }
@@ -613,11 +618,13 @@ size_t ctx_scratch_bytes(const sz_ctx* ctx) {
 void ctx_trim(sz_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
-                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse}) {
+                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse,
+                 &ctx->est_rows}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->cap = 0;
   }
+  ctx->est_ndim = 0;
 }
 
 size_t ctx_fixed_bytes() {
@@ -655,7 +662,8 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   (void)hipDeviceSynchronize();
   batch_plan_free(ctx->batch);
   for (Buf* b : {&ctx->rec, &ctx->codes, &ctx->chunk_words, &ctx->chunk_unpred, &ctx->word_off,
-                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse})
+                 &ctx->unpred_off, &ctx->block_sums, &ctx->ylog, &ctx->signs, &ctx->coarse,
+                 &ctx->est_rows})
     if (b->p) (void)hipFree(b->p);
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
                    ctx->lvl_cost,
@@ -785,16 +793,46 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
       const size_t per = 2 * kMaxLevels;
       CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0,
                                 2 * per * nperm, st), "fill");
-      CHECK_HIP(timed(ctx, "estimate", st, [&] {
-                  hipError_t e = hipSuccess;
-                  for (size_t i = 0; i < nperm && e == hipSuccess; i++) {
-                    EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[i].data());
-                    eg.sampled = 1;
-                    e = launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, ctx->lvl_cost + per * i,
-                                        st);
-                  }
-                  return e;
-                }), "estimate");
+      if (noalloc) {  // (one launch an order: the sampled rows are found by the kernel)
+        CHECK_HIP(timed(ctx, "estimate", st, [&] {
+                    hipError_t e = hipSuccess;
+                    for (size_t i = 0; i < nperm && e == hipSuccess; i++) {
+                      EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[i].data());
+                      eg.sampled = 1;
+                      e = launch_estimate(d_in, dtype, eg, ctx->meta, s.radius,
+                                          ctx->lvl_cost + per * i, st);
+                    }
+                    return e;
+                  }), "estimate");
+      } else {
+        // the sampled rows of this shape (kept while the shape repeats)
+        bool same = ctx->est_ndim == s.ndim && ctx->est_rows.p;
+        for (int d = 0; d < s.ndim; d++) same = same && ctx->est_dims[d] == s.dims[d];
+        if (!same) {
+          const uint64_t nrows_all = s.n / s.dims[s.ndim - 1];
+          std::vector<uint32_t> rows;
+          rows.reserve(nrows_all / 8 + 64);
+          for (uint64_t r = 0; r < nrows_all; r++)
+            if (est_row_sampled(r)) rows.push_back((uint32_t)r);
+          CHECK_HIP(ensure(ctx->est_rows, std::max<size_t>(4, rows.size() * 4)), "hipMalloc(est_rows)");
+          if (!rows.empty())
+            CHECK_HIP(hipMemcpy(ctx->est_rows.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice),
+                      "memcpy");
+          ctx->est_nrows = rows.size();
+          ctx->est_ndim = s.ndim;
+          for (int d = 0; d < kMaxDims; d++) ctx->est_dims[d] = d < s.ndim ? s.dims[d] : 0;
+        }
+        uint8_t pos[kMaxOrders][kMaxDims] = {};
+        for (size_t i = 0; i < nperm; i++)
+          for (int j = 0; j < s.ndim; j++) pos[i][perms[i][j]] = (uint8_t)j;
+        const EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[0].data());
+        CHECK_HIP(timed(ctx, "estimate", st, [&] {
+                    return launch_estimate_orders(d_in, dtype, eg, pos, (uint32_t)nperm,
+                                                  static_cast<const uint32_t*>(ctx->est_rows.p),
+                                                  ctx->est_nrows, ctx->meta, s.radius, per,
+                                                  ctx->lvl_cost, st);
+                  }), "estimate");
+      }
       std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
       CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * per * nperm,
                                hipMemcpyDeviceToHost, st), "memcpy");

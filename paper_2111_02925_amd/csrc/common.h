@@ -152,6 +152,14 @@ __host__ __device__ inline bool est_row_sampled(uint64_t r) {
 }
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st);
+// The sampled estimate of norders dimension orders (orders[k][d]: the place
+// of dimension d in order k) in one launch, over the sampled rows listed in
+// rows[] (ascending flat row indices, est_row_sampled); order k's sums at
+// cost + k * per.
+hipError_t launch_estimate_orders(const void* x, int dtype, const EstGeom& g,
+                                  const uint8_t (*orders)[kMaxDims], uint32_t norders,
+                                  const uint32_t* rows, uint64_t nrows, const Meta* m,
+                                  uint32_t radius, uint64_t per, uint64_t* cost, hipStream_t st);
 hipError_t launch_pass_compress(const void* x, int dtype, int predictor, void* rec,
                                 uint16_t* codes, const PassGeom& g, const Meta* m,
                                 uint32_t radius, hipStream_t st);

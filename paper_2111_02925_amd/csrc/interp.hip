@@ -579,18 +579,114 @@ __device__ __forceinline__ void est_eval(const EstStencil<T>& st, T eb, T inv2eb
   cc = est_cost(st.x - pc, eb, inv2eb, R);
 }
 
+// One unit of the estimate: a run of kSeg columns of the row at coordinates
+// q (all but the last dimension), priced for both predictors; levels 1 and 2
+// into the caller's accumulators, coarser ones into the block's table sh.
+// pos: each dimension's place in the traversal order.
+template <typename T, int J>
+__device__ __forceinline__ void est_unit(const T* __restrict__ x, const EstGeom& g,
+                                         const uint8_t (&pos)[kMaxDims], const uint32_t (&q)[kMaxDims],
+                                         uint32_t seg, bool sampled, T eb, T inv2eb, uint32_t R,
+                                         unsigned long long* sh, uint64_t& acc1l, uint64_t& acc1c,
+                                         uint64_t& acc2l, uint64_t& acc2c) {
+  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
+  const int last = g.ndim - 1;
+  const uint32_t ncol = (uint32_t)g.dims[last];
+  const int pos_last = pos[last];
+  uint32_t base = 0;
+#pragma unroll
+  for (int e = 0; e < kMaxDims - 1; e++)
+    if (e < last) base += q[e] * (uint32_t)g.stride[e];
+  if (sampled && !est_row_sampled(base / ncol)) return;
+  int trow = 64, prow = -1;
+  uint32_t qrow = 0, srow = 0, nrow = 0;
+#pragma unroll
+  for (int e = 0; e < kMaxDims - 1; e++) {
+    const int te = q[e] ? __builtin_ctz(q[e]) : 64;
+    if (e < last && (te < trow || (te == trow && (int)pos[e] > prow))) {
+      trow = te;
+      prow = pos[e];
+      qrow = q[e];
+      srow = (uint32_t)g.stride[e];
+      nrow = (uint32_t)g.dims[e];
+    }
+  }
+  const uint32_t c0 = seg * kSeg;
+  const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
+  const bool odd_along_row = trow > 0 || pos_last > prow;
+  // the odd column's pass (level 1): along the row, or along d_row
+  const uint32_t sd_odd = odd_along_row ? 1u : srow, nd_odd = odd_along_row ? ncol : nrow;
+  uint32_t s1l = 0, s1c = 0, s2l = 0, s2c = 0;
+#pragma unroll
+  for (int j = 0; j < J; j++) {
+    const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
+    const uint64_t ce64 = (uint64_t)c0 + o;
+    const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
+    const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
+    // the even column: level 1 along d_row when t_row = 0, else level
+    // t + 1 along the row or d_row (t = 64: the origin)
+    const int tc = ce ? __builtin_ctz(ce) : 64;
+    const int t = trow == 0 ? 0 : (tc < trow ? tc : trow);
+    const bool e_row = trow != 0 && (tc < trow || (tc == trow && pos_last > prow));
+    const bool e_ok = has_even && t != 64;
+    const uint32_t sp = e_ok ? 1u << t : 0u;
+    // stencils of both columns, every load issued before any is used
+    const EstStencil<T> so = est_fetch(x, base + co, odd_along_row ? co : qrow, nd_odd,
+                                       has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
+    const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
+                                       e_row ? sp : sp * srow);
+    uint32_t cl, cc;
+    est_eval(so, eb, inv2eb, R, cl, cc);
+    if (has_odd) {
+      s1l += cl;
+      s1c += cc;
+    }
+    est_eval(se, eb, inv2eb, R, cl, cc);
+    if (e_ok) {
+      if (t == 0) {
+        s1l += cl;
+        s1c += cc;
+      } else if (t == 1) {
+        s2l += cl;
+        s2c += cc;
+      } else {
+        atomicAdd(&sh[2 * t], (unsigned long long)cl);
+        atomicAdd(&sh[2 * t + 1], (unsigned long long)cc);
+      }
+    }
+  }
+  acc1l += s1l;
+  acc1c += s1c;
+  acc2l += s2l;
+  acc2c += s2c;
+}
+
+// The block's sums into cost: levels 1 and 2 from every lane's accumulators,
+// the coarser levels from the block's table.
+__device__ __forceinline__ void est_flush(uint64_t acc1l, uint64_t acc1c, uint64_t acc2l,
+                                          uint64_t acc2c, unsigned long long* sh,
+                                          unsigned long long* cost) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t v[4] = {acc1l, acc1c, acc2l, acc2c};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if (lane == 0 && v[k]) atomicAdd(&sh[k], (unsigned long long)v[k]);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads)
+    if (sh[i]) atomicAdd(cost + i, sh[i]);
+}
+
 template <typename T, int J>
 __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ x, EstGeom g,
                                                           const Meta* __restrict__ m, uint32_t R,
                                                           unsigned long long* cost) {
-  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
   __shared__ unsigned long long sh[2 * kMaxLevels];
   for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads) sh[i] = 0;
   __syncthreads();
   const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
   const int last = g.ndim - 1;
-  const uint32_t ncol = (uint32_t)g.dims[last];
-  const int pos_last = g.pos[last];
   uint64_t acc1l = 0, acc1c = 0, acc2l = 0, acc2c = 0;  // levels 1 and 2
   const uint32_t nx = gridDim.x % 8 == 0 ? 8 : 1;
   const uint32_t bpx = gridDim.x / nx, xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
@@ -633,83 +729,51 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
         }
       }
     }
-    uint32_t base = 0;
-#pragma unroll
-    for (int e = 0; e < kMaxDims - 1; e++)
-      if (e < last) base += q[e] * (uint32_t)g.stride[e];
-    if (g.sampled && !est_row_sampled(base / ncol)) continue;
-    int trow = 64, prow = -1;
-    uint32_t qrow = 0, srow = 0, nrow = 0;
-#pragma unroll
-    for (int e = 0; e < kMaxDims - 1; e++) {
-      const int te = q[e] ? __builtin_ctz(q[e]) : 64;
-      if (e < last && (te < trow || (te == trow && (int)g.pos[e] > prow))) {
-        trow = te;
-        prow = g.pos[e];
-        qrow = q[e];
-        srow = (uint32_t)g.stride[e];
-        nrow = (uint32_t)g.dims[e];
-      }
-    }
-    const uint32_t c0 = seg * kSeg;
-    const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
-    const bool odd_along_row = trow > 0 || pos_last > prow;
-    // the odd column's pass (level 1): along the row, or along d_row
-    const uint32_t sd_odd = odd_along_row ? 1u : srow, nd_odd = odd_along_row ? ncol : nrow;
-    uint32_t s1l = 0, s1c = 0, s2l = 0, s2c = 0;
-#pragma unroll
-    for (int j = 0; j < J; j++) {
-      const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
-      const uint64_t ce64 = (uint64_t)c0 + o;
-      const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
-      const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
-      // the even column: level 1 along d_row when t_row = 0, else level
-      // t + 1 along the row or d_row (t = 64: the origin)
-      const int tc = ce ? __builtin_ctz(ce) : 64;
-      const int t = trow == 0 ? 0 : (tc < trow ? tc : trow);
-      const bool e_row = trow != 0 && (tc < trow || (tc == trow && pos_last > prow));
-      const bool e_ok = has_even && t != 64;
-      const uint32_t sp = e_ok ? 1u << t : 0u;
-      // stencils of both columns, every load issued before any is used
-      const EstStencil<T> so = est_fetch(x, base + co, odd_along_row ? co : qrow, nd_odd,
-                                         has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
-      const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
-                                         e_row ? sp : sp * srow);
-      uint32_t cl, cc;
-      est_eval(so, eb, inv2eb, R, cl, cc);
-      if (has_odd) {
-        s1l += cl;
-        s1c += cc;
-      }
-      est_eval(se, eb, inv2eb, R, cl, cc);
-      if (e_ok) {
-        if (t == 0) {
-          s1l += cl;
-          s1c += cc;
-        } else if (t == 1) {
-          s2l += cl;
-          s2c += cc;
-        } else {
-          atomicAdd(&sh[2 * t], (unsigned long long)cl);
-          atomicAdd(&sh[2 * t + 1], (unsigned long long)cc);
-        }
-      }
-    }
-    acc1l += s1l;
-    acc1c += s1c;
-    acc2l += s2l;
-    acc2c += s2c;
+    est_unit<T, J>(x, g, g.pos, q, seg, g.sampled != 0, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
+                   acc2c);
   }
-  const uint32_t lane = threadIdx.x & 63;
-  uint64_t v[4] = {acc1l, acc1c, acc2l, acc2c};
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
-    if (lane == 0 && v[k]) atomicAdd(&sh[k], (unsigned long long)v[k]);
-  }
+  est_flush(acc1l, acc1c, acc2l, acc2c, sh, cost);
+}
+
+// The sampled estimate of every dimension order in one launch: blockIdx.y
+// is the order (its positions in pos[y], its sums at cost + y * per), and
+// the units are those of the sampled rows only (rows[], ascending row
+// indices), dealt evenly to the blocks.
+struct EstOrders {
+  uint8_t pos[kMaxOrders][kMaxDims];
+};
+template <typename T, int J>
+__global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __restrict__ x, EstGeom g,
+                                                                 EstOrders o,
+                                                                 const uint32_t* __restrict__ rows,
+                                                                 uint64_t nrows,
+                                                                 const Meta* __restrict__ m,
+                                                                 uint32_t R, uint64_t per,
+                                                                 unsigned long long* cost) {
+  __shared__ unsigned long long sh[2 * kMaxLevels];
+  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads) sh[i] = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads)
-    if (sh[i]) atomicAdd(cost + i, sh[i]);
+  const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
+  const int last = g.ndim - 1;
+  uint8_t pos[kMaxDims];
+#pragma unroll
+  for (int e = 0; e < kMaxDims; e++) pos[e] = o.pos[blockIdx.y][e];
+  uint64_t acc1l = 0, acc1c = 0, acc2l = 0, acc2c = 0;
+  const uint64_t units = nrows * g.segs;
+  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t seg = (uint32_t)(u % g.segs);
+    uint64_t r = rows[u / g.segs];
+    uint32_t q[kMaxDims] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = kMaxDims - 2; e >= 0; --e) {
+      if (e < last) {
+        q[e] = (uint32_t)(r % g.dims[e]);
+        r /= g.dims[e];
+      }
+    }
+    est_unit<T, J>(x, g, pos, q, seg, false, eb, inv2eb, R, sh, acc1l, acc1c, acc2l, acc2c);
+  }
+  est_flush(acc1l, acc1c, acc2l, acc2c, sh, cost + blockIdx.y * per);
 }
 
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
@@ -733,6 +797,38 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
   else
     SZG_EST(4);
 #undef SZG_EST
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_orders(const void* x, int dtype, const EstGeom& g,
+                                  const uint8_t (*orders)[kMaxDims], uint32_t norders,
+                                  const uint32_t* rows, uint64_t nrows, const Meta* m,
+                                  uint32_t radius, uint64_t per, uint64_t* cost, hipStream_t st) {
+  const uint64_t units = nrows * g.segs;
+  if (units == 0 || norders == 0) return hipSuccess;
+  if (norders > (uint32_t)kMaxOrders) return hipErrorInvalidValue;
+  EstOrders o{};
+  for (uint32_t k = 0; k < norders; k++)
+    for (int e = 0; e < kMaxDims; e++) o.pos[k][e] = orders[k][e];
+  const uint64_t bx = std::min<uint64_t>(units, std::max<uint64_t>(64, 4096 / norders));
+  dim3 grid((unsigned)bx, norders), block(kEstThreads);
+  auto* c = reinterpret_cast<unsigned long long*>(cost);
+#define SZG_ESTO(J)                                                                               \
+  do {                                                                                            \
+    if (dtype == SZ_F32)                                                                          \
+      hipLaunchKernelGGL((k_estimate_orders<float, J>), grid, block, 0, st, (const float*)x, g, o, \
+                         rows, nrows, m, radius, per, c);                                         \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_estimate_orders<double, J>), grid, block, 0, st, (const double*)x, g,  \
+                         o, rows, nrows, m, radius, per, c);                                      \
+  } while (0)
+  if (g.pairs == 1)
+    SZG_ESTO(1);
+  else if (g.pairs == 2)
+    SZG_ESTO(2);
+  else
+    SZG_ESTO(4);
+#undef SZG_ESTO
   return hipGetLastError();
 }
 
