@@ -530,6 +530,7 @@ hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out
 // blocks of the same XCD at about the same time.  Flat indices fit 32 bits
 // (fields hold fewer than 2^32 points).
 constexpr uint32_t kEstThreads = 256;
+constexpr uint32_t kEstBlocks = 8192;  // most workgroups of an estimate launch
 
 template <typename T>
 __device__ __forceinline__ uint32_t est_cost(T d, T eb, T inv2eb, uint32_t R) {
@@ -577,6 +578,23 @@ __device__ __forceinline__ void est_eval(const EstStencil<T>& st, T eb, T inv2eb
   }
   cl = est_cost(st.x - pl, eb, inv2eb, R);
   cc = est_cost(st.x - pc, eb, inv2eb, R);
+}
+
+// A value of the lane `k` places up (k > 0) or down the wave, by DPP wave
+// shifts; lanes without a source get 0 (the callers read theirs instead).
+__device__ __forceinline__ uint32_t est_wave_shift(uint32_t v, int k) {
+  if (k == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+  if (k == -1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);
+  const uint32_t w = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x130, 0xF, 0xF, false);  // k == 2
+}
+__device__ __forceinline__ float est_from_lane(float v, int k) {
+  return __uint_as_float(est_wave_shift(__float_as_uint(v), k));
+}
+__device__ __forceinline__ double est_from_lane(double v, int k) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = est_wave_shift((uint32_t)b, k), hi = est_wave_shift((uint32_t)(b >> 32), k);
+  return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
 // One unit of the estimate: a run of kSeg columns of the row at coordinates
@@ -631,10 +649,30 @@ __device__ __forceinline__ void est_unit(const T* __restrict__ x, const EstGeom&
     const bool e_ok = has_even && t != 64;
     const uint32_t sp = e_ok ? 1u << t : 0u;
     // stencils of both columns, every load issued before any is used
-    const EstStencil<T> so = est_fetch(x, base + co, odd_along_row ? co : qrow, nd_odd,
-                                       has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
     const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
                                        e_row ? sp : sp * srow);
+    EstStencil<T> so;
+    if (odd_along_row) {
+      // (block-uniform) the odd column's neighbours along the row are the
+      // even columns of this lane and of lanes -1, +1 and +2, whose values
+      // the even stencils hold: moved across the wave, read only by the
+      // lanes whose neighbour is in another wave or outside the unit
+      so.ha = has_odd && co >= 3;
+      so.hc = has_odd && co + 1 < ncol;
+      so.he = so.hc && co + 3 < ncol;
+      so.x = x[base + co];
+      so.b = se.x;
+      const uint32_t lane = threadIdx.x & 63;
+      const T c_l = est_from_lane(se.x, 1), e_l = est_from_lane(se.x, 2), a_l = est_from_lane(se.x, -1);
+      // a neighbour's value is its lane's when that lane exists and holds it
+      const bool c_ok = lane < 63 && ce + 2 < c1, e_ok2 = lane < 62 && ce + 4 < c1;
+      const bool a_ok = lane > 0 && ce >= c0 + 2;
+      so.c = c_ok ? c_l : x[base + (so.hc ? co + 1 : co)];
+      so.e = e_ok2 ? e_l : x[base + (so.he ? co + 3 : co)];
+      so.a = a_ok ? a_l : x[base + (so.ha ? co - 3 : co)];
+    } else {
+      so = est_fetch(x, base + co, qrow, nd_odd, has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
+    }
     uint32_t cl, cc;
     est_eval(so, eb, inv2eb, R, cl, cc);
     if (has_odd) {
@@ -779,7 +817,8 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __rest
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st) {
   if (g.units == 0) return hipSuccess;
-  dim3 grid((unsigned)(g.units < 4096 ? g.units : 4096)), block(kEstThreads);
+  // (eight waves a SIMD: a unit's loads are waited for before its arithmetic)
+  dim3 grid((unsigned)(g.units < kEstBlocks ? g.units : kEstBlocks)), block(kEstThreads);
   auto* c = reinterpret_cast<unsigned long long*>(cost);
 #define SZG_EST(J)                                                                         \
   do {                                                                                     \
@@ -810,7 +849,7 @@ hipError_t launch_estimate_orders(const void* x, int dtype, const EstGeom& g,
   EstOrders o{};
   for (uint32_t k = 0; k < norders; k++)
     for (int e = 0; e < kMaxDims; e++) o.pos[k][e] = orders[k][e];
-  const uint64_t bx = std::min<uint64_t>(units, std::max<uint64_t>(64, 4096 / norders));
+  const uint64_t bx = std::min<uint64_t>(units, std::max<uint64_t>(64, kEstBlocks / norders));
   dim3 grid((unsigned)bx, norders), block(kEstThreads);
   auto* c = reinterpret_cast<unsigned long long*>(cost);
 #define SZG_ESTO(J)                                                                               \
