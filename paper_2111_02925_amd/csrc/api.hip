@@ -791,11 +791,19 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
       do perms[nperm++] = pm;
       while (std::next_permutation(pm.begin(), pm.begin() + s.ndim));
       const size_t per = 2 * kMaxLevels;
-      CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0,
-                                2 * per * nperm, st), "fill");
-      if (noalloc) {  // (one launch an order: the sampled rows are found by the kernel)
+      // (fields of up to three dimensions) the candidate buckets of one pass
+      const bool cand = s.ndim <= 3;
+      const size_t ncost = cand ? kCandBuckets : per * nperm;
+      CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0, 2 * ncost, st),
+                "fill");
+      if (noalloc) {  // (the sampled rows are found by the kernel)
         CHECK_HIP(timed(ctx, "estimate", st, [&] {
-                    hipError_t e = hipSuccess;
+                    if (cand) {
+                      const EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[0].data());
+                      return launch_estimate_cand(d_in, dtype, eg, nullptr, s.n / s.dims[s.ndim - 1],
+                                                  ctx->meta, s.radius, ctx->lvl_cost, st);
+                    }
+                    hipError_t e = hipSuccess;  // (four dimensions: one launch an order)
                     for (size_t i = 0; i < nperm && e == hipSuccess; i++) {
                       EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[i].data());
                       eg.sampled = 1;
@@ -814,6 +822,13 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
           rows.reserve(nrows_all / 8 + 64);
           for (uint64_t r = 0; r < nrows_all; r++)
             if (est_row_sampled(r)) rows.push_back((uint32_t)r);
+          if (cand) {  // grouped by class (ascending within a class)
+            std::vector<uint64_t> keyed(rows.size());
+            for (size_t i = 0; i < rows.size(); i++)
+              keyed[i] = (uint64_t)cand_row_class(s.ndim, s.dims, rows[i]) << 32 | rows[i];
+            std::sort(keyed.begin(), keyed.end());
+            for (size_t i = 0; i < rows.size(); i++) rows[i] = (uint32_t)keyed[i];
+          }
           CHECK_HIP(ensure(ctx->est_rows, std::max<size_t>(4, rows.size() * 4)), "hipMalloc(est_rows)");
           if (!rows.empty())
             CHECK_HIP(hipMemcpy(ctx->est_rows.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice),
@@ -827,6 +842,11 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
           for (int j = 0; j < s.ndim; j++) pos[i][perms[i][j]] = (uint8_t)j;
         const EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[0].data());
         CHECK_HIP(timed(ctx, "estimate", st, [&] {
+                    if (cand)
+                      return launch_estimate_cand(d_in, dtype, eg,
+                                                  static_cast<const uint32_t*>(ctx->est_rows.p),
+                                                  ctx->est_nrows, ctx->meta, s.radius,
+                                                  ctx->lvl_cost, st);
                     return launch_estimate_orders(d_in, dtype, eg, pos, (uint32_t)nperm,
                                                   static_cast<const uint32_t*>(ctx->est_rows.p),
                                                   ctx->est_nrows, ctx->meta, s.radius, per,
@@ -834,9 +854,17 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                   }), "estimate");
       }
       std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
-      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * per * nperm,
+      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * ncost,
                                hipMemcpyDeviceToHost, st), "memcpy");
       CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+      if (cand) {  // the buckets into each order's sums
+        const std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> bucket = cost;
+        for (size_t i = 0; i < nperm; i++) {
+          uint8_t pi[kMaxDims] = {};
+          for (int j = 0; j < s.ndim; j++) pi[perms[i][j]] = (uint8_t)j;
+          cand_combine(bucket.data(), s.ndim, pi, cost.data() + per * i);
+        }
+      }
       const int L = level_count(s.ndim, s.dims);
       uint64_t best = ~0ull;
       size_t bi = 0;

@@ -152,6 +152,23 @@ __host__ __device__ inline bool est_row_sampled(uint64_t r) {
 }
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st);
+// The sampled estimate of every dimension order of a field of up to three
+// dimensions in one pass: costs per (level, candidate set, dimension) into
+// 2 * 3 * 8 * kMaxLevels buckets (the rows listed in rows[], grouped by
+// cand_row_class for speed, or with rows null, the nrows rows of the field
+// that est_row_sampled takes); cand_combine
+// gives one order's sums (pos[d]: the place of dimension d in the order),
+// 2 * kMaxLevels values (linear, cubic per level).
+constexpr uint32_t kCandBuckets = 2 * 3 * 8 * kMaxLevels;  // (level, set, dimension) x {linear, cubic}
+static_assert(kCandBuckets <= 2 * kMaxLevels * kMaxOrders, "the buckets share the orders' cost buffer");
+hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, const uint32_t* rows,
+                                uint64_t nrows, const Meta* m, uint32_t radius, uint64_t* bucket,
+                                hipStream_t st);
+void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost);
+// The class of row r (flat index over every dimension but the last) that
+// the listed rows are grouped by: 8 x (fewest trailing zeros among its
+// coordinates) + the mask of the dimensions that have them.
+uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r);
 // The sampled estimate of norders dimension orders (orders[k][d]: the place
 // of dimension d in order k) in one launch, over the sampled rows listed in
 // rows[] (ascending flat row indices, est_row_sampled); order k's sums at

@@ -597,6 +597,32 @@ __device__ __forceinline__ double est_from_lane(double v, int k) {
   return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
+// The odd column co = ce + 1's stencil along the row, in a unit of columns
+// [c0, c1) dealt as (even, odd) pairs to consecutive lanes: its neighbours
+// are the even columns of this lane and of lanes -1, +1 and +2, whose values
+// (xe) are moved across the wave, and read only by the lanes whose neighbour
+// is in another wave or outside the unit.
+template <typename T>
+__device__ __forceinline__ EstStencil<T> est_odd_row(const T* __restrict__ x, uint32_t base,
+                                                     uint32_t ce, uint32_t co, bool has_odd,
+                                                     uint32_t c0, uint32_t c1, uint32_t ncol, T xe) {
+  EstStencil<T> so;
+  so.ha = has_odd && co >= 3;
+  so.hc = has_odd && co + 1 < ncol;
+  so.he = so.hc && co + 3 < ncol;
+  so.x = x[base + co];
+  so.b = xe;
+  const uint32_t lane = threadIdx.x & 63;
+  const T c_l = est_from_lane(xe, 1), e_l = est_from_lane(xe, 2), a_l = est_from_lane(xe, -1);
+  // a neighbour's value is its lane's when that lane exists and holds it
+  const bool c_ok = lane < 63 && ce + 2 < c1, e_ok = lane < 62 && ce + 4 < c1;
+  const bool a_ok = lane > 0 && ce >= c0 + 2;
+  so.c = c_ok ? c_l : x[base + (so.hc ? co + 1 : co)];
+  so.e = e_ok ? e_l : x[base + (so.he ? co + 3 : co)];
+  so.a = a_ok ? a_l : x[base + (so.ha ? co - 3 : co)];
+  return so;
+}
+
 // One unit of the estimate: a run of kSeg columns of the row at coordinates
 // q (all but the last dimension), priced for both predictors; levels 1 and 2
 // into the caller's accumulators, coarser ones into the block's table sh.
@@ -652,24 +678,8 @@ __device__ __forceinline__ void est_unit(const T* __restrict__ x, const EstGeom&
     const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
                                        e_row ? sp : sp * srow);
     EstStencil<T> so;
-    if (odd_along_row) {
-      // (block-uniform) the odd column's neighbours along the row are the
-      // even columns of this lane and of lanes -1, +1 and +2, whose values
-      // the even stencils hold: moved across the wave, read only by the
-      // lanes whose neighbour is in another wave or outside the unit
-      so.ha = has_odd && co >= 3;
-      so.hc = has_odd && co + 1 < ncol;
-      so.he = so.hc && co + 3 < ncol;
-      so.x = x[base + co];
-      so.b = se.x;
-      const uint32_t lane = threadIdx.x & 63;
-      const T c_l = est_from_lane(se.x, 1), e_l = est_from_lane(se.x, 2), a_l = est_from_lane(se.x, -1);
-      // a neighbour's value is its lane's when that lane exists and holds it
-      const bool c_ok = lane < 63 && ce + 2 < c1, e_ok2 = lane < 62 && ce + 4 < c1;
-      const bool a_ok = lane > 0 && ce >= c0 + 2;
-      so.c = c_ok ? c_l : x[base + (so.hc ? co + 1 : co)];
-      so.e = e_ok2 ? e_l : x[base + (so.he ? co + 3 : co)];
-      so.a = a_ok ? a_l : x[base + (so.ha ? co - 3 : co)];
+    if (odd_along_row) {  // (block-uniform)
+      so = est_odd_row(x, base, ce, co, has_odd, c0, c1, ncol, se.x);
     } else {
       so = est_fetch(x, base + co, qrow, nd_odd, has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
     }
@@ -837,6 +847,272 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
     SZG_EST(4);
 #undef SZG_EST
   return hipGetLastError();
+}
+
+// The sampled estimate of every dimension order at once (fields of up to
+// three dimensions).  A point p of level t (every coordinate a multiple of
+// s = 2^t, at least one an odd multiple) is visited, under a dimension order,
+// by the pass of the candidate dimension (coordinate an odd multiple of s)
+// that comes last in that order; its stencil along a dimension does not
+// depend on the order.  So every point is priced once along each of its
+// candidate dimensions, into the bucket (t, candidate set C, dimension d),
+// and an order's cost sum for level t + 1 is the sum over C of the bucket of
+// C's last dimension in that order (combined on the host).
+//
+// A row's class is (t_row, R): t_row the fewest trailing zeros among its
+// coordinates other than the column, R the dimensions that have them.  A
+// column c with t_c trailing zeros is on level min(t_c, t_row); its
+// candidates are the column when t_c <= t_row and R when t_row <= t_c.  So a
+// point's buckets are (t_c, {last}) when t_c < t_row (summed over the block
+// by level), (t_row, R + {last}) when t_c = t_row and (t_row, R) when
+// t_c > t_row (summed by lane while the class repeats: the listed rows come
+// grouped by class, and a workgroup takes a contiguous run of them).
+constexpr uint32_t kCandBlocks = 2048;  // most workgroups of the launch
+__host__ __device__ inline uint32_t cand_bucket(uint32_t t, uint32_t C, uint32_t d) {
+  return ((t * 8 + C) * 3 + d) * 2;
+}
+__device__ __forceinline__ void cand_add(unsigned long long* sh, uint32_t b, uint64_t l, uint64_t c) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (int o = 32; o > 0; o >>= 1) {
+    l += __shfl_xor(l, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  if (lane == 0) {
+    if (l) atomicAdd(&sh[b], (unsigned long long)l);
+    if (c) atomicAdd(&sh[b + 1], (unsigned long long)c);
+  }
+}
+// A row class's lane sums: B along R + {last} (index last for the column),
+// Q along R.
+struct CandSums {
+  uint64_t bl[3], bc[3], ql[2], qc[2];
+};
+__device__ __forceinline__ void cand_flush(unsigned long long* sh, CandSums& a, uint32_t tr,
+                                           uint32_t rmask, int last) {
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    if (d <= last && (d == last || ((rmask >> d) & 1u)))
+      cand_add(sh, cand_bucket(tr, rmask | (1u << last), (uint32_t)d), a.bl[d], a.bc[d]);
+    if (d < 2 && d < last && ((rmask >> d) & 1u))
+      cand_add(sh, cand_bucket(tr, rmask, (uint32_t)d), a.ql[d], a.qc[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; d++) a.bl[d] = a.bc[d] = 0;
+  a.ql[0] = a.qc[0] = a.ql[1] = a.qc[1] = 0;
+}
+template <typename T, int J>
+__global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restrict__ x, EstGeom g,
+                                                               const uint32_t* __restrict__ rows,
+                                                               uint64_t nrows,
+                                                               const Meta* __restrict__ m,
+                                                               uint32_t R, unsigned long long* bucket) {
+  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
+  __shared__ unsigned long long sh[kCandBuckets];
+  for (uint32_t i = threadIdx.x; i < kCandBuckets; i += kEstThreads) sh[i] = 0;
+  __syncthreads();
+  const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
+  const int last = g.ndim - 1;
+  const uint32_t ncol = (uint32_t)g.dims[last];
+  uint64_t a0l = 0, a0c = 0, a1l = 0, a1c = 0;  // t_c < t_row, levels 1 and 2
+  CandSums sums = {};
+  uint32_t held_t = 64, held_r = 0;  // the class sums holds (none yet)
+  const uint64_t units = nrows * g.segs;
+  const uint64_t u0 = units * blockIdx.x / gridDim.x, u1 = units * (blockIdx.x + 1) / gridDim.x;
+  for (uint64_t u = u0; u < u1; u++) {
+    // (block-uniform) the unit's row, its coordinates and class
+    const uint64_t k = u / g.segs;
+    const uint32_t seg = (uint32_t)(u - k * g.segs);
+    if (!rows && !est_row_sampled(k)) continue;  // (no list: every row, the sampled ones taken)
+    uint64_t r = rows ? rows[k] : k;
+    const uint32_t base = (uint32_t)(r * ncol);
+    uint32_t q[2] = {0, 0};
+#pragma unroll
+    for (int e = 1; e >= 0; --e) {
+      if (e < last) {
+        q[e] = (uint32_t)(r % g.dims[e]);
+        r /= g.dims[e];
+      }
+    }
+    uint32_t tr = 64, rmask = 0;
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+      const uint32_t te = e < last && q[e] ? (uint32_t)__builtin_ctz(q[e]) : 64u;
+      if (te < tr) {
+        tr = te;
+        rmask = 1u << e;
+      } else if (te == tr && te != 64) {
+        rmask |= 1u << e;
+      }
+    }
+    if (tr != 64 && (tr != held_t || rmask != held_r)) {
+      if (held_t != 64) cand_flush(sh, sums, held_t, held_r, last);
+      held_t = tr;
+      held_r = rmask;
+    }
+    const uint32_t c0 = seg * kSeg;
+    const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
+    uint32_t s0l = 0, s0c = 0, s1l = 0, s1c = 0;  // this unit's level 1 and 2 sums
+    uint32_t ubl[3] = {0, 0, 0}, ubc[3] = {0, 0, 0}, uql[2] = {0, 0}, uqc[2] = {0, 0};
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
+      const uint64_t ce64 = (uint64_t)c0 + o;
+      const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
+      const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
+      const uint32_t tc = ce ? (uint32_t)__builtin_ctz(ce) : 64u;
+      // the even column along the row (t_c <= t_row, not the origin) and
+      // along R (t_row <= t_c); the odd one along the row, and along R when
+      // t_row = 0 -- every load issued before any is used
+      const bool e_row = has_even && tc <= tr && tc != 64;
+      const bool e_cand = has_even && tr <= tc && tr != 64;
+      const uint32_t sr = e_row ? 1u << tc : 0u, sc = e_cand ? 1u << tr : 0u;
+      const T xe = x[base + ce];
+      EstStencil<T> ev_row{}, ev_d[2], od_d[2];
+      if (tr != 0) ev_row = est_fetch(x, base + ce, ce, ncol, sr, sr);
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        if (e < last && ((rmask >> e) & 1u)) {
+          ev_d[e] = est_fetch(x, base + ce, q[e], (uint32_t)g.dims[e], sc, sc * (uint32_t)g.stride[e]);
+          if (tr == 0)
+            od_d[e] = est_fetch(x, base + co, q[e], (uint32_t)g.dims[e], has_odd ? 1u : 0u,
+                                has_odd ? (uint32_t)g.stride[e] : 0u);
+        }
+      }
+      const EstStencil<T> so = est_odd_row(x, base, ce, co, has_odd, c0, c1, ncol, xe);
+      uint32_t cl, cc;
+      est_eval(so, eb, inv2eb, R, cl, cc);
+      if (has_odd) {
+        if (tr == 0) {
+          ubl[last] += cl;
+          ubc[last] += cc;
+        } else {
+          s0l += cl;
+          s0c += cc;
+        }
+      }
+      if (tr != 0) {
+        est_eval(ev_row, eb, inv2eb, R, cl, cc);
+        if (e_row) {
+          if (tc == tr) {
+            ubl[last] += cl;
+            ubc[last] += cc;
+          } else if (tc == 1) {
+            s1l += cl;
+            s1c += cc;
+          } else {
+            const uint32_t b = cand_bucket(tc, 1u << last, (uint32_t)last);
+            atomicAdd(&sh[b], (unsigned long long)cl);
+            atomicAdd(&sh[b + 1], (unsigned long long)cc);
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        if (e < last && ((rmask >> e) & 1u)) {
+          est_eval(ev_d[e], eb, inv2eb, R, cl, cc);
+          if (e_cand) {
+            if (tc == tr) {
+              ubl[e] += cl;
+              ubc[e] += cc;
+            } else {
+              uql[e] += cl;
+              uqc[e] += cc;
+            }
+          }
+          if (tr == 0) {
+            est_eval(od_d[e], eb, inv2eb, R, cl, cc);
+            if (has_odd) {
+              ubl[e] += cl;
+              ubc[e] += cc;
+            }
+          }
+        }
+      }
+    }
+    a0l += s0l;
+    a0c += s0c;
+    a1l += s1l;
+    a1c += s1c;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      sums.bl[d] += ubl[d];
+      sums.bc[d] += ubc[d];
+    }
+    sums.ql[0] += uql[0];
+    sums.qc[0] += uqc[0];
+    sums.ql[1] += uql[1];
+    sums.qc[1] += uqc[1];
+  }
+  if (held_t != 64) cand_flush(sh, sums, held_t, held_r, last);
+  cand_add(sh, cand_bucket(0, 1u << last, (uint32_t)last), a0l, a0c);
+  cand_add(sh, cand_bucket(1, 1u << last, (uint32_t)last), a1l, a1c);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kCandBuckets; i += kEstThreads)
+    if (sh[i]) atomicAdd(bucket + i, sh[i]);
+}
+
+hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, const uint32_t* rows,
+                                uint64_t nrows, const Meta* m, uint32_t radius, uint64_t* bucket,
+                                hipStream_t st) {
+  if (g.ndim < 2 || g.ndim > 3) return hipErrorInvalidValue;
+  const uint64_t units = nrows * g.segs;
+  if (units == 0) return hipSuccess;
+  dim3 grid((unsigned)(units < kCandBlocks ? units : kCandBlocks)), block(kEstThreads);
+  auto* c = reinterpret_cast<unsigned long long*>(bucket);
+#define SZG_CAND(J)                                                                              \
+  do {                                                                                           \
+    if (dtype == SZ_F32)                                                                         \
+      hipLaunchKernelGGL((k_estimate_cand<float, J>), grid, block, 0, st, (const float*)x, g,     \
+                         rows, nrows, m, radius, c);                                             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_estimate_cand<double, J>), grid, block, 0, st, (const double*)x, g,   \
+                         rows, nrows, m, radius, c);                                             \
+  } while (0)
+  if (g.pairs == 1)
+    SZG_CAND(1);
+  else if (g.pairs == 2)
+    SZG_CAND(2);
+  else
+    SZG_CAND(4);
+#undef SZG_CAND
+  return hipGetLastError();
+}
+
+// The class of a row (its coordinates other than the column): the listed
+// rows are grouped by it, so that a workgroup's run of rows changes class
+// rarely.
+uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r) {
+  uint32_t tr = 64, rmask = 0;
+  for (int e = ndim - 2; e >= 0; --e) {
+    const uint64_t qe = r % dims[e];
+    r /= dims[e];
+    const uint32_t te = qe ? (uint32_t)__builtin_ctzll(qe) : 64u;
+    if (te < tr) {
+      tr = te;
+      rmask = 1u << e;
+    } else if (te == tr && te != 64) {
+      rmask |= 1u << e;
+    }
+  }
+  return tr * 8 + rmask;
+}
+
+// An order's cost sums from the buckets: level t + 1 gathers, for every
+// candidate set C, the bucket of C's dimension that comes last in the order.
+void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost) {
+  for (uint32_t t = 0; t < (uint32_t)kMaxLevels; t++) {
+    uint64_t l = 0, c = 0;
+    for (uint32_t C = 1; C < (1u << ndim); C++) {
+      int best = -1;
+      for (int d = 0; d < ndim; d++)
+        if (((C >> d) & 1u) && (best < 0 || pos[d] > pos[best])) best = d;
+      const uint32_t b = cand_bucket(t, C, (uint32_t)best);
+      l += bucket[b];
+      c += bucket[b + 1];
+    }
+    cost[2 * t] = l;
+    cost[2 * t + 1] = c;
+  }
 }
 
 hipError_t launch_estimate_orders(const void* x, int dtype, const EstGeom& g,
