@@ -523,14 +523,16 @@ hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out
 //    points), where each lane finds its own level and dimension.
 // Both columns' stencils are fetched (every load issued before any is used;
 // idle lanes read their row's first point) and evaluated by the same code.
-// Blocks of
-// one XCD (dealt round-robin, block b on XCD b mod 8) share one contiguous
-// eighth of the units and step through it together, neighbouring blocks on
-// neighbouring rows, so the rows and planes the stencils reach are read by
-// blocks of the same XCD at about the same time.  Flat indices fit 32 bits
-// (fields hold fewer than 2^32 points).
+// The full estimate gives a unit (up to 512 columns) to one wave, which
+// works out its geometry once for up to four pairs a lane, and each wave a
+// contiguous run of units; the waves of one XCD (workgroup b on XCD b mod 8)
+// take runs of one contiguous eighth of the field, so the rows and planes
+// the stencils reach are read by waves of the same XCD at about the same
+// time.  Flat indices fit 32 bits (fields hold fewer than 2^32 points).
 constexpr uint32_t kEstThreads = 256;
-constexpr uint32_t kEstBlocks = 8192;  // most workgroups of an estimate launch
+constexpr uint32_t kEstWave = 64;          // lanes of a unit of the full estimate
+constexpr uint32_t kEstWaveBlocks = 2048;  // most workgroups of the full estimate
+constexpr uint32_t kEstBlocks = 8192;      // most workgroups of the per-order estimate
 
 template <typename T>
 __device__ __forceinline__ uint32_t est_cost(T d, T eb, T inv2eb, uint32_t R) {
@@ -547,7 +549,14 @@ struct EstStencil {
   T x, a, b, c, e;
   bool ha, hc, he;
 };
-template <typename T>
+// x[f]; with N (fields of fewer than 2^32 bytes) as a 32-bit byte offset
+// from x, which the loads take as a scalar base plus a lane offset.
+template <bool N, typename T>
+__device__ __forceinline__ T est_ld(const T* __restrict__ x, uint32_t f) {
+  if (N) return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(x) + f * (uint32_t)sizeof(T));
+  return x[f];
+}
+template <bool N, typename T>
 __device__ __forceinline__ EstStencil<T> est_fetch(const T* __restrict__ x, uint32_t f, uint32_t i,
                                                    uint32_t nd, uint32_t s, uint32_t sd) {
   EstStencil<T> st;
@@ -555,11 +564,11 @@ __device__ __forceinline__ EstStencil<T> est_fetch(const T* __restrict__ x, uint
   st.ha = ((i - s) >> 1) >= s;                    // i >= 3s
   st.hc = nd - i > s;                             // i + s < nd
   st.he = st.hc && ((nd - i - s - 1) >> 1) >= s;  // i + 3s < nd
-  st.x = x[f];
-  st.b = x[f - sd];
-  st.c = x[st.hc ? f + sd : f];
-  st.a = x[st.ha ? f - 3 * sd : f];
-  st.e = x[st.he ? f + 3 * sd : f];
+  st.x = est_ld<N>(x, f);
+  st.b = est_ld<N>(x, f - sd);
+  st.c = est_ld<N>(x, st.hc ? f + sd : f);
+  st.a = est_ld<N>(x, st.ha ? f - 3 * sd : f);
+  st.e = est_ld<N>(x, st.he ? f + 3 * sd : f);
   return st;
 }
 // Both costs from a fetched stencil.  Where the whole wave is away from the
@@ -599,102 +608,175 @@ __device__ __forceinline__ double est_from_lane(double v, int k) {
 
 // The odd column co = ce + 1's stencil along the row, in a unit of columns
 // [c0, c1) dealt as (even, odd) pairs to consecutive lanes: its neighbours
-// are the even columns of this lane and of lanes -1, +1 and +2, whose values
-// (xe) are moved across the wave, and read only by the lanes whose neighbour
-// is in another wave or outside the unit.
-template <typename T>
-__device__ __forceinline__ EstStencil<T> est_odd_row(const T* __restrict__ x, uint32_t base,
-                                                     uint32_t ce, uint32_t co, bool has_odd,
-                                                     uint32_t c0, uint32_t c1, uint32_t ncol, T xe) {
+// are the even columns of this lane and of lanes -1, +1 and +2.  The fetch
+// loads the point and those neighbours that no lane of the wave holds (the
+// wave's ends, the unit's ends; absent neighbours read the point itself);
+// the finish takes the others from the even columns' values xe, moved across
+// the wave, once they have arrived.
+template <bool N, typename T>
+__device__ __forceinline__ EstStencil<T> est_odd_row_fetch(const T* __restrict__ x, uint32_t base,
+                                                           uint32_t ce, uint32_t co, bool has_odd,
+                                                           uint32_t c0, uint32_t c1, uint32_t ncol) {
   EstStencil<T> so;
   so.ha = has_odd && co >= 3;
   so.hc = has_odd && co + 1 < ncol;
   so.he = so.hc && co + 3 < ncol;
-  so.x = x[base + co];
-  so.b = xe;
   const uint32_t lane = threadIdx.x & 63;
-  const T c_l = est_from_lane(xe, 1), e_l = est_from_lane(xe, 2), a_l = est_from_lane(xe, -1);
-  // a neighbour's value is its lane's when that lane exists and holds it
-  const bool c_ok = lane < 63 && ce + 2 < c1, e_ok = lane < 62 && ce + 4 < c1;
-  const bool a_ok = lane > 0 && ce >= c0 + 2;
-  so.c = c_ok ? c_l : x[base + (so.hc ? co + 1 : co)];
-  so.e = e_ok ? e_l : x[base + (so.he ? co + 3 : co)];
-  so.a = a_ok ? a_l : x[base + (so.ha ? co - 3 : co)];
+  const bool c_lane = lane < 63 && ce + 2 < c1, e_lane = lane < 62 && ce + 4 < c1;
+  const bool a_lane = lane > 0 && ce >= c0 + 2;
+  so.x = est_ld<N>(x, base + co);
+  so.c = est_ld<N>(x, base + (!c_lane && so.hc ? co + 1 : co));
+  so.e = est_ld<N>(x, base + (!e_lane && so.he ? co + 3 : co));
+  so.a = est_ld<N>(x, base + (!a_lane && so.ha ? co - 3 : co));
   return so;
 }
+template <typename T>
+__device__ __forceinline__ void est_odd_row_finish(EstStencil<T>& so, T xe, uint32_t ce, uint32_t c0,
+                                                   uint32_t c1) {
+  const uint32_t lane = threadIdx.x & 63;
+  const bool c_lane = lane < 63 && ce + 2 < c1, e_lane = lane < 62 && ce + 4 < c1;
+  const bool a_lane = lane > 0 && ce >= c0 + 2;
+  const T c_l = est_from_lane(xe, 1), e_l = est_from_lane(xe, 2), a_l = est_from_lane(xe, -1);
+  so.b = xe;
+  if (c_lane) so.c = c_l;
+  if (e_lane) so.e = e_l;
+  if (a_lane) so.a = a_l;
+}
 
-// One unit of the estimate: a run of kSeg columns of the row at coordinates
-// q (all but the last dimension), priced for both predictors; levels 1 and 2
-// into the caller's accumulators, coarser ones into the block's table sh.
-// pos: each dimension's place in the traversal order.
-template <typename T, int J>
-__device__ __forceinline__ void est_unit(const T* __restrict__ x, const EstGeom& g,
-                                         const uint8_t (&pos)[kMaxDims], const uint32_t (&q)[kMaxDims],
-                                         uint32_t seg, bool sampled, T eb, T inv2eb, uint32_t R,
-                                         unsigned long long* sh, uint64_t& acc1l, uint64_t& acc1c,
-                                         uint64_t& acc2l, uint64_t& acc2c) {
-  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
+// A unit of the estimate: a run of 2 x W x J columns (W lanes, J pairs a
+// lane) of the row at coordinates q (all but the last dimension); its
+// scalars.  t_row is the
+// fewest trailing zeros among q, d_row (place p_row in the order, extent
+// n_row, stride s_row) the dimension latest in the order that has them.
+struct EstUnit {
+  uint32_t base, qrow, srow, nrow, c0, c1;
+  int trow, prow;
+  bool odd_along_row;
+};
+template <uint32_t W, int J>
+__device__ __forceinline__ EstUnit est_unit_at(const EstGeom& g, const uint8_t (&pos)[kMaxDims],
+                                               const uint32_t (&q)[kMaxDims], uint32_t seg) {
+  constexpr uint32_t kSeg = 2 * W * J;
   const int last = g.ndim - 1;
   const uint32_t ncol = (uint32_t)g.dims[last];
-  const int pos_last = pos[last];
-  uint32_t base = 0;
+  EstUnit un;
+  un.base = 0;
 #pragma unroll
   for (int e = 0; e < kMaxDims - 1; e++)
-    if (e < last) base += q[e] * (uint32_t)g.stride[e];
-  if (sampled && !est_row_sampled(base / ncol)) return;
-  int trow = 64, prow = -1;
-  uint32_t qrow = 0, srow = 0, nrow = 0;
+    if (e < last) un.base += q[e] * (uint32_t)g.stride[e];
+  un.trow = 64;
+  un.prow = -1;
+  un.qrow = un.srow = un.nrow = 0;
 #pragma unroll
   for (int e = 0; e < kMaxDims - 1; e++) {
     const int te = q[e] ? __builtin_ctz(q[e]) : 64;
-    if (e < last && (te < trow || (te == trow && (int)pos[e] > prow))) {
-      trow = te;
-      prow = pos[e];
-      qrow = q[e];
-      srow = (uint32_t)g.stride[e];
-      nrow = (uint32_t)g.dims[e];
+    if (e < last && (te < un.trow || (te == un.trow && (int)pos[e] > un.prow))) {
+      un.trow = te;
+      un.prow = pos[e];
+      un.qrow = q[e];
+      un.srow = (uint32_t)g.stride[e];
+      un.nrow = (uint32_t)g.dims[e];
     }
   }
-  const uint32_t c0 = seg * kSeg;
-  const uint32_t c1 = ncol - c0 > kSeg ? c0 + kSeg : ncol;
-  const bool odd_along_row = trow > 0 || pos_last > prow;
-  // the odd column's pass (level 1): along the row, or along d_row
-  const uint32_t sd_odd = odd_along_row ? 1u : srow, nd_odd = odd_along_row ? ncol : nrow;
+  un.c0 = seg * kSeg;
+  un.c1 = ncol - un.c0 > kSeg ? un.c0 + kSeg : ncol;
+  un.odd_along_row = un.trow > 0 || (int)pos[last] > un.prow;
+  return un;
+}
+
+// A unit priced for both predictors, every load issued before any is used;
+// levels 1 and 2 into the caller's accumulators, coarser ones into the
+// block's table sh.  For a row with t_row = 0 the odd column lies on level
+// 1, along the row unless d_row comes later in the order, and the even
+// column on level 1 along d_row; otherwise the odd column lies on level 1
+// along the row, and the even column with t_c trailing zeros on level
+// min(t_c, t_row) + 1, along the row when t_c < t_row or t_c = t_row with the
+// row later in the order than d_row, else along d_row.  W lanes take a unit.
+template <typename T, uint32_t W, int J, bool N>
+__device__ __forceinline__ void est_unit(const T* __restrict__ x, const EstGeom& g, int pos_last,
+                                         const EstUnit& un, T eb, T inv2eb, uint32_t R,
+                                         unsigned long long* sh, uint64_t& acc1l, uint64_t& acc1c,
+                                         uint64_t& acc2l, uint64_t& acc2c) {
+  const uint32_t ncol = (uint32_t)g.dims[g.ndim - 1];
+  const uint32_t base = un.base, rem = un.c1 - un.c0;
+  EstStencil<T> se[J], so[J];
+  if (un.trow == 0) {
+    // (uniform) stencils along d_row at step 1 share the row's neighbour
+    // rows: their presence and offsets are the same in every lane (lanes
+    // without a point read a point of the unit and are not counted)
+    const uint32_t q = un.qrow, sr = un.srow, nr = un.nrow;
+    const bool ha = q >= 3, hc = nr - q > 1, he = hc && nr - q > 3;
+    const uint32_t ob = base - sr, oc = hc ? base + sr : base, oa = ha ? base - 3 * sr : base;
+    const uint32_t oe = he ? base + 3 * sr : base;
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      const uint32_t o = 2 * (threadIdx.x % W + j * W);
+      const bool has_even = o < rem, has_odd = o + 1 < rem;
+      const uint32_t ce = has_even ? un.c0 + o : un.c0, co = has_odd ? ce + 1 : ce;
+      EstStencil<T>& e = se[j];
+      e.ha = ha;
+      e.hc = hc;
+      e.he = he;
+      e.x = est_ld<N>(x, base + ce);
+      e.b = est_ld<N>(x, ob + ce);
+      e.c = est_ld<N>(x, oc + ce);
+      e.a = est_ld<N>(x, oa + ce);
+      e.e = est_ld<N>(x, oe + ce);
+      if (un.odd_along_row) {
+        so[j] = est_odd_row_fetch<N>(x, base, ce, co, has_odd, un.c0, un.c1, ncol);
+      } else {
+        EstStencil<T>& d = so[j];
+        d.ha = ha;
+        d.hc = hc;
+        d.he = he;
+        d.x = est_ld<N>(x, base + co);
+        d.b = est_ld<N>(x, ob + co);
+        d.c = est_ld<N>(x, oc + co);
+        d.a = est_ld<N>(x, oa + co);
+        d.e = est_ld<N>(x, oe + co);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      const uint32_t o = 2 * (threadIdx.x % W + j * W);
+      const bool has_even = o < rem, has_odd = o + 1 < rem;
+      const uint32_t ce = has_even ? un.c0 + o : un.c0, co = has_odd ? ce + 1 : ce;
+      const int tc = ce ? __builtin_ctz(ce) : 64;
+      const int t = tc < un.trow ? tc : un.trow;
+      const bool e_row = tc < un.trow || (tc == un.trow && pos_last > un.prow);
+      const uint32_t sp = has_even && t != 64 ? 1u << t : 0u;
+      se[j] = est_fetch<N>(x, base + ce, e_row ? ce : un.qrow, e_row ? ncol : un.nrow, sp,
+                           e_row ? sp : sp * un.srow);
+      // (t_row > 0: the odd column along the row)
+      so[j] = est_odd_row_fetch<N>(x, base, ce, co, has_odd, un.c0, un.c1, ncol);
+    }
+  }
   uint32_t s1l = 0, s1c = 0, s2l = 0, s2c = 0;
 #pragma unroll
   for (int j = 0; j < J; j++) {
-    const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
-    const uint64_t ce64 = (uint64_t)c0 + o;
-    const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
-    const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
-    // the even column: level 1 along d_row when t_row = 0, else level
-    // t + 1 along the row or d_row (t = 64: the origin)
-    const int tc = ce ? __builtin_ctz(ce) : 64;
-    const int t = trow == 0 ? 0 : (tc < trow ? tc : trow);
-    const bool e_row = trow != 0 && (tc < trow || (tc == trow && pos_last > prow));
-    const bool e_ok = has_even && t != 64;
-    const uint32_t sp = e_ok ? 1u << t : 0u;
-    // stencils of both columns, every load issued before any is used
-    const EstStencil<T> se = est_fetch(x, base + ce, e_row ? ce : qrow, e_row ? ncol : nrow, sp,
-                                       e_row ? sp : sp * srow);
-    EstStencil<T> so;
-    if (odd_along_row) {  // (block-uniform)
-      so = est_odd_row(x, base, ce, co, has_odd, c0, c1, ncol, se.x);
-    } else {
-      so = est_fetch(x, base + co, qrow, nd_odd, has_odd ? 1u : 0u, has_odd ? sd_odd : 0u);
-    }
+    const uint32_t o = 2 * (threadIdx.x % W + j * W);
+    const bool has_even = o < rem, has_odd = o + 1 < rem;
+    const uint32_t ce = has_even ? un.c0 + o : un.c0;
+    if (un.odd_along_row) est_odd_row_finish(so[j], se[j].x, ce, un.c0, un.c1);
     uint32_t cl, cc;
-    est_eval(so, eb, inv2eb, R, cl, cc);
+    est_eval(so[j], eb, inv2eb, R, cl, cc);
     if (has_odd) {
       s1l += cl;
       s1c += cc;
     }
-    est_eval(se, eb, inv2eb, R, cl, cc);
-    if (e_ok) {
-      if (t == 0) {
+    est_eval(se[j], eb, inv2eb, R, cl, cc);
+    if (un.trow == 0) {  // (uniform) level 1
+      if (has_even) {
         s1l += cl;
         s1c += cc;
-      } else if (t == 1) {
+      }
+      continue;
+    }
+    const int tc = ce ? __builtin_ctz(ce) : 64;
+    const int t = tc < un.trow ? tc : un.trow;
+    if (has_even && t != 64) {
+      if (t == 1) {
         s2l += cl;
         s2c += cc;
       } else {
@@ -722,11 +804,11 @@ __device__ __forceinline__ void est_flush(uint64_t acc1l, uint64_t acc1c, uint64
     if (lane == 0 && v[k]) atomicAdd(&sh[k], (unsigned long long)v[k]);
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += kEstThreads)
+  for (uint32_t i = threadIdx.x; i < 2 * kMaxLevels; i += blockDim.x)
     if (sh[i]) atomicAdd(cost + i, sh[i]);
 }
 
-template <typename T, int J>
+template <typename T, int J, bool N>
 __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ x, EstGeom g,
                                                           const Meta* __restrict__ m, uint32_t R,
                                                           unsigned long long* cost) {
@@ -736,49 +818,51 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
   const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
   const int last = g.ndim - 1;
   uint64_t acc1l = 0, acc1c = 0, acc2l = 0, acc2c = 0;  // levels 1 and 2
+  // every wave takes its own contiguous run of units; the waves of one XCD
+  // (workgroup b on XCD b mod 8) take runs of one contiguous eighth, so the
+  // rows and planes the stencils reach are read by waves of the same XCD at
+  // about the same time
   const uint32_t nx = gridDim.x % 8 == 0 ? 8 : 1;
-  const uint32_t bpx = gridDim.x / nx, xcd = blockIdx.x % nx, slot = blockIdx.x / nx;
-  const uint64_t region = (g.units + nx - 1) / nx;
-  const uint64_t u_end = (xcd + 1) * region < g.units ? (xcd + 1) * region : g.units;
-  // (block-uniform; loops unrolled so the geometry stays in scalar
-  // registers) the unit u as (row, segment) and the row as coordinates
-  // q[0..last-1], divided out once and then advanced by bpx units a step
-  // with mixed-radix carries
-  uint64_t u = xcd * region + slot;
-  uint32_t seg = (uint32_t)(u % g.segs);
-  uint32_t q[kMaxDims] = {0, 0, 0, 0}, qi[kMaxDims] = {0, 0, 0, 0};
-  {
-    uint64_t r = u / g.segs, ri = bpx / g.segs;
-#pragma unroll
-    for (int e = kMaxDims - 2; e >= 0; --e) {
-      if (e < last) {
-        q[e] = (uint32_t)(r % g.dims[e]);
-        r /= g.dims[e];
-        qi[e] = (uint32_t)(ri % g.dims[e]);
-        ri /= g.dims[e];
-      }
-    }
-  }
-  const uint32_t seg_inc = (uint32_t)(bpx % g.segs);
-  for (; u < u_end; u += bpx) {
-    if (u != xcd * region + slot) {
-      seg += seg_inc;
-      uint32_t carry = 0;
-      if (seg >= g.segs) {
-        seg -= (uint32_t)g.segs;
-        carry = 1;
-      }
+  const uint32_t wpb = kEstThreads / kEstWave;
+  const uint64_t gw = ((uint64_t)(blockIdx.x % nx) * (gridDim.x / nx) + blockIdx.x / nx) * wpb +
+                      threadIdx.x / kEstWave;
+  const uint64_t nw = (uint64_t)gridDim.x * wpb;
+  const uint64_t u0 = g.units * gw / nw, u1 = g.units * (gw + 1) / nw;
+  if (u0 < u1) {
+    // (wave-uniform; loops unrolled so the geometry stays in scalar
+    // registers) the first unit as (row, segment), the row as coordinates
+    // q[0..last-1]; then advanced a unit at a time with carries
+    uint64_t row = u0 / g.segs;
+    uint32_t seg = (uint32_t)(u0 - row * g.segs);
+    uint32_t q[kMaxDims] = {0, 0, 0, 0};
+    {
+      uint64_t r = row;
 #pragma unroll
       for (int e = kMaxDims - 2; e >= 0; --e) {
         if (e < last) {
-          const uint64_t v = (uint64_t)q[e] + qi[e] + carry;
-          carry = v >= g.dims[e] ? 1u : 0u;
-          q[e] = (uint32_t)(carry ? v - g.dims[e] : v);
+          q[e] = (uint32_t)(r % g.dims[e]);
+          r /= g.dims[e];
         }
       }
     }
-    est_unit<T, J>(x, g, g.pos, q, seg, g.sampled != 0, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
-                   acc2c);
+    for (uint64_t u = u0; u < u1; u++) {
+      if (!g.sampled || est_row_sampled(row)) {
+        const EstUnit un = est_unit_at<kEstWave, J>(g, g.pos, q, seg);
+        est_unit<T, kEstWave, J, N>(x, g, g.pos[last], un, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
+                                    acc2c);
+      }
+      if (++seg == g.segs) {
+        seg = 0;
+        row++;
+#pragma unroll
+        for (int e = kMaxDims - 2; e >= 0; --e) {
+          if (e < last) {
+            if (++q[e] < (uint32_t)g.dims[e]) break;
+            q[e] = 0;
+          }
+        }
+      }
+    }
   }
   est_flush(acc1l, acc1c, acc2l, acc2c, sh, cost);
 }
@@ -819,7 +903,9 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __rest
         r /= g.dims[e];
       }
     }
-    est_unit<T, J>(x, g, pos, q, seg, false, eb, inv2eb, R, sh, acc1l, acc1c, acc2l, acc2c);
+    const EstUnit un = est_unit_at<kEstThreads, J>(g, pos, q, seg);
+    est_unit<T, kEstThreads, J, false>(x, g, pos[last], un, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
+                                       acc2c);
   }
   est_flush(acc1l, acc1c, acc2l, acc2c, sh, cost + blockIdx.y * per);
 }
@@ -827,24 +913,42 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __rest
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st) {
   if (g.units == 0) return hipSuccess;
-  // (eight waves a SIMD: a unit's loads are waited for before its arithmetic)
-  dim3 grid((unsigned)(g.units < kEstBlocks ? g.units : kEstBlocks)), block(kEstThreads);
+  // units of one wave, up to four pairs a lane: a unit is up to 512
+  // columns, whose geometry one wave works out for all of them
+  EstGeom w = g;
+  const uint64_t ncol = g.dims[g.ndim - 1];
+  w.pairs = ncol <= 2 * kEstWave ? 1 : ncol <= 4 * kEstWave ? 2 : 4;
+  w.segs = (ncol + 2 * kEstWave * w.pairs - 1) / (2 * kEstWave * w.pairs);
+  w.units = g.units / g.segs * w.segs;
+  const uint64_t wpb = kEstThreads / kEstWave, nb = (w.units + wpb - 1) / wpb;
+  dim3 grid((unsigned)(nb < kEstWaveBlocks ? nb : kEstWaveBlocks)), block(kEstThreads);
   auto* c = reinterpret_cast<unsigned long long*>(cost);
-#define SZG_EST(J)                                                                         \
-  do {                                                                                     \
-    if (dtype == SZ_F32)                                                                   \
-      hipLaunchKernelGGL((k_estimate<float, J>), grid, block, 0, st, (const float*)x, g, m, \
-                         radius, c);                                                       \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_estimate<double, J>), grid, block, 0, st, (const double*)x, g, \
-                         m, radius, c);                                                    \
+  // (32-bit byte offsets when the field is under 4 GiB)
+  const uint64_t bytes = g.stride[0] * g.dims[0] * (dtype == SZ_F32 ? 4 : 8);
+  const bool narrow = bytes <= 0xFFFFFFFFull;
+#define SZG_EST2(T, J, N)                                                                    \
+  hipLaunchKernelGGL((k_estimate<T, J, N>), grid, block, 0, st, (const T*)x, w, m, radius, c)
+#define SZG_EST(J)                  \
+  do {                              \
+    if (dtype == SZ_F32) {          \
+      if (narrow)                   \
+        SZG_EST2(float, J, true);   \
+      else                          \
+        SZG_EST2(float, J, false);  \
+    } else {                        \
+      if (narrow)                   \
+        SZG_EST2(double, J, true);  \
+      else                          \
+        SZG_EST2(double, J, false); \
+    }                               \
   } while (0)
-  if (g.pairs == 1)
+  if (w.pairs == 1)
     SZG_EST(1);
-  else if (g.pairs == 2)
+  else if (w.pairs == 2)
     SZG_EST(2);
   else
     SZG_EST(4);
+#undef SZG_EST2
 #undef SZG_EST
   return hipGetLastError();
 }
@@ -900,7 +1004,7 @@ __device__ __forceinline__ void cand_flush(unsigned long long* sh, CandSums& a, 
   for (int d = 0; d < 3; d++) a.bl[d] = a.bc[d] = 0;
   a.ql[0] = a.qc[0] = a.ql[1] = a.qc[1] = 0;
 }
-template <typename T, int J>
+template <typename T, int J, bool N>
 __global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restrict__ x, EstGeom g,
                                                                const uint32_t* __restrict__ rows,
                                                                uint64_t nrows,
@@ -966,19 +1070,20 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restri
       const bool e_row = has_even && tc <= tr && tc != 64;
       const bool e_cand = has_even && tr <= tc && tr != 64;
       const uint32_t sr = e_row ? 1u << tc : 0u, sc = e_cand ? 1u << tr : 0u;
-      const T xe = x[base + ce];
+      const T xe = est_ld<N>(x, base + ce);
+      EstStencil<T> so = est_odd_row_fetch<N>(x, base, ce, co, has_odd, c0, c1, ncol);
       EstStencil<T> ev_row{}, ev_d[2], od_d[2];
-      if (tr != 0) ev_row = est_fetch(x, base + ce, ce, ncol, sr, sr);
+      if (tr != 0) ev_row = est_fetch<N>(x, base + ce, ce, ncol, sr, sr);
 #pragma unroll
       for (int e = 0; e < 2; e++) {
         if (e < last && ((rmask >> e) & 1u)) {
-          ev_d[e] = est_fetch(x, base + ce, q[e], (uint32_t)g.dims[e], sc, sc * (uint32_t)g.stride[e]);
+          ev_d[e] = est_fetch<N>(x, base + ce, q[e], (uint32_t)g.dims[e], sc, sc * (uint32_t)g.stride[e]);
           if (tr == 0)
-            od_d[e] = est_fetch(x, base + co, q[e], (uint32_t)g.dims[e], has_odd ? 1u : 0u,
+            od_d[e] = est_fetch<N>(x, base + co, q[e], (uint32_t)g.dims[e], has_odd ? 1u : 0u,
                                 has_odd ? (uint32_t)g.stride[e] : 0u);
         }
       }
-      const EstStencil<T> so = est_odd_row(x, base, ce, co, has_odd, c0, c1, ncol, xe);
+      est_odd_row_finish(so, xe, ce, c0, c1);
       uint32_t cl, cc;
       est_eval(so, eb, inv2eb, R, cl, cc);
       if (has_odd) {
@@ -1059,14 +1164,24 @@ hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, cons
   if (units == 0) return hipSuccess;
   dim3 grid((unsigned)(units < kCandBlocks ? units : kCandBlocks)), block(kEstThreads);
   auto* c = reinterpret_cast<unsigned long long*>(bucket);
-#define SZG_CAND(J)                                                                              \
-  do {                                                                                           \
-    if (dtype == SZ_F32)                                                                         \
-      hipLaunchKernelGGL((k_estimate_cand<float, J>), grid, block, 0, st, (const float*)x, g,     \
-                         rows, nrows, m, radius, c);                                             \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_estimate_cand<double, J>), grid, block, 0, st, (const double*)x, g,   \
-                         rows, nrows, m, radius, c);                                             \
+  const uint64_t bytes = g.stride[0] * g.dims[0] * (dtype == SZ_F32 ? 4 : 8);
+  const bool narrow = bytes <= 0xFFFFFFFFull;
+#define SZG_CAND2(T, J, N)                                                                   \
+  hipLaunchKernelGGL((k_estimate_cand<T, J, N>), grid, block, 0, st, (const T*)x, g, rows, nrows, \
+                     m, radius, c)
+#define SZG_CAND(J)                  \
+  do {                               \
+    if (dtype == SZ_F32) {           \
+      if (narrow)                    \
+        SZG_CAND2(float, J, true);   \
+      else                           \
+        SZG_CAND2(float, J, false);  \
+    } else {                         \
+      if (narrow)                    \
+        SZG_CAND2(double, J, true);  \
+      else                           \
+        SZG_CAND2(double, J, false); \
+    }                                \
   } while (0)
   if (g.pairs == 1)
     SZG_CAND(1);
@@ -1074,6 +1189,7 @@ hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, cons
     SZG_CAND(2);
   else
     SZG_CAND(4);
+#undef SZG_CAND2
 #undef SZG_CAND
   return hipGetLastError();
 }
