@@ -72,7 +72,10 @@ struct sz_ctx {
   uint8_t* enc_len = nullptr;
   uint32_t* symtab = nullptr;
   uint64_t* totals = nullptr;
-  uint64_t* lvl_cost = nullptr;  // adaptive interpolation: [order][level][linear, cubic] cost sums
+  // adaptive interpolation: the orders' sampled sums ([order][level][linear,
+  // cubic], or the candidate buckets), then the chosen order's level sums
+  // and the order chosen on the device
+  uint64_t* lvl_cost = nullptr;
   CodebookScratch cb{};
   DecodeTables dt{};
   Meta* h_meta = nullptr;       // pinned
@@ -420,7 +423,8 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->enc_len, kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->symtab, sizeof(uint32_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->totals, sizeof(uint64_t) * 4), "hipMalloc");
-  CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * 2 * kMaxLevels * kMaxOrders), "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * (kCandBuckets + 2 * kMaxLevels + 1)),
+            "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_a, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_b, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.w, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
@@ -784,12 +788,18 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
     // the cheapest first in lexicographic order
     bool identity = true;
     for (int j = 0; j < s.ndim; j++) identity = identity && s.order[j] == j;
+    uint64_t* const lvl = ctx->lvl_cost + kCandBuckets;  // the chosen order's level sums
+    uint8_t* const chosen = reinterpret_cast<uint8_t*>(lvl + 2 * kMaxLevels);
+    bool device_order = false;  // (the order chosen on the device, read back below)
+    std::array<std::array<uint8_t, kMaxDims>, kMaxOrders> perms;
     if (identity && s.ndim > 1) {
-      std::array<std::array<uint8_t, kMaxDims>, kMaxOrders> perms;
       size_t nperm = 0;
       std::array<uint8_t, kMaxDims> pm{0, 1, 2, 3};
       do perms[nperm++] = pm;
       while (std::next_permutation(pm.begin(), pm.begin() + s.ndim));
+      uint8_t pos[kMaxOrders][kMaxDims] = {};
+      for (size_t i = 0; i < nperm; i++)
+        for (int j = 0; j < s.ndim; j++) pos[i][perms[i][j]] = (uint8_t)j;
       const size_t per = 2 * kMaxLevels;
       // (fields of up to three dimensions) the candidate buckets of one pass
       const bool cand = s.ndim <= 3;
@@ -837,9 +847,6 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
           ctx->est_ndim = s.ndim;
           for (int d = 0; d < kMaxDims; d++) ctx->est_dims[d] = d < s.ndim ? s.dims[d] : 0;
         }
-        uint8_t pos[kMaxOrders][kMaxDims] = {};
-        for (size_t i = 0; i < nperm; i++)
-          for (int j = 0; j < s.ndim; j++) pos[i][perms[i][j]] = (uint8_t)j;
         const EstGeom eg = make_estimate_geom(s.ndim, s.dims, perms[0].data());
         CHECK_HIP(timed(ctx, "estimate", st, [&] {
                     if (cand)
@@ -853,47 +860,46 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                                                   ctx->lvl_cost, st);
                   }), "estimate");
       }
-      std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
-      CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * ncost,
-                               hipMemcpyDeviceToHost, st), "memcpy");
-      CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
-      if (cand) {  // the buckets into each order's sums
-        const std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> bucket = cost;
-        for (size_t i = 0; i < nperm; i++) {
-          uint8_t pi[kMaxDims] = {};
-          for (int j = 0; j < s.ndim; j++) pi[perms[i][j]] = (uint8_t)j;
-          cand_combine(bucket.data(), s.ndim, pi, cost.data() + per * i);
-        }
-      }
       const int L = level_count(s.ndim, s.dims);
-      uint64_t best = ~0ull;
-      size_t bi = 0;
-      for (size_t i = 0; i < nperm; i++) {
-        uint64_t total = 0;
-        for (int l = 1; l <= L; l++) {
-          const uint64_t lin = cost[per * i + 2 * (l - 1)], cub = cost[per * i + 2 * (l - 1) + 1];
-          total += cub < lin ? cub : lin;
+      if (cand) {  // chosen on the device: the full estimate follows with no round trip
+        CHECK_HIP(launch_choose_order(ctx->lvl_cost, s.ndim, pos, (uint32_t)nperm, L, chosen, st),
+                  "choose_order");
+        device_order = true;
+      } else {
+        std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
+        CHECK_HIP(hipMemcpyAsync(cost.data(), ctx->lvl_cost, sizeof(uint64_t) * ncost,
+                                 hipMemcpyDeviceToHost, st), "memcpy");
+        CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        uint64_t best = ~0ull;
+        size_t bi = 0;
+        for (size_t i = 0; i < nperm; i++) {
+          uint64_t total = 0;
+          for (int l = 1; l <= L; l++) {
+            const uint64_t lin = cost[per * i + 2 * (l - 1)], cub = cost[per * i + 2 * (l - 1) + 1];
+            total += cub < lin ? cub : lin;
+          }
+          if (total < best) {
+            best = total;
+            bi = i;
+          }
         }
-        if (total < best) {
-          best = total;
-          bi = i;
-        }
-      }
-      for (int j = 0; j < s.ndim; j++) {
-        s.order[j] = perms[bi][j];
-        hdr[41 + j] = perms[bi][j];
+        for (int j = 0; j < s.ndim; j++) s.order[j] = perms[bi][j];
       }
     }
-    CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->lvl_cost), 0, 4 * kMaxLevels, st),
-              "fill");
-    const EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);
+    CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(lvl), 0, 4 * kMaxLevels, st), "fill");
+    const EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);  // (places: the device's choice)
     CHECK_HIP(timed(ctx, "estimate", st, [&] {
-                return launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, ctx->lvl_cost, st);
+                return launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, lvl, st,
+                                       device_order ? chosen + 1 : nullptr);
               }), "estimate");
-    uint64_t cost[2 * kMaxLevels];
-    CHECK_HIP(hipMemcpyAsync(cost, ctx->lvl_cost, sizeof(cost), hipMemcpyDeviceToHost, st),
-              "memcpy");
+    uint64_t cost[2 * kMaxLevels + 1];  // the level sums, then the device's choice
+    CHECK_HIP(hipMemcpyAsync(cost, lvl, sizeof(cost), hipMemcpyDeviceToHost, st), "memcpy");
     CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (device_order) {
+      const uint8_t bi = static_cast<uint8_t>(cost[2 * kMaxLevels] & 0xFF);
+      for (int j = 0; j < s.ndim; j++) s.order[j] = perms[bi][j];
+    }
+    for (int j = 0; j < s.ndim; j++) hdr[41 + j] = s.order[j];
     uint32_t mask = 0;
     for (int l = 1; l <= kMaxLevels; l++) {
       lvl_pred[l] = cost[2 * (l - 1) + 1] <= cost[2 * (l - 1)] ? SZ_INTERP_CUBIC : SZ_INTERP_LINEAR;

@@ -150,8 +150,10 @@ EstGeom make_estimate_geom(int ndim, const uint64_t* dims, const uint8_t* order)
 __host__ __device__ inline bool est_row_sampled(uint64_t r) {
   return (((uint32_t)r * 0x9E3779B1u) >> 29) == 0;
 }
+// (pos_dev: the order's places read from the device, else g's)
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
-                           uint32_t radius, uint64_t* cost, hipStream_t st);
+                           uint32_t radius, uint64_t* cost, hipStream_t st,
+                           const uint8_t* pos_dev = nullptr);
 // The sampled estimate of every dimension order of a field of up to three
 // dimensions in one pass: costs per (level, candidate set, dimension) into
 // 2 * 3 * 8 * kMaxLevels buckets (the rows listed in rows[], grouped by
@@ -169,6 +171,12 @@ void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t
 // the listed rows are grouped by: 8 x (fewest trailing zeros among its
 // coordinates) + the mask of the dimensions that have them.
 uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r);
+// The order choice from the buckets on the device (no host round trip):
+// of the norders orders (orders[k][d]: the place of dimension d), the one
+// whose sum over levels 1..levels of the cheaper cost sum is least, the
+// first on ties; chosen[0] its index, chosen[1..4] its places.
+hipError_t launch_choose_order(const uint64_t* bucket, int ndim, const uint8_t (*orders)[kMaxDims],
+                               uint32_t norders, int levels, uint8_t* chosen, hipStream_t st);
 // The sampled estimate of norders dimension orders (orders[k][d]: the place
 // of dimension d in order k) in one launch, over the sampled rows listed in
 // rows[] (ascending flat row indices, est_row_sampled); order k's sums at

@@ -605,7 +605,6 @@ __device__ __forceinline__ double est_from_lane(double v, int k) {
   const uint64_t lo = est_wave_shift((uint32_t)b, k), hi = est_wave_shift((uint32_t)(b >> 32), k);
   return __longlong_as_double((long long)((hi << 32) | lo));
 }
-
 // The odd column co = ce + 1's stencil along the row, in a unit of columns
 // [c0, c1) dealt as (even, odd) pairs to consecutive lanes: its neighbours
 // are the even columns of this lane and of lanes -1, +1 and +2.  The fetch
@@ -810,6 +809,7 @@ __device__ __forceinline__ void est_flush(uint64_t acc1l, uint64_t acc1c, uint64
 
 template <typename T, int J, bool N>
 __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ x, EstGeom g,
+                                                          const uint8_t* __restrict__ pos_dev,
                                                           const Meta* __restrict__ m, uint32_t R,
                                                           unsigned long long* cost) {
   __shared__ unsigned long long sh[2 * kMaxLevels];
@@ -817,6 +817,9 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
   __syncthreads();
   const T eb = (T)m->eb, inv2eb = (T)m->inv2eb;
   const int last = g.ndim - 1;
+  uint8_t pos[kMaxDims];  // the order's places: the argument's, or the device's choice
+#pragma unroll
+  for (int e = 0; e < kMaxDims; e++) pos[e] = pos_dev ? pos_dev[e] : g.pos[e];
   uint64_t acc1l = 0, acc1c = 0, acc2l = 0, acc2c = 0;  // levels 1 and 2
   // every wave takes its own contiguous run of units; the waves of one XCD
   // (workgroup b on XCD b mod 8) take runs of one contiguous eighth, so the
@@ -847,8 +850,8 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
     }
     for (uint64_t u = u0; u < u1; u++) {
       if (!g.sampled || est_row_sampled(row)) {
-        const EstUnit un = est_unit_at<kEstWave, J>(g, g.pos, q, seg);
-        est_unit<T, kEstWave, J, N>(x, g, g.pos[last], un, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
+        const EstUnit un = est_unit_at<kEstWave, J>(g, pos, q, seg);
+        est_unit<T, kEstWave, J, N>(x, g, pos[last], un, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
                                     acc2c);
       }
       if (++seg == g.segs) {
@@ -911,7 +914,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __rest
 }
 
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
-                           uint32_t radius, uint64_t* cost, hipStream_t st) {
+                           uint32_t radius, uint64_t* cost, hipStream_t st, const uint8_t* pos_dev) {
   if (g.units == 0) return hipSuccess;
   // units of one wave, up to four pairs a lane: a unit is up to 512
   // columns, whose geometry one wave works out for all of them
@@ -927,7 +930,8 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
   const uint64_t bytes = g.stride[0] * g.dims[0] * (dtype == SZ_F32 ? 4 : 8);
   const bool narrow = bytes <= 0xFFFFFFFFull;
 #define SZG_EST2(T, J, N)                                                                    \
-  hipLaunchKernelGGL((k_estimate<T, J, N>), grid, block, 0, st, (const T*)x, w, m, radius, c)
+  hipLaunchKernelGGL((k_estimate<T, J, N>), grid, block, 0, st, (const T*)x, w, pos_dev, m, radius, \
+                     c)
 #define SZG_EST(J)                  \
   do {                              \
     if (dtype == SZ_F32) {          \
@@ -1215,20 +1219,64 @@ uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r) {
 
 // An order's cost sums from the buckets: level t + 1 gathers, for every
 // candidate set C, the bucket of C's dimension that comes last in the order.
-void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost) {
-  for (uint32_t t = 0; t < (uint32_t)kMaxLevels; t++) {
-    uint64_t l = 0, c = 0;
-    for (uint32_t C = 1; C < (1u << ndim); C++) {
-      int best = -1;
-      for (int d = 0; d < ndim; d++)
-        if (((C >> d) & 1u) && (best < 0 || pos[d] > pos[best])) best = d;
-      const uint32_t b = cand_bucket(t, C, (uint32_t)best);
-      l += bucket[b];
-      c += bucket[b + 1];
-    }
-    cost[2 * t] = l;
-    cost[2 * t + 1] = c;
+__host__ __device__ inline void cand_level(const uint64_t* bucket, int ndim, const uint8_t* pos,
+                                           uint32_t t, uint64_t& l, uint64_t& c) {
+  l = c = 0;
+  for (uint32_t C = 1; C < (1u << ndim); C++) {
+    int best = -1;
+    for (int d = 0; d < ndim; d++)
+      if (((C >> d) & 1u) && (best < 0 || pos[d] > pos[best])) best = d;
+    const uint32_t b = cand_bucket(t, C, (uint32_t)best);
+    l += bucket[b];
+    c += bucket[b + 1];
   }
+}
+void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost) {
+  for (uint32_t t = 0; t < (uint32_t)kMaxLevels; t++) cand_level(bucket, ndim, pos, t, cost[2 * t], cost[2 * t + 1]);
+}
+
+// The order choice on the device: every order's sum over levels 1..L of its
+// cheaper cost sum, the least first in the list (orders[k]: the place of
+// each dimension); chosen[0] the index, chosen[1..] its places.
+__global__ __launch_bounds__(256) void k_choose_order(const uint64_t* __restrict__ bucket_g, int ndim,
+                                                      EstOrders o, uint32_t norders, int L,
+                                                      uint8_t* chosen) {
+  __shared__ uint64_t bucket[kCandBuckets];
+  __shared__ unsigned long long total[kMaxOrders];
+  for (uint32_t i = threadIdx.x; i < kCandBuckets; i += blockDim.x) bucket[i] = bucket_g[i];
+  for (uint32_t i = threadIdx.x; i < kMaxOrders; i += blockDim.x) total[i] = 0;
+  __syncthreads();
+  // a lane per (order, level)
+  for (uint32_t i = threadIdx.x; i < norders * (uint32_t)L; i += blockDim.x) {
+    const uint32_t k = i / (uint32_t)L, t = i % (uint32_t)L;
+    uint64_t l, c;
+    cand_level(bucket, ndim, o.pos[k], t, l, c);
+    atomicAdd(&total[k], (unsigned long long)(c < l ? c : l));
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  uint64_t best = ~0ull;
+  uint32_t bi = 0;
+  for (uint32_t k = 0; k < norders; k++) {
+    if (total[k] < best) {
+      best = total[k];
+      bi = k;
+    }
+  }
+  chosen[0] = (uint8_t)bi;
+  for (int d = 0; d < kMaxDims; d++) chosen[1 + d] = o.pos[bi][d];
+}
+
+hipError_t launch_choose_order(const uint64_t* bucket, int ndim, const uint8_t (*orders)[kMaxDims],
+                               uint32_t norders, int levels, uint8_t* chosen, hipStream_t st) {
+  if (norders == 0 || norders > (uint32_t)kMaxOrders || ndim < 1 || ndim > 3)
+    return hipErrorInvalidValue;
+  EstOrders o{};
+  for (uint32_t k = 0; k < norders; k++)
+    for (int d = 0; d < kMaxDims; d++) o.pos[k][d] = orders[k][d];
+  hipLaunchKernelGGL(k_choose_order, dim3(1), dim3(256), 0, st, bucket, ndim, o, norders, levels,
+                     chosen);
+  return hipGetLastError();
 }
 
 hipError_t launch_estimate_orders(const void* x, int dtype, const EstGeom& g,
