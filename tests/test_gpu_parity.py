@@ -157,6 +157,11 @@ ADAPT_CASES = [
     ("ad-R2-unpred", lambda: synth.random_field((10, 33, 140), seed=66), "rel", 1e-3, 2, 2, 1024, None),
     ("ad-pw-mixed-signs", lambda: mixed_signs((30, 28, 26), 67), "pwrel", 1e-3, 2, 32768, 4096, None),
     ("ad-specials", lambda: specials((20, 22, 24), 68), "rel", 1e-2, 2, 32768, 4096, None),
+    # the default order chosen among 24 (four dimensions, on the host) and
+    # among six in f64 (on the device); the oracle picks (1, 0, 2, 3) and
+    # (2, 1, 0) here
+    ("ad-4d-default", lambda: synth.random_field((6, 10, 8, 40), seed=69), "rel", 1e-3, 2, 32768, 1024, None),
+    ("ad-f64-order", lambda: synth.random_field((21, 40, 70), seed=70, dtype=np.float64), "rel", 1e-3, 2, 32768, 1024, None),
 ]
 
 
