@@ -79,6 +79,7 @@ struct sz_ctx {
   CodebookScratch cb{};
   DecodeTables dt{};
   Meta* h_meta = nullptr;       // pinned
+  uint64_t* h_lvl = nullptr;    // pinned: the adaptive level sums, then the device's order choice
   uint8_t* h_header = nullptr;  // pinned
   uint64_t last_n = 0;
   const uint16_t* last_codes = nullptr;  // the codes of the last compression
@@ -155,6 +156,7 @@ hipEvent_t get_event(sz_ctx* c) {
 // usually a few tens of microseconds, and a blocking wait adds its wake-up
 // time to every call), then waited for by blocking.
 constexpr int kSpinMicros = 500;
+constexpr int kSpinLongMicros = 2000;  // (a wait behind the whole adaptive estimate)
 hipError_t mark(hipEvent_t& ev, hipStream_t st) {
   if (!ev) {
     hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -162,18 +164,18 @@ hipError_t mark(hipEvent_t& ev, hipStream_t st) {
   }
   return hipEventRecord(ev, st);
 }
-hipError_t wait_mark(hipEvent_t ev) {
+hipError_t wait_mark(hipEvent_t ev, int spin_us = kSpinMicros) {
   const auto t0 = std::chrono::steady_clock::now();
   for (;;) {
     const hipError_t e = hipEventQuery(ev);
     if (e != hipErrorNotReady) return e;
-    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros))
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(spin_us))
       return hipEventSynchronize(ev);
   }
 }
-hipError_t wait_stream(sz_ctx* c, hipStream_t st) {
+hipError_t wait_stream(sz_ctx* c, hipStream_t st, int spin_us = kSpinMicros) {
   hipError_t e = mark(c->done, st);
-  return e == hipSuccess ? wait_mark(c->done) : e;
+  return e == hipSuccess ? wait_mark(c->done, spin_us) : e;
 }
 
 template <class F>
@@ -444,6 +446,11 @@ int ensure_fixed(sz_ctx* ctx) {
   ctx->dt.keys_a = ctx->cb.keys_a;
   ctx->dt.keys_b = ctx->cb.keys_b;
   CHECK_HIP(hipHostMalloc((void**)&ctx->h_meta, sizeof(Meta), hipHostMallocDefault), "hipHostMalloc");
+  CHECK_HIP(hipHostMalloc((void**)&ctx->h_lvl, sizeof(uint64_t) * (2 * kMaxLevels + 1),
+                          hipHostMallocDefault), "hipHostMalloc");
+  // the host's markers, made here so that no call creates them
+  CHECK_HIP(hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming), "hipEventCreate");
+  CHECK_HIP(hipEventCreateWithFlags(&ctx->header, hipEventDisableTiming), "hipEventCreate");
   CHECK_HIP(hipHostMalloc((void**)&ctx->h_header, kHeaderBytes, hipHostMallocDefault), "hipHostMalloc");
   return SZ_OK;
 }
@@ -677,6 +684,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
   for (void* p : fixed)
     if (p) (void)hipFree(p);
   if (ctx->h_meta) (void)hipHostFree(ctx->h_meta);
+  if (ctx->h_lvl) (void)hipHostFree(ctx->h_lvl);
   if (ctx->h_header) (void)hipHostFree(ctx->h_header);
   for (auto& p : ctx->pending) {
     (void)hipEventDestroy(p.a);
@@ -892,9 +900,10 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                 return launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, lvl, st,
                                        device_order ? chosen + 1 : nullptr);
               }), "estimate");
-    uint64_t cost[2 * kMaxLevels + 1];  // the level sums, then the device's choice
-    CHECK_HIP(hipMemcpyAsync(cost, lvl, sizeof(cost), hipMemcpyDeviceToHost, st), "memcpy");
-    CHECK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const uint64_t* cost = ctx->h_lvl;  // the level sums, then the device's choice
+    CHECK_HIP(hipMemcpyAsync(ctx->h_lvl, lvl, sizeof(uint64_t) * (2 * kMaxLevels + 1),
+                             hipMemcpyDeviceToHost, st), "memcpy");
+    CHECK_HIP(wait_stream(ctx, st, kSpinLongMicros), "wait");
     if (device_order) {
       const uint8_t bi = static_cast<uint8_t>(cost[2 * kMaxLevels] & 0xFF);
       for (int j = 0; j < s.ndim; j++) s.order[j] = perms[bi][j];
