@@ -531,7 +531,7 @@ hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out
 // time.  Flat indices fit 32 bits (fields hold fewer than 2^32 points).
 constexpr uint32_t kEstThreads = 256;
 constexpr uint32_t kEstWave = 64;          // lanes of a unit of the full estimate
-constexpr uint32_t kEstWaveBlocks = 2048;  // most workgroups of the full estimate
+constexpr uint32_t kEstWaveBlocks = 8192;  // most workgroups of the full estimate
 constexpr uint32_t kEstBlocks = 8192;      // most workgroups of the per-order estimate
 
 template <typename T>
