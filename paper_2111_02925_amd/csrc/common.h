@@ -158,15 +158,13 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
 // dimensions in one pass: costs per (level, candidate set, dimension) into
 // 2 * 3 * 8 * kMaxLevels buckets (the rows listed in rows[], grouped by
 // cand_row_class for speed, or with rows null, the nrows rows of the field
-// that est_row_sampled takes); cand_combine
-// gives one order's sums (pos[d]: the place of dimension d in the order),
-// 2 * kMaxLevels values (linear, cubic per level).
+// that est_row_sampled takes); launch_choose_order adds up each order's
+// sums from them.
 constexpr uint32_t kCandBuckets = 2 * 3 * 8 * kMaxLevels;  // (level, set, dimension) x {linear, cubic}
 static_assert(kCandBuckets <= 2 * kMaxLevels * kMaxOrders, "the buckets share the orders' cost buffer");
 hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, const uint32_t* rows,
                                 uint64_t nrows, const Meta* m, uint32_t radius, uint64_t* bucket,
                                 hipStream_t st);
-void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost);
 // The class of row r (flat index over every dimension but the last) that
 // the listed rows are grouped by: 8 x (fewest trailing zeros among its
 // coordinates) + the mask of the dimensions that have them.

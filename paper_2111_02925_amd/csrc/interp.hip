@@ -1219,7 +1219,7 @@ uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r) {
 
 // An order's cost sums from the buckets: level t + 1 gathers, for every
 // candidate set C, the bucket of C's dimension that comes last in the order.
-__host__ __device__ inline void cand_level(const uint64_t* bucket, int ndim, const uint8_t* pos,
+__device__ __forceinline__ void cand_level(const uint64_t* bucket, int ndim, const uint8_t* pos,
                                            uint32_t t, uint64_t& l, uint64_t& c) {
   l = c = 0;
   for (uint32_t C = 1; C < (1u << ndim); C++) {
@@ -1230,9 +1230,6 @@ __host__ __device__ inline void cand_level(const uint64_t* bucket, int ndim, con
     l += bucket[b];
     c += bucket[b + 1];
   }
-}
-void cand_combine(const uint64_t* bucket, int ndim, const uint8_t* pos, uint64_t* cost) {
-  for (uint32_t t = 0; t < (uint32_t)kMaxLevels; t++) cand_level(bucket, ndim, pos, t, cost[2 * t], cost[2 * t + 1]);
 }
 
 // The order choice on the device: every order's sum over levels 1..L of its
