@@ -974,7 +974,7 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
 // point's buckets are (t_c, {last}) when t_c < t_row (summed over the block
 // by level), (t_row, R + {last}) when t_c = t_row and (t_row, R) when
 // t_c > t_row (summed by lane while the class repeats: the listed rows come
-// grouped by class, and a workgroup takes a contiguous run of them).
+// grouped by class, and a wave takes a contiguous run of them).
 constexpr uint32_t kCandBlocks = 2048;  // most workgroups of the launch
 __host__ __device__ inline uint32_t cand_bucket(uint32_t t, uint32_t C, uint32_t d) {
   return ((t * 8 + C) * 3 + d) * 2;
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restri
                                                                uint64_t nrows,
                                                                const Meta* __restrict__ m,
                                                                uint32_t R, unsigned long long* bucket) {
-  constexpr uint32_t kSeg = 2 * kEstThreads * J;  // columns per unit
+  constexpr uint32_t kSeg = 2 * kEstWave * J;  // columns per unit (one wave's)
   __shared__ unsigned long long sh[kCandBuckets];
   for (uint32_t i = threadIdx.x; i < kCandBuckets; i += kEstThreads) sh[i] = 0;
   __syncthreads();
@@ -1024,10 +1024,13 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restri
   uint64_t a0l = 0, a0c = 0, a1l = 0, a1c = 0;  // t_c < t_row, levels 1 and 2
   CandSums sums = {};
   uint32_t held_t = 64, held_r = 0;  // the class sums holds (none yet)
+  // every wave takes its own contiguous run of units
+  const uint64_t wpb = kEstThreads / kEstWave, nw = (uint64_t)gridDim.x * wpb;
+  const uint64_t gw = (uint64_t)blockIdx.x * wpb + threadIdx.x / kEstWave;
   const uint64_t units = nrows * g.segs;
-  const uint64_t u0 = units * blockIdx.x / gridDim.x, u1 = units * (blockIdx.x + 1) / gridDim.x;
+  const uint64_t u0 = units * gw / nw, u1 = units * (gw + 1) / nw;
   for (uint64_t u = u0; u < u1; u++) {
-    // (block-uniform) the unit's row, its coordinates and class
+    // (wave-uniform) the unit's row, its coordinates and class
     const uint64_t k = u / g.segs;
     const uint32_t seg = (uint32_t)(u - k * g.segs);
     if (!rows && !est_row_sampled(k)) continue;  // (no list: every row, the sampled ones taken)
@@ -1063,7 +1066,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_cand(const T* __restri
     uint32_t ubl[3] = {0, 0, 0}, ubc[3] = {0, 0, 0}, uql[2] = {0, 0}, uqc[2] = {0, 0};
 #pragma unroll
     for (int j = 0; j < J; j++) {
-      const uint32_t o = 2 * (threadIdx.x + j * kEstThreads);
+      const uint32_t o = 2 * (threadIdx.x % kEstWave + j * kEstWave);
       const uint64_t ce64 = (uint64_t)c0 + o;
       const bool has_even = ce64 < c1, has_odd = ce64 + 1 < c1;
       const uint32_t ce = has_even ? (uint32_t)ce64 : c0, co = has_odd ? ce + 1 : ce;
@@ -1164,14 +1167,20 @@ hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, cons
                                 uint64_t nrows, const Meta* m, uint32_t radius, uint64_t* bucket,
                                 hipStream_t st) {
   if (g.ndim < 2 || g.ndim > 3) return hipErrorInvalidValue;
-  const uint64_t units = nrows * g.segs;
+  // units of one wave, up to four pairs a lane (as the full estimate's)
+  EstGeom w = g;
+  const uint64_t ncol = g.dims[g.ndim - 1];
+  w.pairs = ncol <= 2 * kEstWave ? 1 : ncol <= 4 * kEstWave ? 2 : 4;
+  w.segs = (ncol + 2 * kEstWave * w.pairs - 1) / (2 * kEstWave * w.pairs);
+  const uint64_t units = nrows * w.segs, wpb = kEstThreads / kEstWave;
   if (units == 0) return hipSuccess;
-  dim3 grid((unsigned)(units < kCandBlocks ? units : kCandBlocks)), block(kEstThreads);
+  const uint64_t nb = (units + wpb - 1) / wpb;
+  dim3 grid((unsigned)(nb < kCandBlocks ? nb : kCandBlocks)), block(kEstThreads);
   auto* c = reinterpret_cast<unsigned long long*>(bucket);
   const uint64_t bytes = g.stride[0] * g.dims[0] * (dtype == SZ_F32 ? 4 : 8);
   const bool narrow = bytes <= 0xFFFFFFFFull;
 #define SZG_CAND2(T, J, N)                                                                   \
-  hipLaunchKernelGGL((k_estimate_cand<T, J, N>), grid, block, 0, st, (const T*)x, g, rows, nrows, \
+  hipLaunchKernelGGL((k_estimate_cand<T, J, N>), grid, block, 0, st, (const T*)x, w, rows, nrows, \
                      m, radius, c)
 #define SZG_CAND(J)                  \
   do {                               \
@@ -1187,9 +1196,9 @@ hipError_t launch_estimate_cand(const void* x, int dtype, const EstGeom& g, cons
         SZG_CAND2(double, J, false); \
     }                                \
   } while (0)
-  if (g.pairs == 1)
+  if (w.pairs == 1)
     SZG_CAND(1);
-  else if (g.pairs == 2)
+  else if (w.pairs == 2)
     SZG_CAND(2);
   else
     SZG_CAND(4);
