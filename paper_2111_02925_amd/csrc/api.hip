@@ -78,6 +78,7 @@ struct sz_ctx {
   uint64_t* lvl_cost = nullptr;
   CodebookScratch cb{};
   DecodeTables dt{};
+  uint64_t* mm_part = nullptr;  // the range pass's per-workgroup keys (2 x kMinmaxBlocks)
   Meta* h_meta = nullptr;       // pinned
   uint64_t* h_lvl = nullptr;    // pinned: the adaptive level sums, then the device's order choice
   uint8_t* h_header = nullptr;  // pinned
@@ -427,6 +428,7 @@ int ensure_fixed(sz_ctx* ctx) {
   CHECK_HIP(hipMalloc(&ctx->totals, sizeof(uint64_t) * 4), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->lvl_cost, sizeof(uint64_t) * (kCandBuckets + 2 * kMaxLevels + 1)),
             "hipMalloc");
+  CHECK_HIP(hipMalloc(&ctx->mm_part, sizeof(uint64_t) * 2 * kMinmaxBlocks), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_a, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.keys_b, sizeof(uint64_t) * kMaxSym), "hipMalloc");
   CHECK_HIP(hipMalloc(&ctx->cb.w, sizeof(uint32_t) * 2 * kMaxSym), "hipMalloc");
@@ -677,7 +679,7 @@ void sz_ctx_destroy(sz_ctx* ctx) {
                  &ctx->est_rows})
     if (b->p) (void)hipFree(b->p);
   void* fixed[] = {ctx->meta, ctx->hist, ctx->hist_part, ctx->enc_code, ctx->enc_len, ctx->symtab, ctx->totals,
-                   ctx->lvl_cost,
+                   ctx->lvl_cost, ctx->mm_part,
                    ctx->cb.keys_a, ctx->cb.keys_b, ctx->cb.w, ctx->cb.parent, ctx->cb.depth,
                    ctx->cb.merged, ctx->cb.phase_end, ctx->cb.leaf_sym, ctx->dt.lut, ctx->dt.lut2, ctx->dt.l2, ctx->dt.lc,
                    ctx->dt.first, ctx->dt.count, ctx->dt.offset, ctx->dt.sorted_sym};
@@ -782,9 +784,13 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
 
   CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
   if (eb_mode == SZ_EB_REL)
-    CHECK_HIP(timed(ctx, "minmax", st, [&] { return launch_minmax(d_in, dtype, s.n, ctx->meta, st); }),
+    CHECK_HIP(timed(ctx, "minmax", st, [&] {
+                return launch_minmax(d_in, dtype, s.n, ctx->meta, ctx->mm_part, st);
+              }),
               "minmax");
-  CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st), "resolve_eb");
+  CHECK_HIP(launch_resolve_eb(dtype, eb_mode, eb, ctx->meta, st, ctx->mm_part,
+                              eb_mode == SZ_EB_REL && s.n ? (uint32_t)minmax_blocks(s.n) : 0u),
+            "resolve_eb");
   // each level's predictor: the fixed one, or (adaptive) the cheaper one by
   // the levels' cost sums (cubic on ties), recorded as a mask in the header
   int lvl_pred[kMaxLevels + 1];

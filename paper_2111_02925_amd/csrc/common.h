@@ -125,8 +125,18 @@ size_t ctx_fixed_bytes();
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
 hipError_t launch_meta_init(Meta* m, hipStream_t st);
-hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, hipStream_t st);
-hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st);
+// The range pass: minmax_blocks(n) workgroups, each writing its minimum and
+// maximum keys to its pair of part (2 x kMinmaxBlocks u64), which the eb
+// kernel folds into m (nblk = minmax_blocks(n); 0 when the pass did not run).
+constexpr uint32_t kMinmaxBlocks = 2048;
+inline uint64_t minmax_blocks(uint64_t n) {
+  const uint64_t b = (n + 256 * 64 - 1) / (256 * 64);
+  return b < 1 ? 1 : b > kMinmaxBlocks ? kMinmaxBlocks : b;
+}
+hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, uint64_t* part,
+                         hipStream_t st);
+hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st,
+                             const uint64_t* part = nullptr, uint32_t nblk = 0);
 
 hipError_t launch_origin_compress(const void* x, int dtype, void* rec, uint16_t* codes,
                                   const Meta* m, uint32_t radius, hipStream_t st);

@@ -111,11 +111,14 @@ __device__ __forceinline__ void fold_minmax(T v, T& lo, T& hi) {
   hi = __builtin_fmax(hi, fin ? v : -inf);
 }
 
-// Grid-stride reduction with 16-byte loads; one 64-bit atomic pair per block.
-// (bid, nblk): this workgroup among the nblk that share the field.
+// Grid-stride reduction with 16-byte loads.  Each workgroup's keys go to its
+// pair of part[] (summed by the eb kernel: workgroups that end together
+// would otherwise queue on the same two addresses), or with part null, into
+// m by one 64-bit atomic pair.  (bid, nblk): this workgroup among the nblk
+// that share the field.
 template <typename T>
 __device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n, Meta* m,
-                                            uint32_t bid, uint32_t nblk) {
+                                            uint32_t bid, uint32_t nblk, uint64_t* part) {
   constexpr int V = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(V)));
   T vlo = __builtin_inf(), vhi = -__builtin_inf();
@@ -160,7 +163,10 @@ __device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n,
       lo = slo[k] < lo ? slo[k] : lo;
       hi = shi[k] > hi ? shi[k] : hi;
     }
-    if (lo != ~0ull) {
+    if (part) {
+      part[2 * bid] = lo;
+      part[2 * bid + 1] = hi;
+    } else if (lo != ~0ull) {
       atomicMin((unsigned long long*)&m->key_min, (unsigned long long)lo);
       atomicMax((unsigned long long*)&m->key_max, (unsigned long long)hi);
     }
@@ -168,21 +174,21 @@ __device__ __forceinline__ void minmax_body(const T* __restrict__ x, uint64_t n,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_t n, Meta* m) {
-  minmax_body<T>(x, n, m, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_t n, Meta* m,
+                                                uint64_t* part) {
+  minmax_body<T>(x, n, m, blockIdx.x, gridDim.x, part);
 }
 
-hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, hipStream_t st) {
+hipError_t launch_minmax(const void* x, int dtype, uint64_t n, Meta* m, uint64_t* part,
+                         hipStream_t st) {
   if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + 256 * 64 - 1) / (256 * 64);
-  if (blocks < 1) blocks = 1;
-  if (blocks > 2048) blocks = 2048;
+  const uint64_t blocks = minmax_blocks(n);
   if (dtype == SZ_F32)
     hipLaunchKernelGGL(k_minmax<float>, dim3((unsigned)blocks), dim3(256), 0, st,
-                       (const float*)x, n, m);
+                       (const float*)x, n, m, part);
   else
     hipLaunchKernelGGL(k_minmax<double>, dim3((unsigned)blocks), dim3(256), 0, st,
-                       (const double*)x, n, m);
+                       (const double*)x, n, m, part);
   return hipGetLastError();
 }
 
@@ -208,16 +214,46 @@ __device__ __forceinline__ void resolve_eb(int mode, double value, Meta* m) {
   m->inv2eb = (double)inv;
 }
 
+// (nblk > 0: the minimum and maximum keys first, from the nblk pairs of
+// part that k_minmax wrote, folded into m's)
 template <typename T>
-__global__ void k_resolve_eb(int mode, double value, Meta* m) {
-  resolve_eb<T>(mode, value, m);
+__global__ __launch_bounds__(256) void k_resolve_eb(int mode, double value, Meta* m,
+                                                    const uint64_t* __restrict__ part,
+                                                    uint32_t nblk) {
+  if (nblk) {
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint32_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+      lo = part[2 * i] < lo ? part[2 * i] : lo;
+      hi = part[2 * i + 1] > hi ? part[2 * i + 1] : hi;
+    }
+    lo = wave_min_u64(lo);
+    hi = wave_max_u64(hi);
+    __shared__ uint64_t slo[4], shi[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      slo[w] = lo;
+      shi[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+        lo = slo[k] < lo ? slo[k] : lo;
+        hi = shi[k] > hi ? shi[k] : hi;
+      }
+      if (lo < m->key_min) m->key_min = lo;
+      if (hi > m->key_max && lo != ~0ull) m->key_max = hi;
+    }
+  }
+  if (threadIdx.x == 0) resolve_eb<T>(mode, value, m);
 }
 
-hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st) {
+hipError_t launch_resolve_eb(int dtype, int mode, double value, Meta* m, hipStream_t st,
+                             const uint64_t* part, uint32_t nblk) {
+  if (nblk > kMinmaxBlocks || (nblk && !part)) return hipErrorInvalidValue;
   if (dtype == SZ_F32)
-    hipLaunchKernelGGL(k_resolve_eb<float>, dim3(1), dim3(1), 0, st, mode, value, m);
+    hipLaunchKernelGGL(k_resolve_eb<float>, dim3(1), dim3(256), 0, st, mode, value, m, part, nblk);
   else
-    hipLaunchKernelGGL(k_resolve_eb<double>, dim3(1), dim3(1), 0, st, mode, value, m);
+    hipLaunchKernelGGL(k_resolve_eb<double>, dim3(1), dim3(256), 0, st, mode, value, m, part, nblk);
   return hipGetLastError();
 }
 
@@ -1438,7 +1474,7 @@ __global__ __launch_bounds__(256) void k_b_minmax(BLaunch L) {
   uint32_t local;
   if (!batch_job(L, j, local)) return;
   const BField& f = L.f[j.field];
-  minmax_body<T>(static_cast<const T*>(f.x), f.n, f.m, local, j.nblk);
+  minmax_body<T>(static_cast<const T*>(f.x), f.n, f.m, local, j.nblk, nullptr);
 }
 
 hipError_t launch_b_minmax(int dtype, BLaunch L, uint32_t nwg, hipStream_t st) {
