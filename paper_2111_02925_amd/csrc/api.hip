@@ -782,7 +782,8 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
   uint8_t hdr[kHeaderBytes];
   header_template(s, predictor, eb_mode, eb, hdr);
 
-  CHECK_HIP(launch_meta_init(ctx->meta, st), "meta_init");
+  // (the histogram cleared in the same launch)
+  CHECK_HIP(launch_meta_init(ctx->meta, st, ctx->hist, nsym), "meta_init");
   if (eb_mode == SZ_EB_REL)
     CHECK_HIP(timed(ctx, "minmax", st, [&] {
                 return launch_minmax(d_in, dtype, s.n, ctx->meta, ctx->mm_part, st);
@@ -968,7 +969,6 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
                 return e;
               }), "interp");
   }
-  CHECK_HIP(launch_fill_u32(ctx->hist, 0, nsym, st), "fill");
   CHECK_HIP(timed(ctx, "histogram", st,
                   [&] { return launch_histogram(codes, s.n, s.radius, ctx->hist_part, ctx->hist, ctx->meta, st);
                   }),

@@ -124,7 +124,9 @@ size_t ctx_fixed_bytes();
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
-hipError_t launch_meta_init(Meta* m, hipStream_t st);
+// Meta's start values (and, with nzero > 0, zero[0 .. nzero) cleared in the
+// same launch).
+hipError_t launch_meta_init(Meta* m, hipStream_t st, uint32_t* zero = nullptr, uint64_t nzero = 0);
 // The range pass: minmax_blocks(n) workgroups, each writing its minimum and
 // maximum keys to its pair of part (2 x kMinmaxBlocks u64), which the eb
 // kernel folds into m (nblk = minmax_blocks(n); 0 when the pass did not run).

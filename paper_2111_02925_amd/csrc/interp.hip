@@ -52,10 +52,19 @@ __device__ __forceinline__ void meta_init(Meta* m) {
   m->hist_far = 0;
 }
 
-__global__ void k_meta_init(Meta* m) { meta_init(m); }
+// (with nzero > 0, also zero[0 .. nzero), in the same launch)
+__global__ void k_meta_init(Meta* m, uint32_t* zero, uint64_t nzero) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) meta_init(m);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nzero;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    zero[i] = 0;
+}
 
-hipError_t launch_meta_init(Meta* m, hipStream_t st) {
-  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(1), 0, st, m);
+hipError_t launch_meta_init(Meta* m, hipStream_t st, uint32_t* zero, uint64_t nzero) {
+  if (nzero && !zero) return hipErrorInvalidValue;
+  uint64_t blocks = (nzero + 255) / 256;
+  blocks = blocks < 1 ? 1 : blocks > 256 ? 256 : blocks;
+  hipLaunchKernelGGL(k_meta_init, dim3((unsigned)blocks), dim3(256), 0, st, m, zero, nzero);
   return hipGetLastError();
 }
 
