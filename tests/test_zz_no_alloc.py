@@ -41,6 +41,11 @@ SEQUENCE = [
      "rel", 1e-4, "linear"),
     ("lognormal 64x60x50 f32 adaptive", lambda: synth.lognormal_grf((64, 60, 50), seed=63),
      "rel", 1e-3, "adaptive"),
+    # the order choice of two and four dimensions (rows sampled in the kernel)
+    ("climate 181x362 f32 adaptive", lambda: synth.climate_2d((181, 362), seed=4, dtype=np.float32),
+     "rel", 1e-3, "adaptive"),
+    ("random 6x10x8x40 f32 adaptive", lambda: synth.random_field((6, 10, 8, 40), seed=69),
+     "rel", 1e-3, "adaptive"),
     ("lognormal 30x20x26 f32 lorenzo abs", lambda: synth.lognormal_grf((30, 20, 26), seed=64),
      "abs", 1e-2, "lorenzo"),
 ]
