@@ -568,8 +568,8 @@ hipError_t launch_small_levels_recon(const uint16_t* codes, int dtype, void* out
 //    points), where each lane finds its own level and dimension.
 // Both columns' stencils are fetched (every load issued before any is used;
 // idle lanes read their row's first point) and evaluated by the same code.
-// The full estimate gives a unit (up to 512 columns) to one wave, which
-// works out its geometry once for up to four pairs a lane, and each wave a
+// The full estimate gives a unit (up to 256 columns) to one wave, which
+// works out its geometry once for up to two pairs a lane, and each wave a
 // contiguous run of units; the waves of one XCD (workgroup b on XCD b mod 8)
 // take runs of one contiguous eighth of the field, so the rows and planes
 // the stencils reach are read by waves of the same XCD at about the same
@@ -961,11 +961,12 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate_orders(const T* __rest
 hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Meta* m,
                            uint32_t radius, uint64_t* cost, hipStream_t st, const uint8_t* pos_dev) {
   if (g.units == 0) return hipSuccess;
-  // units of one wave, up to four pairs a lane: a unit is up to 512
-  // columns, whose geometry one wave works out for all of them
+  // units of one wave, up to two pairs a lane: a unit is up to 256 columns,
+  // whose geometry one wave works out for all of them (four pairs a lane,
+  // fewer waves of more registers, ran 3 % slower)
   EstGeom w = g;
   const uint64_t ncol = g.dims[g.ndim - 1];
-  w.pairs = ncol <= 2 * kEstWave ? 1 : ncol <= 4 * kEstWave ? 2 : 4;
+  w.pairs = ncol <= 2 * kEstWave ? 1 : 2;
   w.segs = (ncol + 2 * kEstWave * w.pairs - 1) / (2 * kEstWave * w.pairs);
   w.units = g.units / g.segs * w.segs;
   const uint64_t wpb = kEstThreads / kEstWave, nb = (w.units + wpb - 1) / wpb;
@@ -993,10 +994,8 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
   } while (0)
   if (w.pairs == 1)
     SZG_EST(1);
-  else if (w.pairs == 2)
-    SZG_EST(2);
   else
-    SZG_EST(4);
+    SZG_EST(2);
 #undef SZG_EST2
 #undef SZG_EST
   return hipGetLastError();
