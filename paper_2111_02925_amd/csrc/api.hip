@@ -877,8 +877,9 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
       }
       const int L = level_count(s.ndim, s.dims);
       if (cand) {  // chosen on the device: the full estimate follows with no round trip
-        CHECK_HIP(launch_choose_order(ctx->lvl_cost, s.ndim, pos, (uint32_t)nperm, L, chosen, st),
-                  "choose_order");
+        // (the chosen order's sums over the sampled rows seed the level sums)
+        CHECK_HIP(launch_choose_order(ctx->lvl_cost, s.ndim, pos, (uint32_t)nperm, L, chosen, lvl,
+                                      st), "choose_order");
         device_order = true;
       } else {
         std::array<uint64_t, 2 * kMaxLevels * kMaxOrders> cost;
@@ -901,8 +902,11 @@ static int compress_core(sz_ctx* ctx, const void* d_in, int dtype, int ndim, con
         for (int j = 0; j < s.ndim; j++) s.order[j] = perms[bi][j];
       }
     }
-    CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(lvl), 0, 4 * kMaxLevels, st), "fill");
-    const EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);  // (places: the device's choice)
+    if (!device_order)
+      CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(lvl), 0, 4 * kMaxLevels, st), "fill");
+    // (places: the device's choice, whose sampled rows are summed already)
+    EstGeom eg = make_estimate_geom(s.ndim, s.dims, s.order);
+    if (device_order) eg.sampled = 2;
     CHECK_HIP(timed(ctx, "estimate", st, [&] {
                 return launch_estimate(d_in, dtype, eg, ctx->meta, s.radius, lvl, st,
                                        device_order ? chosen + 1 : nullptr);

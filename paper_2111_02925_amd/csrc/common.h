@@ -153,7 +153,7 @@ struct EstGeom {
   uint32_t pairs;         // column pairs a lane takes per unit (1, 2 or 4)
   uint64_t segs;          // units per row along the last dimension
   uint64_t units;         // rows x segs
-  uint32_t sampled;       // 1: only the rows est_row_sampled takes
+  uint32_t sampled;       // 1: only the rows est_row_sampled takes; 2: only the others
 };
 EstGeom make_estimate_geom(int ndim, const uint64_t* dims, const uint8_t* order);
 // The rows that price the dimension orders: row index r when the top three
@@ -184,9 +184,12 @@ uint32_t cand_row_class(int ndim, const uint64_t* dims, uint64_t r);
 // The order choice from the buckets on the device (no host round trip):
 // of the norders orders (orders[k][d]: the place of dimension d), the one
 // whose sum over levels 1..levels of the cheaper cost sum is least, the
-// first on ties; chosen[0] its index, chosen[1..4] its places.
+// first on ties; chosen[0] its index, chosen[1..4] its places; with lvl
+// non-null, the chosen order's sums over the sampled rows in lvl (2 x
+// kMaxLevels: linear, cubic per level).
 hipError_t launch_choose_order(const uint64_t* bucket, int ndim, const uint8_t (*orders)[kMaxDims],
-                               uint32_t norders, int levels, uint8_t* chosen, hipStream_t st);
+                               uint32_t norders, int levels, uint8_t* chosen, uint64_t* lvl,
+                               hipStream_t st);
 // The sampled estimate of norders dimension orders (orders[k][d]: the place
 // of dimension d in order k) in one launch, over the sampled rows listed in
 // rows[] (ascending flat row indices, est_row_sampled); order k's sums at

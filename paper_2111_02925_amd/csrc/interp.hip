@@ -894,7 +894,7 @@ __global__ __launch_bounds__(kEstThreads) void k_estimate(const T* __restrict__ 
       }
     }
     for (uint64_t u = u0; u < u1; u++) {
-      if (!g.sampled || est_row_sampled(row)) {
+      if (g.sampled == 0 || (g.sampled == 1) == est_row_sampled(row)) {
         const EstUnit un = est_unit_at<kEstWave, J>(g, pos, q, seg);
         est_unit<T, kEstWave, J, N>(x, g, pos[last], un, eb, inv2eb, R, sh, acc1l, acc1c, acc2l,
                                     acc2c);
@@ -1287,10 +1287,12 @@ __device__ __forceinline__ void cand_level(const uint64_t* bucket, int ndim, con
 
 // The order choice on the device: every order's sum over levels 1..L of its
 // cheaper cost sum, the least first in the list (orders[k]: the place of
-// each dimension); chosen[0] the index, chosen[1..] its places.
+// each dimension); chosen[0] the index, chosen[1..] its places.  With lvl
+// non-null, the chosen order's sums over the sampled rows go to lvl (2 per
+// level, every level), so that the full estimate need only add the others.
 __global__ __launch_bounds__(256) void k_choose_order(const uint64_t* __restrict__ bucket_g, int ndim,
                                                       EstOrders o, uint32_t norders, int L,
-                                                      uint8_t* chosen) {
+                                                      uint8_t* chosen, uint64_t* lvl) {
   __shared__ uint64_t bucket[kCandBuckets];
   __shared__ unsigned long long total[kMaxOrders];
   for (uint32_t i = threadIdx.x; i < kCandBuckets; i += blockDim.x) bucket[i] = bucket_g[i];
@@ -1304,28 +1306,35 @@ __global__ __launch_bounds__(256) void k_choose_order(const uint64_t* __restrict
     atomicAdd(&total[k], (unsigned long long)(c < l ? c : l));
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  uint64_t best = ~0ull;
-  uint32_t bi = 0;
-  for (uint32_t k = 0; k < norders; k++) {
-    if (total[k] < best) {
-      best = total[k];
-      bi = k;
+  __shared__ uint32_t sbi;
+  if (threadIdx.x == 0) {
+    uint64_t best = ~0ull;
+    uint32_t bi = 0;
+    for (uint32_t k = 0; k < norders; k++) {
+      if (total[k] < best) {
+        best = total[k];
+        bi = k;
+      }
     }
+    chosen[0] = (uint8_t)bi;
+    for (int d = 0; d < kMaxDims; d++) chosen[1 + d] = o.pos[bi][d];
+    sbi = bi;
   }
-  chosen[0] = (uint8_t)bi;
-  for (int d = 0; d < kMaxDims; d++) chosen[1 + d] = o.pos[bi][d];
+  __syncthreads();
+  if (lvl && threadIdx.x < (uint32_t)kMaxLevels)
+    cand_level(bucket, ndim, o.pos[sbi], threadIdx.x, lvl[2 * threadIdx.x], lvl[2 * threadIdx.x + 1]);
 }
 
 hipError_t launch_choose_order(const uint64_t* bucket, int ndim, const uint8_t (*orders)[kMaxDims],
-                               uint32_t norders, int levels, uint8_t* chosen, hipStream_t st) {
+                               uint32_t norders, int levels, uint8_t* chosen, uint64_t* lvl,
+                               hipStream_t st) {
   if (norders == 0 || norders > (uint32_t)kMaxOrders || ndim < 1 || ndim > 3)
     return hipErrorInvalidValue;
   EstOrders o{};
   for (uint32_t k = 0; k < norders; k++)
     for (int d = 0; d < kMaxDims; d++) o.pos[k][d] = orders[k][d];
   hipLaunchKernelGGL(k_choose_order, dim3(1), dim3(256), 0, st, bucket, ndim, o, norders, levels,
-                     chosen);
+                     chosen, lvl);
   return hipGetLastError();
 }
 
