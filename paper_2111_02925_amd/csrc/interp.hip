@@ -1009,11 +1009,12 @@ hipError_t launch_estimate(const void* x, int dtype, const EstGeom& g, const Met
 // depend on the order.  So every point is priced once along each of its
 // candidate dimensions, into the bucket (t, candidate set C, dimension d),
 // and an order's cost sum for level t + 1 is the sum over C of the bucket of
-// C's last dimension in that order (combined on the host).
+// C's last dimension in that order (combined on the device by
+// k_choose_order).
 //
 // A row's class is (t_row, R): t_row the fewest trailing zeros among its
 // coordinates other than the column, R the dimensions that have them.  A
-// column c with t_c trailing zeros is on level min(t_c, t_row); its
+// column c with t_c trailing zeros holds a point of t = min(t_c, t_row); its
 // candidates are the column when t_c <= t_row and R when t_row <= t_c.  So a
 // point's buckets are (t_c, {last}) when t_c < t_row (summed over the block
 // by level), (t_row, R + {last}) when t_c = t_row and (t_row, R) when
