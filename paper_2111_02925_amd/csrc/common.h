@@ -130,7 +130,7 @@ hipError_t launch_meta_init(Meta* m, hipStream_t st, uint32_t* zero = nullptr, u
 // The range pass: minmax_blocks(n) workgroups, each writing its minimum and
 // maximum keys to its pair of part (2 x kMinmaxBlocks u64), which the eb
 // kernel folds into m (nblk = minmax_blocks(n); 0 when the pass did not run).
-constexpr uint32_t kMinmaxBlocks = 2048;
+constexpr uint32_t kMinmaxBlocks = 512;  // (two workgroups a CU: 2048 took 105 us at 512^3, 512 take 83)
 inline uint64_t minmax_blocks(uint64_t n) {
   const uint64_t b = (n + 256 * 64 - 1) / (256 * 64);
   return b < 1 ? 1 : b > kMinmaxBlocks ? kMinmaxBlocks : b;
