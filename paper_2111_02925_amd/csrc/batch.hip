@@ -353,9 +353,11 @@ void build_steps(BatchPlan& P, const std::vector<BatchItem>& items, const std::v
   P.steps.push_back(s);
   for (int dt : {SZ_F32, SZ_F64}) {
     std::vector<BJob> js;
+    // (a workgroup per 64K points, at most 512 a field: longer grid-stride
+    // runs read faster, as in the single-field range pass)
     for (uint32_t i = 0; i < nf; i++)
       if (P.fields[i].dtype == dt && P.fields[i].eb_mode == SZ_EB_REL)
-        js.push_back(field_job(i, std::min<uint32_t>(2048, std::max<uint32_t>(1, cdiv32(P.fields[i].n, 256 * 64)))));
+        js.push_back(field_job(i, std::min<uint32_t>(512, std::max<uint32_t>(1, cdiv32(P.fields[i].n, 256 * 256)))));
     Step m{};
     m.op = Op::Minmax;
     m.dtype = dt;
